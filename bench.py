@@ -1,0 +1,182 @@
+"""Benchmark: time-to-rtol of deflated GMRES(50) on one MI355X.
+
+Workload: 1024 x 1024 Q1 convection-diffusion (1,050,625 unknowns, 9,443,329
+stored entries), per-element log-normal diffusion (sigma = 1), beta = (100, 0),
+b ~ U[-1, 1], 64 subdomain-indicator deflation vectors, GMRES(50), rtol 1e-8,
+zero initial guess.  Synthetic, seeded inputs, resident in HBM before timing.
+
+One step = the plain FP64 solve followed by the mixed-precision solve (FP32
+inner GMRES with an FP16-stored basis inside FP64 iterative refinement) of the
+same system, both to a true FP64 relative residual <= 1e-8.  `value` is the
+median time-to-rtol of the mixed solve; the FP64 time and the ratio are
+reported beside it.
+
+Prints one JSON line.  `roofline` covers the dominant Arnoldi kernel (timed
+with HIP events on the solver's stream during the timed steps);
+`cpu_baseline` times the CPU oracle on a bounded sample of the same solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-rtol 1e-8 (s) + SpMV/Arnoldi HBM GB/s; mixed vs FP64 GMRES"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sysm, m, fp64_iters, sample_iters):
+    """Oracle (plain C, FP64, one thread) on `sample_iters` inner steps of the
+    same system; time-to-rtol extrapolated with the solve's iteration count."""
+    import oracle
+    t0 = time.perf_counter()
+    res = oracle.gmres(sysm, m, 0.0, sample_iters)
+    dt = time.perf_counter() - t0
+    per_iter = dt / max(res.iters, 1)
+    return dict(value=per_iter * fp64_iters, unit="s", cores=1, kind="oracle",
+                sample=(f"{res.iters} fixed-count deflated GMRES({m}) steps of the same "
+                        f"1,050,625-unknown system incl. setup ({dt:.1f} s), scaled to the "
+                        f"{fp64_iters} steps the FP64 solve needs to reach rtol 1e-8"),
+                seconds_per_iter=per_iter, sample_seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mesh", type=int, default=1024)
+    ap.add_argument("--cpu-sample-iters", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1906_04051_amd import gmres as G
+    from paper_1906_04051_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    cfg = W.CONFIGS[2]
+    m = cfg["m"]
+    log(f"[bench] generating config 2 at mesh {args.mesh}")
+    sysm = W.make_config(2, mesh=args.mesh)
+    d = G.upload(sysm)
+    common = dict(m=m, rtol=1e-8, max_iters=200000)
+    plans = {}
+    if args.only in ("both", "fp64"):
+        plans["fp64"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
+                               d["z_vals"], r=sysm.r, precision="fp64", **common)
+    if args.only in ("both", "mixed"):
+        plans["mixed"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
+                                d["z_vals"], r=sysm.r, precision="mixed_f16", inner_rtol=1e-3,
+                                inner_max_iters=100000, max_refine=40, **common)
+    for k, p in plans.items():
+        log(f"[bench] autotune {k}: {p.autotune()}")
+    b = d["b"]
+    x = torch.empty_like(b)
+
+    def run(name, timing):
+        p = plans[name]
+        p.set_timing(timing)
+        t0 = time.perf_counter()
+        _, info = p.solve(b, out=x)
+        dt = time.perf_counter() - t0
+        kt = p.kernel_times() if timing else None
+        return dt, info, kt
+
+    for w in range(args.warmup):
+        for name in plans:
+            dt, info, _ = run(name, False)
+            log(f"[bench] warmup {name}: {dt:.3f} s iters {info['iters']} status {info['status_name']} "
+                f"rel_res_true {info['rel_res_true']:.3e}")
+
+    timing = not args.no_timing
+    times = {k: [] for k in plans}
+    infos = {}
+    ktot = {}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for step in range(args.steps):
+        for name in plans:
+            dt, info, kt = run(name, timing)
+            times[name].append(dt)
+            infos[name] = info
+            if kt:
+                for kk, v in kt.items():
+                    a = ktot.setdefault((name, kk), dict(launches=0.0, ms=0.0, bytes=0.0))
+                    for f in ("launches", "ms", "bytes"):
+                        a[f] += v[f]
+            log(f"[bench] step {step} {name}: {dt:.3f} s iters {info['iters']} "
+                f"refinements {info['refinements']} status {info['status_name']} "
+                f"rel_res_true {info['rel_res_true']:.3e}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    headline = "mixed" if "mixed" in med else "fp64"
+    out = {
+        "metric": METRIC,
+        "value": med[headline],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * total / max(args.steps, 1),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32/f16+f64" if headline == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"q1_convection_diffusion_{args.mesh}x{args.mesh}_lognormal",
+                   "unknowns": sysm.n, "nnz": sysm.nnz, "restart_m": m, "deflation_vectors": sysm.r,
+                   "rtol": 1e-8, "step": "+".join(plans)},
+    }
+    for k in plans:
+        out[f"time_to_rtol_{k}_s"] = med[k]
+        out[f"iters_{k}"] = infos[k]["iters"]
+        out[f"rel_res_true_{k}"] = infos[k]["rel_res_true"]
+    if "mixed" in med and "fp64" in med:
+        out["mixed_speedup_vs_fp64"] = med["fp64"] / med["mixed"]
+        out["refinements_mixed"] = infos["mixed"]["refinements"]
+    if ktot:
+        per = {}
+        for (name, kk), v in ktot.items():
+            if v["launches"] > 0:
+                per[f"{name}.{kk}"] = dict(launches=int(v["launches"]), avg_us=1000 * v["ms"] / v["launches"],
+                                           GBs=v["bytes"] / (v["ms"] * 1e6), total_ms=v["ms"])
+        out["kernels"] = per
+        # Dominant kernel: most total time in the FP64 solve (else the mixed one).
+        src = "fp64" if "fp64" in plans else "mixed"
+        cand = {kk: v for (nm, kk), v in ktot.items() if nm == src and v["launches"] > 0}
+        dom = max(cand, key=lambda kk: cand[kk]["ms"])
+        v = cand[dom]
+        achieved = v["bytes"] / (v["ms"] * 1e6)
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": f"{src}.{dom}", "launches": int(v["launches"]),
+                           "avg_launch_us": 1000 * v["ms"] / v["launches"],
+                           "bytes_per_launch_avg": v["bytes"] / v["launches"]}
+    if not args.no_cpu_baseline:
+        fp64_iters = infos["fp64"]["iters"] if "fp64" in infos else infos[headline]["iters"]
+        log(f"[bench] cpu baseline: oracle, {args.cpu_sample_iters} steps")
+        out["cpu_baseline"] = cpu_baseline(sysm, m, fp64_iters, args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

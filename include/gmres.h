@@ -1,0 +1,189 @@
+/*
+ * gmres.h -- C interface of the MI355X (gfx950) deflated GMRES(m) library.
+ *
+ * The solver computes x with A x = b by restarted GMRES(m) (arXiv 1906.04051,
+ * Sec. 3.2: Arnoldi basis of the Krylov space, eq. krylov-basis; least squares
+ * with the Hessenberg matrix reduced by plane rotations, eqs. arg and
+ * hessenberg; residual estimate |gamma_{k+1}|, eq. res; restarts from x_m;
+ * termination on ||b - A x|| / ||b - A x0|| <= rtol, eq. relative) applied to
+ * the deflated operator P A, P = I - A Z E^{-1} Z^T with E = Z^T A Z for a
+ * caller-supplied basis Z (the role of U and T_r = U^T A U in Sec. 3.3,
+ * eqs. precond2 and tau_mat).  The returned solution carries the coarse
+ * correction x = x_hat + Z E^{-1} Z^T (b - A x_hat), so b - A x = P (b - A x_hat)
+ * and the stopping test is on the true residual of x.
+ *
+ * Conventions for every function:
+ *   - Pointers without the suffix _h are DEVICE pointers (hipMalloc / torch
+ *     CUDA tensors) of the device current when gmres_setup was called; _h
+ *     pointers are host memory.
+ *   - Matrices are CSR with int32 row pointers and column indices (0-based)
+ *     and float64 values (Sec. 4: CSR storage, double precision).
+ *   - Functions return a gmres_status: negative values are errors (outputs are
+ *     untouched unless stated), positive values are non-fatal outcomes.  The
+ *     message of the last error on the calling thread is gmres_last_error().
+ *   - All device work is enqueued on the plan's stream; functions that report
+ *     results on the host synchronise that stream before returning.
+ *   - No function aborts, throws or prints.
+ */
+#ifndef GMRES_MI355X_H
+#define GMRES_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmres_plan_s* gmres_plan;
+
+typedef enum {
+    GMRES_OK = 0,           /* converged: ||b - A x|| <= rtol * ||b - A x0|| */
+    GMRES_MAXITER = 1,      /* iteration cap reached; x holds the last iterate (with rtol = 0
+                               this is the normal end of the fixed-count protocol, Sec. 4) */
+    GMRES_BREAKDOWN = 2,    /* reserved: breakdowns are resolved by the true-residual test */
+    GMRES_STAGNATED = 3,    /* mixed precision: refinement stopped reducing the FP64 residual */
+    GMRES_EINVAL = -1,      /* invalid argument or malformed CSR */
+    GMRES_ESINGULAR = -2,   /* E = Z^T A Z is singular (|pivot| <= r * eps * max|E|) */
+    GMRES_ENONFINITE = -3,  /* NaN or Inf in A, Z, b or x0 */
+    GMRES_EDEVICE = -4,     /* HIP runtime error */
+    GMRES_ENOMEM = -5       /* device allocation failed */
+} gmres_status;
+
+typedef enum {
+    GMRES_FP64 = 0,          /* FP64 values, basis, vectors and reductions */
+    GMRES_MIXED_F32 = 1,     /* FP64 iterative refinement around an FP32 inner solve (FP32 basis) */
+    GMRES_MIXED_F16 = 2      /* as above with an FP16-stored basis (per-vector scale) */
+} gmres_precision;
+
+typedef struct {
+    int32_t m;                /* restart length, 1 <= m <= 96 (Sec. 3.2, GMRES(m)) */
+    int64_t max_iters;        /* cap on inner Arnoldi steps over all restarts (FP64 path) */
+    double  rtol;             /* relative tolerance on ||b - A x||; 0 = run exactly max_iters
+                                 steps (the paper's fixed-count protocol, Sec. 4) */
+    double  r0_norm_override; /* > 0: use as ||b - A x0|| (resume from a checkpointed x) */
+    int32_t precision;        /* gmres_precision */
+    double  inner_rtol;       /* mixed: relative tolerance of each inner solve */
+    int32_t max_refine;       /* mixed: cap on refinement steps */
+    int64_t inner_max_iters;  /* mixed: cap on inner steps per refinement */
+    int32_t use_graph;        /* 1: replay each restart cycle as a captured hipGraph */
+    int32_t record_history;   /* 1: keep |gamma_{k+1}| per step (gmres_history) */
+    int32_t spmv_lanes;       /* lanes per CSR row in SpMV (1..64, power of two); 0 = auto */
+    int32_t num_blocks;       /* workgroups of the streaming kernels; 0 = auto */
+    int32_t batch_wg;         /* batched: threads per workgroup (256, 512, 1024); 0 = auto */
+    int32_t batch_lanes;      /* batched: SpMV lanes per row (4, 8, 16, 32); 0 = auto */
+} gmres_opts;
+
+typedef struct {
+    int64_t iters;            /* inner Arnoldi steps (all restarts, all refinements) */
+    int32_t cycles;           /* restart cycles */
+    int32_t refinements;      /* mixed: refinement steps */
+    int32_t status;           /* gmres_status */
+    int32_t pad;
+    double  rho0;             /* ||b - A x0|| (or the override) */
+    double  rel_res;          /* ||P (b - A x_hat)|| / rho0 at exit (= true relative residual of x) */
+    double  rel_res_true;     /* ||b - A x|| / rho0 recomputed from the returned x (FP64) */
+    double  solve_ms;         /* host wall time of the call */
+} gmres_info;
+
+/* Fills *o with defaults: m = 30, max_iters = 10000, rtol = 1e-8, FP64,
+ * inner_rtol = 1e-3 (FP16 basis) , max_refine = 30, inner_max_iters = 20000,
+ * use_graph = 1, everything else 0 (auto). */
+void gmres_default_opts(gmres_opts* o);
+
+/*
+ * Builds a plan for nsys independent systems stored as one block-diagonal CSR
+ * matrix of n_total = sys_row_off_h[nsys] rows (nsys = 1: a single system).
+ * Rows [sys_row_off_h[s], sys_row_off_h[s+1]) form system s; their column
+ * indices must lie in the same range.  Z is an n_total x r_total CSR matrix
+ * whose columns [sys_zcol_off_h[s], sys_zcol_off_h[s+1]) belong to system s
+ * (r_s = 0 allowed: plain GMRES(m)); r_s <= 256.  z_* may be NULL when
+ * r_total = 0.
+ *
+ * Setup (Sec. 3.3 analogue, done once): validates A and Z, copies them into
+ * plan-owned device memory, builds Z^T, the compact product A Z, E_s = Z^T A Z
+ * per system, its LU factors with partial pivoting and the explicit inverse;
+ * for need_adjoint also A^T, A^T Z and (E^T)^{-1}; FP32 copies for mixed
+ * precision.  The library allocates the plan's device memory itself; it is
+ * released by gmres_destroy.  stream: the HIP stream for all work (0 = null
+ * stream).  Errors: EINVAL (sizes, CSR, m, r_s > 256, a row of A Z with more
+ * than 64 deflation columns), ENONFINITE, ESINGULAR, ENOMEM, EDEVICE; *out is
+ * NULL on error.
+ */
+gmres_status gmres_setup(gmres_plan* out, int32_t nsys, const int64_t* sys_row_off_h,
+                         const int64_t* sys_zcol_off_h, const int32_t* rowptr,
+                         const int32_t* colind, const double* vals, int64_t nnz,
+                         const int32_t* z_rowptr, const int32_t* z_colind, const double* z_vals,
+                         int64_t z_nnz, const gmres_opts* opts, int32_t need_adjoint,
+                         hipStream_t stream);
+
+/*
+ * Solves A x = b for a single-system plan (nsys = 1) with the plan's options
+ * (FP64 or mixed-precision refinement).  b: n doubles; x0: n doubles or NULL
+ * (zero initial guess, the paper's usual choice); x: n doubles (output; may
+ * alias x0, not b).  info_h: optional host struct.  Returns the solve status
+ * (OK, MAXITER, STAGNATED) or an error.
+ */
+gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double* x,
+                         gmres_info* info_h);
+
+/*
+ * Solves every system of the plan in one persistent kernel launch (FP64),
+ * with a convergence state per system.  b, x0 (or NULL), x: n_total doubles
+ * in the block layout of the plan.  infos_h: optional host array of nsys
+ * structs (solve_ms holds that system's device solve time).  Returns OK when
+ * every system converged, else the first non-OK system status.
+ */
+gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0, double* x,
+                                 gmres_info* infos_h);
+
+/*
+ * Adjoint of x = A^{-1} b for a single-system plan built with need_adjoint:
+ * solves A^T lambda = grad_x with the same deflated GMRES(m) in FP64 (on A^T,
+ * A^T Z and E^T), then grad_b = lambda and grad_vals[k] = -lambda_i x_j for
+ * every stored entry k = (i, j) of A.  x: the forward solution (n doubles).
+ * grad_b: n doubles; grad_vals: nnz doubles (either may be NULL to skip).
+ */
+gmres_status gmres_adjoint(gmres_plan p, const double* x, const double* grad_x, double* grad_b,
+                           double* grad_vals, gmres_info* info_h);
+
+/* Replaces the values of A (same pattern; nnz doubles, device) and rebuilds
+ * A Z, E and its inverse, the FP32 copies and A^T's values.  ENONFINITE /
+ * ESINGULAR as in setup (the plan keeps the new values either way). */
+gmres_status gmres_update_values(gmres_plan p, const double* vals);
+
+/* y = A x with the plan's FP64 SpMV kernel (n doubles each). */
+gmres_status gmres_spmv(gmres_plan p, const double* x, double* y);
+
+/* Copies min(cap, iters) entries of the |gamma_{k+1}| history of the last
+ * solve (record_history = 1) to hist_h; returns the number copied or < 0. */
+int64_t gmres_history(gmres_plan p, double* hist_h, int64_t cap);
+
+/* Times candidate SpMV lane counts and streaming grid sizes on the plan's
+ * matrix (and, for batches, batched workgroup shapes) with HIP events, keeps
+ * the fastest in the plan, and reports them through *chosen_h (4 ints:
+ * spmv_lanes, num_blocks, batch_wg, batch_lanes; may be NULL). */
+gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h);
+
+/* Per-kernel timing of the last solve made with timing enabled
+ * (gmres_set_timing): for kernel class k (0 spmv, 1 pass1, 2 pass2, 3 pass3)
+ * writes {launches, total_ms, total_algorithmic_bytes} to out_h[3*k ..]. */
+gmres_status gmres_set_timing(gmres_plan p, int32_t enable);
+gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 12 doubles */);
+
+/* Switches the stream used by later calls. */
+gmres_status gmres_set_stream(gmres_plan p, hipStream_t stream);
+
+/* Releases the plan and its device memory (NULL allowed). */
+void gmres_destroy(gmres_plan p);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* gmres_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMRES_MI355X_H */

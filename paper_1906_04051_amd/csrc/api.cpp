@@ -1,0 +1,1092 @@
+// C interface of the deflated GMRES(m) library: plan setup, the host side of
+// the solve loops, and the batched and adjoint entry points.
+//
+// The host never waits inside a restart cycle: a cycle (m Arnoldi steps, the
+// end-of-cycle update and the restart decision) is enqueued as a whole --
+// optionally as one captured hipGraph -- and the host reads the device control
+// block of cycle c while cycle c + 1 is already queued.  One host/device
+// round trip per cycle, none per step (the paper found host-side reductions
+// and least squares costly, Sec. 4.4).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gmres.h"
+#include "internal.hpp"
+
+using namespace gm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gmres_status fail(gmres_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_OK(call)                                                                  \
+    do {                                                                              \
+        hipError_t _e = (call);                                                       \
+        if (_e != hipSuccess)                                                         \
+            return fail(GMRES_EDEVICE, std::string(#call ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+// Algorithmic-byte accounting and HIP-event timing of the streaming kernels.
+struct Timer {
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;
+    struct Rec { int kind; int cycle; int j; double bytes; int ev; };
+    std::vector<Rec> recs;
+    int used = 0;
+    double launches[4] = {0, 0, 0, 0};
+    double ms[4] = {0, 0, 0, 0};
+    double bytes[4] = {0, 0, 0, 0};
+
+    hipEvent_t ev(int i) {
+        while ((int)pool.size() <= i) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            pool.push_back(e);
+        }
+        return pool[i];
+    }
+    ~Timer() {
+        for (auto e : pool) hipEventDestroy(e);
+    }
+    void reset() {
+        recs.clear();
+        used = 0;
+        for (int k = 0; k < 4; ++k) launches[k] = ms[k] = bytes[k] = 0;
+    }
+};
+
+struct Plan;
+
+}  // namespace
+
+struct gmres_plan_s {
+    int device = 0;
+    hipStream_t user_stream = nullptr;
+    hipStream_t st = nullptr;           // plan-owned stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int nsys = 1;
+    int64_t n = 0, nnz = 0, znnz = 0;
+    int R = 0;
+    std::vector<int64_t> row_off, zcol_off, e_off_h;
+    gmres_opts o{};
+    int need_adjoint = 0;
+    std::vector<void*> allocs;
+
+    // plan-owned copies of the inputs
+    int *rowptr = nullptr, *colind = nullptr;
+    double* vals = nullptr;
+    int *zrp = nullptr, *zci = nullptr;
+    double* zv = nullptr;
+    float* vals32 = nullptr;
+    int64_t *d_row_off = nullptr, *d_zcol_off = nullptr, *d_e_off = nullptr;
+    int* d_flags = nullptr;
+
+    // Z^T
+    int *ztrp = nullptr, *ztci = nullptr, *ztperm = nullptr;
+    double* ztv = nullptr;
+    int MC = 1, CH = 2048;
+    // A Z (compact)
+    int *azrp = nullptr, *azci = nullptr;
+    double* azv = nullptr;
+    float* azv32 = nullptr;
+    int64_t az_nnz = 0;
+    double *E = nullptr, *Einv = nullptr;
+    // adjoint operator
+    int *trp = nullptr, *tci = nullptr, *tperm = nullptr;
+    double* tv = nullptr;
+    int *atzrp = nullptr, *atzci = nullptr;
+    double* atzv = nullptr;
+    int64_t atz_nnz = 0;
+
+    // single-system Krylov workspace
+    int NB = 1, L = 8, NB_cap = 1;
+    int64_t ldv = 0;
+    void* V = nullptr;
+    double *y = nullptr, *w = nullptr, *pv = nullptr, *rv = nullptr, *xh = nullptr, *bws = nullptr;
+    double *xo = nullptr, *r64 = nullptr, *dvec = nullptr;
+    double* part = nullptr;
+    double *h1, *h2, *coef1, *coef2, *H, *Hraw, *cs, *sn, *g, *vscale, *sigma, *sigma0, *scal;
+    double *tpart = nullptr, *s_step = nullptr, *s_res = nullptr;
+    Ctrl* ctrl = nullptr;
+    Ctrl* ctrl_h = nullptr;             // pinned, 2 snapshots
+    hipEvent_t ev_cyc[2] = {nullptr, nullptr};
+    double* hist = nullptr;
+    int64_t hist_cap = 0;
+    int64_t hist_len = 0;
+    int* cyc_k = nullptr;
+    int64_t cyc_cap = 0;
+
+    // graphs: [op (0 fwd, 1 adj)][prec]
+    hipGraphExec_t gexec[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    hipGraph_t graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+
+    // batched
+    int batch_wg = 256, batch_L = 8;
+    double *bV = nullptr, *bW = nullptr;
+    int* border = nullptr;
+    int* bticket = nullptr;
+    int64_t* bout_i = nullptr;
+    double* bout_d = nullptr;
+    int64_t* d_v_off = nullptr;
+
+    Timer timer;
+};
+
+namespace {
+
+template <typename T>
+gmres_status dalloc(gmres_plan_s* p, T** ptr, int64_t count) {
+    *ptr = nullptr;
+    if (count <= 0) return GMRES_OK;
+    void* q = nullptr;
+    const size_t bytes = ((size_t)count * sizeof(T) + 255) & ~(size_t)255;
+    if (hipMalloc(&q, bytes) != hipSuccess)
+        return fail(GMRES_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    p->allocs.push_back(q);
+    *ptr = reinterpret_cast<T*>(q);
+    return GMRES_OK;
+}
+
+#define CHECK(expr)                          \
+    do {                                     \
+        gmres_status _s = (expr);            \
+        if (_s != GMRES_OK) return _s;       \
+    } while (0)
+
+gmres_status to_status(int s, const char* what) {
+    switch (s) {
+        case kStatusOk: return GMRES_OK;
+        case kStatusInval: return fail(GMRES_EINVAL, std::string(what) + ": invalid input");
+        case kStatusSingular: return fail(GMRES_ESINGULAR, std::string(what) + ": E = Z^T A Z is singular");
+        case kStatusNonFinite: return fail(GMRES_ENONFINITE, std::string(what) + ": non-finite value");
+        case kStatusNoMem: return fail(GMRES_ENOMEM, std::string(what) + ": out of device memory");
+        default: return fail(GMRES_EDEVICE, std::string(what) + ": device error");
+    }
+}
+
+int default_lanes(int64_t n, int64_t nnz) {
+    const double rho = n > 0 ? (double)nnz / (double)n : 1.0;
+    if (rho <= 6) return 4;
+    if (rho <= 12) return 8;
+    if (rho <= 24) return 16;
+    return 32;
+}
+
+// Builds A Z (compact CSR) for the operator (rowptr, colind, vals).
+gmres_status build_az(gmres_plan_s* p, const int* rp, const int* ci, const double* v, int** azrp,
+                      int** azci, double** azv, int64_t* nnz_out) {
+    SetupArgs sa{p->st, p->nsys, p->n, p->nnz, p->znnz, p->R, p->d_row_off, p->d_zcol_off,
+                 rp, ci, v, p->zrp, p->zci, p->zv};
+    CHECK(dalloc(p, azrp, p->n + 1));
+    int64_t cnt = 0;
+    int s = az_count(sa, rp, ci, *azrp, &cnt);
+    if (s == kStatusInval)
+        return fail(GMRES_EINVAL, "a row of A*Z reaches more than 64 deflation columns");
+    CHECK(to_status(s, "A*Z"));
+    CHECK(dalloc(p, azci, cnt));
+    CHECK(dalloc(p, azv, cnt));
+    az_fill(sa, rp, ci, v, *azrp, *azci, *azv);
+    *nnz_out = cnt;
+    return GMRES_OK;
+}
+
+// (Re)computes everything derived from the values of A.
+gmres_status refresh_values(gmres_plan_s* p) {
+    SetupArgs sa{p->st, p->nsys, p->n, p->nnz, p->znnz, p->R, p->d_row_off, p->d_zcol_off,
+                 p->rowptr, p->colind, p->vals, p->zrp, p->zci, p->zv};
+    if (p->R > 0) {
+        az_fill(sa, p->rowptr, p->colind, p->vals, p->azrp, p->azci, p->azv);
+        build_coarse(sa, p->ztrp, p->ztci, p->ztv, p->azrp, p->azci, p->azv, p->d_e_off, p->E);
+        CHECK(to_status(lu_inverse(p->st, p->nsys, p->d_zcol_off, p->d_e_off, p->E, p->Einv,
+                                   p->d_flags), "coarse LU"));
+        if (p->azv32) to_f32(p->st, p->az_nnz, p->azv, p->azv32);
+    }
+    if (p->vals32) to_f32(p->st, p->nnz, p->vals, p->vals32);
+    if (p->need_adjoint) {
+        gather_values(p->st, p->nnz, p->tperm, p->vals, p->tv);
+        if (p->R > 0) az_fill(sa, p->trp, p->tci, p->tv, p->atzrp, p->atzci, p->atzv);
+    }
+    HIP_OK(hipStreamSynchronize(p->st));
+    return GMRES_OK;
+}
+
+gmres_status alloc_krylov(gmres_plan_s* p) {
+    const int m = p->o.m;
+    const int64_t n = p->n;
+    p->ldv = (n + 63) & ~int64_t(63);
+    double* Vd = nullptr;
+    CHECK(dalloc(p, &Vd, (int64_t)(m + 1) * p->ldv));
+    p->V = Vd;
+    for (double** q : {&p->y, &p->w, &p->pv, &p->rv, &p->xh, &p->bws, &p->xo, &p->r64, &p->dvec})
+        CHECK(dalloc(p, q, n));
+    p->NB_cap = std::max(p->NB, (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 2048));
+    CHECK(dalloc(p, &p->part, (int64_t)(m + 2) * p->NB_cap));
+    const int64_t small = 4 * (m + 1) + 2 * (int64_t)(m + 1) * m + 2 * m + 2 * (m + 1) + 16;
+    double* s = nullptr;
+    CHECK(dalloc(p, &s, small));
+    p->h1 = s; s += m + 1;
+    p->h2 = s; s += m + 1;
+    p->coef1 = s; s += m + 1;
+    p->coef2 = s; s += m + 1;
+    p->H = s; s += (int64_t)(m + 1) * m;
+    p->Hraw = s; s += (int64_t)(m + 1) * m;
+    p->cs = s; s += m;
+    p->sn = s; s += m;
+    p->g = s; s += m + 1;
+    p->vscale = s; s += m + 1;
+    p->sigma = s; s += 1;
+    p->sigma0 = s; s += 1;
+    p->scal = s; s += 8;
+    if (p->R > 0) {
+        CHECK(dalloc(p, &p->tpart, (int64_t)p->R * p->MC));
+        CHECK(dalloc(p, &p->s_step, p->R));
+        CHECK(dalloc(p, &p->s_res, p->R));
+    }
+    CHECK(dalloc(p, &p->ctrl, 1));
+    HIP_OK(hipHostMalloc((void**)&p->ctrl_h, 2 * sizeof(Ctrl), 0));
+    HIP_OK(hipEventCreateWithFlags(&p->ev_cyc[0], hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&p->ev_cyc[1], hipEventDisableTiming));
+    p->cyc_cap = 1 << 16;
+    CHECK(dalloc(p, &p->cyc_k, p->cyc_cap));
+    return GMRES_OK;
+}
+
+EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
+    EngineArgs a{};
+    a.st = p->st;
+    a.prec = prec;
+    a.n = (int)p->n;
+    a.nscale = std::sqrt((double)p->n);
+    a.L = p->L;
+    a.NB = p->NB;
+    a.m = p->o.m;
+    a.nslot = p->o.m + 1;
+    a.ldv = p->ldv;
+    a.V = p->V;
+    a.y = p->y;
+    a.w = p->w;
+    a.p = p->pv;
+    a.r = p->rv;
+    a.xh = p->xh;
+    const bool f64 = (prec == kPrecF64);
+    if (op == 0) {
+        a.rowptr = p->rowptr;
+        a.colind = p->colind;
+        a.vals = f64 ? (const void*)p->vals : (const void*)p->vals32;
+        a.azrp = p->azrp;
+        a.azci = p->azci;
+        a.azv = f64 ? (const void*)p->azv : (const void*)p->azv32;
+        a.trans = 0;
+    } else {
+        a.rowptr = p->trp;
+        a.colind = p->tci;
+        a.vals = p->tv;
+        a.azrp = p->atzrp;
+        a.azci = p->atzci;
+        a.azv = p->atzv;
+        a.trans = 1;
+    }
+    a.R = p->R;
+    a.MC = p->MC;
+    a.CH = p->CH;
+    a.ztrp = p->ztrp;
+    a.ztci = p->ztci;
+    a.ztv = p->ztv;
+    a.tpart = p->tpart;
+    a.Einv = p->Einv;
+    a.s_step = p->s_step;
+    a.s_res = p->s_res;
+    a.part = p->part;
+    a.h1 = p->h1;
+    a.h2 = p->h2;
+    a.coef1 = p->coef1;
+    a.coef2 = p->coef2;
+    a.H = p->H;
+    a.cs = p->cs;
+    a.sn = p->sn;
+    a.g = p->g;
+    a.vscale = p->vscale;
+    a.sigma = p->sigma;
+    a.sigma0 = p->sigma0;
+    a.hist = p->o.record_history ? p->hist : nullptr;
+    a.hist_cap = p->hist_cap;
+    a.Hraw = p->Hraw;
+    a.ctrl = p->ctrl;
+    a.cyc_k = p->cyc_k;
+    a.cyc_cap = (int)std::min<int64_t>(p->cyc_cap, INT32_MAX);
+    return a;
+}
+
+double type_bytes(int prec, int what) {
+    // what: 0 matrix value, 1 basis entry, 2 work-vector entry
+    if (prec == kPrecF64) return 8.0;
+    if (what == 1 && prec == kPrecF16) return 2.0;
+    return 4.0;
+}
+
+// Host side of the timer hooks called by the engine around streaming kernels.
+struct TimerHook final : KTimer {
+    gmres_plan_s* p;
+    int prec;
+    int op;
+    int cycle = 0;
+    int open_ev = -1;
+    TimerHook(gmres_plan_s* pp, int pr, int o) : p(pp), prec(pr), op(o) {}
+    double kernel_bytes(int kind, int j) const {
+        const double n = (double)p->n, nnz = (double)p->nnz;
+        const double bv = type_bytes(prec, 1), bw = type_bytes(prec, 2), ba = type_bytes(prec, 0);
+        const double nv = j + 1;
+        const double az = p->R > 0 ? 4.0 * (n + 1) + (4.0 + ba) * (double)p->az_nnz + 8.0 * p->R : 0.0;
+        switch (kind) {
+            case 0: return (ba + 4.0) * nnz + 4.0 * (n + 1) + bv * n + bw * n;
+            case 1: return bw * n + az + bv * n * nv + bw * n;
+            case 2: return bv * n * nv + 2.0 * bw * n;
+            default: return bv * n * nv + bw * n + bv * n;
+        }
+    }
+    void begin(int kind, int j) override {
+        Timer& t = p->timer;
+        const int e0 = t.used++;
+        t.used++;
+        hipEventRecord(t.ev(e0), p->st);
+        t.recs.push_back({kind, cycle, j, kernel_bytes(kind, j), e0});
+    }
+    void end(int, int) override {
+        Timer& t = p->timer;
+        hipEventRecord(t.ev(t.recs.back().ev + 1), p->st);
+    }
+};
+
+// Reads back the events of one engine run: launches of cycle c (in enqueue
+// order) at step j did work only when j < k of device cycle c.
+void collect_timer(gmres_plan_s* p, int64_t ncycles_dev) {
+    Timer& t = p->timer;
+    if (t.recs.empty()) return;
+    std::vector<int> ks((size_t)std::max<int64_t>(ncycles_dev, 1), 0);
+    const int64_t nk = std::min<int64_t>(ncycles_dev, p->cyc_cap);
+    if (nk > 0) hipMemcpy(ks.data(), p->cyc_k, nk * sizeof(int), hipMemcpyDeviceToHost);
+    for (const auto& r : t.recs) {
+        if (r.cycle >= nk || r.j >= ks[r.cycle]) continue;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t.pool[r.ev], t.pool[r.ev + 1]);
+        t.launches[r.kind] += 1;
+        t.ms[r.kind] += ms;
+        t.bytes[r.kind] += r.bytes;
+    }
+    t.recs.clear();
+    t.used = 0;
+}
+
+gmres_status ensure_graph(gmres_plan_s* p, int op, int prec, const void* b) {
+    if (p->gexec[op][prec]) return GMRES_OK;
+    EngineArgs a = make_args(p, op, prec);
+    hipGraph_t gph = nullptr;
+    HIP_OK(hipStreamBeginCapture(p->st, hipStreamCaptureModeThreadLocal));
+    launch_cycle(a, b);
+    HIP_OK(hipStreamEndCapture(p->st, &gph));
+    hipGraphExec_t ex = nullptr;
+    HIP_OK(hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0));
+    p->graph[op][prec] = gph;
+    p->gexec[op][prec] = ex;
+    return GMRES_OK;
+}
+
+// Runs restarted cycles of one engine from p->xh until the control block says
+// done.  b: the engine's right-hand side (type WT).  Returns the final control
+// block in *out.
+gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double rtol,
+                        double r0_override, int64_t max_iters, Ctrl* out) {
+    const bool timing = p->timer.enabled;
+    const bool graph = p->o.use_graph && !timing;
+    EngineArgs a = make_args(p, op, prec);
+    TimerHook hook(p, prec, op);
+    if (timing) a.timer = &hook;
+    if (graph) CHECK(ensure_graph(p, op, prec, b));
+    launch_ctrl_reset(p->st, p->ctrl, max_iters);
+    launch_restart_init(a, b, rtol, r0_override);
+    auto enqueue = [&](int c) -> gmres_status {
+        if (graph) {
+            HIP_OK(hipGraphLaunch(p->gexec[op][prec], p->st));
+        } else {
+            hook.cycle = c;
+            launch_cycle(a, b);
+        }
+        HIP_OK(hipMemcpyAsync(&p->ctrl_h[c & 1], p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, p->st));
+        HIP_OK(hipEventRecord(p->ev_cyc[c & 1], p->st));
+        return GMRES_OK;
+    };
+    const int64_t cap = max_iters + 3;
+    CHECK(enqueue(0));
+    bool finished = false;
+    for (int64_t c = 1; c <= cap + 1; ++c) {
+        if (c <= cap) CHECK(enqueue((int)c));
+        HIP_OK(hipEventSynchronize(p->ev_cyc[(c - 1) & 1]));
+        if (p->ctrl_h[(c - 1) & 1].done) {
+            finished = true;
+            break;
+        }
+    }
+    HIP_OK(hipStreamSynchronize(p->st));
+    HIP_OK(hipMemcpy(out, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (timing) collect_timer(p, out->cycles);
+    if (!finished) return fail(GMRES_EDEVICE, "solve loop did not terminate");
+    return GMRES_OK;
+}
+
+// ||b - A x|| in FP64 (scratch: p->w, partial slot of p->part).
+gmres_status true_residual(gmres_plan_s* p, const double* b, const double* x, double* nrm) {
+    const int slot = p->o.m + 1;
+    launch_residual_f64(p->st, p->L, p->NB, (int)p->n, p->rowptr, p->colind, p->vals, x, b, p->w,
+                        p->part, slot);
+    launch_sum_slot(p->st, p->part, p->NB, slot, p->scal);
+    double h = 0;
+    HIP_OK(hipMemcpyAsync(&h, p->scal, sizeof(double), hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipStreamSynchronize(p->st));
+    *nrm = std::sqrt(h);
+    return GMRES_OK;
+}
+
+gmres_status enter(gmres_plan_s* p) {
+    HIP_OK(hipSetDevice(p->device));
+    HIP_OK(hipEventRecord(p->ev_in, p->user_stream));
+    HIP_OK(hipStreamWaitEvent(p->st, p->ev_in, 0));
+    return GMRES_OK;
+}
+
+gmres_status leave(gmres_plan_s* p) {
+    HIP_OK(hipEventRecord(p->ev_out, p->st));
+    HIP_OK(hipStreamWaitEvent(p->user_stream, p->ev_out, 0));
+    return GMRES_OK;
+}
+
+// FP64 solve of op (0: A, 1: A^T) for right-hand side b (device, n) from x0
+// (or zero) into x.  Fills info (iters/cycles/status/rho0/rel_res).
+gmres_status solve_f64(gmres_plan_s* p, int op, const double* b, const double* x0, double* x,
+                       double rtol, double r0_override, int64_t max_iters, gmres_info* info) {
+    const int64_t n = p->n;
+    launch_copy(p->st, b, p->bws, n);
+    if (x0) launch_copy(p->st, x0, p->xh, n);
+    else launch_fill(p->st, p->xh, n, 0.0);
+    Ctrl c{};
+    CHECK(run_engine(p, op, kPrecF64, p->bws, rtol, r0_override, max_iters, &c));
+    launch_correct(p->st, p->NB, (int)n, p->zrp, p->zci, p->zv, p->s_res, p->R, p->xh, x);
+    info->iters += c.its;
+    info->cycles += c.cycles;
+    info->status = c.status;
+    info->rho0 = c.rho0;
+    info->rel_res = c.rho0 > 0 ? c.beta / c.rho0 : 0.0;
+    return GMRES_OK;
+}
+
+gmres_status solve_mixed(gmres_plan_s* p, const double* b, const double* x0, double* x,
+                         gmres_info* info) {
+    const int64_t n = p->n;
+    const gmres_opts& o = p->o;
+    const int slot = o.m + 1;
+    if (x0) launch_copy(p->st, x0, p->xo, n);
+    else launch_fill(p->st, p->xo, n, 0.0);
+    // r = b - A x (FP64), ||r||^2 into scal[0]
+    auto outer_residual = [&](double* nrm2_h) -> gmres_status {
+        launch_residual_f64(p->st, p->L, p->NB, (int)n, p->rowptr, p->colind, p->vals, p->xo, b,
+                            p->r64, p->part, slot);
+        launch_sum_slot(p->st, p->part, p->NB, slot, p->scal);
+        HIP_OK(hipMemcpyAsync(nrm2_h, p->scal, sizeof(double), hipMemcpyDeviceToHost, p->st));
+        HIP_OK(hipStreamSynchronize(p->st));
+        return GMRES_OK;
+    };
+    double nrm2 = 0;
+    CHECK(outer_residual(&nrm2));
+    if (!std::isfinite(nrm2)) return fail(GMRES_ENONFINITE, "non-finite residual");
+    const double rho0 = o.r0_norm_override > 0 ? o.r0_norm_override : std::sqrt(nrm2);
+    const double target = o.rtol * rho0;
+    info->rho0 = rho0;
+    int prec = (o.precision == GMRES_MIXED_F16) ? kPrecF16 : kPrecF32;
+    double rho_prev = INFINITY;
+    int status = GMRES_MAXITER;
+    int stalls = 0;
+    for (int ref = 0;; ++ref) {
+        const double rho = std::sqrt(nrm2);
+        if (rho <= target) {
+            status = GMRES_OK;
+            break;
+        }
+        if (ref >= o.max_refine) {
+            status = GMRES_STAGNATED;
+            break;
+        }
+        if (rho > 0.5 * rho_prev) {
+            // No contraction: raise the inner precision (FP16 basis -> FP32
+            // basis -> FP64 inner solve to the final tolerance).
+            ++stalls;
+            if (prec == kPrecF16) prec = kPrecF32;
+            else prec = kPrecF64;
+        }
+        rho_prev = rho;
+        if (prec == kPrecF64) {
+            gmres_info sub{};
+            const int64_t left = std::max<int64_t>(o.max_iters - info->iters, 1);
+            CHECK(solve_f64(p, 0, b, p->xo, p->xo, o.rtol, rho0, left, &sub));
+            info->iters += sub.iters;
+            info->cycles += sub.cycles;
+            info->refinements = ref + 1;
+            CHECK(outer_residual(&nrm2));
+            status = (std::sqrt(nrm2) <= target * (1 + 1e-12)) ? GMRES_OK : GMRES_STAGNATED;
+            break;
+        }
+        // Inner solve of A d = r / ||r|| in reduced precision.
+        launch_scale_to_f32(p->st, p->NB, (int)n, p->r64, p->scal, reinterpret_cast<float*>(p->bws));
+        launch_fill(p->st, p->xh, n, 0.0);
+        Ctrl c{};
+        CHECK(run_engine(p, 0, prec, p->bws, o.inner_rtol, 0.0, o.inner_max_iters, &c));
+        launch_correct(p->st, p->NB, (int)n, p->zrp, p->zci, p->zv, p->s_res, p->R, p->xh, p->dvec);
+        info->iters += c.its;
+        info->cycles += c.cycles;
+        info->refinements = ref + 1;
+        launch_axpy_norm(p->st, p->NB, (int)n, p->scal, p->dvec, p->xo);
+        CHECK(outer_residual(&nrm2));
+        if (!std::isfinite(nrm2)) return fail(GMRES_ENONFINITE, "non-finite residual");
+        (void)stalls;
+    }
+    launch_copy(p->st, p->xo, x, n);
+    info->status = status;
+    info->rel_res = rho0 > 0 ? std::sqrt(nrm2) / rho0 : 0.0;
+    return GMRES_OK;
+}
+
+}  // namespace
+
+// =====================================================================  C ABI
+
+extern "C" {
+
+void gmres_default_opts(gmres_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->m = 30;
+    o->max_iters = 10000;
+    o->rtol = 1e-8;
+    o->precision = GMRES_FP64;
+    o->inner_rtol = 1e-3;
+    o->max_refine = 30;
+    o->inner_max_iters = 20000;
+    o->use_graph = 1;
+}
+
+const char* gmres_last_error(void) { return g_last_error.c_str(); }
+
+void gmres_destroy(gmres_plan p) {
+    if (!p) return;
+    hipSetDevice(p->device);
+    if (p->st) hipStreamSynchronize(p->st);
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            if (p->gexec[a][b]) hipGraphExecDestroy(p->gexec[a][b]);
+            if (p->graph[a][b]) hipGraphDestroy(p->graph[a][b]);
+        }
+    for (void* q : p->allocs) hipFree(q);
+    if (p->ctrl_h) hipHostFree(p->ctrl_h);
+    for (auto e : {p->ev_cyc[0], p->ev_cyc[1], p->ev_in, p->ev_out})
+        if (e) hipEventDestroy(e);
+    if (p->st) hipStreamDestroy(p->st);
+    delete p;
+}
+
+static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys_row_off_h,
+                               const int64_t* sys_zcol_off_h, const int32_t* rowptr,
+                               const int32_t* colind, const double* vals, int64_t nnz,
+                               const int32_t* z_rowptr, const int32_t* z_colind,
+                               const double* z_vals, int64_t z_nnz, const gmres_opts* opts,
+                               int32_t need_adjoint, hipStream_t stream) {
+    if (nsys < 1 || !sys_row_off_h || !rowptr || !opts)
+        return fail(GMRES_EINVAL, "nsys, sys_row_off_h, rowptr and opts are required");
+    p->o = *opts;
+    if (p->o.m < 1 || p->o.m > kMaxM) return fail(GMRES_EINVAL, "m must be in [1, 96]");
+    if (p->o.max_iters < 0 || !(p->o.rtol >= 0.0))
+        return fail(GMRES_EINVAL, "max_iters >= 0 and rtol >= 0 required");
+    if (p->o.precision < 0 || p->o.precision > 2) return fail(GMRES_EINVAL, "unknown precision");
+    if (p->o.precision != GMRES_FP64 && (!(p->o.inner_rtol > 0.0) || p->o.inner_rtol >= 1.0))
+        return fail(GMRES_EINVAL, "inner_rtol must be in (0, 1)");
+    if (p->o.spmv_lanes != 0 && (p->o.spmv_lanes < 1 || p->o.spmv_lanes > 64 ||
+                                 (p->o.spmv_lanes & (p->o.spmv_lanes - 1))))
+        return fail(GMRES_EINVAL, "spmv_lanes must be a power of two in [1, 64]");
+    p->nsys = nsys;
+    p->row_off.assign(sys_row_off_h, sys_row_off_h + nsys + 1);
+    if (sys_zcol_off_h) p->zcol_off.assign(sys_zcol_off_h, sys_zcol_off_h + nsys + 1);
+    else p->zcol_off.assign(nsys + 1, 0);
+    if (p->row_off[0] != 0 || p->zcol_off[0] != 0)
+        return fail(GMRES_EINVAL, "offsets must start at 0");
+    for (int s = 0; s < nsys; ++s) {
+        if (p->row_off[s + 1] <= p->row_off[s]) return fail(GMRES_EINVAL, "empty or negative system");
+        const int64_t r = p->zcol_off[s + 1] - p->zcol_off[s];
+        if (r < 0 || r > kMaxR) return fail(GMRES_EINVAL, "deflation count per system must be in [0, 256]");
+        if (r > p->row_off[s + 1] - p->row_off[s])
+            return fail(GMRES_EINVAL, "more deflation vectors than unknowns");
+    }
+    p->n = p->row_off[nsys];
+    p->nnz = nnz;
+    p->R = (int)p->zcol_off[nsys];
+    p->znnz = p->R > 0 ? z_nnz : 0;
+    if (p->n >= INT32_MAX || nnz < 0 || nnz >= INT32_MAX || p->znnz >= INT32_MAX)
+        return fail(GMRES_EINVAL, "sizes exceed the int32 CSR range");
+    if (nnz > 0 && (!colind || !vals)) return fail(GMRES_EINVAL, "colind/vals required");
+    if (p->R > 0 && (!z_rowptr || (p->znnz > 0 && (!z_colind || !z_vals))))
+        return fail(GMRES_EINVAL, "Z arrays required when r > 0");
+    p->need_adjoint = need_adjoint ? 1 : 0;
+    if (p->need_adjoint && nsys != 1) return fail(GMRES_EINVAL, "the adjoint needs a single-system plan");
+
+    HIP_OK(hipGetDevice(&p->device));
+    p->user_stream = stream;
+    HIP_OK(hipStreamCreateWithFlags(&p->st, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
+    CHECK(enter(p));
+
+    // Plan-owned copies of A and Z.
+    const int64_t n = p->n;
+    CHECK(dalloc(p, &p->rowptr, n + 1));
+    CHECK(dalloc(p, &p->colind, std::max<int64_t>(nnz, 1)));
+    CHECK(dalloc(p, &p->vals, std::max<int64_t>(nnz, 1)));
+    HIP_OK(hipMemcpyAsync(p->rowptr, rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, p->st));
+    if (nnz > 0) {
+        HIP_OK(hipMemcpyAsync(p->colind, colind, nnz * sizeof(int), hipMemcpyDeviceToDevice, p->st));
+        HIP_OK(hipMemcpyAsync(p->vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, p->st));
+    }
+    if (p->R > 0) {
+        CHECK(dalloc(p, &p->zrp, n + 1));
+        CHECK(dalloc(p, &p->zci, std::max<int64_t>(p->znnz, 1)));
+        CHECK(dalloc(p, &p->zv, std::max<int64_t>(p->znnz, 1)));
+        HIP_OK(hipMemcpyAsync(p->zrp, z_rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, p->st));
+        if (p->znnz > 0) {
+            HIP_OK(hipMemcpyAsync(p->zci, z_colind, p->znnz * sizeof(int), hipMemcpyDeviceToDevice, p->st));
+            HIP_OK(hipMemcpyAsync(p->zv, z_vals, p->znnz * sizeof(double), hipMemcpyDeviceToDevice, p->st));
+        }
+    }
+    CHECK(dalloc(p, &p->d_row_off, nsys + 1));
+    CHECK(dalloc(p, &p->d_zcol_off, nsys + 1));
+    CHECK(dalloc(p, &p->d_e_off, nsys + 1));
+    CHECK(dalloc(p, &p->d_flags, 4));
+    p->e_off_h.assign(nsys + 1, 0);
+    for (int s = 0; s < nsys; ++s) {
+        const int64_t r = p->zcol_off[s + 1] - p->zcol_off[s];
+        p->e_off_h[s + 1] = p->e_off_h[s] + r * r;
+    }
+    HIP_OK(hipMemcpyAsync(p->d_row_off, p->row_off.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, p->st));
+    HIP_OK(hipMemcpyAsync(p->d_zcol_off, p->zcol_off.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, p->st));
+    HIP_OK(hipMemcpyAsync(p->d_e_off, p->e_off_h.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, p->st));
+
+    SetupArgs sa{p->st, nsys, n, nnz, p->znnz, p->R, p->d_row_off, p->d_zcol_off,
+                 p->rowptr, p->colind, p->vals, p->zrp, p->zci, p->zv};
+    CHECK(to_status(setup_validate(sa, p->d_flags), "input validation"));
+
+    // Z^T and the coarse operator.
+    if (p->R > 0) {
+        CHECK(dalloc(p, &p->ztrp, p->R + 1));
+        CHECK(dalloc(p, &p->ztci, std::max<int64_t>(p->znnz, 1)));
+        CHECK(dalloc(p, &p->ztperm, std::max<int64_t>(p->znnz, 1)));
+        CHECK(dalloc(p, &p->ztv, std::max<int64_t>(p->znnz, 1)));
+        CHECK(to_status(build_transpose(p->st, n, p->R, p->znnz, p->zrp, p->zci, p->ztrp, p->ztci,
+                                        p->ztperm), "Z transpose"));
+        gather_values(p->st, p->znnz, p->ztperm, p->zv, p->ztv);
+        const int maxrow = zt_max_row(p->st, p->R, p->ztrp, p->d_flags);
+        p->CH = 2048;
+        p->MC = std::max(1, (maxrow + p->CH - 1) / p->CH);
+        CHECK(build_az(p, p->rowptr, p->colind, p->vals, &p->azrp, &p->azci, &p->azv, &p->az_nnz));
+        CHECK(dalloc(p, &p->E, std::max<int64_t>(p->e_off_h[nsys], 1)));
+        CHECK(dalloc(p, &p->Einv, std::max<int64_t>(p->e_off_h[nsys], 1)));
+    }
+    if (p->o.precision != GMRES_FP64) {
+        CHECK(dalloc(p, &p->vals32, std::max<int64_t>(nnz, 1)));
+        if (p->R > 0) CHECK(dalloc(p, &p->azv32, std::max<int64_t>(p->az_nnz, 1)));
+    }
+    if (p->need_adjoint) {
+        CHECK(dalloc(p, &p->trp, n + 1));
+        CHECK(dalloc(p, &p->tci, std::max<int64_t>(nnz, 1)));
+        CHECK(dalloc(p, &p->tperm, std::max<int64_t>(nnz, 1)));
+        CHECK(dalloc(p, &p->tv, std::max<int64_t>(nnz, 1)));
+        CHECK(to_status(build_transpose(p->st, n, n, nnz, p->rowptr, p->colind, p->trp, p->tci,
+                                        p->tperm), "A transpose"));
+        gather_values(p->st, nnz, p->tperm, p->vals, p->tv);
+        if (p->R > 0)
+            CHECK(build_az(p, p->trp, p->tci, p->tv, &p->atzrp, &p->atzci, &p->atzv, &p->atz_nnz));
+    }
+    CHECK(refresh_values(p));
+
+    p->L = p->o.spmv_lanes > 0 ? p->o.spmv_lanes : default_lanes(n, nnz);
+    p->NB = p->o.num_blocks > 0 ? p->o.num_blocks
+                                : (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 1024);
+    if (nsys == 1) CHECK(alloc_krylov(p));
+    p->batch_wg = p->o.batch_wg > 0 ? p->o.batch_wg : 256;
+    p->batch_L = p->o.batch_lanes > 0 ? p->o.batch_lanes : 8;
+    HIP_OK(hipStreamSynchronize(p->st));
+    CHECK(leave(p));
+    return GMRES_OK;
+}
+
+gmres_status gmres_setup(gmres_plan* out, int32_t nsys, const int64_t* sys_row_off_h,
+                         const int64_t* sys_zcol_off_h, const int32_t* rowptr,
+                         const int32_t* colind, const double* vals, int64_t nnz,
+                         const int32_t* z_rowptr, const int32_t* z_colind, const double* z_vals,
+                         int64_t z_nnz, const gmres_opts* opts, int32_t need_adjoint,
+                         hipStream_t stream) {
+    if (!out) return fail(GMRES_EINVAL, "out is NULL");
+    *out = nullptr;
+    gmres_plan_s* p = new (std::nothrow) gmres_plan_s();
+    if (!p) return fail(GMRES_ENOMEM, "host allocation failed");
+    gmres_status s = setup_impl(p, nsys, sys_row_off_h, sys_zcol_off_h, rowptr, colind, vals, nnz,
+                                z_rowptr, z_colind, z_vals, z_nnz, opts, need_adjoint, stream);
+    if (s != GMRES_OK) {
+        std::string msg = g_last_error;
+        gmres_destroy(p);
+        g_last_error = msg;
+        return s;
+    }
+    *out = p;
+    return GMRES_OK;
+}
+
+gmres_status gmres_set_stream(gmres_plan p, hipStream_t stream) {
+    if (!p) return fail(GMRES_EINVAL, "plan is NULL");
+    p->user_stream = stream;
+    return GMRES_OK;
+}
+
+static gmres_status ensure_history(gmres_plan_s* p, int64_t need) {
+    if (!p->o.record_history) return GMRES_OK;
+    need = std::max<int64_t>(need, 1);
+    if (p->hist_cap >= need) return GMRES_OK;
+    CHECK(dalloc(p, &p->hist, need));
+    p->hist_cap = need;
+    for (int a = 0; a < 2; ++a)     // graphs hold the old history pointer
+        for (int b = 0; b < 3; ++b) {
+            if (p->gexec[a][b]) hipGraphExecDestroy(p->gexec[a][b]);
+            if (p->graph[a][b]) hipGraphDestroy(p->graph[a][b]);
+            p->gexec[a][b] = nullptr;
+            p->graph[a][b] = nullptr;
+        }
+    return GMRES_OK;
+}
+
+gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double* x,
+                         gmres_info* info_h) {
+    if (!p || !b || !x) return fail(GMRES_EINVAL, "plan, b and x are required");
+    if (p->nsys != 1) return fail(GMRES_EINVAL, "gmres_solve needs a single-system plan");
+    if (x == b) return fail(GMRES_EINVAL, "x must not alias b");
+    const auto t0 = std::chrono::steady_clock::now();
+    CHECK(enter(p));
+    gmres_info info{};
+    const int64_t hist_need = p->o.precision == GMRES_FP64
+                                  ? p->o.max_iters
+                                  : p->o.inner_max_iters;
+    CHECK(ensure_history(p, std::min<int64_t>(hist_need, int64_t(1) << 26)));
+    p->timer.reset();
+    if (p->o.precision == GMRES_FP64) {
+        CHECK(solve_f64(p, 0, b, x0, x, p->o.rtol, p->o.r0_norm_override, p->o.max_iters, &info));
+    } else {
+        CHECK(solve_mixed(p, b, x0, x, &info));
+    }
+    p->hist_len = info.iters;
+    double nrm = 0;
+    CHECK(true_residual(p, b, x, &nrm));
+    info.rel_res_true = info.rho0 > 0 ? nrm / info.rho0 : 0.0;
+    CHECK(leave(p));
+    info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info_h) *info_h = info;
+    if (info.status == kStatusNonFinite) return fail(GMRES_ENONFINITE, "non-finite value in b, x0 or the iteration");
+    return (gmres_status)info.status;
+}
+
+gmres_status gmres_adjoint(gmres_plan p, const double* x, const double* grad_x, double* grad_b,
+                           double* grad_vals, gmres_info* info_h) {
+    if (!p || !x || !grad_x) return fail(GMRES_EINVAL, "plan, x and grad_x are required");
+    if (!p->need_adjoint) return fail(GMRES_EINVAL, "plan was built without need_adjoint");
+    const auto t0 = std::chrono::steady_clock::now();
+    CHECK(enter(p));
+    gmres_info info{};
+    p->timer.reset();
+    CHECK(solve_f64(p, 1, grad_x, nullptr, p->dvec, p->o.rtol, 0.0, p->o.max_iters, &info));
+    if (grad_b) launch_copy(p->st, p->dvec, grad_b, p->n);
+    if (grad_vals)
+        gm::grad_vals(p->st, p->n, p->rowptr, p->colind, p->dvec, x, grad_vals);
+    // True residual of the adjoint system ||grad_x - A^T lambda||.
+    const int slot = p->o.m + 1;
+    launch_residual_f64(p->st, p->L, p->NB, (int)p->n, p->trp, p->tci, p->tv, p->dvec, grad_x, p->w,
+                        p->part, slot);
+    launch_sum_slot(p->st, p->part, p->NB, slot, p->scal);
+    double h = 0;
+    HIP_OK(hipMemcpyAsync(&h, p->scal, sizeof(double), hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipStreamSynchronize(p->st));
+    info.rel_res_true = info.rho0 > 0 ? std::sqrt(h) / info.rho0 : 0.0;
+    CHECK(leave(p));
+    info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info_h) *info_h = info;
+    return (gmres_status)info.status;
+}
+
+gmres_status gmres_update_values(gmres_plan p, const double* vals) {
+    if (!p || (!vals && p->nnz > 0)) return fail(GMRES_EINVAL, "plan and vals are required");
+    CHECK(enter(p));
+    if (p->nnz > 0)
+        HIP_OK(hipMemcpyAsync(p->vals, vals, p->nnz * sizeof(double), hipMemcpyDeviceToDevice, p->st));
+    SetupArgs sa{p->st, p->nsys, p->n, p->nnz, p->znnz, p->R, p->d_row_off, p->d_zcol_off,
+                 p->rowptr, p->colind, p->vals, p->zrp, p->zci, p->zv};
+    CHECK(to_status(setup_validate(sa, p->d_flags), "value validation"));
+    CHECK(refresh_values(p));
+    CHECK(leave(p));
+    return GMRES_OK;
+}
+
+gmres_status gmres_spmv(gmres_plan p, const double* x, double* y) {
+    if (!p || !x || !y) return fail(GMRES_EINVAL, "plan, x and y are required");
+    CHECK(enter(p));
+    launch_spmv_f64(p->st, p->L, p->NB > 0 ? p->NB : 1, (int)p->n, p->rowptr, p->colind, p->vals, x, y);
+    HIP_OK(hipGetLastError());
+    CHECK(leave(p));
+    HIP_OK(hipStreamSynchronize(p->st));
+    return GMRES_OK;
+}
+
+int64_t gmres_history(gmres_plan p, double* hist_h, int64_t cap) {
+    if (!p || !hist_h || !p->hist) return -1;
+    const int64_t k = std::min<int64_t>(std::min<int64_t>(cap, p->hist_len), p->hist_cap);
+    if (k > 0 && hipMemcpy(hist_h, p->hist, k * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    return k;
+}
+
+static void drop_graphs(gmres_plan_s* p) {
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            if (p->gexec[a][b]) hipGraphExecDestroy(p->gexec[a][b]);
+            if (p->graph[a][b]) hipGraphDestroy(p->graph[a][b]);
+            p->gexec[a][b] = nullptr;
+            p->graph[a][b] = nullptr;
+        }
+}
+
+static gmres_status batch_alloc(gmres_plan_s* p) {
+    if (p->bV) return GMRES_OK;
+    const int ns = p->nsys;
+    const int m = p->o.m;
+    CHECK(dalloc(p, &p->bV, (int64_t)(m + 1) * p->n));
+    CHECK(dalloc(p, &p->bW, 3 * p->n));
+    CHECK(dalloc(p, &p->border, ns));
+    CHECK(dalloc(p, &p->bticket, 1));
+    CHECK(dalloc(p, &p->bout_i, 3 * (int64_t)ns));
+    CHECK(dalloc(p, &p->bout_d, 4 * (int64_t)ns + ns));
+    CHECK(dalloc(p, &p->d_v_off, ns));
+    // Largest systems first: order by nnz, then rows.
+    std::vector<int32_t> rp_at(ns + 1);
+    for (int s = 0; s <= ns; ++s)
+        HIP_OK(hipMemcpy(&rp_at[s], p->rowptr + p->row_off[s], sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int> order(ns);
+    for (int s = 0; s < ns; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int64_t wa = (int64_t)(rp_at[a + 1] - rp_at[a]) + (p->row_off[a + 1] - p->row_off[a]);
+        const int64_t wb = (int64_t)(rp_at[b + 1] - rp_at[b]) + (p->row_off[b + 1] - p->row_off[b]);
+        return wa > wb;
+    });
+    std::vector<int64_t> voff(ns);
+    for (int s = 0; s < ns; ++s) voff[s] = (int64_t)(m + 1) * p->row_off[s];
+    HIP_OK(hipMemcpy(p->border, order.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->d_v_off, voff.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice));
+    return GMRES_OK;
+}
+
+static gmres_status run_batched(gmres_plan_s* p, const double* b, const double* x0, double* x,
+                                int64_t max_iters, int wg, int lanes) {
+    HIP_OK(hipMemsetAsync(p->bticket, 0, sizeof(int), p->st));
+    BatchArgs a{};
+    a.st = p->st;
+    a.nsys = p->nsys;
+    a.m = p->o.m;
+    a.L = lanes;
+    a.wg = wg;
+    a.max_iters = max_iters;
+    a.rtol = p->o.rtol;
+    a.row_off = p->d_row_off;
+    a.zcol_off = p->d_zcol_off;
+    a.e_off = p->d_e_off;
+    a.v_off = p->d_v_off;
+    a.order = p->border;
+    a.rowptr = p->rowptr;
+    a.colind = p->colind;
+    a.vals = p->vals;
+    a.azrp = p->azrp;
+    a.azci = p->azci;
+    a.azv = p->azv;
+    a.zrp = p->zrp;
+    a.zci = p->zci;
+    a.zv = p->zv;
+    a.ztrp = p->ztrp;
+    a.ztci = p->ztci;
+    a.ztv = p->ztv;
+    a.Einv = p->Einv;
+    a.b = b;
+    a.x0 = x0;
+    a.x = x;
+    a.V = p->bV;
+    a.W = p->bW;
+    a.ticket = p->bticket;
+    a.out_i = p->bout_i;
+    a.out_d = p->bout_d;
+    int cus = 0;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
+    const int per_cu = std::max(1, 1024 / wg);
+    const int nwg = std::max(1, std::min(p->nsys, cus * per_cu));
+    launch_batched(a, nwg);
+    HIP_OK(hipGetLastError());
+    return GMRES_OK;
+}
+
+gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0, double* x,
+                                 gmres_info* infos_h) {
+    if (!p || !b || !x) return fail(GMRES_EINVAL, "plan, b and x are required");
+    if (p->o.m > 64) return fail(GMRES_EINVAL, "the batched solver supports m <= 64");
+    if (x == b) return fail(GMRES_EINVAL, "x must not alias b");
+    const auto t0 = std::chrono::steady_clock::now();
+    CHECK(enter(p));
+    CHECK(batch_alloc(p));
+    CHECK(run_batched(p, b, x0, x, p->o.max_iters, p->batch_wg, p->batch_L));
+    double* nr = p->bout_d + 4 * (int64_t)p->nsys;
+    launch_seg_resid(p->st, p->nsys, p->d_row_off, p->rowptr, p->colind, p->vals, x, b, nr);
+    const int ns = p->nsys;
+    std::vector<int64_t> oi(3 * (size_t)ns);
+    std::vector<double> od(5 * (size_t)ns);
+    HIP_OK(hipMemcpyAsync(oi.data(), p->bout_i, oi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipMemcpyAsync(od.data(), p->bout_d, od.size() * sizeof(double), hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipStreamSynchronize(p->st));
+    CHECK(leave(p));
+    int clk_khz = 0;
+    HIP_OK(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, p->device));
+    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    gmres_status worst = GMRES_OK;
+    for (int s = 0; s < ns; ++s) {
+        gmres_info in{};
+        in.iters = oi[3 * s];
+        in.cycles = (int32_t)oi[3 * s + 1];
+        in.status = (int32_t)oi[3 * s + 2];
+        in.rho0 = od[4 * s];
+        in.rel_res = od[4 * s + 1];
+        in.rel_res_true = in.rho0 > 0 ? std::sqrt(od[4 * ns + s]) / in.rho0 : 0.0;
+        in.solve_ms = clk_khz > 0 ? (od[4 * s + 3] - od[4 * s + 2]) / (double)clk_khz : wall;
+        if (infos_h) infos_h[s] = in;
+        if (worst == GMRES_OK && in.status != GMRES_OK) worst = (gmres_status)in.status;
+    }
+    if (worst < 0) return fail(worst, "a system of the batch failed");
+    return worst;
+}
+
+gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
+    if (!p) return fail(GMRES_EINVAL, "plan is NULL");
+    CHECK(enter(p));
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    auto time_it = [&](auto&& fn, int reps) -> double {
+        fn();
+        hipEventRecord(e0, p->st);
+        for (int r = 0; r < reps; ++r) fn();
+        hipEventRecord(e1, p->st);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        return ms / reps;
+    };
+    if (p->nsys == 1) {
+        // SpMV lanes per row, then the streaming grid size (SpMV + a mid-cycle
+        // pass 2, the dominant Arnoldi kernel).
+        const int n = (int)p->n;
+        launch_fill(p->st, (double*)p->V, (int64_t)(p->o.m + 1) * p->ldv, 1.0 / std::sqrt((double)n));
+        launch_fill(p->st, p->w, n, 1.0);
+        launch_fill(p->st, p->coef1, p->o.m + 1, 1e-3);
+        double best = 1e30;
+        int bestL = p->L;
+        for (int L : {2, 4, 8, 16, 32}) {
+            const double t = time_it([&] {
+                launch_spmv_f64(p->st, L, p->NB, n, p->rowptr, p->colind, p->vals, (double*)p->V, p->y);
+            }, 10);
+            if (t < best) { best = t; bestL = L; }
+        }
+        p->L = bestL;
+        const int nb_cap = p->NB_cap;
+        double bestt = 1e30;
+        int bestNB = p->NB;
+        const int nv = std::max(1, p->o.m / 2);
+        for (int nb : {256, 512, 1024, 2048}) {
+            if (nb > nb_cap) continue;
+            const int saved = p->NB;
+            p->NB = nb;
+            EngineArgs a = make_args(p, 0, kPrecF64);
+            const double t = time_it([&] {
+                launch_spmv_f64(p->st, p->L, nb, n, p->rowptr, p->colind, p->vals, (double*)p->V, p->y);
+                launch_pass_probe(a, 2, nv);
+            }, 10);
+            p->NB = saved;
+            if (t < bestt) { bestt = t; bestNB = nb; }
+        }
+        p->NB = bestNB;
+        launch_fill(p->st, (double*)p->V, (int64_t)(p->o.m + 1) * p->ldv, 0.0);
+        drop_graphs(p);
+    } else {
+        // Batched: workgroup size and SpMV lanes, timed on one restart cycle.
+        CHECK(batch_alloc(p));
+        double* bb = p->bW;   // right-hand side of ones in the first work vector block
+        double* xx = nullptr;
+        CHECK(dalloc(p, &xx, p->n));
+        double* ones = nullptr;
+        CHECK(dalloc(p, &ones, p->n));
+        launch_fill(p->st, ones, p->n, 1.0);
+        (void)bb;
+        double best = 1e30;
+        for (int wg : {256, 512}) {
+            for (int L : {4, 8, 16}) {
+                const double t = time_it([&] {
+                    run_batched(p, ones, nullptr, xx, p->o.m, wg, L);
+                }, 2);
+                if (t < best) { best = t; p->batch_wg = wg; p->batch_L = L; }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    HIP_OK(hipStreamSynchronize(p->st));
+    CHECK(leave(p));
+    if (chosen_h) {
+        chosen_h[0] = p->L;
+        chosen_h[1] = p->NB;
+        chosen_h[2] = p->batch_wg;
+        chosen_h[3] = p->batch_L;
+    }
+    return GMRES_OK;
+}
+
+gmres_status gmres_set_timing(gmres_plan p, int32_t enable) {
+    if (!p) return fail(GMRES_EINVAL, "plan is NULL");
+    p->timer.enabled = enable != 0;
+    p->timer.reset();
+    return GMRES_OK;
+}
+
+gmres_status gmres_kernel_times(gmres_plan p, double* out_h) {
+    if (!p || !out_h) return fail(GMRES_EINVAL, "plan and out_h are required");
+    for (int k = 0; k < 4; ++k) {
+        out_h[3 * k + 0] = p->timer.launches[k];
+        out_h[3 * k + 1] = p->timer.ms[k];
+        out_h[3 * k + 2] = p->timer.bytes[k];
+    }
+    return GMRES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal device/host definitions shared by the HIP translation units of the
+// deflated GMRES(m) library.  Not part of the public interface (include/gmres.h).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gm {
+
+constexpr int kWG = 256;            // threads per workgroup of the streaming kernels
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kMaxM = 96;           // largest supported restart length m
+constexpr int kMaxR = 256;          // largest deflation count per system (coarse solve in one WG)
+constexpr int kAzRowMax = 64;       // largest row length of the compact A*Z operator
+
+// Device-resident control block of one solve.  Every kernel of a restart
+// cycle reads it, so the host launches whole cycles without synchronising.
+struct Ctrl {
+    int64_t its;          // inner Arnoldi steps so far (all cycles)
+    int64_t max_iters;
+    int32_t cycles;
+    int32_t stop;         // current cycle has ended (converged estimate, breakdown or cap)
+    int32_t done;         // solve has ended
+    int32_t status;       // gmres_status at exit
+    int32_t k;            // number of basis vectors used by the current cycle
+    int32_t breakdown;
+    double rho0;          // ||b - A x0||
+    double target;        // rtol * rho0
+    double beta;          // ||P r|| at the last restart
+    double wpre2;         // ||P A v_j||^2 before orthogonalisation (breakdown test)
+    double inner_scale;   // mixed precision: ||r|| of the current refinement
+    int64_t pad[4];
+};
+
+// ---------------------------------------------------------------- reductions
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum over a workgroup of kWG threads; result valid in every thread.
+// `lds` needs kWG / kWave entries.  Fixed order: butterfly within waves,
+// then waves 0..3 in order.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+    __syncthreads();
+    T s = lds[0];
+#pragma unroll
+    for (int i = 1; i < kWG / kWave; ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+// Half-precision basis storage helpers.
+__device__ __forceinline__ float ld_f(const __half* p) { return __half2float(*p); }
+__device__ __forceinline__ float ld_f(const float* p) { return *p; }
+__device__ __forceinline__ double ld_f(const double* p) { return *p; }
+__device__ __forceinline__ void st_v(__half* p, float v) { *p = __float2half_rn(v); }
+__device__ __forceinline__ void st_v(float* p, float v) { *p = v; }
+__device__ __forceinline__ void st_v(double* p, double v) { *p = v; }
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace gm

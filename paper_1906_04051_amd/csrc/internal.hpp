@@ -1,0 +1,160 @@
+// Internal declarations shared by the translation units of the library.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace gm {
+
+// Status values (mirror gmres_status in include/gmres.h).
+constexpr int kStatusOk = 0;
+constexpr int kStatusMaxIter = 1;
+constexpr int kStatusBreakdown = 2;
+constexpr int kStatusStagnated = 3;
+constexpr int kStatusInval = -1;
+constexpr int kStatusSingular = -2;
+constexpr int kStatusNonFinite = -3;
+constexpr int kStatusDevice = -4;
+constexpr int kStatusNoMem = -5;
+
+// Precision of one solve engine.
+constexpr int kPrecF64 = 0;   // FP64 values, basis, vectors and accumulation
+constexpr int kPrecF32 = 1;   // FP32 values, basis, vectors and accumulation
+constexpr int kPrecF16 = 2;   // FP32 values/vectors/accumulation, FP16 basis
+
+// Hooks around the streaming kernels of a step (HIP-event timing).
+// kind: 0 SpMV, 1 pass 1, 2 pass 2, 3 pass 3; j: step index in the cycle.
+struct KTimer {
+    virtual void begin(int kind, int j) = 0;
+    virtual void end(int kind, int j) = 0;
+    virtual ~KTimer() = default;
+};
+
+// Everything one solve engine needs: the operator (A or A^T), the deflation
+// data, and the Krylov workspace.
+struct EngineArgs {
+    hipStream_t st;
+    int prec;
+    int n;
+    double nscale;          // sqrt(n): FP16 storage scale numerator
+    int L;                  // SpMV lanes per row
+    int NB;                 // workgroups of the streaming kernels (partial-sum count)
+    int m;
+    int nslot;              // index of the norm slot in `part`
+    int64_t ldv;            // basis column stride (elements)
+    void* V;
+    void *y, *w, *p, *r;    // work vectors (type WT)
+    double* xh;             // current iterate (FP64)
+    const int *rowptr, *colind;
+    const void* vals;       // AT
+    const int *azrp, *azci; // compact A Z (CSR, n rows)
+    const void* azv;        // AT
+    int R, MC, CH;          // deflation count, Z^T chunks per row, chunk length
+    const int *ztrp, *ztci; // Z^T (CSR, R rows)
+    const double* ztv;
+    double* tpart;          // R * MC partial sums of Z^T y
+    const double* Einv;     // explicit E^{-1}, column-major R x R
+    int trans;              // apply E^{-T} (adjoint operator)
+    double *s_step, *s_res; // coarse solutions (per step / per restart)
+    double* part;           // (m + 2) * NB partial sums
+    double *h1, *h2, *coef1, *coef2;
+    double *H, *cs, *sn, *g, *vscale;
+    double *sigma, *sigma0;
+    double* hist;           // optional |gamma_{k+1}| history
+    int64_t hist_cap;       // entries of hist
+    double* Hraw;           // optional unrotated Hessenberg of the last cycle
+    Ctrl* ctrl;
+    int* cyc_k;             // optional: basis size k of every cycle
+    int cyc_cap;
+    KTimer* timer;          // optional
+};
+
+// krylov.hip
+void launch_restart_init(const EngineArgs& a, const void* b, double rtol, double r0_override);
+void launch_cycle(const EngineArgs& a, const void* b);
+void launch_correct(hipStream_t st, int NB, int n, const int* zrp, const int* zci, const double* zv,
+                    const double* s, int R, const double* xh, double* x);
+void launch_residual_f64(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
+                         const double* v, const double* x, const double* b, double* r, double* part,
+                         int slot);
+void launch_sum_slot(hipStream_t st, const double* part, int NB, int slot, double* out);
+void launch_spmv_f64(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
+                     const double* v, const double* x, double* y);
+void launch_spmv_f32(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
+                     const float* v, const float* x, float* y);
+void launch_scale_to_f32(hipStream_t st, int NB, int n, const double* r, const double* nrm2,
+                         float* out);
+void launch_axpy_norm(hipStream_t st, int NB, int n, const double* nrm2, const double* d, double* x);
+void launch_ctrl_reset(hipStream_t st, Ctrl* c, int64_t max_iters);
+void launch_fill(hipStream_t st, double* p, int64_t n, double v);
+void launch_copy(hipStream_t st, const double* a, double* b, int64_t n);
+
+// setup.hip
+struct SetupArgs {
+    hipStream_t st;
+    int nsys;
+    int64_t n, nnz, znnz;
+    int R;                                   // total deflation columns
+    const int64_t* d_sys_row_off;            // device copies, nsys + 1
+    const int64_t* d_sys_zcol_off;
+    const int *rowptr, *colind;
+    const double* vals;
+    const int *zrp, *zci;
+    const double* zv;
+};
+int setup_validate(const SetupArgs& a, int* d_flags);       // returns a status
+int build_transpose(hipStream_t st, int64_t nrows, int64_t ncols, int64_t nnz, const int* rowptr,
+                    const int* colind, int* trowptr, int* tcolind, int* tperm);
+void gather_values(hipStream_t st, int64_t nnz, const int* perm, const double* src, double* dst);
+int az_count(const SetupArgs& a, const int* rowptr, const int* colind, int* az_rowptr,
+             int64_t* az_nnz);
+void az_fill(const SetupArgs& a, const int* rowptr, const int* colind, const double* vals,
+             const int* az_rowptr, int* az_colind, double* az_vals);
+void build_coarse(const SetupArgs& a, const int* ztrp, const int* ztci, const double* ztv,
+                  const int* azrp, const int* azci, const double* azv, const int64_t* d_e_off,
+                  double* E);
+int lu_inverse(hipStream_t st, int nsys, const int64_t* d_sys_zcol_off, const int64_t* d_e_off,
+               double* E, double* Einv, int* d_flags);
+void to_f32(hipStream_t st, int64_t n, const double* src, float* dst);
+void grad_vals(hipStream_t st, int64_t n, const int* rowptr, const int* colind, const double* lam,
+               const double* x, double* g);
+int zt_max_row(hipStream_t st, int R, const int* ztrp, int* d_tmp);
+
+// batched.hip
+struct BatchArgs {
+    hipStream_t st;
+    int nsys, m, L, wg;
+    int64_t max_iters;
+    double rtol;
+    const int64_t *row_off, *zcol_off, *e_off, *v_off;   // device
+    const int* order;                                     // systems by decreasing work
+    const int *rowptr, *colind;
+    const double* vals;
+    const int *azrp, *azci;
+    const double* azv;
+    const int *zrp, *zci;
+    const double* zv;
+    const int *ztrp, *ztci;
+    const double* ztv;
+    const double* Einv;
+    const double *b, *x0;
+    double* x;
+    double* V;               // per-system basis regions
+    double* W;               // per-system work vectors (3 per row)
+    double* small;           // per-system small state
+    int64_t small_stride;
+    int* ticket;
+    int64_t* out_i;          // per system: its, cycles, status
+    double* out_d;           // per system: rho0, rel_res, t_start, t_end
+};
+void launch_batched(const BatchArgs& a, int nwg);
+void launch_seg_resid(hipStream_t st, int nsys, const int64_t* row_off, const int* rowptr,
+                      const int* colind, const double* vals, const double* x, const double* b,
+                      double* out);
+// One launch of a pass kernel (FP64) for tuning: kind 1, 2 or 3 at nv columns.
+void launch_pass_probe(const EngineArgs& a, int kind, int nv);
+
+}  // namespace gm

@@ -1,0 +1,465 @@
+// Setup kernels of a solver plan: input validation, CSR transposes (Z^T and,
+// for the adjoint, A^T), the compact coarse operator A Z, the coarse matrix
+// E = Z^T A Z per system and its explicit inverse through an LU factorisation
+// with partial pivoting (the coarse matrix is the analogue of the paper's
+// T_r = U^T A U, arXiv 1906.04051 Sec. 3.3, eq. tau_mat).
+//
+// All pattern work is deterministic: transposes use a stable radix sort, A Z
+// rows accumulate in CSR order, E entries in Z^T order.
+#include <hipcub/hipcub.hpp>
+
+#include "internal.hpp"
+
+namespace gm {
+
+__device__ __forceinline__ int sys_of_row(const int64_t* off, int nsys, int64_t i) {
+    int lo = 0, hi = nsys;           // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// flags bit 0: malformed CSR / index out of the row's system block;
+// bit 1: non-finite value.
+__global__ void k_validate(int nsys, int64_t n, int64_t nnz, int64_t znnz,
+                           const int64_t* __restrict__ row_off, const int64_t* __restrict__ zcol_off,
+                           const int* __restrict__ rowptr, const int* __restrict__ colind,
+                           const double* __restrict__ vals, const int* __restrict__ zrp,
+                           const int* __restrict__ zci, const double* __restrict__ zv,
+                           int* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        if (rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) atomicOr(flags, 1);
+        if (zrp && (zrp[0] != 0 || (int64_t)zrp[n] != znnz)) atomicOr(flags, 1);
+    }
+    if (i >= n) return;
+    const int s = sys_of_row(row_off, nsys, i);
+    const int64_t c0 = row_off[s], c1 = row_off[s + 1];
+    int f = 0;
+    const int k0 = rowptr[i], k1 = rowptr[i + 1];
+    if (k1 < k0 || k0 < 0 || (int64_t)k1 > nnz) {
+        f |= 1;
+    } else {
+        for (int k = k0; k < k1; ++k) {
+            const int c = colind[k];
+            if (c < c0 || c >= c1) f |= 1;
+            if (!isfinite(vals[k])) f |= 2;
+        }
+    }
+    if (zrp) {
+        const int q0 = zrp[i], q1 = zrp[i + 1];
+        const int64_t a0 = zcol_off[s], a1 = zcol_off[s + 1];
+        if (q1 < q0 || q0 < 0 || (int64_t)q1 > znnz) {
+            f |= 1;
+        } else {
+            for (int q = q0; q < q1; ++q) {
+                const int a = zci[q];
+                if (a < a0 || a >= a1) f |= 1;
+                if (!isfinite(zv[q])) f |= 2;
+            }
+        }
+    }
+    if (f) atomicOr(flags, f);
+}
+
+int setup_validate(const SetupArgs& a, int* d_flags) {
+    if (hipMemsetAsync(d_flags, 0, sizeof(int), a.st) != hipSuccess) return kStatusDevice;
+    const int64_t nb = (a.n + kWG - 1) / kWG;
+    k_validate<<<(unsigned)std::max<int64_t>(nb, 1), kWG, 0, a.st>>>(
+        a.nsys, a.n, a.nnz, a.znnz, a.d_sys_row_off, a.d_sys_zcol_off, a.rowptr, a.colind, a.vals,
+        a.R > 0 ? a.zrp : nullptr, a.zci, a.zv, d_flags);
+    int h = 0;
+    if (hipMemcpyAsync(&h, d_flags, sizeof(int), hipMemcpyDeviceToHost, a.st) != hipSuccess ||
+        hipStreamSynchronize(a.st) != hipSuccess)
+        return kStatusDevice;
+    if (h & 1) return kStatusInval;
+    if (h & 2) return kStatusNonFinite;
+    return kStatusOk;
+}
+
+// ------------------------------------------------------------- transpose
+
+__global__ void k_row_of(int64_t n, const int* __restrict__ rowptr, int* __restrict__ row_of) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) row_of[k] = (int)i;
+}
+
+__global__ void k_iota(int64_t n, int* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int)i;
+}
+
+// trowptr[c] = first position q with key[q] >= c (keys sorted).
+__global__ void k_bounds(int64_t nnz, int64_t ncols, const int* __restrict__ keys,
+                         int* __restrict__ trowptr) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > nnz) return;
+    const int64_t prev = (q == 0) ? -1 : keys[q - 1];
+    const int64_t cur = (q == nnz) ? ncols : keys[q];
+    for (int64_t c = prev + 1; c <= cur; ++c) trowptr[c] = (int)q;
+}
+
+__global__ void k_take_rows(int64_t nnz, const int* __restrict__ perm, const int* __restrict__ row_of,
+                            int* __restrict__ tcolind) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) tcolind[q] = row_of[perm[q]];
+}
+
+__global__ void k_gather(int64_t nnz, const int* __restrict__ perm, const double* __restrict__ src,
+                         double* __restrict__ dst) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) dst[q] = src[perm[q]];
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>((n + kWG - 1) / kWG, 1); }
+
+// Transpose of an nrows x ncols CSR pattern: a stable sort of the entries by
+// column keeps every row of the transpose in increasing original-row order.
+// tperm[q] is the original entry index of transposed entry q.
+int build_transpose(hipStream_t st, int64_t nrows, int64_t ncols, int64_t nnz, const int* rowptr,
+                    const int* colind, int* trowptr, int* tcolind, int* tperm) {
+    if (nnz == 0) {
+        k_bounds<<<1, kWG, 0, st>>>(0, ncols, colind, trowptr);
+        return hipGetLastError() == hipSuccess ? kStatusOk : kStatusDevice;
+    }
+    int *row_of = nullptr, *keys_out = nullptr, *iota = nullptr;
+    void* tmp = nullptr;
+    size_t tmp_bytes = 0;
+    int end_bit = 1;
+    while ((int64_t(1) << end_bit) < ncols) ++end_bit;
+    int status = kStatusOk;
+    if (hipMalloc(&row_of, nnz * sizeof(int)) != hipSuccess ||
+        hipMalloc(&keys_out, nnz * sizeof(int)) != hipSuccess ||
+        hipMalloc(&iota, nnz * sizeof(int)) != hipSuccess) {
+        status = kStatusNoMem;
+    } else {
+        k_row_of<<<blocks_for(nrows), kWG, 0, st>>>(nrows, rowptr, row_of);
+        k_iota<<<blocks_for(nnz), kWG, 0, st>>>(nnz, iota);
+        hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, colind, keys_out, iota, tperm,
+                                           (int)nnz, 0, end_bit, st);
+        if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
+            status = kStatusNoMem;
+        } else {
+            hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, colind, keys_out, iota, tperm, (int)nnz,
+                                               0, end_bit, st);
+            k_bounds<<<blocks_for(nnz + 1), kWG, 0, st>>>(nnz, ncols, keys_out, trowptr);
+            k_take_rows<<<blocks_for(nnz), kWG, 0, st>>>(nnz, tperm, row_of, tcolind);
+            if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+        }
+    }
+    hipFree(row_of);
+    hipFree(keys_out);
+    hipFree(iota);
+    hipFree(tmp);
+    return status;
+}
+
+void gather_values(hipStream_t st, int64_t nnz, const int* perm, const double* src, double* dst) {
+    if (nnz > 0) k_gather<<<blocks_for(nnz), kWG, 0, st>>>(nnz, perm, src, dst);
+}
+
+// ------------------------------------------------------------ compact A Z
+// Row i of A Z has an entry for every deflation column reached through the
+// columns of row i of A; values accumulate in CSR order (A row, then Z row).
+
+__global__ void k_az_count(int64_t n, const int* __restrict__ rowptr, const int* __restrict__ colind,
+                           const int* __restrict__ zrp, const int* __restrict__ zci,
+                           int* __restrict__ cnt, int* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cols[kAzRowMax];
+    int nc = 0;
+    bool over = false;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int j = colind[k];
+        for (int q = zrp[j]; q < zrp[j + 1]; ++q) {
+            const int a = zci[q];
+            bool found = false;
+            for (int t = 0; t < nc; ++t) found |= (cols[t] == a);
+            if (!found) {
+                if (nc < kAzRowMax) cols[nc++] = a;
+                else over = true;
+            }
+        }
+    }
+    cnt[i] = nc;
+    if (over) atomicOr(flags, 1);
+}
+
+__global__ void k_az_fill(int64_t n, const int* __restrict__ rowptr, const int* __restrict__ colind,
+                          const double* __restrict__ vals, const int* __restrict__ zrp,
+                          const int* __restrict__ zci, const double* __restrict__ zv,
+                          const int* __restrict__ azrp, int* __restrict__ azci,
+                          double* __restrict__ azv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cols[kAzRowMax];
+    double acc[kAzRowMax];
+    int nc = 0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int j = colind[k];
+        const double aij = vals[k];
+        for (int q = zrp[j]; q < zrp[j + 1]; ++q) {
+            const int a = zci[q];
+            int t = 0;
+            while (t < nc && cols[t] != a) ++t;
+            if (t == nc) {
+                cols[nc] = a;
+                acc[nc] = 0.0;
+                ++nc;
+            }
+            acc[t] += aij * zv[q];
+        }
+    }
+    // Sorted by deflation column (insertion sort; rows are short).
+    for (int t = 1; t < nc; ++t) {
+        const int c = cols[t];
+        const double v = acc[t];
+        int u = t - 1;
+        while (u >= 0 && cols[u] > c) {
+            cols[u + 1] = cols[u];
+            acc[u + 1] = acc[u];
+            --u;
+        }
+        cols[u + 1] = c;
+        acc[u + 1] = v;
+    }
+    const int o = azrp[i];
+    for (int t = 0; t < nc; ++t) {
+        azci[o + t] = cols[t];
+        azv[o + t] = acc[t];
+    }
+}
+
+int az_count(const SetupArgs& a, const int* rowptr, const int* colind, int* az_rowptr,
+             int64_t* az_nnz) {
+    int* cnt = nullptr;
+    int* flags = nullptr;
+    void* tmp = nullptr;
+    size_t tmp_bytes = 0;
+    int status = kStatusOk;
+    if (hipMalloc(&cnt, (a.n + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&flags, sizeof(int)) != hipSuccess) {
+        hipFree(cnt);
+        hipFree(flags);
+        return kStatusNoMem;
+    }
+    hipMemsetAsync(flags, 0, sizeof(int), a.st);
+    hipMemsetAsync(cnt + a.n, 0, sizeof(int), a.st);
+    k_az_count<<<blocks_for(a.n), kWG, 0, a.st>>>(a.n, rowptr, colind, a.zrp, a.zci, cnt, flags);
+    hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, az_rowptr, (int)(a.n + 1), a.st);
+    if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
+        status = kStatusNoMem;
+    } else {
+        hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, az_rowptr, (int)(a.n + 1), a.st);
+        int h[2] = {0, 0};
+        hipMemcpyAsync(&h[0], flags, sizeof(int), hipMemcpyDeviceToHost, a.st);
+        hipMemcpyAsync(&h[1], az_rowptr + a.n, sizeof(int), hipMemcpyDeviceToHost, a.st);
+        if (hipStreamSynchronize(a.st) != hipSuccess) status = kStatusDevice;
+        else if (h[0]) status = kStatusInval;
+        *az_nnz = h[1];
+    }
+    hipFree(cnt);
+    hipFree(flags);
+    hipFree(tmp);
+    return status;
+}
+
+void az_fill(const SetupArgs& a, const int* rowptr, const int* colind, const double* vals,
+             const int* az_rowptr, int* az_colind, double* az_vals) {
+    k_az_fill<<<blocks_for(a.n), kWG, 0, a.st>>>(a.n, rowptr, colind, vals, a.zrp, a.zci, a.zv,
+                                                 az_rowptr, az_colind, az_vals);
+}
+
+// ------------------------------------------------------- coarse matrix E
+// One thread per entry E_s[a][k] = sum_{i in Z^T row a} z_ia (A Z)_{i,k}
+// (row-major per system, offsets e_off).
+__global__ void k_build_e(int nsys, const int64_t* __restrict__ zcol_off,
+                          const int64_t* __restrict__ e_off, const int* __restrict__ ztrp,
+                          const int* __restrict__ ztci, const double* __restrict__ ztv,
+                          const int* __restrict__ azrp, const int* __restrict__ azci,
+                          const double* __restrict__ azv, double* __restrict__ E) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= e_off[nsys]) return;
+    const int s = sys_of_row(e_off, nsys, p);
+    const int64_t c0 = zcol_off[s];
+    const int r = (int)(zcol_off[s + 1] - c0);
+    const int64_t loc = p - e_off[s];
+    const int a = (int)(loc / r), k = (int)(loc % r);
+    const int col = (int)(c0 + k);
+    double acc = 0.0;
+    for (int q = ztrp[c0 + a]; q < ztrp[c0 + a + 1]; ++q) {
+        const int i = ztci[q];
+        for (int t = azrp[i]; t < azrp[i + 1]; ++t)
+            if (azci[t] == col) acc += ztv[q] * azv[t];
+    }
+    E[p] = acc;
+}
+
+void build_coarse(const SetupArgs& a, const int* ztrp, const int* ztci, const double* ztv,
+                  const int* azrp, const int* azci, const double* azv, const int64_t* d_e_off,
+                  double* E) {
+    int64_t total = 0;
+    hipMemcpyAsync(&total, d_e_off + a.nsys, sizeof(int64_t), hipMemcpyDeviceToHost, a.st);
+    hipStreamSynchronize(a.st);
+    if (total > 0)
+        k_build_e<<<blocks_for(total), kWG, 0, a.st>>>(a.nsys, a.d_sys_zcol_off, d_e_off, ztrp, ztci,
+                                                      ztv, azrp, azci, azv, E);
+}
+
+// LU with partial pivoting of each E_s (row-major, in place; one workgroup per
+// system), then the explicit inverse column by column, stored column-major
+// (Einv_s[a*r + i] = (E_s^{-1})_{i,a}).  Pivot = first row of largest |.|;
+// singular when |pivot| <= r * eps * max|E_s| (flags bit 2).
+__global__ __launch_bounds__(kWG) void k_lu_inverse(const int64_t* __restrict__ zcol_off,
+                                                    const int64_t* __restrict__ e_off,
+                                                    double* __restrict__ Eall,
+                                                    double* __restrict__ Einv_all,
+                                                    int* __restrict__ flags) {
+    const int s = blockIdx.x;
+    const int r = (int)(zcol_off[s + 1] - zcol_off[s]);
+    if (r == 0) return;
+    double* E = Eall + e_off[s];
+    double* X = Einv_all + e_off[s];
+    __shared__ double rv[kWG];
+    __shared__ int ri[kWG];
+    __shared__ int piv[kMaxR];
+    __shared__ int sing;
+    // max |E|
+    double mx = 0.0;
+    for (int64_t q = threadIdx.x; q < (int64_t)r * r; q += kWG) mx = fmax(mx, fabs(E[q]));
+    rv[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = kWG / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) rv[threadIdx.x] = fmax(rv[threadIdx.x], rv[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const double tiny = (double)r * 2.220446049250313e-16 * rv[0];
+    if (threadIdx.x == 0) sing = 0;
+    __syncthreads();
+    for (int k = 0; k < r; ++k) {
+        double best = -1.0;
+        int bi = r;
+        for (int i = k + threadIdx.x; i < r; i += kWG) {
+            const double v = fabs(E[(int64_t)i * r + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        rv[threadIdx.x] = best;
+        ri[threadIdx.x] = bi;
+        __syncthreads();
+        for (int o = kWG / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                const double b2 = rv[threadIdx.x + o];
+                const int i2 = ri[threadIdx.x + o];
+                if (b2 > rv[threadIdx.x] || (b2 == rv[threadIdx.x] && i2 < ri[threadIdx.x])) {
+                    rv[threadIdx.x] = b2;
+                    ri[threadIdx.x] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        const int p = ri[0];
+        if (threadIdx.x == 0) {
+            piv[k] = p;
+            if (!(rv[0] > tiny)) sing = 1;
+        }
+        __syncthreads();
+        if (sing) break;
+        if (p != k)
+            for (int j = threadIdx.x; j < r; j += kWG) {
+                const double t = E[(int64_t)k * r + j];
+                E[(int64_t)k * r + j] = E[(int64_t)p * r + j];
+                E[(int64_t)p * r + j] = t;
+            }
+        __syncthreads();
+        const double pk = E[(int64_t)k * r + k];
+        for (int i = k + 1 + threadIdx.x; i < r; i += kWG) E[(int64_t)i * r + k] /= pk;
+        __syncthreads();
+        const int64_t w = r - k - 1;
+        for (int64_t q = threadIdx.x; q < w * w; q += kWG) {
+            const int i = k + 1 + (int)(q / w), j = k + 1 + (int)(q % w);
+            E[(int64_t)i * r + j] -= E[(int64_t)i * r + k] * E[(int64_t)k * r + j];
+        }
+        __syncthreads();
+    }
+    if (sing) {
+        if (threadIdx.x == 0) atomicOr(flags, 4);
+        return;
+    }
+    // Column a of the inverse: solve (P L U) x = e_a.
+    for (int a = threadIdx.x; a < r; a += kWG) {
+        double* x = X + (int64_t)a * r;
+        for (int i = 0; i < r; ++i) x[i] = (i == a) ? 1.0 : 0.0;
+        for (int k = 0; k < r; ++k)
+            if (piv[k] != k) {
+                const double t = x[k];
+                x[k] = x[piv[k]];
+                x[piv[k]] = t;
+            }
+        for (int i = 0; i < r; ++i) {
+            double v = x[i];
+            for (int j = 0; j < i; ++j) v -= E[(int64_t)i * r + j] * x[j];
+            x[i] = v;
+        }
+        for (int i = r - 1; i >= 0; --i) {
+            double v = x[i];
+            for (int j = i + 1; j < r; ++j) v -= E[(int64_t)i * r + j] * x[j];
+            x[i] = v / E[(int64_t)i * r + i];
+        }
+    }
+}
+
+int lu_inverse(hipStream_t st, int nsys, const int64_t* d_sys_zcol_off, const int64_t* d_e_off,
+               double* E, double* Einv, int* d_flags) {
+    hipMemsetAsync(d_flags, 0, sizeof(int), st);
+    k_lu_inverse<<<nsys, kWG, 0, st>>>(d_sys_zcol_off, d_e_off, E, Einv, d_flags);
+    int h = 0;
+    hipMemcpyAsync(&h, d_flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) return kStatusDevice;
+    return (h & 4) ? kStatusSingular : kStatusOk;
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_to_f32(int64_t n, const double* __restrict__ s, float* __restrict__ d) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+
+void to_f32(hipStream_t st, int64_t n, const double* src, float* dst) {
+    if (n > 0) k_to_f32<<<blocks_for(n), kWG, 0, st>>>(n, src, dst);
+}
+
+// dL/dA_ij = -lambda_i x_j on the pattern of A.
+__global__ void k_grad_vals(int64_t n, const int* __restrict__ rowptr, const int* __restrict__ colind,
+                            const double* __restrict__ lam, const double* __restrict__ x,
+                            double* __restrict__ g) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double li = lam[i];
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) g[k] = -li * x[colind[k]];
+}
+
+void grad_vals(hipStream_t st, int64_t n, const int* rowptr, const int* colind, const double* lam,
+               const double* x, double* g) {
+    k_grad_vals<<<blocks_for(n), kWG, 0, st>>>(n, rowptr, colind, lam, x, g);
+}
+
+__global__ void k_max_row(int R, const int* __restrict__ rp, int* __restrict__ out) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < R) atomicMax(out, rp[a + 1] - rp[a]);
+}
+
+int zt_max_row(hipStream_t st, int R, const int* ztrp, int* d_tmp) {
+    hipMemsetAsync(d_tmp, 0, sizeof(int), st);
+    if (R > 0) k_max_row<<<blocks_for(R), kWG, 0, st>>>(R, ztrp, d_tmp);
+    int h = 0;
+    hipMemcpyAsync(&h, d_tmp, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    return h;
+}
+
+}  // namespace gm

@@ -1,0 +1,46 @@
+"""Host-side checks of the C interface (no GPU needed): the library loads and
+exports every function include/gmres.h declares; struct layouts of the binding
+match the header's field order."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1906_04051_amd import gmres as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    hdr = open(os.path.join(ROOT, "include", "gmres.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmres_[a-z_]+)\s*\(", hdr)))
+
+
+def test_header_declares_binding_exports():
+    assert _declared() == sorted(G.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(G.LIB_PATH):
+        pytest.fail("libgmres_mi355x.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(G.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_struct_fields_follow_header_order():
+    hdr = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "gmres.h")).read(), flags=re.S)
+    for cname, pyst in (("gmres_opts", G.GmresOpts), ("gmres_info", G.GmresInfo)):
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", hdr).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = re.findall(r"(\w+)\s*(?:,|;)", body)
+        assert names == [f for f, _ in pyst._fields_], (cname, names)
+
+
+def test_default_opts_roundtrip():
+    o = G.default_opts(m=50, rtol=1e-10, precision="mixed_f16")
+    assert o.m == 50 and o.rtol == 1e-10 and o.precision == 2 and o.use_graph == 1
+    with pytest.raises(TypeError):
+        G.default_opts(bogus=1)
