@@ -50,6 +50,28 @@ def cpu_baseline(sysm, m, fp64_iters, sample_iters):
                 seconds_per_iter=per_iter, sample_seconds=dt)
 
 
+def pmc_sample(sysm, d, m, tuned):
+    """Two fixed-count restart cycles of the FP64 solve (the timed launch
+    configuration) and one 512 MiB device copy (512 MiB read + 512 MiB
+    written), for FETCH_SIZE / WRITE_SIZE counter runs."""
+    import torch
+    from paper_1906_04051_amd import gmres as G
+    q = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"], d["z_vals"],
+               r=sysm.r, precision="fp64", m=m, rtol=0.0, max_iters=2 * m,
+               spmv_lanes=tuned["spmv_lanes"], num_blocks=tuned["num_blocks"])
+    q.set_timing(True)
+    _, info = q.solve(d["b"])
+    kt = q.kernel_times()
+    src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    per = {k: dict(launches=int(v["launches"]), bytes_per_launch=v["bytes"] / max(v["launches"], 1),
+                   avg_us=1000 * v["ms"] / max(v["launches"], 1)) for k, v in kt.items()}
+    print(json.dumps({"pmc_sample": per, "iters": info["iters"], "copy_bytes_each_way": 512 << 20}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +82,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="short fixed-count FP64 run (two restart cycles) plus a copy of known "
+                         "size, for hardware-counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -85,9 +110,14 @@ def main():
         plans["mixed"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
                                 d["z_vals"], r=sysm.r, precision="mixed_f16", inner_rtol=1e-3,
                                 inner_max_iters=100000, max_refine=40, **common)
+    tuned = {}
     for k, p in plans.items():
-        log(f"[bench] autotune {k}: {p.autotune()}")
+        tuned[k] = p.autotune()
+        log(f"[bench] autotune {k}: {tuned[k]}")
     b = d["b"]
+    if args.pmc_sample:
+        pmc_sample(sysm, d, m, tuned["fp64"])
+        return
     x = torch.empty_like(b)
 
     def run(name, timing):

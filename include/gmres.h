@@ -70,10 +70,17 @@ typedef struct {
     int64_t inner_max_iters;  /* mixed: cap on inner steps per refinement */
     int32_t use_graph;        /* 1: replay each restart cycle as a captured hipGraph */
     int32_t record_history;   /* 1: keep |gamma_{k+1}| per step (gmres_history) */
-    int32_t spmv_lanes;       /* lanes per CSR row in SpMV (1..64, power of two); 0 = auto */
+    int32_t spmv_lanes;       /* SpMV variant: lanes per CSR row (1..64, power of two), or
+                                 -256 / -128 for the LDS-staged row stream with that many
+                                 rows per workgroup; 0 = auto */
     int32_t num_blocks;       /* workgroups of the streaming kernels; 0 = auto */
     int32_t batch_wg;         /* batched: threads per workgroup (256, 512, 1024); 0 = auto */
     int32_t batch_lanes;      /* batched: SpMV lanes per row (4, 8, 16, 32); 0 = auto */
+    int32_t ortho;            /* single-system Arnoldi: 0 = CGS2 in three sweeps over the basis
+                                 (project, re-project, update); 1 = CGS2 in two sweeps with lagged
+                                 normalisation (the SpMV of step j+1 runs on the once-projected
+                                 vector; the second update is folded into the next sweep through
+                                 the Arnoldi relation).  Equal in exact arithmetic. */
 } gmres_opts;
 
 typedef struct {
@@ -90,7 +97,7 @@ typedef struct {
 
 /* Fills *o with defaults: m = 30, max_iters = 10000, rtol = 1e-8, FP64,
  * inner_rtol = 1e-3 (FP16 basis) , max_refine = 30, inner_max_iters = 20000,
- * use_graph = 1, everything else 0 (auto). */
+ * use_graph = 1, ortho = 1, everything else 0 (auto). */
 void gmres_default_opts(gmres_opts* o);
 
 /*

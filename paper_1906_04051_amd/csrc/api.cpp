@@ -97,12 +97,33 @@ struct gmres_plan_s {
     int *ztrp = nullptr, *ztci = nullptr, *ztperm = nullptr;
     double* ztv = nullptr;
     int MC = 1, CH = 2048;
+    // per-block deflation slots for the fused Z^T y, per stream block size
+    int slots_rb = 0;
+    int *bb_ptr = nullptr, *bb_col = nullptr, *ab_ptr = nullptr, *ab_slot = nullptr;
+    int* slot_pos = nullptr;
+    // single-entry row copies: Z (n rows), A Z and A^T Z (ldv rows, padded)
+    int* zc1 = nullptr;
+    double* zv1 = nullptr;
+    int *azc1 = nullptr, *atzc1 = nullptr;
+    double *azv1 = nullptr, *atzv1 = nullptr;
+    float* azv1f = nullptr;
+    int64_t nslots = 0;
+    int64_t tpart_cap = 0;
     // A Z (compact)
     int *azrp = nullptr, *azci = nullptr;
     double* azv = nullptr;
     float* azv32 = nullptr;
     int64_t az_nnz = 0;
     double *E = nullptr, *Einv = nullptr;
+    // sliced ELL copies (forward op / adjoint op)
+    int *sell_off = nullptr, *sell_col = nullptr, *sell_src = nullptr;
+    double* sell_v64 = nullptr;
+    float* sell_v32 = nullptr;
+    int64_t sell_total = 0;
+    int sell_wmax = 0, tsell_wmax = 0;
+    int *tsell_off = nullptr, *tsell_col = nullptr, *tsell_src = nullptr;
+    double* tsell_v64 = nullptr;
+    int64_t tsell_total = 0;
     // adjoint operator
     int *trp = nullptr, *tci = nullptr, *tperm = nullptr;
     double* tv = nullptr;
@@ -112,12 +133,14 @@ struct gmres_plan_s {
 
     // single-system Krylov workspace
     int NB = 1, L = 8, NB_cap = 1;
+    int last_prec = 0;
     int64_t ldv = 0;
     void* V = nullptr;
     double *y = nullptr, *w = nullptr, *pv = nullptr, *rv = nullptr, *xh = nullptr, *bws = nullptr;
     double *xo = nullptr, *r64 = nullptr, *dvec = nullptr;
     double* part = nullptr;
     double *h1, *h2, *coef1, *coef2, *H, *Hraw, *cs, *sn, *g, *vscale, *sigma, *sigma0, *scal;
+    double *cc = nullptr, *lag = nullptr;
     double *tpart = nullptr, *s_step = nullptr, *s_res = nullptr;
     Ctrl* ctrl = nullptr;
     Ctrl* ctrl_h = nullptr;             // pinned, 2 snapshots
@@ -176,12 +199,16 @@ gmres_status to_status(int s, const char* what) {
     }
 }
 
+// SpMV variant: > 0 lanes per row; -256 / -128 LDS-staged stream with that
+// many rows per block; kSell (-64) sliced ELL (short rows: FEM stencils).
 int default_lanes(int64_t n, int64_t nnz) {
     const double rho = n > 0 ? (double)nnz / (double)n : 1.0;
-    if (rho <= 6) return 4;
-    if (rho <= 12) return 8;
-    if (rho <= 24) return 16;
+    if (rho <= 40) return kSell;
     return 32;
+}
+
+int max_row_len(hipStream_t st, int64_t n, const int* rp, int* d_tmp) {
+    return zt_max_row(st, (int)n, rp, d_tmp);
 }
 
 // Builds A Z (compact CSR) for the operator (rowptr, colind, vals).
@@ -202,6 +229,13 @@ gmres_status build_az(gmres_plan_s* p, const int* rp, const int* ci, const doubl
     return GMRES_OK;
 }
 
+// Single-entry (ELL-1) copies of A Z / A^T Z for the pass-1 deflation.
+void refresh_ell1(gmres_plan_s* p) {
+    if (p->R == 0 || !p->azc1) return;
+    ell1_build(p->st, p->n, p->azrp, p->azci, p->azv, p->azc1, p->azv1, p->azv1f);
+    if (p->atzc1) ell1_build(p->st, p->n, p->atzrp, p->atzci, p->atzv, p->atzc1, p->atzv1, nullptr);
+}
+
 // (Re)computes everything derived from the values of A.
 gmres_status refresh_values(gmres_plan_s* p) {
     SetupArgs sa{p->st, p->nsys, p->n, p->nnz, p->znnz, p->R, p->d_row_off, p->d_zcol_off,
@@ -214,11 +248,43 @@ gmres_status refresh_values(gmres_plan_s* p) {
         if (p->azv32) to_f32(p->st, p->az_nnz, p->azv, p->azv32);
     }
     if (p->vals32) to_f32(p->st, p->nnz, p->vals, p->vals32);
+    if (p->sell_src) sell_values(p->st, p->sell_total, p->sell_src, p->vals, p->sell_v64, p->sell_v32);
     if (p->need_adjoint) {
         gather_values(p->st, p->nnz, p->tperm, p->vals, p->tv);
+        if (p->tsell_src) sell_values(p->st, p->tsell_total, p->tsell_src, p->tv, p->tsell_v64, nullptr);
         if (p->R > 0) az_fill(sa, p->trp, p->tci, p->tv, p->atzrp, p->atzci, p->atzv);
     }
+    refresh_ell1(p);
     HIP_OK(hipStreamSynchronize(p->st));
+    return GMRES_OK;
+}
+
+gmres_status clear_typed(gmres_plan_s* p);
+
+// Builds (or rebuilds for another block size) the per-block deflation slots
+// used by the fused Z^T y of the stream SpMV.  Falls back to the separate
+// Z^T pass when a row block reaches more than 64 deflation columns.
+gmres_status ensure_slots(gmres_plan_s* p) {
+    const int rb = (p->L == kSell || p->L == -256) ? 256 : (p->L == -128 ? 128 : 0);
+    if (p->R == 0 || rb == 0 || rb == p->slots_rb) return GMRES_OK;
+    for (int* q : {p->bb_ptr, p->bb_col, p->ab_ptr, p->ab_slot, p->slot_pos}) hipFree(q);
+    p->bb_ptr = p->bb_col = p->ab_ptr = p->ab_slot = p->slot_pos = nullptr;
+    p->slots_rb = 0;
+    int64_t ns = 0;
+    int s = build_block_slots(p->st, p->n, rb, p->R, p->zrp, p->zci, &p->bb_ptr, &p->bb_col,
+                              &p->ab_ptr, &p->ab_slot, &ns, p->d_flags);
+    if (s == kStatusInval) return GMRES_OK;          // dense Z: keep the separate pass
+    CHECK(to_status(s, "deflation slots"));
+    if (ns > p->tpart_cap) {
+        double* t = nullptr;
+        CHECK(dalloc(p, &t, ns));
+        p->tpart = t;
+        p->tpart_cap = ns;
+    }
+    HIP_OK(hipMalloc(&p->slot_pos, std::max<int64_t>(ns, 1) * sizeof(int)));
+    invperm(p->st, ns, p->ab_slot, p->slot_pos);
+    p->nslots = ns;
+    p->slots_rb = rb;
     return GMRES_OK;
 }
 
@@ -229,11 +295,14 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
     double* Vd = nullptr;
     CHECK(dalloc(p, &Vd, (int64_t)(m + 1) * p->ldv));
     p->V = Vd;
-    for (double** q : {&p->y, &p->w, &p->pv, &p->rv, &p->xh, &p->bws, &p->xo, &p->r64, &p->dvec})
-        CHECK(dalloc(p, q, n));
+    // Typed work vectors are read in whole 16-byte tiles: they hold ldv
+    // entries and their padding stays zero.
+    for (double** q : {&p->y, &p->w, &p->pv, &p->rv}) CHECK(dalloc(p, q, p->ldv));
+    for (double** q : {&p->xh, &p->bws, &p->xo, &p->r64, &p->dvec}) CHECK(dalloc(p, q, n));
+    CHECK(clear_typed(p));
     p->NB_cap = std::max(p->NB, (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 2048));
     CHECK(dalloc(p, &p->part, (int64_t)(m + 2) * p->NB_cap));
-    const int64_t small = 4 * (m + 1) + 2 * (int64_t)(m + 1) * m + 2 * m + 2 * (m + 1) + 16;
+    const int64_t small = 5 * (m + 1) + 2 * (int64_t)(m + 1) * m + 2 * m + 2 * (m + 1) + 24;
     double* s = nullptr;
     CHECK(dalloc(p, &s, small));
     p->h1 = s; s += m + 1;
@@ -249,10 +318,32 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
     p->sigma = s; s += 1;
     p->sigma0 = s; s += 1;
     p->scal = s; s += 8;
+    p->cc = s; s += m + 1;
+    p->lag = s; s += 4;
     if (p->R > 0) {
-        CHECK(dalloc(p, &p->tpart, (int64_t)p->R * p->MC));
+        CHECK(dalloc(p, &p->tpart, std::max<int64_t>((int64_t)p->R * p->MC, p->tpart_cap)));
         CHECK(dalloc(p, &p->s_step, p->R));
         CHECK(dalloc(p, &p->s_res, p->R));
+    }
+    p->tpart_cap = std::max<int64_t>(p->tpart_cap, (int64_t)p->R * p->MC);
+    CHECK(ensure_slots(p));
+    if (p->R > 0) {
+        // Padded to ldv rows: padding reads as "no entry" (-1) with value 0.
+        CHECK(dalloc(p, &p->azc1, p->ldv));
+        CHECK(dalloc(p, &p->azv1, p->ldv));
+        HIP_OK(hipMemsetAsync(p->azc1, 0xFF, p->ldv * sizeof(int), p->st));
+        HIP_OK(hipMemsetAsync(p->azv1, 0, p->ldv * sizeof(double), p->st));
+        if (p->o.precision != GMRES_FP64) {
+            CHECK(dalloc(p, &p->azv1f, p->ldv));
+            HIP_OK(hipMemsetAsync(p->azv1f, 0, p->ldv * sizeof(float), p->st));
+        }
+        if (p->need_adjoint) {
+            CHECK(dalloc(p, &p->atzc1, p->ldv));
+            CHECK(dalloc(p, &p->atzv1, p->ldv));
+            HIP_OK(hipMemsetAsync(p->atzc1, 0xFF, p->ldv * sizeof(int), p->st));
+            HIP_OK(hipMemsetAsync(p->atzv1, 0, p->ldv * sizeof(double), p->st));
+        }
+        refresh_ell1(p);
     }
     CHECK(dalloc(p, &p->ctrl, 1));
     HIP_OK(hipHostMalloc((void**)&p->ctrl_h, 2 * sizeof(Ctrl), 0));
@@ -260,6 +351,15 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
     HIP_OK(hipEventCreateWithFlags(&p->ev_cyc[1], hipEventDisableTiming));
     p->cyc_cap = 1 << 16;
     CHECK(dalloc(p, &p->cyc_k, p->cyc_cap));
+    return GMRES_OK;
+}
+
+// Zeroes the basis and the typed work vectors (their padding must read as
+// zero in whichever precision the next engine uses).
+gmres_status clear_typed(gmres_plan_s* p) {
+    HIP_OK(hipMemsetAsync(p->V, 0, (size_t)(p->o.m + 1) * p->ldv * sizeof(double), p->st));
+    for (double* q : {p->y, p->w, p->pv, p->rv})
+        HIP_OK(hipMemsetAsync(q, 0, (size_t)p->ldv * sizeof(double), p->st));
     return GMRES_OK;
 }
 
@@ -306,6 +406,35 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.ztv = p->ztv;
     a.tpart = p->tpart;
     a.Einv = p->Einv;
+    const int rb = (p->L == kSell || p->L == -256) ? 256 : (p->L == -128 ? 128 : 0);
+    a.fuse_rb = (p->R > 0 && rb != 0 && rb == p->slots_rb) ? rb : 0;
+    if (op == 0) {
+        a.sell_off = p->sell_off;
+        a.sell_col = p->sell_col;
+        a.sell_val = f64 ? (const void*)p->sell_v64 : (const void*)p->sell_v32;
+        a.sell_wmax = p->sell_wmax;
+    } else {
+        a.sell_wmax = p->tsell_wmax;
+        a.sell_off = p->tsell_off;
+        a.sell_col = p->tsell_col;
+        a.sell_val = p->tsell_v64;
+    }
+    a.zrp = p->zrp;
+    a.zci = p->zci;
+    a.zv = p->zv;
+    a.bb_ptr = p->bb_ptr;
+    a.bb_col = p->bb_col;
+    a.ab_ptr = p->ab_ptr;
+    a.slot_pos = p->slot_pos;
+    a.zc1 = p->zc1;
+    a.zv1 = p->zv1;
+    if (op == 0) {
+        a.azc1 = p->azc1;
+        a.azv1 = f64 ? (const void*)p->azv1 : (const void*)p->azv1f;
+    } else {
+        a.azc1 = p->atzc1;
+        a.azv1 = p->atzv1;
+    }
     a.s_step = p->s_step;
     a.s_res = p->s_res;
     a.part = p->part;
@@ -324,6 +453,9 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.hist_cap = p->hist_cap;
     a.Hraw = p->Hraw;
     a.ctrl = p->ctrl;
+    a.lagged = p->o.ortho == 1 ? 1 : 0;
+    a.cc = p->cc;
+    a.lag = p->lag;
     a.cyc_k = p->cyc_k;
     a.cyc_cap = (int)std::min<int64_t>(p->cyc_cap, INT32_MAX);
     return a;
@@ -343,7 +475,8 @@ struct TimerHook final : KTimer {
     int op;
     int cycle = 0;
     int open_ev = -1;
-    TimerHook(gmres_plan_s* pp, int pr, int o) : p(pp), prec(pr), op(o) {}
+    bool lagged = false;
+    TimerHook(gmres_plan_s* pp, int pr, int o) : p(pp), prec(pr), op(o), lagged(pp->o.ortho == 1) {}
     double kernel_bytes(int kind, int j) const {
         const double n = (double)p->n, nnz = (double)p->nnz;
         const double bv = type_bytes(prec, 1), bw = type_bytes(prec, 2), ba = type_bytes(prec, 0);
@@ -351,7 +484,10 @@ struct TimerHook final : KTimer {
         const double az = p->R > 0 ? 4.0 * (n + 1) + (4.0 + ba) * (double)p->az_nnz + 8.0 * p->R : 0.0;
         switch (kind) {
             case 0: return (ba + 4.0) * nnz + 4.0 * (n + 1) + bv * n + bw * n;
-            case 1: return bw * n + az + bv * n * nv + bw * n;
+            case 1:
+                if (lagged && j > 0)   // reads V_0..j-1, w1, u; writes v_j, w
+                    return bv * n * (nv - 1) + bv * n + 3.0 * bw * n + az;
+                return bw * n + az + bv * n * nv + bw * n;
             case 2: return bv * n * nv + 2.0 * bw * n;
             default: return bv * n * nv + bw * n + bv * n;
         }
@@ -392,6 +528,7 @@ void collect_timer(gmres_plan_s* p, int64_t ncycles_dev) {
 gmres_status ensure_graph(gmres_plan_s* p, int op, int prec, const void* b) {
     if (p->gexec[op][prec]) return GMRES_OK;
     EngineArgs a = make_args(p, op, prec);
+    a.trust_est = (prec != kPrecF64) ? 1 : 0;   // reduced-precision engines only run inner solves
     hipGraph_t gph = nullptr;
     HIP_OK(hipStreamBeginCapture(p->st, hipStreamCaptureModeThreadLocal));
     launch_cycle(a, b);
@@ -407,13 +544,18 @@ gmres_status ensure_graph(gmres_plan_s* p, int op, int prec, const void* b) {
 // done.  b: the engine's right-hand side (type WT).  Returns the final control
 // block in *out.
 gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double rtol,
-                        double r0_override, int64_t max_iters, Ctrl* out) {
+                        double r0_override, int64_t max_iters, Ctrl* out, bool trust_est = false) {
     const bool timing = p->timer.enabled;
     const bool graph = p->o.use_graph && !timing;
     EngineArgs a = make_args(p, op, prec);
+    a.trust_est = trust_est ? 1 : 0;
     TimerHook hook(p, prec, op);
     if (timing) a.timer = &hook;
     if (graph) CHECK(ensure_graph(p, op, prec, b));
+    if (prec != p->last_prec) {
+        CHECK(clear_typed(p));
+        p->last_prec = prec;
+    }
     launch_ctrl_reset(p->st, p->ctrl, max_iters);
     launch_restart_init(a, b, rtol, r0_override);
     auto enqueue = [&](int c) -> gmres_status {
@@ -446,10 +588,25 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
 }
 
 // ||b - A x|| in FP64 (scratch: p->w, partial slot of p->part).
+void spmv_f64(gmres_plan_s* p, int L, int NB, const double* x, double* y) {
+    if (L == kSell)
+        launch_spmv_sell_f64(p->st, NB, (int)p->n, p->sell_off, p->sell_col, p->sell_v64, x, y);
+    else
+        launch_spmv_f64(p->st, L, NB, (int)p->n, p->rowptr, p->colind, p->vals, x, y);
+}
+
+void residual_f64(gmres_plan_s* p, const double* x, const double* b, double* r, int slot) {
+    if (p->L == kSell)
+        launch_residual_sell_f64(p->st, p->NB, (int)p->n, p->sell_off, p->sell_col, p->sell_v64, x,
+                                 b, r, p->part, slot);
+    else
+        launch_residual_f64(p->st, p->L, p->NB, (int)p->n, p->rowptr, p->colind, p->vals, x, b, r,
+                            p->part, slot);
+}
+
 gmres_status true_residual(gmres_plan_s* p, const double* b, const double* x, double* nrm) {
     const int slot = p->o.m + 1;
-    launch_residual_f64(p->st, p->L, p->NB, (int)p->n, p->rowptr, p->colind, p->vals, x, b, p->w,
-                        p->part, slot);
+    residual_f64(p, x, b, p->w, slot);
     launch_sum_slot(p->st, p->part, p->NB, slot, p->scal);
     double h = 0;
     HIP_OK(hipMemcpyAsync(&h, p->scal, sizeof(double), hipMemcpyDeviceToHost, p->st));
@@ -499,8 +656,7 @@ gmres_status solve_mixed(gmres_plan_s* p, const double* b, const double* x0, dou
     else launch_fill(p->st, p->xo, n, 0.0);
     // r = b - A x (FP64), ||r||^2 into scal[0]
     auto outer_residual = [&](double* nrm2_h) -> gmres_status {
-        launch_residual_f64(p->st, p->L, p->NB, (int)n, p->rowptr, p->colind, p->vals, p->xo, b,
-                            p->r64, p->part, slot);
+        residual_f64(p, p->xo, b, p->r64, slot);
         launch_sum_slot(p->st, p->part, p->NB, slot, p->scal);
         HIP_OK(hipMemcpyAsync(nrm2_h, p->scal, sizeof(double), hipMemcpyDeviceToHost, p->st));
         HIP_OK(hipStreamSynchronize(p->st));
@@ -549,7 +705,7 @@ gmres_status solve_mixed(gmres_plan_s* p, const double* b, const double* x0, dou
         launch_scale_to_f32(p->st, p->NB, (int)n, p->r64, p->scal, reinterpret_cast<float*>(p->bws));
         launch_fill(p->st, p->xh, n, 0.0);
         Ctrl c{};
-        CHECK(run_engine(p, 0, prec, p->bws, o.inner_rtol, 0.0, o.inner_max_iters, &c));
+        CHECK(run_engine(p, 0, prec, p->bws, o.inner_rtol, 0.0, o.inner_max_iters, &c, true));
         launch_correct(p->st, p->NB, (int)n, p->zrp, p->zci, p->zv, p->s_res, p->R, p->xh, p->dvec);
         info->iters += c.its;
         info->cycles += c.cycles;
@@ -582,6 +738,7 @@ void gmres_default_opts(gmres_opts* o) {
     o->max_refine = 30;
     o->inner_max_iters = 20000;
     o->use_graph = 1;
+    o->ortho = 1;
 }
 
 const char* gmres_last_error(void) { return g_last_error.c_str(); }
@@ -596,6 +753,8 @@ void gmres_destroy(gmres_plan p) {
             if (p->graph[a][b]) hipGraphDestroy(p->graph[a][b]);
         }
     for (void* q : p->allocs) hipFree(q);
+    for (int* q : {p->bb_ptr, p->bb_col, p->ab_ptr, p->ab_slot, p->slot_pos}) hipFree(q);
+    for (int* q : {p->sell_off, p->sell_col, p->sell_src, p->tsell_off, p->tsell_col, p->tsell_src}) hipFree(q);
     if (p->ctrl_h) hipHostFree(p->ctrl_h);
     for (auto e : {p->ev_cyc[0], p->ev_cyc[1], p->ev_in, p->ev_out})
         if (e) hipEventDestroy(e);
@@ -616,11 +775,13 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     if (p->o.max_iters < 0 || !(p->o.rtol >= 0.0))
         return fail(GMRES_EINVAL, "max_iters >= 0 and rtol >= 0 required");
     if (p->o.precision < 0 || p->o.precision > 2) return fail(GMRES_EINVAL, "unknown precision");
+    if (p->o.ortho < 0 || p->o.ortho > 1) return fail(GMRES_EINVAL, "unknown orthogonalisation variant");
     if (p->o.precision != GMRES_FP64 && (!(p->o.inner_rtol > 0.0) || p->o.inner_rtol >= 1.0))
         return fail(GMRES_EINVAL, "inner_rtol must be in (0, 1)");
-    if (p->o.spmv_lanes != 0 && (p->o.spmv_lanes < 1 || p->o.spmv_lanes > 64 ||
-                                 (p->o.spmv_lanes & (p->o.spmv_lanes - 1))))
-        return fail(GMRES_EINVAL, "spmv_lanes must be a power of two in [1, 64]");
+    if (p->o.spmv_lanes != 0 && p->o.spmv_lanes != -256 && p->o.spmv_lanes != -128 &&
+        p->o.spmv_lanes != kSell &&
+        (p->o.spmv_lanes < 1 || p->o.spmv_lanes > 64 || (p->o.spmv_lanes & (p->o.spmv_lanes - 1))))
+        return fail(GMRES_EINVAL, "spmv_lanes must be a power of two in [1, 64], -64, -128 or -256");
     p->nsys = nsys;
     p->row_off.assign(sys_row_off_h, sys_row_off_h + nsys + 1);
     if (sys_zcol_off_h) p->zcol_off.assign(sys_zcol_off_h, sys_zcol_off_h + nsys + 1);
@@ -699,6 +860,9 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
         CHECK(to_status(build_transpose(p->st, n, p->R, p->znnz, p->zrp, p->zci, p->ztrp, p->ztci,
                                         p->ztperm), "Z transpose"));
         gather_values(p->st, p->znnz, p->ztperm, p->zv, p->ztv);
+        CHECK(dalloc(p, &p->zc1, n));
+        CHECK(dalloc(p, &p->zv1, n));
+        ell1_build(p->st, n, p->zrp, p->zci, p->zv, p->zc1, p->zv1, nullptr);
         const int maxrow = zt_max_row(p->st, p->R, p->ztrp, p->d_flags);
         p->CH = 2048;
         p->MC = std::max(1, (maxrow + p->CH - 1) / p->CH);
@@ -721,9 +885,25 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
         if (p->R > 0)
             CHECK(build_az(p, p->trp, p->tci, p->tv, &p->atzrp, &p->atzci, &p->atzv, &p->atz_nnz));
     }
+    // Sliced ELL copies for the SpMV (values filled by refresh_values).
+    {
+        int* tmp_src = nullptr;
+        CHECK(to_status(sell_build(p->st, n, p->rowptr, p->colind, &p->sell_off, &p->sell_col,
+                                   &tmp_src, &p->sell_total), "sliced ELL"));
+        p->sell_src = tmp_src;
+        p->sell_wmax = max_row_len(p->st, n, p->rowptr, p->d_flags);
+        CHECK(dalloc(p, &p->sell_v64, std::max<int64_t>(p->sell_total, 1)));
+        if (p->o.precision != GMRES_FP64) CHECK(dalloc(p, &p->sell_v32, std::max<int64_t>(p->sell_total, 1)));
+        if (p->need_adjoint) {
+            CHECK(to_status(sell_build(p->st, n, p->trp, p->tci, &p->tsell_off, &p->tsell_col,
+                                       &p->tsell_src, &p->tsell_total), "sliced ELL (A^T)"));
+            CHECK(dalloc(p, &p->tsell_v64, std::max<int64_t>(p->tsell_total, 1)));
+            p->tsell_wmax = max_row_len(p->st, n, p->trp, p->d_flags);
+        }
+    }
     CHECK(refresh_values(p));
 
-    p->L = p->o.spmv_lanes > 0 ? p->o.spmv_lanes : default_lanes(n, nnz);
+    p->L = p->o.spmv_lanes != 0 ? p->o.spmv_lanes : default_lanes(n, nnz);
     p->NB = p->o.num_blocks > 0 ? p->o.num_blocks
                                 : (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 1024);
     if (nsys == 1) CHECK(alloc_krylov(p));
@@ -850,7 +1030,7 @@ gmres_status gmres_update_values(gmres_plan p, const double* vals) {
 gmres_status gmres_spmv(gmres_plan p, const double* x, double* y) {
     if (!p || !x || !y) return fail(GMRES_EINVAL, "plan, x and y are required");
     CHECK(enter(p));
-    launch_spmv_f64(p->st, p->L, p->NB > 0 ? p->NB : 1, (int)p->n, p->rowptr, p->colind, p->vals, x, y);
+    spmv_f64(p, p->L, p->NB > 0 ? p->NB : 1, x, y);
     HIP_OK(hipGetLastError());
     CHECK(leave(p));
     HIP_OK(hipStreamSynchronize(p->st));
@@ -1013,10 +1193,8 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
         launch_fill(p->st, p->coef1, p->o.m + 1, 1e-3);
         double best = 1e30;
         int bestL = p->L;
-        for (int L : {2, 4, 8, 16, 32}) {
-            const double t = time_it([&] {
-                launch_spmv_f64(p->st, L, p->NB, n, p->rowptr, p->colind, p->vals, (double*)p->V, p->y);
-            }, 10);
+        for (int L : {kSell, -256, 2, 4, 8, 16, 32}) {
+            const double t = time_it([&] { spmv_f64(p, L, p->NB, (double*)p->V, p->y); }, 10);
             if (t < best) { best = t; bestL = L; }
         }
         p->L = bestL;
@@ -1024,20 +1202,24 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
         double bestt = 1e30;
         int bestNB = p->NB;
         const int nv = std::max(1, p->o.m / 2);
-        for (int nb : {256, 512, 1024, 2048}) {
+        for (int nb : {256, 512, 768, 1024, 1536, 2048}) {
             if (nb > nb_cap) continue;
             const int saved = p->NB;
             p->NB = nb;
-            EngineArgs a = make_args(p, 0, kPrecF64);
+            const int tprec = p->o.precision == GMRES_MIXED_F16 ? kPrecF16
+                              : (p->o.precision == GMRES_MIXED_F32 ? kPrecF32 : kPrecF64);
+            EngineArgs a = make_args(p, 0, tprec);
             const double t = time_it([&] {
-                launch_spmv_f64(p->st, p->L, nb, n, p->rowptr, p->colind, p->vals, (double*)p->V, p->y);
+                spmv_f64(p, p->L, nb, (double*)p->V, p->y);
                 launch_pass_probe(a, 2, nv);
             }, 10);
             p->NB = saved;
             if (t < bestt) { bestt = t; bestNB = nb; }
         }
         p->NB = bestNB;
-        launch_fill(p->st, (double*)p->V, (int64_t)(p->o.m + 1) * p->ldv, 0.0);
+        CHECK(clear_typed(p));
+        p->last_prec = kPrecF64;
+        CHECK(ensure_slots(p));
         drop_graphs(p);
     } else {
         // Batched: workgroup size and SpMV lanes, timed on one restart cycle.

@@ -247,21 +247,17 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 }
                 const double hn = sqrt(bsum<WGS>(accn, sred));
                 if (threadIdx.x == 0) {
-                    double col[MB + 1];
-                    for (int k = 0; k < nv; ++k) col[k] = h1[k] + h2[k];
-                    col[nv] = hn;
                     const int bd = !(hn > 2.220446049250313e-16 * sqrt(wpre2));
+                    double a0 = h1[0] + h2[0];
                     for (int i = 0; i < j; ++i) {
-                        const double p = col[i], q = col[i + 1];
-                        col[i] = cs[i] * p + sn[i] * q;
-                        col[i + 1] = -sn[i] * p + cs[i] * q;
+                        const double c = cs[i], sv = sn[i], bb = h1[i + 1] + h2[i + 1];
+                        Hs[i * MB + j] = c * a0 + sv * bb;
+                        a0 = -sv * a0 + c * bb;
                     }
-                    const double p = col[j], q = col[j + 1];
-                    double rho = hypot(p, q);
-                    if (q == 0.0) { cs[j] = 1.0; sn[j] = 0.0; rho = p; }
-                    else { cs[j] = p / rho; sn[j] = q / rho; }
-                    col[j] = rho;
-                    for (int k = 0; k <= j; ++k) Hs[k * MB + j] = col[k];
+                    double rho = hypot(a0, hn);
+                    if (hn == 0.0) { cs[j] = 1.0; sn[j] = 0.0; rho = a0; }
+                    else { cs[j] = a0 / rho; sn[j] = hn / rho; }
+                    Hs[j * MB + j] = rho;
                     g[j + 1] = -sn[j] * g[j];
                     g[j] = cs[j] * g[j];
                     vscale[nv] = bd ? 0.0 : 1.0 / hn;
@@ -272,17 +268,15 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 kk = nv;
                 if (s_flag) break;
             }
-            // y_k = R^{-1} g, x += V_k y_k
-            if (threadIdx.x == 0) {
-                double yv[MB];
-                for (int i = kk - 1; i >= 0; --i) {
-                    double s = g[i];
-                    for (int q = i + 1; q < kk; ++q) s -= Hs[i * MB + q] * yv[q];
-                    yv[i] = s / Hs[i * MB + i];
-                }
-                for (int i = 0; i < kk; ++i) coef[i] = yv[i] * vscale[i];
-            }
+            // y_k = R^{-1} g (column-oriented, all threads), x += V_k y_k
+            for (int i = threadIdx.x; i < kk; i += WGS) h2[i] = g[i];
             __syncthreads();
+            for (int i = kk - 1; i >= 0; --i) {
+                const double yi = h2[i] / Hs[i * MB + i];
+                for (int l = threadIdx.x; l < i; l += WGS) h2[l] -= Hs[l * MB + i] * yi;
+                if (threadIdx.x == 0) coef[i] = yi * vscale[i];
+                __syncthreads();
+            }
             for (int i = threadIdx.x; i < n; i += WGS) {
                 double acc = 0;
                 for (int t = 0; t < kk; ++t) acc += V[(int64_t)t * ldv + i] * coef[t];

@@ -14,6 +14,7 @@ constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kMaxM = 96;           // largest supported restart length m
 constexpr int kMaxR = 256;          // largest deflation count per system (coarse solve in one WG)
 constexpr int kAzRowMax = 64;       // largest row length of the compact A*Z operator
+constexpr int kBlockColsMax = 64;   // deflation columns per SpMV row block (fused Z^T y)
 
 // Device-resident control block of one solve.  Every kernel of a restart
 // cycle reads it, so the host launches whole cycles without synchronising.
@@ -31,7 +32,9 @@ struct Ctrl {
     double beta;          // ||P r|| at the last restart
     double wpre2;         // ||P A v_j||^2 before orthogonalisation (breakdown test)
     double inner_scale;   // mixed precision: ||r|| of the current refinement
-    int64_t pad[4];
+    int32_t est_conv;     // some cycle's estimate |gamma_{k+1}| met the target
+    int32_t pad32;
+    int64_t pad[3];
 };
 
 // ---------------------------------------------------------------- reductions
@@ -55,6 +58,20 @@ __device__ __forceinline__ T block_sum(T v, T* lds) {
     T s = lds[0];
 #pragma unroll
     for (int i = 1; i < kWG / kWave; ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+// Sum over a workgroup of NT threads (fixed order), valid in every thread.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum_n(T v, T* lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+    __syncthreads();
+    T s = lds[0];
+#pragma unroll
+    for (int i = 1; i < NT / kWave; ++i) s += lds[i];
     __syncthreads();
     return s;
 }

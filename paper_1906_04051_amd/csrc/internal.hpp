@@ -9,6 +9,9 @@
 
 namespace gm {
 
+// SpMV variant code for the sliced-ELL kernel.
+constexpr int kSell = -64;
+
 // Status values (mirror gmres_status in include/gmres.h).
 constexpr int kStatusOk = 0;
 constexpr int kStatusMaxIter = 1;
@@ -58,6 +61,19 @@ struct EngineArgs {
     double* tpart;          // R * MC partial sums of Z^T y
     const double* Einv;     // explicit E^{-1}, column-major R x R
     int trans;              // apply E^{-T} (adjoint operator)
+    // Fused Z^T y in the stream SpMV (valid when fuse_rb == RB of the SpMV).
+    int fuse_rb;            // 0: separate Z^T pass
+    const int *zrp, *zci;   // Z (CSR, n rows)
+    const double* zv;
+    const int *bb_ptr, *bb_col, *ab_ptr, *slot_pos;   // slot_pos: slot -> column-contiguous position
+    const int* zc1;         // Z single-entry rows (ELL-1)
+    const double* zv1;
+    const int* azc1;        // A Z single-entry rows (ELL-1) of the operator
+    const void* azv1;       // AT
+    // Sliced ELL copy of the operator (used when L == kSell).
+    const int *sell_off, *sell_col;
+    const void* sell_val;   // AT
+    int sell_wmax;          // widest slice (entries per row)
     double *s_step, *s_res; // coarse solutions (per step / per restart)
     double* part;           // (m + 2) * NB partial sums
     double *h1, *h2, *coef1, *coef2;
@@ -70,6 +86,10 @@ struct EngineArgs {
     int* cyc_k;             // optional: basis size k of every cycle
     int cyc_cap;
     KTimer* timer;          // optional
+    int trust_est;          // inner solves of the refinement: end on the estimate
+    int lagged;             // two-pass CGS2 with lagged normalisation
+    double* cc;             // lagged: coefficients (Hbar h2) of the next step, m + 1
+    double* lag;            // lagged: h2_last, 1/hn, sigma
 };
 
 // krylov.hip
@@ -83,6 +103,11 @@ void launch_residual_f64(hipStream_t st, int L, int NB, int n, const int* rp, co
 void launch_sum_slot(hipStream_t st, const double* part, int NB, int slot, double* out);
 void launch_spmv_f64(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
                      const double* v, const double* x, double* y);
+void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
+                          const double* val, const double* x, double* y);
+void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
+                              const double* val, const double* x, const double* b, double* r,
+                              double* part, int slot);
 void launch_spmv_f32(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
                      const float* v, const float* x, float* y);
 void launch_scale_to_f32(hipStream_t st, int NB, int n, const double* r, const double* nrm2,
@@ -122,6 +147,20 @@ void to_f32(hipStream_t st, int64_t n, const double* src, float* dst);
 void grad_vals(hipStream_t st, int64_t n, const int* rowptr, const int* colind, const double* lam,
                const double* x, double* g);
 int zt_max_row(hipStream_t st, int R, const int* ztrp, int* d_tmp);
+// Sliced ELL (64-row slices) of a CSR matrix; buffers hipMalloc'ed here.
+int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
+               int** scol, int** src, int64_t* total);
+void sell_values(hipStream_t st, int64_t total, const int* src, const double* vals, double* v64,
+                 float* v32);
+// Single-entry row copies of a CSR (see setup.hip); c1 may be NULL (values only).
+void ell1_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const double* v, int* c1,
+                double* v1, float* v1f);
+void invperm(hipStream_t st, int64_t m, const int* perm, int* pos);
+// Per-block deflation slots for the fused Z^T y (see setup.hip).  Buffers are
+// hipMalloc'ed here; the caller owns them.
+int build_block_slots(hipStream_t st, int64_t n, int RB, int R, const int* zrp, const int* zci,
+                      int** bb_ptr, int** bb_col, int** ab_ptr, int** ab_slot, int64_t* nslots,
+                      int* d_flags);
 
 // batched.hip
 struct BatchArgs {

@@ -26,6 +26,10 @@ __device__ __forceinline__ bool gated(const Ctrl* c, int gate) {
     return c->done != 0 || (gate == 2 && c->stop != 0);
 }
 
+constexpr int kCT = 1024;   // threads of the coarse-solve kernels
+__device__ void coarse_matvec(int R, const double* __restrict__ Einv, int trans, const double* t,
+                              double* __restrict__ s, double* red);
+
 // ------------------------------------------------------------------- SpMV
 // y = scale * A x, L lanes per row (row-per-group; L = 64 is row-per-wavefront).
 template <int L, typename AT, typename XT, typename YT, typename ACC>
@@ -47,6 +51,238 @@ __global__ __launch_bounds__(kWG) void k_spmv(int n, const int* __restrict__ row
         for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
         if (lane == 0) y[row] = (YT)(s * scale);
     }
+}
+
+// LDS-staged CSR stream (one row per thread, RB rows per block): the block's
+// contiguous range of values and column indices is first copied to LDS with
+// coalesced loads, then each thread forms its row's dot product from LDS and
+// gathers x.  MODE 0: y = scale * A x.  MODE 1: y = b - A x and per-block
+// partial sums of ||y||^2 into part[slot*NB + block].  Blocks whose entries do
+// not fit the staging buffer read their rows directly.
+// ZT: also the deflation partials of Z^T y -- one block sum per deflation
+// column the row block reaches (bb_col), written to tpart[slot] (fixed order).
+template <int RB, int MODE, bool ZT, typename AT, typename XT, typename BT, typename YT, typename ACC>
+__global__ __launch_bounds__(RB) void k_spmv_stream(int n, const int* __restrict__ rowptr,
+                                                    const int* __restrict__ colind,
+                                                    const AT* __restrict__ vals,
+                                                    const XT* __restrict__ x,
+                                                    const double* __restrict__ scale_ptr,
+                                                    const BT* __restrict__ b, YT* __restrict__ y,
+                                                    double* __restrict__ part, int slot, int NB,
+                                                    const int* __restrict__ zrp,
+                                                    const int* __restrict__ zci,
+                                                    const double* __restrict__ zv,
+                                                    const int* __restrict__ bb_ptr,
+                                                    const int* __restrict__ bb_col,
+                                                    const int* __restrict__ slot_pos,
+                                                    const int* __restrict__ zc1,
+                                                    const double* __restrict__ zv1,
+                                                    double* __restrict__ tpart,
+                                                    const Ctrl* ctrl, int gate) {
+    if (gated(ctrl, gate)) return;
+    constexpr int CAP = 4096;
+    __shared__ AT sv[CAP];
+    __shared__ int sc[CAP];
+    __shared__ ACC red[RB / kWave];
+    const ACC scale = (MODE == 0 && scale_ptr) ? (ACC)(*scale_ptr) : (ACC)1;
+    ACC nrm = 0;
+    for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
+        const int64_t rend = min((int64_t)n, r0 + RB);
+        const int k0 = rowptr[r0];
+        const int cnt = rowptr[rend] - k0;
+        const int64_t row = r0 + threadIdx.x;
+        int zc = -1;
+        ACC zvv = 0;
+        if (ZT && row < rend) {
+            zc = zc1[row];
+            zvv = (ACC)zv1[row];
+        }
+        ACC acc = 0;
+        if (cnt <= CAP) {
+            for (int q = threadIdx.x; q < cnt; q += RB) {
+                sv[q] = vals[k0 + q];
+                sc[q] = colind[k0 + q];
+            }
+            __syncthreads();
+            if (row < rend) {
+                const int a = rowptr[row] - k0, e = rowptr[row + 1] - k0;
+                for (int q = a; q < e; ++q) acc += (ACC)sv[q] * (ACC)ld_f(x + sc[q]);
+            }
+            __syncthreads();
+        } else if (row < rend) {
+            for (int k = rowptr[row]; k < rowptr[row + 1]; ++k) acc += (ACC)vals[k] * (ACC)ld_f(x + colind[k]);
+        }
+        ACC yi = 0;
+        if (row < rend) {
+            if (MODE == 0) {
+                const YT v = (YT)(acc * scale);
+                y[row] = v;
+                yi = (ACC)v;
+            } else {
+                const YT v = (YT)((ACC)b[row] - acc);
+                y[row] = v;
+                yi = (ACC)v;
+                nrm += yi * yi;
+            }
+        }
+        if (ZT) {
+            const int64_t blk = r0 / RB;
+            const int l1 = bb_ptr[blk + 1];
+            for (int l = bb_ptr[blk]; l < l1; ++l) {
+                const int col = bb_col[l];
+                ACC c = 0;
+                if (row < rend) {
+                    if (zc >= 0) {
+                        if (zc == col) c = zvv * yi;
+                    } else if (zc == -2) {
+                        for (int q = zrp[row]; q < zrp[row + 1]; ++q)
+                            if (zci[q] == col) c += (ACC)zv[q] * yi;
+                    }
+                }
+                c = block_sum_n<RB>(c, red);
+                if (threadIdx.x == 0) tpart[slot_pos[l]] = (double)c;
+            }
+        }
+    }
+    if (MODE == 1) {
+        const ACC t = block_sum_n<RB>(nrm, red);
+        if (threadIdx.x == 0) part[(int64_t)slot * NB + blockIdx.x] = (double)t;
+    }
+}
+
+// Sliced-ELL SpMV: one wavefront per 64-row slice, 256 rows per block, so
+// every load instruction reads 64 consecutive entries of one slice column.
+// MODE / ZT as for the stream kernel (RB = 256 row blocks for the slots).
+template <int MODE, bool ZT, int WMAX, typename AT, typename XT, typename BT, typename YT, typename ACC>
+__global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict__ off,
+                                                   const int* __restrict__ scol,
+                                                   const AT* __restrict__ sval,
+                                                   const XT* __restrict__ x,
+                                                   const double* __restrict__ scale_ptr,
+                                                   const BT* __restrict__ b, YT* __restrict__ y,
+                                                   double* __restrict__ part, int slot, int NB,
+                                                   const int* __restrict__ zrp,
+                                                   const int* __restrict__ zci,
+                                                   const double* __restrict__ zv,
+                                                   const int* __restrict__ bb_ptr,
+                                                   const int* __restrict__ bb_col,
+                                                   const int* __restrict__ slot_pos,
+                                                   const int* __restrict__ zc1,
+                                                   const double* __restrict__ zv1,
+                                                   double* __restrict__ tpart, const Ctrl* ctrl,
+                                                   int gate) {
+    if (gated(ctrl, gate)) return;
+    __shared__ ACC red[kWG / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const ACC scale = (MODE == 0 && scale_ptr) ? (ACC)(*scale_ptr) : (ACC)1;
+    ACC nrm = 0;
+    for (int64_t r0 = (int64_t)blockIdx.x * kWG; r0 < n; r0 += (int64_t)gridDim.x * kWG) {
+        const int64_t row = r0 + threadIdx.x;
+        int zc = -1;
+        ACC zvv = 0;
+        if (ZT && row < n) {
+            zc = zc1[row];
+            zvv = (ACC)zv1[row];
+        }
+        ACC acc = 0;
+        if (row < n) {
+            const int64_t sl = r0 / kWave + wv;
+            const int q0 = off[sl];
+            const int w = (off[sl + 1] - q0) / kWave;
+            const int q = q0 + lane;
+            if (w <= WMAX) {
+                // Column indices and values of the whole row first, then the gathers.
+                int cc[WMAX];
+                AT vv[WMAX];
+#pragma unroll
+                for (int k = 0; k < WMAX; ++k)
+                    if (k < w) {
+                        cc[k] = scol[q + k * kWave];
+                        vv[k] = sval[q + k * kWave];
+                    }
+                ACC xv[WMAX];
+#pragma unroll
+                for (int k = 0; k < WMAX; ++k)
+                    if (k < w) xv[k] = (ACC)ld_f(x + cc[k]);
+#pragma unroll
+                for (int k = 0; k < WMAX; ++k)
+                    if (k < w) acc += (ACC)vv[k] * xv[k];
+            } else {
+#pragma unroll 4
+                for (int k = 0; k < w; ++k)
+                    acc += (ACC)sval[q + k * kWave] * (ACC)ld_f(x + scol[q + k * kWave]);
+            }
+        }
+        ACC yi = 0;
+        if (row < n) {
+            if (MODE == 0) {
+                const YT v = (YT)(acc * scale);
+                y[row] = v;
+                yi = (ACC)v;
+            } else {
+                const YT v = (YT)((ACC)b[row] - acc);
+                y[row] = v;
+                yi = (ACC)v;
+                nrm += yi * yi;
+            }
+        }
+        if (ZT) {
+            const int64_t blk = r0 / kWG;
+            const int l1 = bb_ptr[blk + 1];
+            for (int l = bb_ptr[blk]; l < l1; ++l) {
+                const int col = bb_col[l];
+                ACC c = 0;
+                if (row < n) {
+                    if (zc >= 0) {
+                        if (zc == col) c = zvv * yi;
+                    } else if (zc == -2) {
+                        for (int q = zrp[row]; q < zrp[row + 1]; ++q)
+                            if (zci[q] == col) c += (ACC)zv[q] * yi;
+                    }
+                }
+                c = block_sum_n<kWG>(c, red);
+                if (threadIdx.x == 0) tpart[slot_pos[l]] = (double)c;
+            }
+        }
+    }
+    if (MODE == 1) {
+        const ACC t = block_sum_n<kWG>(nrm, red);
+        if (threadIdx.x == 0) part[(int64_t)slot * NB + blockIdx.x] = (double)t;
+    }
+}
+
+// s = E^{-1} t with t_a = sum of the slots of deflation column a, which are
+// stored contiguously (tpart[ab_ptr[a] .. ab_ptr[a+1]), increasing row blocks);
+// each column's range is split over G = kCT / R threads whose partial sums
+// are added in order.
+__global__ __launch_bounds__(kCT) void k_coarse_slots(int R, const int* __restrict__ ab_ptr,
+                                                      const double* __restrict__ tpart,
+                                                      const double* __restrict__ Einv, int trans,
+                                                      double* __restrict__ s, const Ctrl* ctrl,
+                                                      int gate) {
+    if (gated(ctrl, gate)) return;
+    __shared__ double t[kMaxR];
+    __shared__ double red[kCT];
+    const int G = max(1, kCT / R);
+    const int grp = threadIdx.x / R, a = threadIdx.x % R;
+    double acc = 0;
+    if (grp < G) {
+        const int q0 = ab_ptr[a], q1 = ab_ptr[a + 1];
+        const int span = (q1 - q0 + G - 1) / G;
+        const int b0 = q0 + grp * span, b1 = min(q1, b0 + span);
+#pragma unroll 8
+        for (int q = b0; q < b1; ++q) acc += tpart[q];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double v = red[threadIdx.x];
+        for (int q = 1; q < G; ++q) v += red[q * R + threadIdx.x];
+        t[threadIdx.x] = v;
+    }
+    __syncthreads();
+    coarse_matvec(R, Einv, trans, t, s, red);
 }
 
 // r = b - A x (x in FP64), plus per-workgroup partial sums of ||r||^2 into
@@ -100,37 +336,114 @@ __global__ __launch_bounds__(kWG) void k_zt(int R, int MC, int CH, const int* __
     if (threadIdx.x == 0) tpart[(int64_t)a * MC + c] = s;
 }
 
-// s = E^{-1} t with t = sum over chunks of tpart (fixed order).  Einv is the
-// explicit inverse of E built from its LU factors at setup, column-major
-// (Einv[i][a] at Einv[a*R + i]); `trans` applies E^{-T} instead (adjoint).
-__global__ __launch_bounds__(kWG) void k_coarse(int R, int MC, const double* __restrict__ tpart,
+// s = E^{-1} t (or E^{-T} t for the adjoint, `trans`), with the explicit
+// inverse from setup stored column-major (Einv[i][a] at Einv[a*R + i]).  All
+// kCT threads take part: output i is split over G = kCT / R thread groups, each
+// summing a contiguous range of a, then the G partial sums are added in order.
+__device__ void coarse_matvec(int R, const double* __restrict__ Einv, int trans, const double* t,
+                              double* __restrict__ s, double* red /* kCT */) {
+    const int G = max(1, kCT / R);
+    const int grp = threadIdx.x / R, i = threadIdx.x % R;
+    double acc = 0;
+    if (grp < G) {
+        const int span = (R + G - 1) / G;
+        const int a0 = grp * span, a1 = min(R, a0 + span);
+        if (!trans) {
+#pragma unroll 8
+            for (int a = a0; a < a1; ++a) acc += Einv[(int64_t)a * R + i] * t[a];
+        } else {
+#pragma unroll 8
+            for (int a = a0; a < a1; ++a) acc += Einv[(int64_t)i * R + a] * t[a];
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double v = red[threadIdx.x];
+        for (int q = 1; q < G; ++q) v += red[q * R + threadIdx.x];
+        s[threadIdx.x] = v;
+    }
+}
+
+// s = E^{-1} t with t = sum over chunks of tpart (fixed order).
+__global__ __launch_bounds__(kCT) void k_coarse(int R, int MC, const double* __restrict__ tpart,
                                                 const double* __restrict__ Einv, int trans,
                                                 double* __restrict__ s, const Ctrl* ctrl,
                                                 int gate) {
     if (gated(ctrl, gate)) return;
     __shared__ double t[kMaxR];
-    for (int a = threadIdx.x; a < R; a += kWG) {
+    __shared__ double red[kCT];
+    for (int a = threadIdx.x; a < R; a += kCT) {
         double acc = 0;
         for (int c = 0; c < MC; ++c) acc += tpart[(int64_t)a * MC + c];
         t[a] = acc;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < R; i += kWG) {
-        double acc = 0;
-        if (!trans)
-            for (int a = 0; a < R; ++a) acc += Einv[(int64_t)a * R + i] * t[a];
-        else
-            for (int a = 0; a < R; ++a) acc += Einv[(int64_t)i * R + a] * t[a];
-        s[i] = acc;
-    }
+    coarse_matvec(R, Einv, trans, t, s, red);
 }
 
 // ------------------------------------------------------------- CGS2 passes
-// Lane layout: T consecutive lanes share one row; lane `sub` of the group owns
-// basis columns k = sub, sub + T, sub + 2T, ... so each lane keeps JMAX / T
-// basis entries and dot accumulators in registers.
+// Lane layout: each lane moves 16 bytes of a basis column per load, i.e. a
+// tile of R = 16 / sizeof(VT) consecutive rows (2 FP64, 4 FP32, 8 FP16).  T
+// consecutive lanes share one tile; lane `sub` owns basis columns
+// k = sub, sub + T, ... so it keeps JMAX / T raw 16-byte tiles and as many dot
+// accumulators in registers.  Vectors are padded with zeros to a multiple of
+// 64 entries, so whole tiles are read and written; only the deflation rows
+// are bounded by n.
 
-// Sum over the T lanes of a row group (butterfly; same value in all of them).
+template <typename T, int R, typename ACC>
+__device__ __forceinline__ void load_tile(const T* __restrict__ p, ACC (&out)[R]) {
+    constexpr int NC = (R * (int)sizeof(T) + 15) / 16;
+    T tmp[NC * 16 / sizeof(T)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint4 u = reinterpret_cast<const uint4*>(p)[c];
+        __builtin_memcpy(reinterpret_cast<char*>(tmp) + 16 * c, &u, 16);
+    }
+#pragma unroll
+    for (int e = 0; e < R; ++e) out[e] = (ACC)ld_f(tmp + e);
+}
+
+template <typename T, int R, typename ACC>
+__device__ __forceinline__ void store_tile(T* __restrict__ p, const ACC (&in)[R]) {
+    constexpr int NC = (R * (int)sizeof(T) + 15) / 16;
+    T tmp[NC * 16 / sizeof(T)];
+#pragma unroll
+    for (int e = 0; e < R; ++e) st_v(tmp + e, in[e]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        uint4 u;
+        __builtin_memcpy(&u, reinterpret_cast<const char*>(tmp) + 16 * c, 16);
+        reinterpret_cast<uint4*>(p)[c] = u;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void load_ints(const int* __restrict__ p, int (&out)[R]) {
+    if constexpr (R == 2) {
+        const uint2 u = *reinterpret_cast<const uint2*>(p);
+        out[0] = (int)u.x;
+        out[1] = (int)u.y;
+    } else {
+#pragma unroll
+        for (int c = 0; c < R / 4; ++c) {
+            const uint4 u = reinterpret_cast<const uint4*>(p)[c];
+            out[4 * c] = (int)u.x;
+            out[4 * c + 1] = (int)u.y;
+            out[4 * c + 2] = (int)u.z;
+            out[4 * c + 3] = (int)u.w;
+        }
+    }
+}
+
+template <typename VT, typename ACC>
+__device__ __forceinline__ ACC raw_at(const uint4& u, int e) {
+    VT tmp[16 / sizeof(VT)];
+    __builtin_memcpy(tmp, &u, 16);
+    return (ACC)ld_f(tmp + e);
+}
+
+// Sum over the T lanes of a tile group (butterfly; same value in all of them).
 template <int T, typename ACC>
 __device__ __forceinline__ ACC group_sum(ACC v) {
 #pragma unroll
@@ -182,11 +495,14 @@ __global__ __launch_bounds__(kWG) void k_pass1(int n, int64_t ldv, const VT* __r
                                                const int* __restrict__ azrp,
                                                const int* __restrict__ azci,
                                                const AZT* __restrict__ azv,
+                                               const int* __restrict__ azc1,
+                                               const AZT* __restrict__ azv1,
                                                const double* __restrict__ s, int R,
                                                WT* __restrict__ w, double* __restrict__ part,
                                                int nslot, int NB, const Ctrl* ctrl, int gate) {
     if (gated(ctrl, gate)) return;
     constexpr int JT = JMAX / T;
+    constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC s_l[kMaxR];
     __shared__ ACC red[kWG / kWave][JMAX + 1];
     for (int a = threadIdx.x; a < R; a += kWG) s_l[a] = (ACC)s[a];
@@ -196,22 +512,47 @@ __global__ __launch_bounds__(kWG) void k_pass1(int n, int64_t ldv, const VT* __r
 #pragma unroll
     for (int q = 0; q < JT; ++q) acc[q] = 0;
     ACC accn = 0;
-    const int64_t stride = (int64_t)gridDim.x * (kWG / T);
-    for (int64_t i = ((int64_t)blockIdx.x * kWG + threadIdx.x) / T; i < n; i += stride) {
-        ACC wi = (ACC)y[i];
-        if (R > 0)
-            for (int q = azrp[i]; q < azrp[i + 1]; ++q) wi -= (ACC)azv[q] * s_l[azci[q]];
-        if (sub == 0) {
-            w[i] = (WT)wi;
-            accn += wi * wi;
+    const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
+    for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
+        // All basis tiles of this lane are requested before any arithmetic.
+        uint4 raw[JT];
+#pragma unroll
+        for (int q = 0; q < JT; ++q) {
+            const int k = sub + q * T;
+            if (k < nv) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
         }
-        ACC vv[JT];
+        ACC wv[RT];
+        load_tile<WT, RT, ACC>(y + i0, wv);
+        if (R > 0) {
+            int ac[RT];
+            ACC av[RT];
+            load_ints<RT>(azc1 + i0, ac);
+            load_tile<AZT, RT, ACC>(azv1 + i0, av);
 #pragma unroll
-        for (int q = 0; q < JT; ++q)
-            if (sub + q * T < nv) vv[q] = (ACC)ld_f(V + (sub + q * T) * ldv + i);
+            for (int e = 0; e < RT; ++e) {
+                if (ac[e] >= 0) {
+                    wv[e] -= av[e] * s_l[ac[e]];
+                } else if (ac[e] == -2) {
+                    const int64_t i = i0 + e;
+                    for (int q = azrp[i]; q < azrp[i + 1]; ++q) wv[e] -= (ACC)azv[q] * s_l[azci[q]];
+                }
+            }
+        }
+        if (sub == 0) {
+            store_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
-        for (int q = 0; q < JT; ++q)
-            if (sub + q * T < nv) acc[q] += vv[q] * wi;
+            for (int e = 0; e < RT; ++e) accn += wv[e] * wv[e];
+        }
+#pragma unroll
+        for (int q = 0; q < JT; ++q) {
+            const int k = sub + q * T;
+            if (k < nv) {
+                ACC t = 0;
+#pragma unroll
+                for (int e = 0; e < RT; ++e) t += raw_at<VT, ACC>(raw[q], e) * wv[e];
+                acc[q] += t;
+            }
+        }
     }
     store_partials<JMAX, T, ACC>(acc, accn, nv, red, part, nslot, NB);
 }
@@ -225,6 +566,7 @@ __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __r
                                                const Ctrl* ctrl, int gate) {
     if (gated(ctrl, gate)) return;
     constexpr int JT = JMAX / T;
+    constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
     __shared__ ACC red[kWG / kWave][JMAX + 1];
     for (int k = threadIdx.x; k < nv; k += kWG) c_l[k] = (ACC)coef[k];
@@ -234,24 +576,41 @@ __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __r
 #pragma unroll
     for (int q = 0; q < JT; ++q) acc[q] = 0;
     ACC accn = 0;
-    const int64_t stride = (int64_t)gridDim.x * (kWG / T);
-    for (int64_t i = ((int64_t)blockIdx.x * kWG + threadIdx.x) / T; i < n; i += stride) {
-        ACC vv[JT];
+    const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
+    for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
+        uint4 raw[JT];
 #pragma unroll
-        for (int q = 0; q < JT; ++q)
-            if (sub + q * T < nv) vv[q] = (ACC)ld_f(V + (sub + q * T) * ldv + i);
-        ACC u = 0;
+        for (int q = 0; q < JT; ++q) {
+            const int k = sub + q * T;
+            if (k < nv) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
+        }
+        ACC wv[RT];
+        load_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
-        for (int q = 0; q < JT; ++q)
-            if (sub + q * T < nv) u += vv[q] * c_l[sub + q * T];
-        const ACC wi = (ACC)w[i] - group_sum<T>(u);
+        for (int e = 0; e < RT; ++e) {
+            ACC u = 0;
+#pragma unroll
+            for (int q = 0; q < JT; ++q) {
+                const int k = sub + q * T;
+                if (k < nv) u += raw_at<VT, ACC>(raw[q], e) * c_l[k];
+            }
+            wv[e] -= group_sum<T>(u);
+        }
         if (sub == 0) {
-            w[i] = (WT)wi;
-            accn += wi * wi;
+            store_tile<WT, RT, ACC>(w + i0, wv);
+#pragma unroll
+            for (int e = 0; e < RT; ++e) accn += wv[e] * wv[e];
         }
 #pragma unroll
-        for (int q = 0; q < JT; ++q)
-            if (sub + q * T < nv) acc[q] += vv[q] * wi;
+        for (int q = 0; q < JT; ++q) {
+            const int k = sub + q * T;
+            if (k < nv) {
+                ACC t = 0;
+#pragma unroll
+                for (int e = 0; e < RT; ++e) t += raw_at<VT, ACC>(raw[q], e) * wv[e];
+                acc[q] += t;
+            }
+        }
     }
     store_partials<JMAX, T, ACC>(acc, accn, nv, red, part, nslot, NB);
 }
@@ -267,6 +626,7 @@ __global__ __launch_bounds__(kWG) void k_pass3(int n, int64_t ldv, VT* __restric
                                                const Ctrl* ctrl, int gate) {
     if (gated(ctrl, gate)) return;
     constexpr int JT = JMAX / T;
+    constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
     __shared__ ACC red[kWG / kWave];
     for (int k = threadIdx.x; k < nv; k += kWG) c_l[k] = (ACC)coef[k];
@@ -275,24 +635,181 @@ __global__ __launch_bounds__(kWG) void k_pass3(int n, int64_t ldv, VT* __restric
     VT* __restrict__ vout = V + nv * ldv;
     const int sub = threadIdx.x & (T - 1);
     ACC accn = 0;
-    const int64_t stride = (int64_t)gridDim.x * (kWG / T);
-    for (int64_t i = ((int64_t)blockIdx.x * kWG + threadIdx.x) / T; i < n; i += stride) {
-        ACC vv[JT];
+    const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
+    for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
+        uint4 raw[JT];
 #pragma unroll
-        for (int q = 0; q < JT; ++q)
-            if (sub + q * T < nv) vv[q] = (ACC)ld_f(V + (sub + q * T) * ldv + i);
-        ACC u = 0;
+        for (int q = 0; q < JT; ++q) {
+            const int k = sub + q * T;
+            if (k < nv) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
+        }
+        ACC wv[RT];
+        load_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
-        for (int q = 0; q < JT; ++q)
-            if (sub + q * T < nv) u += vv[q] * c_l[sub + q * T];
-        const ACC wi = (ACC)w[i] - group_sum<T>(u);
+        for (int e = 0; e < RT; ++e) {
+            ACC u = 0;
+#pragma unroll
+            for (int q = 0; q < JT; ++q) {
+                const int k = sub + q * T;
+                if (k < nv) u += raw_at<VT, ACC>(raw[q], e) * c_l[k];
+            }
+            wv[e] -= group_sum<T>(u);
+        }
         if (sub == 0) {
-            st_v(vout + i, wi * sg);
-            accn += wi * wi;
+            ACC ov[RT];
+#pragma unroll
+            for (int e = 0; e < RT; ++e) {
+                ov[e] = wv[e] * sg;
+                accn += wv[e] * wv[e];
+            }
+            store_tile<VT, RT, ACC>(vout + i0, ov);
         }
     }
     const ACC t = block_sum(accn, red);
     if (threadIdx.x == 0) part[(int64_t)nslot * NB + blockIdx.x] = (double)t;
+}
+
+// ------------------------------------------- two-pass CGS2, lagged normalisation
+// Step j (>= 1) of the lagged variant starts from the previous step's
+// once-projected vector w1 = w_{j-1} - V h1 (not yet re-orthogonalised or
+// normalised), its second-projection coefficients h2 and the estimate
+// hn = ||w1 - V h2|| = sqrt(||w1||^2 - ||h2||^2).  The SpMV runs on w1:
+// u = A w1.  This pass then, in one sweep over V_{0..j-1}:
+//   w2 = w1 - V h2                       (second Gram-Schmidt update of w1),
+//   v_j = w2 / hn                        (stored as sigma * w2),
+//   w_j = P A v_j = (P u - sum_l v_l c_l - w2 h2_{j-1}) / hn,
+// where P A V = V Hbar (the Arnoldi relation) gives P A (V h2) = V (Hbar h2),
+// c = Hbar h2 restricted to rows l < j, and the last row's term is
+// hn h2_{j-1} v_j = w2 h2_{j-1}; then the partial dots of w_j with v_0..v_j
+// and ||w_j||^2.  So each step sweeps the basis twice instead of three times.
+// lag[0] = h2_{j-1}, lag[1] = 1/hn, lag[2] = sigma (storage scale of v_j).
+template <int JMAX, int T, typename VT, typename WT, typename AZT, typename ACC>
+__global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __restrict__ V, int nvr,
+                                                   WT* __restrict__ w, const WT* __restrict__ y,
+                                                   const int* __restrict__ azrp,
+                                                   const int* __restrict__ azci,
+                                                   const AZT* __restrict__ azv,
+                                                   const int* __restrict__ azc1,
+                                                   const AZT* __restrict__ azv1,
+                                                   const double* __restrict__ s, int R,
+                                                   const double* __restrict__ coef2,
+                                                   const double* __restrict__ cc,
+                                                   const double* __restrict__ lag,
+                                                   double* __restrict__ part, int nslot, int NB,
+                                                   const Ctrl* ctrl, int gate) {
+    if (gated(ctrl, gate)) return;
+    constexpr int JT = JMAX / T;
+    constexpr int RT = 16 / sizeof(VT);
+    __shared__ ACC s_l[kMaxR];
+    __shared__ ACC c2_l[JMAX], cc_l[JMAX];
+    __shared__ ACC red[kWG / kWave][JMAX + 2];
+    for (int a = threadIdx.x; a < R; a += kWG) s_l[a] = (ACC)s[a];
+    for (int k = threadIdx.x; k < nvr; k += kWG) {
+        c2_l[k] = (ACC)coef2[k];
+        cc_l[k] = (ACC)cc[k];
+    }
+    __syncthreads();
+    const ACC h2last = (ACC)lag[0], ihn = (ACC)lag[1], sg = (ACC)lag[2];
+    VT* __restrict__ vout = V + nvr * ldv;
+    const int sub = threadIdx.x & (T - 1);
+    ACC acc[JT];
+#pragma unroll
+    for (int q = 0; q < JT; ++q) acc[q] = 0;
+    ACC accn = 0, accd = 0;
+    const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
+    for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
+        uint4 raw[JT];
+#pragma unroll
+        for (int q = 0; q < JT; ++q) {
+            const int k = sub + q * T;
+            if (k < nvr) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
+        }
+        ACC w1[RT], u[RT];
+        load_tile<WT, RT, ACC>(w + i0, w1);
+        load_tile<WT, RT, ACC>(y + i0, u);
+        if (R > 0) {
+            int ac[RT];
+            ACC av[RT];
+            load_ints<RT>(azc1 + i0, ac);
+            load_tile<AZT, RT, ACC>(azv1 + i0, av);
+#pragma unroll
+            for (int e = 0; e < RT; ++e) {
+                if (ac[e] >= 0) {
+                    u[e] -= av[e] * s_l[ac[e]];
+                } else if (ac[e] == -2) {
+                    const int64_t i = i0 + e;
+                    for (int q = azrp[i]; q < azrp[i + 1]; ++q) u[e] -= (ACC)azv[q] * s_l[azci[q]];
+                }
+            }
+        }
+        ACC sv[RT], wn[RT];
+#pragma unroll
+        for (int e = 0; e < RT; ++e) {
+            ACC a2 = 0, a3 = 0;
+#pragma unroll
+            for (int q = 0; q < JT; ++q) {
+                const int k = sub + q * T;
+                if (k < nvr) {
+                    const ACC vk = raw_at<VT, ACC>(raw[q], e);
+                    a2 += vk * c2_l[k];
+                    a3 += vk * cc_l[k];
+                }
+            }
+            a2 = group_sum<T>(a2);
+            a3 = group_sum<T>(a3);
+            const ACC w2 = w1[e] - a2;
+            VT stv;
+            st_v(&stv, w2 * sg);
+            sv[e] = (ACC)ld_f(&stv);
+            wn[e] = (u[e] - a3 - w2 * h2last) * ihn;
+        }
+        if (sub == 0) {
+            store_tile<VT, RT, ACC>(vout + i0, sv);
+            store_tile<WT, RT, ACC>(w + i0, wn);
+#pragma unroll
+            for (int e = 0; e < RT; ++e) {
+                accn += wn[e] * wn[e];
+                accd += sv[e] * wn[e];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < JT; ++q) {
+            const int k = sub + q * T;
+            if (k < nvr) {
+                ACC t = 0;
+#pragma unroll
+                for (int e = 0; e < RT; ++e) t += raw_at<VT, ACC>(raw[q], e) * wn[e];
+                acc[q] += t;
+            }
+        }
+    }
+    // Partials: columns 0..nvr-1 from acc, column nvr from accd, norm slot.
+    const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+        if (q * T < nvr) {
+            ACC t = acc[q];
+#pragma unroll
+            for (int o = kWave / 2; o >= T; o >>= 1) t += __shfl_xor(t, o, kWave);
+            const int k = sub + q * T;
+            if (ln < T && k < nvr) red[wv][k] = t;
+        }
+    }
+    {
+        const ACC t = wave_sum(accd);
+        if (ln == 0) red[wv][nvr] = t;
+        const ACC t2 = wave_sum(accn);
+        if (ln == 0) red[wv][JMAX + 1] = t2;
+    }
+    __syncthreads();
+    const int tk = threadIdx.x;
+    if (tk <= nvr || tk == JMAX + 1) {
+        ACC t = red[0][tk];
+#pragma unroll
+        for (int q = 1; q < kWG / kWave; ++q) t += red[q][tk];
+        const int slot = (tk == JMAX + 1) ? nslot : tk;
+        part[(int64_t)slot * NB + blockIdx.x] = (double)t;
+    }
 }
 
 // Finish the partial sums of one pass (one workgroup per slot, fixed order).
@@ -328,7 +845,9 @@ __global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ part,
 // h_{j+1,j} = ||w||; apply the stored rotations, form the new one (rho =
 // hypot(a, b), c = a/rho, s = b/rho), update g, and decide whether the cycle
 // ends: |g_{j+1}| <= rtol*rho0 (eq. res), lucky breakdown
-// (h_{j+1,j} <= eps * ||P A v_j||) or the iteration cap.
+// (h_{j+1,j} <= eps * ||P A v_j||) or the iteration cap.  The column and the
+// rotations are staged in LDS; one lane runs the rotation chain.
+template <bool LAG>
 __global__ __launch_bounds__(kWave) void k_givens(int j, int m, const double* __restrict__ part,
                                                   int NB, int nslot, const double* __restrict__ h1,
                                                   const double* __restrict__ h2,
@@ -337,67 +856,119 @@ __global__ __launch_bounds__(kWave) void k_givens(int j, int m, const double* __
                                                   double* __restrict__ vscale,
                                                   const double* __restrict__ sigma,
                                                   double* __restrict__ hist, int64_t hist_cap,
-                                                  double* __restrict__ Hraw, Ctrl* ctrl, int gate) {
+                                                  double* __restrict__ Hraw, double* __restrict__ cc,
+                                                  double* __restrict__ lag, Ctrl* ctrl, int gate) {
     if (gated(ctrl, gate)) return;
+    __shared__ double col[kMaxM + 1], cl[kMaxM], sl[kMaxM], h2l[kMaxM + 1];
     double acc = 0;
     for (int q = threadIdx.x; q < NB; q += kWave) acc += part[(int64_t)nslot * NB + q];
     acc = wave_sum(acc);
-    if (threadIdx.x != 0) return;
-    const double hn = sqrt(acc);
-    double col[kMaxM + 1];
-    for (int k = 0; k <= j; ++k) col[k] = h1[k] + h2[k];
-    col[j + 1] = hn;
-    if (Hraw)
-        for (int k = 0; k <= j + 1; ++k) Hraw[(int64_t)k * m + j] = col[k];
-    const double wpre = sqrt(ctrl->wpre2);
-    const int bd = !(hn > 2.220446049250313e-16 * wpre);
-    for (int i = 0; i < j; ++i) {
-        const double a = col[i], c = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * c;
-        col[i + 1] = -sn[i] * a + cs[i] * c;
+    if (LAG) {
+        // acc = ||w1||^2; ||w2||^2 = ||w1||^2 - ||h2||^2 (h2 against orthonormal v's).
+        double q2 = 0;
+        for (int i = threadIdx.x; i <= j; i += kWave) {
+            const double v = h2[i];
+            h2l[i] = v;
+            q2 += v * v;
+        }
+        q2 = wave_sum(q2);
+        acc = fmax(acc - q2, 0.0);
     }
-    const double a = col[j], c = col[j + 1];
-    double rho = hypot(a, c);
-    if (c == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
+    for (int i = threadIdx.x; i <= j; i += kWave) col[i] = h1[i] + h2[i];
+    for (int i = threadIdx.x; i < j; i += kWave) {
+        cl[i] = cs[i];
+        sl[i] = sn[i];
+    }
+    __syncthreads();
+    const double hn = sqrt(acc);
+    if (Hraw) {
+        for (int i = threadIdx.x; i <= j; i += kWave) Hraw[(int64_t)i * m + j] = col[i];
+        if (threadIdx.x == 0) Hraw[(int64_t)(j + 1) * m + j] = hn;
+    }
+    if (LAG) {
+        // Coefficients of the next lagged step: c_l = sum_k Hbar[l][k] h2_k
+        // (rows l <= j, columns k = max(l-1, 0) .. j of the unrotated Hbar),
+        // times vscale[l]; column j of Hbar is col[] / hn (not yet in Hraw for
+        // every lane, so use the staged values).
+        __syncthreads();
+        for (int l = threadIdx.x; l <= j; l += kWave) {
+            double v = 0;
+            for (int k = (l > 0 ? l - 1 : 0); k < j; ++k) v += Hraw[(int64_t)l * m + k] * h2l[k];
+            v += col[l] * h2l[j];
+            cc[l] = v * vscale[l];
+        }
+    }
+    if (threadIdx.x != 0) return;
+    const double wpre = sqrt(ctrl->wpre2);
+    // The lagged norm comes from a difference of squares: its rounding error is
+    // about sqrt(eps) * ||w1||, so a breakdown is declared below that level.
+    const double bd_tol = LAG ? 1.4901161193847656e-08 : 2.220446049250313e-16;
+    const int bd = !(hn > bd_tol * wpre);
+    double a = col[0];
+#pragma unroll 8
+    for (int i = 0; i < j; ++i) {
+        const double c = cl[i], sv = sl[i], bb = col[i + 1];
+        H[(int64_t)i * m + j] = c * a + sv * bb;
+        a = -sv * a + c * bb;
+    }
+    double rho = hypot(a, hn);
+    double cj, sj;
+    if (hn == 0.0) {
+        cj = 1.0;
+        sj = 0.0;
         rho = a;
     } else {
-        cs[j] = a / rho;
-        sn[j] = c / rho;
+        cj = a / rho;
+        sj = hn / rho;
     }
-    col[j] = rho;
-    col[j + 1] = 0.0;
-    for (int k = 0; k <= j + 1; ++k) H[(int64_t)k * m + j] = col[k];
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
+    cs[j] = cj;
+    sn[j] = sj;
+    H[(int64_t)j * m + j] = rho;
+    H[(int64_t)(j + 1) * m + j] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = cj * gj;
     vscale[j + 1] = bd ? 0.0 : 1.0 / ((*sigma) * hn);
+    if (LAG) {
+        lag[0] = h2l[j];
+        lag[1] = bd ? 0.0 : 1.0 / hn;
+        lag[2] = *sigma;
+    }
     const int64_t its = ctrl->its + 1;
     ctrl->its = its;
-    if (hist && its - 1 < hist_cap) hist[its - 1] = fabs(g[j + 1]);
+    if (hist && its - 1 < hist_cap) hist[its - 1] = fabs(sj * gj);
     ctrl->k = j + 1;
     ctrl->breakdown = bd;
-    if (fabs(g[j + 1]) <= ctrl->target || bd || its >= ctrl->max_iters) ctrl->stop = 1;
+    const bool est = fabs(sj * gj) <= ctrl->target;
+    if (est) ctrl->est_conv = 1;
+    if (est || bd || its >= ctrl->max_iters) ctrl->stop = 1;
 }
 
-// Back substitution R_k y = g_{1:k}; coef[i] = y_i * vscale[i] (coefficient of
-// stored_i in x_hat += V_k y).
-__global__ __launch_bounds__(kWave) void k_backsolve(int m, const double* __restrict__ H,
-                                                     const double* __restrict__ g,
-                                                     const double* __restrict__ vscale,
-                                                     double* __restrict__ coef, int* cyc_k,
-                                                     int cyc_cap, Ctrl* ctrl, int gate) {
+// Back substitution R_k y = g_{1:k} (column-oriented, R staged in LDS);
+// coef[i] = y_i * vscale[i] (coefficient of stored_i in x_hat += V_k y).
+__global__ __launch_bounds__(kWG) void k_backsolve(int m, const double* __restrict__ H,
+                                                   const double* __restrict__ g,
+                                                   const double* __restrict__ vscale,
+                                                   double* __restrict__ coef, int* cyc_k,
+                                                   int cyc_cap, Ctrl* ctrl, int gate) {
     if (gated(ctrl, gate)) return;
-    if (threadIdx.x != 0) return;
+    __shared__ double Rl[kMaxM * kMaxM];
+    __shared__ double gl[kMaxM], yl[kMaxM];
     const int k = ctrl->k;
-    if (cyc_k && ctrl->cycles - 1 < cyc_cap) cyc_k[ctrl->cycles - 1] = k;
-    double y[kMaxM];
-    for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int q = i + 1; q < k; ++q) s -= H[(int64_t)i * m + q] * y[q];
-        y[i] = s / H[(int64_t)i * m + i];
+    if (threadIdx.x == 0 && cyc_k && ctrl->cycles - 1 < cyc_cap) cyc_k[ctrl->cycles - 1] = k;
+    for (int q = threadIdx.x; q < k * k; q += kWG) {
+        const int i = q / k, c = q % k;
+        Rl[q] = (c >= i) ? H[(int64_t)i * m + c] : 0.0;
     }
-    for (int i = 0; i < k; ++i) coef[i] = y[i] * vscale[i];
+    for (int i = threadIdx.x; i < k; i += kWG) gl[i] = g[i];
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+        const double yi = gl[i] / Rl[i * k + i];
+        for (int l = threadIdx.x; l < i; l += kWG) gl[l] -= Rl[l * k + i] * yi;
+        if (threadIdx.x == 0) yl[i] = yi;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < k; i += kWG) coef[i] = yl[i] * vscale[i];
 }
 
 // x_hat += sum_{t < k} stored_t * coef[t]  (eq. new_sol); k from the control block.
@@ -453,7 +1024,8 @@ __global__ void k_init(const double* __restrict__ part, int NB, int nslot, doubl
 // new cycle with g = beta e1 and v_1 = p / beta.
 __global__ void k_decide(const double* __restrict__ part, int NB, int nslot, int m,
                          int half_store, double nscale, double* __restrict__ g,
-                         double* __restrict__ vscale, double* __restrict__ sigma0, Ctrl* ctrl) {
+                         double* __restrict__ vscale, double* __restrict__ sigma0, int trust_est,
+                         Ctrl* ctrl) {
     __shared__ double red[kWG / kWave];
     if (ctrl->done) return;
     double acc = 0;
@@ -465,7 +1037,7 @@ __global__ void k_decide(const double* __restrict__ part, int NB, int nslot, int
     if (!isfinite(beta)) {
         ctrl->done = 1;
         ctrl->status = kStatusNonFinite;
-    } else if (beta <= ctrl->target) {
+    } else if (beta <= ctrl->target || (trust_est && ctrl->est_conv)) {
         ctrl->done = 1;
         ctrl->status = kStatusOk;
     } else if (ctrl->its >= ctrl->max_iters) {
@@ -569,6 +1141,14 @@ static void spmv_dispatch(int L, int NB, hipStream_t st, int n, const int* rp, c
                           const AT* v, const XT* x, const double* scale, YT* y, const Ctrl* c,
                           int gate) {
     dim3 g(NB), b(kWG);
+    if (L == -256) {
+        k_spmv_stream<256, 0, false, AT, XT, double, YT, ACC><<<g, 256, 0, st>>>(n, rp, ci, v, x, scale, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
+        return;
+    }
+    if (L <= 0) {
+        k_spmv_stream<128, 0, false, AT, XT, double, YT, ACC><<<g, 128, 0, st>>>(n, rp, ci, v, x, scale, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
+        return;
+    }
     switch (L) {
         case 1: k_spmv<1, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
         case 2: k_spmv<2, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
@@ -585,6 +1165,14 @@ static void residual_dispatch(int L, int NB, hipStream_t st, int n, const int* r
                               const AT* v, const double* x, const BT* b, RT* r, double* part,
                               int slot, const Ctrl* c, int gate) {
     dim3 g(NB), bl(kWG);
+    if (L == -256) {
+        k_spmv_stream<256, 1, false, AT, double, BT, RT, ACC><<<g, 256, 0, st>>>(n, rp, ci, v, x, nullptr, b, r, part, slot, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
+        return;
+    }
+    if (L <= 0) {
+        k_spmv_stream<128, 1, false, AT, double, BT, RT, ACC><<<g, 128, 0, st>>>(n, rp, ci, v, x, nullptr, b, r, part, slot, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
+        return;
+    }
     switch (L) {
         case 1: k_residual<1, AT, BT, RT, ACC><<<g, bl, 0, st>>>(n, rp, ci, v, x, b, r, part, slot, NB, c, gate); break;
         case 2: k_residual<2, AT, BT, RT, ACC><<<g, bl, 0, st>>>(n, rp, ci, v, x, b, r, part, slot, NB, c, gate); break;
@@ -596,6 +1184,44 @@ static void residual_dispatch(int L, int NB, hipStream_t st, int n, const int* r
     }
 }
 
+// Stream SpMV (MODE 0) or residual (MODE 1) with the fused Z^T partials.
+template <int MODE, typename AT, typename XT, typename BT, typename YT, typename ACC>
+static void stream_fused(const EngineArgs& e, const AT* vals, const XT* x, const double* scale,
+                         const BT* b, YT* y, int slot, int gate) {
+    if (e.fuse_rb == 256)
+        k_spmv_stream<256, MODE, true, AT, XT, BT, YT, ACC><<<e.NB, 256, 0, e.st>>>(
+            e.n, e.rowptr, e.colind, vals, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
+            e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
+    else
+        k_spmv_stream<128, MODE, true, AT, XT, BT, YT, ACC><<<e.NB, 128, 0, e.st>>>(
+            e.n, e.rowptr, e.colind, vals, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
+            e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
+}
+
+template <int MODE, int WMAX, typename AT, typename XT, typename BT, typename YT, typename ACC>
+static void sell_launch_w(const EngineArgs& e, const XT* x, const double* scale, const BT* b, YT* y,
+                          int slot, int gate) {
+    const AT* sv = reinterpret_cast<const AT*>(e.sell_val);
+    // MODE 0 needs no per-block partials: one block per 256-row block.  MODE 1
+    // writes one norm partial per block, so it keeps the NB-block grid.
+    const int grid = MODE == 0 ? (int)std::max<int64_t>(1, ((int64_t)e.n + kWG - 1) / kWG) : e.NB;
+    if (e.R > 0 && e.fuse_rb == 256)
+        k_spmv_sell<MODE, true, WMAX, AT, XT, BT, YT, ACC><<<grid, kWG, 0, e.st>>>(
+            e.n, e.sell_off, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
+            e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
+    else
+        k_spmv_sell<MODE, false, WMAX, AT, XT, BT, YT, ACC><<<grid, kWG, 0, e.st>>>(
+            e.n, e.sell_off, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, nullptr, nullptr,
+            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, e.ctrl, gate);
+}
+
+template <int MODE, typename AT, typename XT, typename BT, typename YT, typename ACC>
+static void sell_launch(const EngineArgs& e, const XT* x, const double* scale, const BT* b, YT* y,
+                        int slot, int gate) {
+    if (e.sell_wmax <= 12) sell_launch_w<MODE, 12, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    else sell_launch_w<MODE, 32, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+}
+
 static int jmax_for(int nv) {
     if (nv <= 8) return 8;
     if (nv <= 16) return 16;
@@ -605,12 +1231,11 @@ static int jmax_for(int nv) {
     return 96;
 }
 
-// Lanes per row of the pass kernels: keep JMAX / T register entries per lane
-// at or below 24 (FP64) / 48 (FP32) so no instantiation spills.
+// Lanes per tile of the pass kernels: at most 16 basis tiles (64 VGPRs) per
+// lane, so no instantiation spills.
 template <int J, typename ACC>
 struct LanesFor {
-    static constexpr int kCap = sizeof(ACC) == 8 ? 24 : 48;
-    static constexpr int value = J <= kCap ? 1 : (J <= 2 * kCap ? 2 : 4);
+    static constexpr int value = J <= 16 ? 1 : (J <= 32 ? 2 : (J <= 64 ? 4 : 8));
 };
 
 #define GM_JMAX_SWITCH(nv, ACCT, CALL)                                                         \
@@ -640,41 +1265,68 @@ struct Engine {
     WT* r() const { return reinterpret_cast<WT*>(e.r); }
     const AT* vals() const { return reinterpret_cast<const AT*>(e.vals); }
     const AT* azv() const { return reinterpret_cast<const AT*>(e.azv); }
+    const AT* azv1() const { return reinterpret_cast<const AT*>(e.azv1); }
     static constexpr int kHalf = std::is_same<VT, __half>::value ? 1 : 0;
+
+    bool fused() const { return e.R > 0 && e.fuse_rb != 0; }
+
+    void coarse_slots(double* s, int gate) const {
+        k_coarse_slots<<<1, kCT, 0, e.st>>>(e.R, e.ab_ptr, e.tpart, e.Einv, e.trans, s, e.ctrl,
+                                            gate);
+    }
 
     void coarse(const WT* vec, double* s, int gate) const {
         if (e.R == 0) return;
         k_zt<WT><<<e.R * e.MC, kWG, 0, e.st>>>(e.R, e.MC, e.CH, e.ztrp, e.ztci, e.ztv, vec, e.tpart,
                                               e.ctrl, gate);
-        k_coarse<<<1, kWG, 0, e.st>>>(e.R, e.MC, e.tpart, e.Einv, e.trans, s, e.ctrl, gate);
+        k_coarse<<<1, kCT, 0, e.st>>>(e.R, e.MC, e.tpart, e.Einv, e.trans, s, e.ctrl, gate);
     }
 
     // Residual of x_hat, its deflated version p = P r into e.p, and the
     // restart decision (or the initialisation when `init`).
     template <typename BT>
     void restart_block(const BT* b, bool init, double rtol, double r0_override) const {
-        residual_dispatch<AT, BT, WT, ACC>(e.L, e.NB, e.st, e.n, e.rowptr, e.colind, vals(), e.xh, b,
-                                           r(), e.part, e.nslot, e.ctrl, init ? 0 : 1);
-        if (init) k_init<<<1, kWG, 0, e.st>>>(e.part, e.NB, e.nslot, rtol, r0_override, e.ctrl);
-        coarse(r(), e.s_res, init ? 0 : 1);
+        if (e.L == kSell) {
+            sell_launch<1, AT, double, BT, WT, ACC>(e, e.xh, nullptr, b, r(), e.nslot, init ? 0 : 1);
+            if (init) k_init<<<1, kWG, 0, e.st>>>(e.part, e.NB, e.nslot, rtol, r0_override, e.ctrl);
+            if (fused()) coarse_slots(e.s_res, init ? 0 : 1);
+            else coarse(r(), e.s_res, init ? 0 : 1);
+        } else if (fused()) {
+            stream_fused<1, AT, double, BT, WT, ACC>(e, vals(), e.xh, nullptr, b, r(), e.nslot,
+                                                      init ? 0 : 1);
+            if (init) k_init<<<1, kWG, 0, e.st>>>(e.part, e.NB, e.nslot, rtol, r0_override, e.ctrl);
+            coarse_slots(e.s_res, init ? 0 : 1);
+        } else {
+            residual_dispatch<AT, BT, WT, ACC>(e.L, e.NB, e.st, e.n, e.rowptr, e.colind, vals(), e.xh,
+                                               b, r(), e.part, e.nslot, e.ctrl, init ? 0 : 1);
+            if (init) k_init<<<1, kWG, 0, e.st>>>(e.part, e.NB, e.nslot, rtol, r0_override, e.ctrl);
+            coarse(r(), e.s_res, init ? 0 : 1);
+        }
         k_pass1<8, 1, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(e.n, e.ldv, V(), 0, r(), e.azrp, e.azci,
-                                                            azv(), e.s_res, e.R, p(), e.part,
+                                                            azv(), e.azc1, azv1(), e.s_res, e.R, p(), e.part,
                                                             e.nslot, e.NB, e.ctrl, 1);
         k_decide<<<1, kWG, 0, e.st>>>(e.part, e.NB, e.nslot, e.m, kHalf, e.nscale, e.g, e.vscale,
-                                      e.sigma0, e.ctrl);
+                                      e.sigma0, e.trust_est, e.ctrl);
         k_store_v0<VT, WT><<<e.NB, kWG, 0, e.st>>>(e.n, p(), e.sigma0, Vcol(0), e.ctrl, 1);
     }
 
     void step(int j) const {
         const int nv = j + 1;
         if (e.timer) e.timer->begin(0, j);
-        spmv_dispatch<AT, VT, WT, ACC>(e.L, e.NB, e.st, e.n, e.rowptr, e.colind, vals(), Vcol(j),
-                                       e.vscale + j, y(), e.ctrl, 2);
+        if (e.L == kSell)
+            sell_launch<0, AT, VT, double, WT, ACC>(e, Vcol(j), e.vscale + j, nullptr, y(), 0, 2);
+        else if (fused())
+            stream_fused<0, AT, VT, double, WT, ACC>(e, vals(), Vcol(j), e.vscale + j, nullptr, y(),
+                                                      0, 2);
+        else
+            spmv_dispatch<AT, VT, WT, ACC>(e.L, e.NB, e.st, e.n, e.rowptr, e.colind, vals(), Vcol(j),
+                                           e.vscale + j, y(), e.ctrl, 2);
         if (e.timer) e.timer->end(0, j);
-        coarse(y(), e.s_step, 2);
+        if (fused()) coarse_slots(e.s_step, 2);
+        else coarse(y(), e.s_step, 2);
         if (e.timer) e.timer->begin(1, j);
         GM_JMAX_SWITCH(nv, ACC, (k_pass1<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
-                               e.n, e.ldv, V(), nv, y(), e.azrp, e.azci, azv(), e.s_step, e.R, w(),
+                               e.n, e.ldv, V(), nv, y(), e.azrp, e.azci, azv(), e.azc1, azv1(), e.s_step, e.R, w(),
                                e.part, e.nslot, e.NB, e.ctrl, 2)));
         if (e.timer) e.timer->end(1, j);
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
@@ -690,15 +1342,69 @@ struct Engine {
                                e.n, e.ldv, V(), nv, w(), e.coef2, e.sigma, e.part, e.nslot, e.NB,
                                e.ctrl, 2)));
         if (e.timer) e.timer->end(3, j);
-        k_givens<<<1, kWave, 0, e.st>>>(j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs, e.sn,
-                                        e.g, e.vscale, e.sigma, e.hist, e.hist_cap, e.Hraw, e.ctrl, 2);
+        k_givens<false><<<1, kWave, 0, e.st>>>(j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
+                                               e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap,
+                                               e.Hraw, nullptr, nullptr, e.ctrl, 2);
+    }
+
+    // Step j of the two-pass variant (see k_pass1_lag).
+    void step_lag(int j) const {
+        const int nv = j + 1;
+        if (e.timer) e.timer->begin(0, j);
+        if (j == 0) {
+            spmv_any<VT>(Vcol(0), e.vscale);
+        } else {
+            spmv_any<WT>(w(), nullptr);
+        }
+        if (e.timer) e.timer->end(0, j);
+        if (fused()) coarse_slots(e.s_step, 2);
+        else coarse(y(), e.s_step, 2);
+        if (e.timer) e.timer->begin(1, j);
+        if (j == 0) {
+            k_pass1<8, 1, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
+                e.n, e.ldv, V(), 1, y(), e.azrp, e.azci, azv(), e.azc1, azv1(), e.s_step, e.R, w(),
+                e.part, e.nslot, e.NB, e.ctrl, 2);
+        } else {
+            GM_JMAX_SWITCH(j, ACC, (k_pass1_lag<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
+                                      e.n, e.ldv, V(), j, w(), y(), e.azrp, e.azci, azv(), e.azc1,
+                                      azv1(), e.s_step, e.R, e.coef2, e.cc, e.lag, e.part, e.nslot,
+                                      e.NB, e.ctrl, 2)));
+        }
+        if (e.timer) e.timer->end(1, j);
+        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
+                                           kHalf, e.nscale, e.sigma, e.ctrl, 2);
+        if (e.timer) e.timer->begin(2, j);
+        GM_JMAX_SWITCH(nv, ACC, (k_pass2<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
+                                    e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, e.NB, e.ctrl, 2)));
+        if (e.timer) e.timer->end(2, j);
+        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
+                                           kHalf, e.nscale, e.sigma, e.ctrl, 2);
+        k_givens<true><<<1, kWave, 0, e.st>>>(j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
+                                              e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap,
+                                              e.Hraw, e.cc, e.lag, e.ctrl, 2);
+    }
+
+    // y = scale * A x for the step's input vector x (type XT), with the fused
+    // Z^T y partials when available.
+    template <typename XT>
+    void spmv_any(const XT* x, const double* scale) const {
+        if (e.L == kSell)
+            sell_launch<0, AT, XT, double, WT, ACC>(e, x, scale, nullptr, y(), 0, 2);
+        else if (fused())
+            stream_fused<0, AT, XT, double, WT, ACC>(e, vals(), x, scale, nullptr, y(), 0, 2);
+        else
+            spmv_dispatch<AT, XT, WT, ACC>(e.L, e.NB, e.st, e.n, e.rowptr, e.colind, vals(), x, scale,
+                                           y(), e.ctrl, 2);
     }
 
     template <typename BT>
     void cycle(const BT* b) const {
-        for (int j = 0; j < e.m; ++j) step(j);
-        k_backsolve<<<1, kWave, 0, e.st>>>(e.m, e.H, e.g, e.vscale, e.coef1, e.cyc_k, e.cyc_cap,
-                                           e.ctrl, 1);
+        for (int j = 0; j < e.m; ++j) {
+            if (e.lagged) step_lag(j);
+            else step(j);
+        }
+        k_backsolve<<<1, kWG, 0, e.st>>>(e.m, e.H, e.g, e.vscale, e.coef1, e.cyc_k, e.cyc_cap,
+                                         e.ctrl, 1);
         k_xupdate<VT><<<e.NB, kWG, 0, e.st>>>(e.n, e.ldv, V(), e.coef1, e.xh, e.ctrl, 1);
         restart_block(b, false, 0.0, 0.0);
     }
@@ -721,18 +1427,16 @@ void launch_cycle(const EngineArgs& a, const void* b) {
     }
 }
 
-void launch_pass_probe(const EngineArgs& e, int kind, int nv) {
-    using VT = double;
-    using WT = double;
-    using ACC = double;
-    using AT = double;
+template <typename AT, typename VT, typename WT, typename ACC>
+static void pass_probe(const EngineArgs& e, int kind, int nv) {
     const VT* V = reinterpret_cast<const VT*>(e.V);
     WT* y = reinterpret_cast<WT*>(e.y);
     WT* w = reinterpret_cast<WT*>(e.w);
     if (kind == 1) {
         GM_JMAX_SWITCH(nv, ACC, (k_pass1<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
-                                    e.n, e.ldv, V, nv, y, e.azrp, e.azci, (const AT*)e.azv, e.s_step,
-                                    e.R, w, e.part, e.nslot, e.NB, nullptr, 0)));
+                                    e.n, e.ldv, V, nv, y, e.azrp, e.azci, (const AT*)e.azv, e.azc1,
+                                    (const AT*)e.azv1, e.s_step, e.R, w, e.part, e.nslot, e.NB,
+                                    nullptr, 0)));
     } else if (kind == 2) {
         GM_JMAX_SWITCH(nv, ACC, (k_pass2<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
                                     e.n, e.ldv, V, nv, w, e.coef1, e.part, e.nslot, e.NB, nullptr, 0)));
@@ -740,6 +1444,15 @@ void launch_pass_probe(const EngineArgs& e, int kind, int nv) {
         GM_JMAX_SWITCH(nv, ACC, (k_pass3<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
                                     e.n, e.ldv, (VT*)V, nv, w, e.coef2, e.sigma, e.part, e.nslot,
                                     e.NB, nullptr, 0)));
+    }
+}
+
+// One launch of a pass kernel in the engine's precision (tuning probes).
+void launch_pass_probe(const EngineArgs& e, int kind, int nv) {
+    switch (e.prec) {
+        case kPrecF64: pass_probe<double, double, double, double>(e, kind, nv); break;
+        case kPrecF32: pass_probe<float, float, float, float>(e, kind, nv); break;
+        default: pass_probe<float, __half, float, float>(e, kind, nv); break;
     }
 }
 
@@ -762,6 +1475,21 @@ void launch_sum_slot(hipStream_t st, const double* part, int NB, int slot, doubl
 void launch_spmv_f64(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
                      const double* v, const double* x, double* y) {
     spmv_dispatch<double, double, double, double>(L, NB, st, n, rp, ci, v, x, nullptr, y, nullptr, 0);
+}
+
+void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
+                          const double* val, const double* x, double* y) {
+    k_spmv_sell<0, false, 32, double, double, double, double, double><<<NB, kWG, 0, st>>>(
+        n, off, col, val, x, nullptr, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+}
+
+void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
+                              const double* val, const double* x, const double* b, double* r,
+                              double* part, int slot) {
+    k_spmv_sell<1, false, 32, double, double, double, double, double><<<NB, kWG, 0, st>>>(
+        n, off, col, val, x, nullptr, b, r, part, slot, NB, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 
 void launch_spmv_f32(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,

@@ -422,6 +422,249 @@ int lu_inverse(hipStream_t st, int nsys, const int64_t* d_sys_zcol_off, const in
     return (h & 4) ? kStatusSingular : kStatusOk;
 }
 
+// --------------------------------------------------------- sliced ELL (SELL-64)
+// Rows are grouped in slices of 64 (one wavefront); slice s stores its rows'
+// entries column-major, width = longest row of the slice: entry (row, k) at
+// off[s] + k*64 + (row % 64).  Padding entries point at the row itself with a
+// zero value.  src[q] is the CSR index of entry q (-1 for padding), used to
+// refresh values.
+
+__global__ void k_sell_width(int64_t n, const int* __restrict__ rowptr, int* __restrict__ wsz) {
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nsl = (n + 63) / 64;
+    if (sl > nsl) return;
+    if (sl == nsl) { wsz[sl] = 0; return; }
+    int w = 0;
+    for (int64_t i = sl * 64; i < min(n, sl * 64 + 64); ++i) w = max(w, rowptr[i + 1] - rowptr[i]);
+    wsz[sl] = w * 64;
+}
+
+__global__ void k_sell_fill(int64_t n, const int* __restrict__ rowptr, const int* __restrict__ colind,
+                            const int* __restrict__ off, int* __restrict__ scol, int* __restrict__ src) {
+    const int64_t sl = (int64_t)blockIdx.x;     // one block of 64 threads per slice
+    const int64_t i = sl * 64 + threadIdx.x;
+    const int w = (off[sl + 1] - off[sl]) / 64;
+    const int base = off[sl] + threadIdx.x;
+    const int k0 = i < n ? rowptr[i] : 0;
+    const int len = i < n ? rowptr[i + 1] - k0 : 0;
+    for (int k = 0; k < w; ++k) {
+        const int q = base + k * 64;
+        if (k < len) {
+            scol[q] = colind[k0 + k];
+            src[q] = k0 + k;
+        } else {
+            scol[q] = i < n ? (int)i : 0;
+            src[q] = -1;
+        }
+    }
+}
+
+__global__ void k_sell_vals(int64_t m, const int* __restrict__ src, const double* __restrict__ vals,
+                            double* __restrict__ v64, float* __restrict__ v32) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const int k = src[q];
+    const double v = k >= 0 ? vals[k] : 0.0;
+    if (v64) v64[q] = v;
+    if (v32) v32[q] = (float)v;
+}
+
+int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
+               int** scol, int** src, int64_t* total) {
+    const int64_t nsl = (n + 63) / 64;
+    *off = *scol = *src = nullptr;
+    int* wsz = nullptr;
+    void* tmp = nullptr;
+    size_t tb = 0;
+    int status = kStatusOk;
+    if (hipMalloc(off, (nsl + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&wsz, (nsl + 1) * sizeof(int)) != hipSuccess)
+        status = kStatusNoMem;
+    int h = 0;
+    if (status == kStatusOk) {
+        k_sell_width<<<blocks_for(nsl + 1), kWG, 0, st>>>(n, rowptr, wsz);
+        hipcub::DeviceScan::ExclusiveSum(nullptr, tb, wsz, *off, (int)(nsl + 1), st);
+        if (hipMalloc(&tmp, tb) != hipSuccess) status = kStatusNoMem;
+    }
+    if (status == kStatusOk) {
+        hipcub::DeviceScan::ExclusiveSum(tmp, tb, wsz, *off, (int)(nsl + 1), st);
+        hipMemcpyAsync(&h, *off + nsl, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+    }
+    if (status == kStatusOk && (hipMalloc(scol, std::max(h, 1) * sizeof(int)) != hipSuccess ||
+                                hipMalloc(src, std::max(h, 1) * sizeof(int)) != hipSuccess))
+        status = kStatusNoMem;
+    if (status == kStatusOk) {
+        if (nsl > 0) k_sell_fill<<<(unsigned)nsl, 64, 0, st>>>(n, rowptr, colind, *off, *scol, *src);
+        if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+    }
+    hipFree(wsz);
+    hipFree(tmp);
+    if (status != kStatusOk) {
+        hipFree(*off);
+        hipFree(*scol);
+        hipFree(*src);
+        *off = *scol = *src = nullptr;
+    }
+    *total = h;
+    return status;
+}
+
+void sell_values(hipStream_t st, int64_t total, const int* src, const double* vals, double* v64,
+                 float* v32) {
+    if (total > 0) k_sell_vals<<<blocks_for(total), kWG, 0, st>>>(total, src, vals, v64, v32);
+}
+
+// ------------------------------------------------- per-block deflation slots
+// For the SpMV epilogue that forms Z^T y: row block b (rows [b*RB, (b+1)*RB))
+// gets the sorted list of deflation columns its rows reach through Z
+// (bb_col[bb_ptr[b] .. bb_ptr[b+1]), one partial-sum slot each); for every
+// deflation column a, ab_slot[ab_ptr[a] .. ab_ptr[a+1]) lists its slots in
+// increasing block order, so the coarse solve sums them in a fixed order.
+
+__device__ int block_cols(int64_t n, int RB, int64_t blk, const int* __restrict__ zrp,
+                          const int* __restrict__ zci, int* cols, bool* over) {
+    int nc = 0;
+    const int64_t r0 = blk * RB, r1 = min(n, r0 + RB);
+    for (int64_t i = r0; i < r1; ++i)
+        for (int q = zrp[i]; q < zrp[i + 1]; ++q) {
+            const int a = zci[q];
+            int t = 0;
+            while (t < nc && cols[t] < a) ++t;
+            if (t < nc && cols[t] == a) continue;
+            if (nc == kBlockColsMax) { *over = true; continue; }
+            for (int u = nc; u > t; --u) cols[u] = cols[u - 1];
+            cols[t] = a;
+            ++nc;
+        }
+    return nc;
+}
+
+__global__ void k_block_cols(int64_t n, int RB, int64_t nblk, const int* __restrict__ zrp,
+                             const int* __restrict__ zci, const int* __restrict__ bb_ptr,
+                             int* __restrict__ cnt_or_cols, int* __restrict__ flags) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    int cols[kBlockColsMax];
+    bool over = false;
+    const int nc = block_cols(n, RB, b, zrp, zci, cols, &over);
+    if (over) atomicOr(flags, 1);
+    if (!bb_ptr) {
+        cnt_or_cols[b] = nc;
+    } else {
+        for (int t = 0; t < nc; ++t) cnt_or_cols[bb_ptr[b] + t] = cols[t];
+    }
+}
+
+int build_block_slots(hipStream_t st, int64_t n, int RB, int R, const int* zrp, const int* zci,
+                      int** bb_ptr, int** bb_col, int** ab_ptr, int** ab_slot, int64_t* nslots,
+                      int* d_flags) {
+    const int64_t nblk = (n + RB - 1) / RB;
+    *bb_ptr = *bb_col = *ab_ptr = *ab_slot = nullptr;
+    int* cnt = nullptr;
+    void* tmp = nullptr;
+    size_t tb = 0;
+    int status = kStatusOk;
+    if (hipMalloc(bb_ptr, (nblk + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&cnt, (nblk + 1) * sizeof(int)) != hipSuccess) {
+        status = kStatusNoMem;
+    }
+    int h[2] = {0, 0};
+    if (status == kStatusOk) {
+        hipMemsetAsync(d_flags, 0, sizeof(int), st);
+        hipMemsetAsync(cnt + nblk, 0, sizeof(int), st);
+        k_block_cols<<<blocks_for(nblk), kWG, 0, st>>>(n, RB, nblk, zrp, zci, nullptr, cnt, d_flags);
+        hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, *bb_ptr, (int)(nblk + 1), st);
+        if (hipMalloc(&tmp, tb) != hipSuccess) status = kStatusNoMem;
+    }
+    if (status == kStatusOk) {
+        hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, *bb_ptr, (int)(nblk + 1), st);
+        hipMemcpyAsync(&h[0], d_flags, sizeof(int), hipMemcpyDeviceToHost, st);
+        hipMemcpyAsync(&h[1], *bb_ptr + nblk, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+        else if (h[0]) status = kStatusInval;      // some block reaches too many columns
+    }
+    hipFree(tmp);
+    tmp = nullptr;
+    const int64_t ns = h[1];
+    *nslots = ns;
+    int *keys_out = nullptr, *iota = nullptr;
+    if (status == kStatusOk) {
+        if (hipMalloc(bb_col, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc(ab_ptr, (R + 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc(ab_slot, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc(&keys_out, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc(&iota, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess)
+            status = kStatusNoMem;
+    }
+    if (status == kStatusOk) {
+        k_block_cols<<<blocks_for(nblk), kWG, 0, st>>>(n, RB, nblk, zrp, zci, *bb_ptr, *bb_col, d_flags);
+        k_iota<<<blocks_for(ns), kWG, 0, st>>>(ns, iota);
+        int end_bit = 1;
+        while ((int64_t(1) << end_bit) < R) ++end_bit;
+        hipcub::DeviceRadixSort::SortPairs(nullptr, tb, *bb_col, keys_out, iota, *ab_slot, (int)ns, 0,
+                                           end_bit, st);
+        if (hipMalloc(&tmp, tb) != hipSuccess) {
+            status = kStatusNoMem;
+        } else {
+            hipcub::DeviceRadixSort::SortPairs(tmp, tb, *bb_col, keys_out, iota, *ab_slot, (int)ns, 0,
+                                               end_bit, st);
+            k_bounds<<<blocks_for(ns + 1), kWG, 0, st>>>(ns, R, keys_out, *ab_ptr);
+            if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+        }
+    }
+    hipFree(tmp);
+    hipFree(cnt);
+    hipFree(keys_out);
+    hipFree(iota);
+    if (status != kStatusOk) {
+        hipFree(*bb_ptr);
+        hipFree(*bb_col);
+        hipFree(*ab_ptr);
+        hipFree(*ab_slot);
+        *bb_ptr = *bb_col = *ab_ptr = *ab_slot = nullptr;
+    }
+    return status;
+}
+
+// ---------------------------------------------- single-entry row copies (ELL-1)
+// c1[i] = the only column of row i (>= 0), -1 for an empty row, -2 for a row
+// with several entries (the CSR is used for those); v1[i] its value.  Lets the
+// streaming kernels read one coalesced (column, value) pair per row.
+__global__ void k_ell1(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
+                       const double* __restrict__ v, int* __restrict__ c1, double* __restrict__ v1,
+                       float* __restrict__ v1f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int q0 = rp[i], q1 = rp[i + 1];
+    int c = -1;
+    double val = 0.0;
+    if (q1 - q0 == 1) {
+        c = ci[q0];
+        val = v[q0];
+    } else if (q1 - q0 > 1) {
+        c = -2;
+    }
+    if (c1) c1[i] = c;
+    v1[i] = val;
+    if (v1f) v1f[i] = (float)val;
+}
+
+void ell1_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const double* v, int* c1,
+                double* v1, float* v1f) {
+    if (n > 0) k_ell1<<<blocks_for(n), kWG, 0, st>>>(n, rp, ci, v, c1, v1, v1f);
+}
+
+// Inverse permutation: pos[perm[q]] = q.
+__global__ void k_invperm(int64_t m, const int* __restrict__ perm, int* __restrict__ pos) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) pos[perm[q]] = (int)q;
+}
+
+void invperm(hipStream_t st, int64_t m, const int* perm, int* pos) {
+    if (m > 0) k_invperm<<<blocks_for(m), kWG, 0, st>>>(m, perm, pos);
+}
+
 // ------------------------------------------------------------ small kernels
 
 __global__ void k_to_f32(int64_t n, const double* __restrict__ s, float* __restrict__ d) {

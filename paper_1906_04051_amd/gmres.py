@@ -34,7 +34,8 @@ class GmresOpts(C.Structure):
                 ("inner_rtol", C.c_double), ("max_refine", C.c_int32),
                 ("inner_max_iters", C.c_int64), ("use_graph", C.c_int32),
                 ("record_history", C.c_int32), ("spmv_lanes", C.c_int32),
-                ("num_blocks", C.c_int32), ("batch_wg", C.c_int32), ("batch_lanes", C.c_int32)]
+                ("num_blocks", C.c_int32), ("batch_wg", C.c_int32), ("batch_lanes", C.c_int32),
+                ("ortho", C.c_int32)]
 
 
 class GmresInfo(C.Structure):

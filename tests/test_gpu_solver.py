@@ -113,23 +113,24 @@ def _gpu_solve(s, b=None, x0=None, **opts):
     return out, info, plan
 
 
-def test_config1_trajectory_parity():
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_config1_trajectory_parity(ortho):
     s = W.make_config(1)
     ref_tol = oracle.gmres(s, 30, 1e-8, 2000)
     K = ref_tol.iters
     ref = oracle.gmres(s, 30, 0.0, K)
-    say("config 1 fixed-count K =", K)
-    x, info, _ = _gpu_solve(s, m=30, rtol=0.0, max_iters=K)
+    say("config 1 fixed-count K =", K, "ortho", ortho)
+    x, info, _ = _gpu_solve(s, m=30, rtol=0.0, max_iters=K, ortho=ortho)
     assert info["iters"] == K and info["status_name"] == "MAXITER"
     assert rel(x, ref.x) <= 1e-8
     assert abs(info["rel_res"] - ref.rel_res_deflated) <= 1e-6 * ref.rel_res_deflated + 1e-14
 
 
-@pytest.mark.parametrize("use_graph", [1, 0])
-def test_config1_to_tolerance(use_graph):
+@pytest.mark.parametrize("use_graph,ortho", [(1, 1), (0, 1), (1, 0)])
+def test_config1_to_tolerance(use_graph, ortho):
     s = W.make_config(1)
     ref = oracle.gmres(s, 30, 1e-8, 2000)
-    x, info, _ = _gpu_solve(s, m=30, rtol=1e-8, max_iters=2000, use_graph=use_graph)
+    x, info, _ = _gpu_solve(s, m=30, rtol=1e-8, max_iters=2000, use_graph=use_graph, ortho=ortho)
     say("config 1 iters gpu/oracle", info["iters"], ref.iters)
     assert info["status_name"] == "OK"
     assert abs(info["iters"] - ref.iters) <= 1
@@ -139,10 +140,11 @@ def test_config1_to_tolerance(use_graph):
     assert abs(info["rel_res_true"] - np.linalg.norm(r) / ref.rho0) <= 1e-12
 
 
-def test_residual_history_matches_oracle():
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_residual_history_matches_oracle(ortho):
     s = W.make_config(1, mesh=32)
     ref = oracle.gmres(s, 30, 1e-8, 2000, history=True)
-    plan, d = G().plan_for(s, m=30, rtol=1e-8, max_iters=2000, record_history=1)
+    plan, d = G().plan_for(s, m=30, rtol=1e-8, max_iters=2000, record_history=1, ortho=ortho)
     x, info = plan.solve(d["b"])
     h = plan.history()
     k = min(len(h), len(ref.history))
@@ -151,19 +153,20 @@ def test_residual_history_matches_oracle():
     assert relerr.max() <= 1e-6
 
 
+@pytest.mark.parametrize("ortho", [0, 1])
 @pytest.mark.parametrize("mesh,s_sub,m", [(5, 2, 7), (13, 3, 20), (37, 4, 30), (91, 8, 50), (150, 5, 80)])
-def test_ragged_sizes_and_restart_lengths(mesh, s_sub, m):
+def test_ragged_sizes_and_restart_lengths(mesh, s_sub, m, ortho):
     # n = (mesh+1)^2 is never a multiple of the 256-thread workgroup.
     sysm = W.convection_diffusion_lognormal(mesh, beta=(30.0, 5.0), sigma=1.0, s=s_sub,
                                             seed_seq=W.config_seed(100 + mesh))
     ref_tol = oracle.gmres(sysm, m, 1e-9, 5000)
     K = min(ref_tol.iters, 3 * m + 5)
     ref = oracle.gmres(sysm, m, 0.0, K)
-    say("ragged mesh", mesh, "n", sysm.n, "m", m, "K", K)
-    x, info, _ = _gpu_solve(sysm, m=m, rtol=0.0, max_iters=K)
+    say("ragged mesh", mesh, "n", sysm.n, "m", m, "K", K, "ortho", ortho)
+    x, info, _ = _gpu_solve(sysm, m=m, rtol=0.0, max_iters=K, ortho=ortho)
     assert info["iters"] == K
     assert rel(x, ref.x) <= 1e-8
-    x2, info2, _ = _gpu_solve(sysm, m=m, rtol=1e-9, max_iters=5000)
+    x2, info2, _ = _gpu_solve(sysm, m=m, rtol=1e-9, max_iters=5000, ortho=ortho)
     assert abs(info2["iters"] - ref_tol.iters) <= 1
     assert rel(x2, ref_tol.x) <= 1e-8
 
@@ -186,24 +189,25 @@ def test_resume_from_checkpoint():
     assert rel(x2, full.x) <= 1e-8
 
 
-def test_degenerate_cases():
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_degenerate_cases(ortho):
     n = 300
     b = np.linspace(1.0, 2.0, n)
     # A = I: one step.
-    x, info, _ = _gpu_solve(W.from_dense(np.eye(n), b), m=10, rtol=1e-12, max_iters=50)
+    x, info, _ = _gpu_solve(W.from_dense(np.eye(n), b), m=10, rtol=1e-12, max_iters=50, ortho=ortho)
     assert info["iters"] == 1 and np.allclose(x, b, rtol=1e-14)
     # Four distinct eigenvalues: four steps.
     d = np.repeat([1.0, 2.0, 5.0, -3.0], n // 4)
-    x, info, _ = _gpu_solve(W.from_dense(np.diag(d), b), m=20, rtol=1e-13, max_iters=100)
+    x, info, _ = _gpu_solve(W.from_dense(np.diag(d), b), m=20, rtol=1e-13, max_iters=100, ortho=ortho)
     assert info["iters"] == 4 and np.allclose(x, b / d, rtol=1e-12)
     # rho0 = 0 (b = A x0 exactly): immediate return with x = x0.
     s = W.make_config(1, mesh=16)
     s0 = copy.copy(s)
     s0.b = np.zeros(s.n)
-    x, info, _ = _gpu_solve(s0, m=10, rtol=1e-8, max_iters=100)
+    x, info, _ = _gpu_solve(s0, m=10, rtol=1e-8, max_iters=100, ortho=ortho)
     assert info["iters"] == 0 and info["status_name"] == "OK" and not np.any(x)
     x0 = np.random.default_rng(1).standard_normal(n)
-    x, info, _ = _gpu_solve(W.from_dense(np.eye(n), x0), x0=x0, m=10, rtol=1e-8, max_iters=100)
+    x, info, _ = _gpu_solve(W.from_dense(np.eye(n), x0), x0=x0, m=10, rtol=1e-8, max_iters=100, ortho=ortho)
     assert info["iters"] == 0 and info["status_name"] == "OK"
     assert np.array_equal(x, x0)
     # Z = I: the coarse solve alone gives the answer after zero steps.
@@ -211,14 +215,14 @@ def test_degenerate_cases():
     nz = 40
     A = rng.standard_normal((nz, nz)) / np.sqrt(nz) + 4 * np.eye(nz)
     bz = rng.standard_normal(nz)
-    x, info, _ = _gpu_solve(W.from_dense(A, bz, Z=np.eye(nz)), m=5, rtol=1e-12, max_iters=50)
+    x, info, _ = _gpu_solve(W.from_dense(A, bz, Z=np.eye(nz)), m=5, rtol=1e-12, max_iters=50, ortho=ortho)
     assert info["iters"] == 0 and rel(x, np.linalg.solve(A, bz)) <= 1e-12
     # Cyclic shift with m < N: stagnation, MAXITER.
     nc = 64
     Ac = np.roll(np.eye(nc), 1, axis=0)
     bc = np.zeros(nc)
     bc[0] = 1.0
-    x, info, _ = _gpu_solve(W.from_dense(Ac, bc), m=8, rtol=1e-8, max_iters=64)
+    x, info, _ = _gpu_solve(W.from_dense(Ac, bc), m=8, rtol=1e-8, max_iters=64, ortho=ortho)
     assert info["status_name"] == "MAXITER" and info["iters"] == 64
 
 
@@ -291,14 +295,16 @@ def _forward_error_bound(s, x1, x2, rho0, rtol):
     return (r1 + r2) / smin
 
 
+@pytest.mark.parametrize("ortho", [0, 1])
 @pytest.mark.parametrize("prec", ["mixed_f32", "mixed_f16"])
 @pytest.mark.parametrize("cfg,mesh", [(1, 32), (2, 48), (5, 32)])
-def test_mixed_precision_reaches_fp64_accuracy(prec, cfg, mesh):
+def test_mixed_precision_reaches_fp64_accuracy(prec, cfg, mesh, ortho):
     s = W.make_config(cfg, mesh=mesh)
     m = W.CONFIGS[cfg]["m"]
     ref = oracle.gmres(s, m, 1e-8, 20000)
     inner = 1e-3 if prec == "mixed_f16" else 1e-5
-    x, info, _ = _gpu_solve(s, m=m, rtol=1e-8, max_iters=20000, precision=prec, inner_rtol=inner)
+    x, info, _ = _gpu_solve(s, m=m, rtol=1e-8, max_iters=20000, precision=prec, inner_rtol=inner,
+                            ortho=ortho)
     r = host_residual(s, x)
     err = rel(x, ref.x)
     say(prec, "config", cfg, "mesh", mesh, "iters", info["iters"], "refinements",
