@@ -30,6 +30,29 @@ if ROOT not in sys.path:
 METRIC = "time-to-rtol 1e-8 (s) + SpMV/Arnoldi HBM GB/s; mixed vs FP64 GMRES"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel (FP64 first Gram-Schmidt sweep of the
+# two-sweep variant, steps j = 1..49 of GMRES(50)) from FETCH_SIZE and
+# WRITE_SIZE counter runs of `bench.py --pmc-sample`, each scaled by what the
+# same counter reads for a 512 MiB device copy (FETCH_SIZE reads 262,162 KiB
+# for the 524,288 KiB read: x2.0; WRITE_SIZE reads 524,288 KiB: x1.0).
+# Valid only while the kernel sources hash to `sources_sha256`.
+TRAFFIC = {
+    "kind": "pass1_lag",
+    "sources_sha256": None,
+    "bytes_per_launch": None,
+}
+KERNEL_SOURCES = ("paper_1906_04051_amd/csrc/krylov.hip", "paper_1906_04051_amd/csrc/common.hpp",
+                  "paper_1906_04051_amd/csrc/internal.hpp")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -68,8 +91,8 @@ def pmc_sample(sysm, d, m, tuned):
     torch.cuda.synchronize()
     per = {k: dict(launches=int(v["launches"]), bytes_per_launch=v["bytes"] / max(v["launches"], 1),
                    avg_us=1000 * v["ms"] / max(v["launches"], 1)) for k, v in kt.items()}
-    print(json.dumps({"pmc_sample": per, "iters": info["iters"], "copy_bytes_each_way": 512 << 20}),
-          flush=True)
+    print(json.dumps({"pmc_sample": per, "iters": info["iters"], "copy_bytes_each_way": 512 << 20,
+                      "kernel_sources_sha256": kernel_sources_sha256()}), flush=True)
 
 
 def main():
@@ -82,6 +105,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--mixed-basis", choices=["f16", "f32"], default="f16",
+                    help="storage of the Krylov basis in the inner FP32 solves")
+    ap.add_argument("--inner-rtol", type=float, default=None,
+                    help="tolerance of each inner solve (default 1e-3 for f16, 1e-5 for f32)")
+    ap.add_argument("--ortho", type=int, default=1, choices=[0, 1],
+                    help="0: CGS2 in three sweeps; 1: CGS2 in two sweeps (lagged normalisation)")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short fixed-count FP64 run (two restart cycles) plus a copy of known "
                          "size, for hardware-counter collection")
@@ -101,15 +130,16 @@ def main():
     log(f"[bench] generating config 2 at mesh {args.mesh}")
     sysm = W.make_config(2, mesh=args.mesh)
     d = G.upload(sysm)
-    common = dict(m=m, rtol=1e-8, max_iters=200000)
+    common = dict(m=m, rtol=1e-8, max_iters=200000, ortho=args.ortho)
+    inner = args.inner_rtol if args.inner_rtol else (1e-3 if args.mixed_basis == "f16" else 1e-5)
     plans = {}
     if args.only in ("both", "fp64"):
         plans["fp64"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
                                d["z_vals"], r=sysm.r, precision="fp64", **common)
     if args.only in ("both", "mixed"):
         plans["mixed"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
-                                d["z_vals"], r=sysm.r, precision="mixed_f16", inner_rtol=1e-3,
-                                inner_max_iters=100000, max_refine=40, **common)
+                                d["z_vals"], r=sysm.r, precision="mixed_" + args.mixed_basis,
+                                inner_rtol=inner, inner_max_iters=100000, max_refine=40, **common)
     tuned = {}
     for k, p in plans.items():
         tuned[k] = p.autotune()
@@ -170,11 +200,12 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f32/f16+f64" if headline == "mixed" else "f64",
+        "dtype": (f"f32/{args.mixed_basis}+f64" if headline == "mixed" else "f64"),
         "data": "synthetic",
         "config": {"workload": f"q1_convection_diffusion_{args.mesh}x{args.mesh}_lognormal",
                    "unknowns": sysm.n, "nnz": sysm.nnz, "restart_m": m, "deflation_vectors": sysm.r,
-                   "rtol": 1e-8, "step": "+".join(plans)},
+                   "rtol": 1e-8, "step": "+".join(plans), "ortho": args.ortho,
+                   "mixed_basis": args.mixed_basis, "inner_rtol": inner},
     }
     for k in plans:
         out[f"time_to_rtol_{k}_s"] = med[k]
@@ -196,8 +227,13 @@ def main():
         dom = max(cand, key=lambda kk: cand[kk]["ms"])
         v = cand[dom]
         achieved = v["bytes"] / (v["ms"] * 1e6)
+        traffic = None
+        if (src == "fp64" and dom == TRAFFIC["kind"] and TRAFFIC["bytes_per_launch"]
+                and TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
+            traffic = TRAFFIC["bytes_per_launch"]
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "traffic_unit": "bytes/launch",
                            "kernel": f"{src}.{dom}", "launches": int(v["launches"]),
                            "avg_launch_us": 1000 * v["ms"] / v["launches"],
                            "bytes_per_launch_avg": v["bytes"] / v["launches"]}

@@ -174,11 +174,15 @@ int64_t gmres_history(gmres_plan p, double* hist_h, int64_t cap);
  * spmv_lanes, num_blocks, batch_wg, batch_lanes; may be NULL). */
 gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h);
 
-/* Per-kernel timing of the last solve made with timing enabled
- * (gmres_set_timing): for kernel class k (0 spmv, 1 pass1, 2 pass2, 3 pass3)
- * writes {launches, total_ms, total_algorithmic_bytes} to out_h[3*k ..]. */
+/* Per-kernel timing of the last solve (or adjoint) made with timing enabled
+ * (gmres_set_timing; timed solves run without graphs).  Each timed kernel carries a pair of HIP events in its own
+ * dispatch, so the times are kernel execution times.  For kernel class k
+ * (0 SpMV, 1 first Gram-Schmidt sweep, 2 second sweep, 3 third sweep of the
+ * three-sweep variant, 4 first sweep of the two-sweep variant at steps j > 0)
+ * writes {launches, total_ms, total_algorithmic_bytes} to out_h[3*k ..];
+ * launches that found their cycle already ended are not counted. */
 gmres_status gmres_set_timing(gmres_plan p, int32_t enable);
-gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 12 doubles */);
+gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 15 doubles */);
 
 /* Switches the stream used by later calls. */
 gmres_status gmres_set_stream(gmres_plan p, hipStream_t stream);

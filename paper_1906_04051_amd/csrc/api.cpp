@@ -45,9 +45,12 @@ struct Timer {
     struct Rec { int kind; int cycle; int j; double bytes; int ev; };
     std::vector<Rec> recs;
     int used = 0;
-    double launches[4] = {0, 0, 0, 0};
-    double ms[4] = {0, 0, 0, 0};
-    double bytes[4] = {0, 0, 0, 0};
+    // Kernel classes: 0 SpMV, 1 first sweep, 2 second sweep, 3 third sweep
+    // (three-sweep CGS2), 4 first sweep of the two-sweep variant at j > 0.
+    static constexpr int kKinds = 5;
+    double launches[kKinds] = {};
+    double ms[kKinds] = {};
+    double bytes[kKinds] = {};
 
     hipEvent_t ev(int i) {
         while ((int)pool.size() <= i) {
@@ -63,7 +66,7 @@ struct Timer {
     void reset() {
         recs.clear();
         used = 0;
-        for (int k = 0; k < 4; ++k) launches[k] = ms[k] = bytes[k] = 0;
+        for (int k = 0; k < kKinds; ++k) launches[k] = ms[k] = bytes[k] = 0;
     }
 };
 
@@ -492,16 +495,20 @@ struct TimerHook final : KTimer {
             default: return bv * n * nv + bw * n + bv * n;
         }
     }
+    // The events go into the dispatch of the next kernel (its own start and
+    // end timestamps), not around it as markers on the stream.
     void begin(int kind, int j) override {
         Timer& t = p->timer;
         const int e0 = t.used++;
         t.used++;
-        hipEventRecord(t.ev(e0), p->st);
-        t.recs.push_back({kind, cycle, j, kernel_bytes(kind, j), e0});
+        arm_kernel_events(t.ev(e0), t.ev(e0 + 1));
+        const int cls = (lagged && kind == 1 && j > 0) ? 4 : kind;
+        t.recs.push_back({cls, cycle, j, kernel_bytes(kind, j), e0});
     }
     void end(int, int) override {
-        Timer& t = p->timer;
-        hipEventRecord(t.ev(t.recs.back().ev + 1), p->st);
+        // A timed launch that did not go through the event-carrying path
+        // leaves its record unusable.
+        if (disarm_kernel_events()) p->timer.recs.back().cycle = -1;
     }
 };
 
@@ -514,7 +521,7 @@ void collect_timer(gmres_plan_s* p, int64_t ncycles_dev) {
     const int64_t nk = std::min<int64_t>(ncycles_dev, p->cyc_cap);
     if (nk > 0) hipMemcpy(ks.data(), p->cyc_k, nk * sizeof(int), hipMemcpyDeviceToHost);
     for (const auto& r : t.recs) {
-        if (r.cycle >= nk || r.j >= ks[r.cycle]) continue;
+        if (r.cycle < 0 || r.cycle >= nk || r.j >= ks[r.cycle]) continue;
         float ms = 0.f;
         hipEventElapsedTime(&ms, t.pool[r.ev], t.pool[r.ev + 1]);
         t.launches[r.kind] += 1;
@@ -1211,8 +1218,10 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
             EngineArgs a = make_args(p, 0, tprec);
             const double t = time_it([&] {
                 spmv_f64(p, p->L, nb, (double*)p->V, p->y);
+                launch_pass_probe(a, 1, nv);
                 launch_pass_probe(a, 2, nv);
-            }, 10);
+                launch_pass_probe(a, 3, nv);
+            }, 6);
             p->NB = saved;
             if (t < bestt) { bestt = t; bestNB = nb; }
         }
@@ -1263,7 +1272,7 @@ gmres_status gmres_set_timing(gmres_plan p, int32_t enable) {
 
 gmres_status gmres_kernel_times(gmres_plan p, double* out_h) {
     if (!p || !out_h) return fail(GMRES_EINVAL, "plan and out_h are required");
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < Timer::kKinds; ++k) {
         out_h[3 * k + 0] = p->timer.launches[k];
         out_h[3 * k + 1] = p->timer.ms[k];
         out_h[3 * k + 2] = p->timer.bytes[k];

@@ -30,17 +30,34 @@ __device__ __forceinline__ double bsum(double v, double* red) {
     return s;
 }
 
-// Reduce acc[0..nv) and accn over the workgroup into out[0..nv], out[nv] = norm.
-template <int WGS, int MB>
-__device__ __forceinline__ void bsum_multi(const double (&acc)[MB], double accn, int nv,
-                                           double (*red)[MB + 1], double* out) {
-    constexpr int NW = WGS / kWave;
-    const int w = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
+// Lane layout of the passes: T consecutive lanes share one row; lane `sub`
+// owns basis columns k = sub, sub + T, ... (JT = MB / T of them), so each lane
+// keeps JT basis values and dot accumulators in registers.
+template <int T>
+__device__ __forceinline__ double gsum(double v) {
 #pragma unroll
-    for (int k = 0; k < MB; ++k)
-        if (k < nv) {
-            const double t = wave_sum(acc[k]);
-            if (ln == 0) red[w][k] = t;
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Workgroup sums of acc[q] (column sub + q*T) into out[k] for k < nv and of
+// accn into out[nv].  Fixed order: butterfly over lanes of equal `sub`, then
+// waves in order.
+template <int WGS, int MB, int T>
+__device__ __forceinline__ void bsum_cols(const double (&acc)[MB / T], double accn, int nv,
+                                          double (*red)[MB + 1], double* out) {
+    constexpr int NW = WGS / kWave;
+    constexpr int JT = MB / T;
+    const int w = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
+    const int sub = ln & (T - 1);
+#pragma unroll
+    for (int q = 0; q < JT; ++q)
+        if (q * T < nv) {
+            double t = acc[q];
+#pragma unroll
+            for (int o = kWave / 2; o >= T; o >>= 1) t += __shfl_xor(t, o, kWave);
+            const int k = sub + q * T;
+            if (ln < T && k < nv) red[w][k] = t;
         }
     {
         const double t = wave_sum(accn);
@@ -61,6 +78,9 @@ template <int WGS, int L, int MB>
 __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
     constexpr int NW = WGS / kWave;
     constexpr int kRows = WGS / L;
+    constexpr int T = MB / 8;            // lanes per row in the passes (8 columns per lane)
+    constexpr int JT = MB / T;
+    constexpr int PR = WGS / T;          // rows per pass iteration
     __shared__ double red[NW][MB + 1];
     __shared__ double sred[NW];
     __shared__ double Hs[(MB + 1) * MB];
@@ -190,19 +210,26 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 __syncthreads();
                 coarse(y);
                 // pass 1: w = P y; dots with stored basis; ||w||^2
-                double acc[MB];
+                const int sub = threadIdx.x & (T - 1);
+                double acc[JT];
 #pragma unroll
-                for (int k = 0; k < MB; ++k) acc[k] = 0;
+                for (int q = 0; q < JT; ++q) acc[q] = 0;
                 accn = 0;
-                for (int i = threadIdx.x; i < n; i += WGS) {
-                    const double wi = (R > 0) ? deflate_row(r0 + i, y[i]) : y[i];
-                    w[i] = wi;
+                for (int i = threadIdx.x / T; i < n; i += PR) {
+                    double vv[JT];
 #pragma unroll
-                    for (int k = 0; k < MB; ++k)
-                        if (k < nv) acc[k] += V[(int64_t)k * ldv + i] * wi;
-                    accn += wi * wi;
+                    for (int q = 0; q < JT; ++q)
+                        if (sub + q * T < nv) vv[q] = V[(int64_t)(sub + q * T) * ldv + i];
+                    const double wi = (R > 0) ? deflate_row(r0 + i, y[i]) : y[i];
+                    if (sub == 0) {
+                        w[i] = wi;
+                        accn += wi * wi;
+                    }
+#pragma unroll
+                    for (int q = 0; q < JT; ++q)
+                        if (sub + q * T < nv) acc[q] += vv[q] * wi;
                 }
-                bsum_multi<WGS, MB>(acc, accn, nv, red, h1);
+                bsum_cols<WGS, MB, T>(acc, accn, nv, red, h1);
                 const double wpre2 = h1[nv];
                 for (int k = threadIdx.x; k < nv; k += WGS) {
                     h1[k] *= vscale[k];
@@ -211,24 +238,27 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 __syncthreads();
                 // pass 2
 #pragma unroll
-                for (int k = 0; k < MB; ++k) acc[k] = 0;
+                for (int q = 0; q < JT; ++q) acc[q] = 0;
                 accn = 0;
-                for (int i = threadIdx.x; i < n; i += WGS) {
-                    double vv[MB];
+                for (int i = threadIdx.x / T; i < n; i += PR) {
+                    double vv[JT];
 #pragma unroll
-                    for (int k = 0; k < MB; ++k)
-                        if (k < nv) vv[k] = V[(int64_t)k * ldv + i];
-                    double wi = w[i];
+                    for (int q = 0; q < JT; ++q)
+                        if (sub + q * T < nv) vv[q] = V[(int64_t)(sub + q * T) * ldv + i];
+                    double u = 0;
 #pragma unroll
-                    for (int k = 0; k < MB; ++k)
-                        if (k < nv) wi -= vv[k] * coef[k];
-                    w[i] = wi;
+                    for (int q = 0; q < JT; ++q)
+                        if (sub + q * T < nv) u += vv[q] * coef[sub + q * T];
+                    const double wi = w[i] - gsum<T>(u);
+                    if (sub == 0) {
+                        w[i] = wi;
+                        accn += wi * wi;
+                    }
 #pragma unroll
-                    for (int k = 0; k < MB; ++k)
-                        if (k < nv) acc[k] += vv[k] * wi;
-                    accn += wi * wi;
+                    for (int q = 0; q < JT; ++q)
+                        if (sub + q * T < nv) acc[q] += vv[q] * wi;
                 }
-                bsum_multi<WGS, MB>(acc, accn, nv, red, h2);
+                bsum_cols<WGS, MB, T>(acc, accn, nv, red, h2);
                 for (int k = threadIdx.x; k < nv; k += WGS) {
                     h2[k] *= vscale[k];
                     coef[k] = h2[k] * vscale[k];
@@ -237,13 +267,16 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 // pass 3: new basis column
                 double* vout = V + (int64_t)nv * ldv;
                 accn = 0;
-                for (int i = threadIdx.x; i < n; i += WGS) {
-                    double wi = w[i];
+                for (int i = threadIdx.x / T; i < n; i += PR) {
+                    double u = 0;
 #pragma unroll
-                    for (int k = 0; k < MB; ++k)
-                        if (k < nv) wi -= V[(int64_t)k * ldv + i] * coef[k];
-                    vout[i] = wi;
-                    accn += wi * wi;
+                    for (int q = 0; q < JT; ++q)
+                        if (sub + q * T < nv) u += V[(int64_t)(sub + q * T) * ldv + i] * coef[sub + q * T];
+                    const double wi = w[i] - gsum<T>(u);
+                    if (sub == 0) {
+                        vout[i] = wi;
+                        accn += wi * wi;
+                    }
                 }
                 const double hn = sqrt(bsum<WGS>(accn, sred));
                 if (threadIdx.x == 0) {

@@ -93,6 +93,11 @@ struct EngineArgs {
 };
 
 // krylov.hip
+// Timing events for the next timed launch of the engine on this thread
+// (start / end of that kernel's execution); disarm returns true when the
+// armed pair was not consumed by a launch.
+void arm_kernel_events(hipEvent_t start, hipEvent_t stop);
+bool disarm_kernel_events();
 void launch_restart_init(const EngineArgs& a, const void* b, double rtol, double r0_override);
 void launch_cycle(const EngineArgs& a, const void* b);
 void launch_correct(hipStream_t st, int NB, int n, const int* zrp, const int* zci, const double* zv,

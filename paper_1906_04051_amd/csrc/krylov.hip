@@ -17,6 +17,8 @@
 // Every kernel reads the device control block first and returns at once when
 // the solve (gate 1) or the current cycle (gate 2) has ended, so the host can
 // enqueue a whole cycle without waiting.
+#include <hip/hip_ext.h>
+
 #include "internal.hpp"
 
 namespace gm {
@@ -29,6 +31,42 @@ __device__ __forceinline__ bool gated(const Ctrl* c, int gate) {
 constexpr int kCT = 1024;   // threads of the coarse-solve kernels
 __device__ void coarse_matvec(int R, const double* __restrict__ Einv, int trans, const double* t,
                               double* __restrict__ s, double* red);
+
+// Deflation partials of one row block (fused Z^T y epilogue): for each of the
+// block's slots l (deflation column bb_col[l]), the sum over the block's rows
+// of z * y restricted to that column.  Wave sums per slot, one barrier, then
+// the waves' sums in order; written to tpart[slot_pos[l]].
+template <int NT, typename ACC>
+__device__ __forceinline__ void block_slots(int l0, int l1, const int* __restrict__ bb_col,
+                                            const int* __restrict__ slot_pos, int zc, ACC zvv,
+                                            ACC yi, bool valid, int64_t row,
+                                            const int* __restrict__ zrp, const int* __restrict__ zci,
+                                            const double* __restrict__ zv, double* __restrict__ tpart,
+                                            double (*sred)[kBlockColsMax]) {
+    const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
+    for (int l = l0; l < l1; ++l) {
+        const int col = bb_col[l];
+        ACC c = 0;
+        if (valid) {
+            if (zc >= 0) {
+                if (zc == col) c = zvv * yi;
+            } else if (zc == -2) {
+                for (int q = zrp[row]; q < zrp[row + 1]; ++q)
+                    if (zci[q] == col) c += (ACC)zv[q] * yi;
+            }
+        }
+        c = wave_sum(c);
+        if (ln == 0) sred[wv][l - l0] = (double)c;
+    }
+    __syncthreads();
+    for (int l = l0 + threadIdx.x; l < l1; l += NT) {
+        double t = sred[0][l - l0];
+#pragma unroll
+        for (int q = 1; q < NT / kWave; ++q) t += sred[q][l - l0];
+        tpart[slot_pos[l]] = t;
+    }
+    __syncthreads();
+}
 
 // ------------------------------------------------------------------- SpMV
 // y = scale * A x, L lanes per row (row-per-group; L = 64 is row-per-wavefront).
@@ -84,6 +122,7 @@ __global__ __launch_bounds__(RB) void k_spmv_stream(int n, const int* __restrict
     __shared__ AT sv[CAP];
     __shared__ int sc[CAP];
     __shared__ ACC red[RB / kWave];
+    __shared__ double sred[ZT ? RB / kWave : 1][kBlockColsMax];
     const ACC scale = (MODE == 0 && scale_ptr) ? (ACC)(*scale_ptr) : (ACC)1;
     ACC nrm = 0;
     for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
@@ -127,21 +166,8 @@ __global__ __launch_bounds__(RB) void k_spmv_stream(int n, const int* __restrict
         }
         if (ZT) {
             const int64_t blk = r0 / RB;
-            const int l1 = bb_ptr[blk + 1];
-            for (int l = bb_ptr[blk]; l < l1; ++l) {
-                const int col = bb_col[l];
-                ACC c = 0;
-                if (row < rend) {
-                    if (zc >= 0) {
-                        if (zc == col) c = zvv * yi;
-                    } else if (zc == -2) {
-                        for (int q = zrp[row]; q < zrp[row + 1]; ++q)
-                            if (zci[q] == col) c += (ACC)zv[q] * yi;
-                    }
-                }
-                c = block_sum_n<RB>(c, red);
-                if (threadIdx.x == 0) tpart[slot_pos[l]] = (double)c;
-            }
+            block_slots<RB, ACC>(bb_ptr[blk], bb_ptr[blk + 1], bb_col, slot_pos, zc, zvv, yi,
+                                 row < rend, row, zrp, zci, zv, tpart, sred);
         }
     }
     if (MODE == 1) {
@@ -173,6 +199,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
                                                    int gate) {
     if (gated(ctrl, gate)) return;
     __shared__ ACC red[kWG / kWave];
+    __shared__ double sred[ZT ? kWG / kWave : 1][kBlockColsMax];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const ACC scale = (MODE == 0 && scale_ptr) ? (ACC)(*scale_ptr) : (ACC)1;
@@ -229,21 +256,8 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
         }
         if (ZT) {
             const int64_t blk = r0 / kWG;
-            const int l1 = bb_ptr[blk + 1];
-            for (int l = bb_ptr[blk]; l < l1; ++l) {
-                const int col = bb_col[l];
-                ACC c = 0;
-                if (row < n) {
-                    if (zc >= 0) {
-                        if (zc == col) c = zvv * yi;
-                    } else if (zc == -2) {
-                        for (int q = zrp[row]; q < zrp[row + 1]; ++q)
-                            if (zci[q] == col) c += (ACC)zv[q] * yi;
-                    }
-                }
-                c = block_sum_n<kWG>(c, red);
-                if (threadIdx.x == 0) tpart[slot_pos[l]] = (double)c;
-            }
+            block_slots<kWG, ACC>(bb_ptr[blk], bb_ptr[blk + 1], bb_col, slot_pos, zc, zvv, yi,
+                                  row < n, row, zrp, zci, zv, tpart, sred);
         }
     }
     if (MODE == 1) {
@@ -847,8 +861,10 @@ __global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ part,
 // ends: |g_{j+1}| <= rtol*rho0 (eq. res), lucky breakdown
 // (h_{j+1,j} <= eps * ||P A v_j||) or the iteration cap.  The column and the
 // rotations are staged in LDS; one lane runs the rotation chain.
+constexpr int kGT = 256;   // threads of the Givens kernel
+
 template <bool LAG>
-__global__ __launch_bounds__(kWave) void k_givens(int j, int m, const double* __restrict__ part,
+__global__ __launch_bounds__(kGT) void k_givens(int j, int m, const double* __restrict__ part,
                                                   int NB, int nslot, const double* __restrict__ h1,
                                                   const double* __restrict__ h2,
                                                   double* __restrict__ H, double* __restrict__ cs,
@@ -860,40 +876,42 @@ __global__ __launch_bounds__(kWave) void k_givens(int j, int m, const double* __
                                                   double* __restrict__ lag, Ctrl* ctrl, int gate) {
     if (gated(ctrl, gate)) return;
     __shared__ double col[kMaxM + 1], cl[kMaxM], sl[kMaxM], h2l[kMaxM + 1];
+    __shared__ double red[kGT / kWave];
+    __shared__ double hb[LAG ? (kMaxM + 1) * kMaxM : 1];   // Hbar band, rows 0..j, cols 0..j-1
     double acc = 0;
-    for (int q = threadIdx.x; q < NB; q += kWave) acc += part[(int64_t)nslot * NB + q];
-    acc = wave_sum(acc);
+    for (int q = threadIdx.x; q < NB; q += kGT) acc += part[(int64_t)nslot * NB + q];
+    acc = block_sum_n<kGT>(acc, red);
     if (LAG) {
+        for (int i = threadIdx.x; i <= j; i += kGT) h2l[i] = h2[i];
+        __syncthreads();
         // acc = ||w1||^2; ||w2||^2 = ||w1||^2 - ||h2||^2 (h2 against orthonormal v's).
         double q2 = 0;
-        for (int i = threadIdx.x; i <= j; i += kWave) {
-            const double v = h2[i];
-            h2l[i] = v;
-            q2 += v * v;
-        }
-        q2 = wave_sum(q2);
+        for (int i = threadIdx.x; i <= j; i += kGT) q2 += h2l[i] * h2l[i];
+        q2 = block_sum_n<kGT>(q2, red);
         acc = fmax(acc - q2, 0.0);
+        for (int q = threadIdx.x; q < (j + 1) * j; q += kGT) {
+            const int l = q / j, k = q % j;
+            hb[q] = (k >= l - 1) ? Hraw[(int64_t)l * m + k] : 0.0;
+        }
     }
-    for (int i = threadIdx.x; i <= j; i += kWave) col[i] = h1[i] + h2[i];
-    for (int i = threadIdx.x; i < j; i += kWave) {
+    for (int i = threadIdx.x; i <= j; i += kGT) col[i] = h1[i] + (LAG ? h2l[i] : h2[i]);
+    for (int i = threadIdx.x; i < j; i += kGT) {
         cl[i] = cs[i];
         sl[i] = sn[i];
     }
     __syncthreads();
     const double hn = sqrt(acc);
     if (Hraw) {
-        for (int i = threadIdx.x; i <= j; i += kWave) Hraw[(int64_t)i * m + j] = col[i];
+        for (int i = threadIdx.x; i <= j; i += kGT) Hraw[(int64_t)i * m + j] = col[i];
         if (threadIdx.x == 0) Hraw[(int64_t)(j + 1) * m + j] = hn;
     }
     if (LAG) {
-        // Coefficients of the next lagged step: c_l = sum_k Hbar[l][k] h2_k
-        // (rows l <= j, columns k = max(l-1, 0) .. j of the unrotated Hbar),
-        // times vscale[l]; column j of Hbar is col[] / hn (not yet in Hraw for
-        // every lane, so use the staged values).
-        __syncthreads();
-        for (int l = threadIdx.x; l <= j; l += kWave) {
+        // Coefficients of the next lagged step: c_l = sum_k Hbar[l][k] h2_k over
+        // the unrotated Hbar (rows l <= j, columns 0..j; column j is col[]),
+        // times vscale[l].
+        for (int l = threadIdx.x; l <= j; l += kGT) {
             double v = 0;
-            for (int k = (l > 0 ? l - 1 : 0); k < j; ++k) v += Hraw[(int64_t)l * m + k] * h2l[k];
+            for (int k = (l > 0 ? l - 1 : 0); k < j; ++k) v += hb[l * j + k] * h2l[k];
             v += col[l] * h2l[j];
             cc[l] = v * vscale[l];
         }
@@ -1136,27 +1154,57 @@ __global__ __launch_bounds__(kWG) void k_copy_f64(const double* __restrict__ a, 
 // ====================================================================== host
 // Launch helpers used by the solve engine.  All launches go to `st`.
 
+// Per-kernel timing: arm_kernel_events() hands a pair of timing events to the
+// next kernel enqueued through launch() on this thread; that launch records
+// the kernel's own start and end timestamps in them (hipExtLaunchKernel), so
+// the elapsed time covers the kernel alone, as a kernel trace reports it.
+static thread_local hipEvent_t t_ev_start = nullptr;
+static thread_local hipEvent_t t_ev_stop = nullptr;
+
+void arm_kernel_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+bool disarm_kernel_events() {
+    const bool pending = t_ev_start != nullptr;
+    t_ev_start = t_ev_stop = nullptr;
+    return pending;
+}
+
+template <typename... KA, typename... A>
+static inline void launch(void (*k)(KA...), dim3 g, dim3 b, uint32_t sh, hipStream_t st,
+                          A... args) {
+    if (t_ev_start) {
+        hipEvent_t e0 = t_ev_start, e1 = t_ev_stop;
+        t_ev_start = t_ev_stop = nullptr;
+        hipExtLaunchKernelGGL(k, g, b, sh, st, e0, e1, 0u, static_cast<KA>(args)...);
+    } else {
+        k<<<g, b, sh, st>>>(static_cast<KA>(args)...);
+    }
+}
+
 template <typename AT, typename XT, typename YT, typename ACC>
 static void spmv_dispatch(int L, int NB, hipStream_t st, int n, const int* rp, const int* ci,
                           const AT* v, const XT* x, const double* scale, YT* y, const Ctrl* c,
                           int gate) {
     dim3 g(NB), b(kWG);
     if (L == -256) {
-        k_spmv_stream<256, 0, false, AT, XT, double, YT, ACC><<<g, 256, 0, st>>>(n, rp, ci, v, x, scale, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
+        launch(k_spmv_stream<256, 0, false, AT, XT, double, YT, ACC>, g, 256, 0, st, n, rp, ci, v, x, scale, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
         return;
     }
     if (L <= 0) {
-        k_spmv_stream<128, 0, false, AT, XT, double, YT, ACC><<<g, 128, 0, st>>>(n, rp, ci, v, x, scale, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
+        launch(k_spmv_stream<128, 0, false, AT, XT, double, YT, ACC>, g, 128, 0, st, n, rp, ci, v, x, scale, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, gate);
         return;
     }
     switch (L) {
-        case 1: k_spmv<1, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
-        case 2: k_spmv<2, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
-        case 4: k_spmv<4, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
-        case 8: k_spmv<8, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
-        case 16: k_spmv<16, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
-        case 32: k_spmv<32, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
-        default: k_spmv<64, AT, XT, YT, ACC><<<g, b, 0, st>>>(n, rp, ci, v, x, scale, y, c, gate); break;
+        case 1: launch(k_spmv<1, AT, XT, YT, ACC>, g, b, 0, st, n, rp, ci, v, x, scale, y, c, gate); break;
+        case 2: launch(k_spmv<2, AT, XT, YT, ACC>, g, b, 0, st, n, rp, ci, v, x, scale, y, c, gate); break;
+        case 4: launch(k_spmv<4, AT, XT, YT, ACC>, g, b, 0, st, n, rp, ci, v, x, scale, y, c, gate); break;
+        case 8: launch(k_spmv<8, AT, XT, YT, ACC>, g, b, 0, st, n, rp, ci, v, x, scale, y, c, gate); break;
+        case 16: launch(k_spmv<16, AT, XT, YT, ACC>, g, b, 0, st, n, rp, ci, v, x, scale, y, c, gate); break;
+        case 32: launch(k_spmv<32, AT, XT, YT, ACC>, g, b, 0, st, n, rp, ci, v, x, scale, y, c, gate); break;
+        default: launch(k_spmv<64, AT, XT, YT, ACC>, g, b, 0, st, n, rp, ci, v, x, scale, y, c, gate); break;
     }
 }
 
@@ -1189,11 +1237,11 @@ template <int MODE, typename AT, typename XT, typename BT, typename YT, typename
 static void stream_fused(const EngineArgs& e, const AT* vals, const XT* x, const double* scale,
                          const BT* b, YT* y, int slot, int gate) {
     if (e.fuse_rb == 256)
-        k_spmv_stream<256, MODE, true, AT, XT, BT, YT, ACC><<<e.NB, 256, 0, e.st>>>(
+        launch(k_spmv_stream<256, MODE, true, AT, XT, BT, YT, ACC>, e.NB, 256, 0, e.st, 
             e.n, e.rowptr, e.colind, vals, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
             e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
     else
-        k_spmv_stream<128, MODE, true, AT, XT, BT, YT, ACC><<<e.NB, 128, 0, e.st>>>(
+        launch(k_spmv_stream<128, MODE, true, AT, XT, BT, YT, ACC>, e.NB, 128, 0, e.st, 
             e.n, e.rowptr, e.colind, vals, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
             e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
 }
@@ -1206,11 +1254,11 @@ static void sell_launch_w(const EngineArgs& e, const XT* x, const double* scale,
     // writes one norm partial per block, so it keeps the NB-block grid.
     const int grid = MODE == 0 ? (int)std::max<int64_t>(1, ((int64_t)e.n + kWG - 1) / kWG) : e.NB;
     if (e.R > 0 && e.fuse_rb == 256)
-        k_spmv_sell<MODE, true, WMAX, AT, XT, BT, YT, ACC><<<grid, kWG, 0, e.st>>>(
+        launch(k_spmv_sell<MODE, true, WMAX, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st, 
             e.n, e.sell_off, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
             e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
     else
-        k_spmv_sell<MODE, false, WMAX, AT, XT, BT, YT, ACC><<<grid, kWG, 0, e.st>>>(
+        launch(k_spmv_sell<MODE, false, WMAX, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st, 
             e.n, e.sell_off, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, nullptr, nullptr,
             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, e.ctrl, gate);
 }
@@ -1233,19 +1281,21 @@ static int jmax_for(int nv) {
 
 // Lanes per tile of the pass kernels: at most 16 basis tiles (64 VGPRs) per
 // lane, so no instantiation spills.
-template <int J, typename ACC>
+template <int J, typename VT>
 struct LanesFor {
-    static constexpr int value = J <= 16 ? 1 : (J <= 32 ? 2 : (J <= 64 ? 4 : 8));
+    static constexpr int base = J <= 16 ? 1 : (J <= 32 ? 2 : (J <= 64 ? 4 : 8));
+    // A 16-byte FP16 tile holds 8 rows: halve the columns per lane.
+    static constexpr int value = sizeof(VT) == 2 ? 2 * base : base;
 };
 
-#define GM_JMAX_SWITCH(nv, ACCT, CALL)                                                         \
+#define GM_JMAX_SWITCH(nv, VTT, CALL)                                                         \
     switch (jmax_for(nv)) {                                                                    \
-        case 8: { constexpr int J = 8; constexpr int T = LanesFor<J, ACCT>::value; CALL; } break;   \
-        case 16: { constexpr int J = 16; constexpr int T = LanesFor<J, ACCT>::value; CALL; } break; \
-        case 32: { constexpr int J = 32; constexpr int T = LanesFor<J, ACCT>::value; CALL; } break; \
-        case 48: { constexpr int J = 48; constexpr int T = LanesFor<J, ACCT>::value; CALL; } break; \
-        case 64: { constexpr int J = 64; constexpr int T = LanesFor<J, ACCT>::value; CALL; } break; \
-        default: { constexpr int J = 96; constexpr int T = LanesFor<J, ACCT>::value; CALL; } break; \
+        case 8: { constexpr int J = 8; constexpr int T = LanesFor<J, VTT>::value; CALL; } break;   \
+        case 16: { constexpr int J = 16; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
+        case 32: { constexpr int J = 32; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
+        case 48: { constexpr int J = 48; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
+        case 64: { constexpr int J = 64; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
+        default: { constexpr int J = 96; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
     }
 
 // ---------------------------------------------------------------- engine
@@ -1325,24 +1375,24 @@ struct Engine {
         if (fused()) coarse_slots(e.s_step, 2);
         else coarse(y(), e.s_step, 2);
         if (e.timer) e.timer->begin(1, j);
-        GM_JMAX_SWITCH(nv, ACC, (k_pass1<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
+        GM_JMAX_SWITCH(nv, VT, (launch(k_pass1<J, T, VT, WT, AT, ACC>, e.NB, kWG, 0, e.st, 
                                e.n, e.ldv, V(), nv, y(), e.azrp, e.azci, azv(), e.azc1, azv1(), e.s_step, e.R, w(),
                                e.part, e.nslot, e.NB, e.ctrl, 2)));
         if (e.timer) e.timer->end(1, j);
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
         if (e.timer) e.timer->begin(2, j);
-        GM_JMAX_SWITCH(nv, ACC, (k_pass2<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
+        GM_JMAX_SWITCH(nv, VT, (launch(k_pass2<J, T, VT, WT, ACC>, e.NB, kWG, 0, e.st, 
                                e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, e.NB, e.ctrl, 2)));
         if (e.timer) e.timer->end(2, j);
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
         if (e.timer) e.timer->begin(3, j);
-        GM_JMAX_SWITCH(nv, ACC, (k_pass3<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
+        GM_JMAX_SWITCH(nv, VT, (launch(k_pass3<J, T, VT, WT, ACC>, e.NB, kWG, 0, e.st, 
                                e.n, e.ldv, V(), nv, w(), e.coef2, e.sigma, e.part, e.nslot, e.NB,
                                e.ctrl, 2)));
         if (e.timer) e.timer->end(3, j);
-        k_givens<false><<<1, kWave, 0, e.st>>>(j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
+        launch(k_givens<false>, 1, kGT, 0, e.st, j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
                                                e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap,
                                                e.Hraw, nullptr, nullptr, e.ctrl, 2);
     }
@@ -1361,11 +1411,11 @@ struct Engine {
         else coarse(y(), e.s_step, 2);
         if (e.timer) e.timer->begin(1, j);
         if (j == 0) {
-            k_pass1<8, 1, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
+            launch(k_pass1<8, 1, VT, WT, AT, ACC>, e.NB, kWG, 0, e.st, 
                 e.n, e.ldv, V(), 1, y(), e.azrp, e.azci, azv(), e.azc1, azv1(), e.s_step, e.R, w(),
                 e.part, e.nslot, e.NB, e.ctrl, 2);
         } else {
-            GM_JMAX_SWITCH(j, ACC, (k_pass1_lag<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
+            GM_JMAX_SWITCH(j, VT, (launch(k_pass1_lag<J, T, VT, WT, AT, ACC>, e.NB, kWG, 0, e.st, 
                                       e.n, e.ldv, V(), j, w(), y(), e.azrp, e.azci, azv(), e.azc1,
                                       azv1(), e.s_step, e.R, e.coef2, e.cc, e.lag, e.part, e.nslot,
                                       e.NB, e.ctrl, 2)));
@@ -1374,12 +1424,12 @@ struct Engine {
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
         if (e.timer) e.timer->begin(2, j);
-        GM_JMAX_SWITCH(nv, ACC, (k_pass2<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
+        GM_JMAX_SWITCH(nv, VT, (launch(k_pass2<J, T, VT, WT, ACC>, e.NB, kWG, 0, e.st, 
                                     e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, e.NB, e.ctrl, 2)));
         if (e.timer) e.timer->end(2, j);
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
-        k_givens<true><<<1, kWave, 0, e.st>>>(j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
+        launch(k_givens<true>, 1, kGT, 0, e.st, j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
                                               e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap,
                                               e.Hraw, e.cc, e.lag, e.ctrl, 2);
     }
@@ -1433,15 +1483,15 @@ static void pass_probe(const EngineArgs& e, int kind, int nv) {
     WT* y = reinterpret_cast<WT*>(e.y);
     WT* w = reinterpret_cast<WT*>(e.w);
     if (kind == 1) {
-        GM_JMAX_SWITCH(nv, ACC, (k_pass1<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
+        GM_JMAX_SWITCH(nv, VT, (k_pass1<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
                                     e.n, e.ldv, V, nv, y, e.azrp, e.azci, (const AT*)e.azv, e.azc1,
                                     (const AT*)e.azv1, e.s_step, e.R, w, e.part, e.nslot, e.NB,
                                     nullptr, 0)));
     } else if (kind == 2) {
-        GM_JMAX_SWITCH(nv, ACC, (k_pass2<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
+        GM_JMAX_SWITCH(nv, VT, (k_pass2<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
                                     e.n, e.ldv, V, nv, w, e.coef1, e.part, e.nslot, e.NB, nullptr, 0)));
     } else {
-        GM_JMAX_SWITCH(nv, ACC, (k_pass3<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
+        GM_JMAX_SWITCH(nv, VT, (k_pass3<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
                                     e.n, e.ldv, (VT*)V, nv, w, e.coef2, e.sigma, e.part, e.nslot,
                                     e.NB, nullptr, 0)));
     }

@@ -246,9 +246,9 @@ class Plan:
         _check(self._lib.gmres_set_timing(self._h, int(bool(enable))))
 
     def kernel_times(self) -> dict:
-        out = (C.c_double * 12)()
+        out = (C.c_double * 15)()
         _check(self._lib.gmres_kernel_times(self._h, out))
-        names = ["spmv", "pass1", "pass2", "pass3"]
+        names = ["spmv", "pass1", "pass2", "pass3", "pass1_lag"]
         return {nm: dict(launches=out[3 * k], ms=out[3 * k + 1], bytes=out[3 * k + 2])
                 for k, nm in enumerate(names)}
 
