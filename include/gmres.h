@@ -174,14 +174,19 @@ int64_t gmres_history(gmres_plan p, double* hist_h, int64_t cap);
  * spmv_lanes, num_blocks, batch_wg, batch_lanes; may be NULL). */
 gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h);
 
-/* Per-kernel timing of the last solve (or adjoint) made with timing enabled
- * (gmres_set_timing; timed solves run without graphs).  Each timed kernel carries a pair of HIP events in its own
- * dispatch, so the times are kernel execution times.  For kernel class k
- * (0 SpMV, 1 first Gram-Schmidt sweep, 2 second sweep, 3 third sweep of the
- * three-sweep variant, 4 first sweep of the two-sweep variant at steps j > 0)
- * writes {launches, total_ms, total_algorithmic_bytes} to out_h[3*k ..];
- * launches that found their cycle already ended are not counted. */
-gmres_status gmres_set_timing(gmres_plan p, int32_t enable);
+/* Per-kernel timing.  gmres_set_timing(p, period): 0 = off (the default);
+ * period >= 1 = in later solves every period-th restart cycle (0, period,
+ * 2*period, ...) is enqueued kernel by kernel, each timed kernel carrying a
+ * pair of HIP events in its own dispatch (kernel execution time, as a kernel
+ * trace reports it); the other cycles run as usual (graph replay when
+ * use_graph).  EINVAL for period < 0.
+ * gmres_kernel_times: totals over the timed cycles of the last solve (or
+ * adjoint): for kernel class k (0 SpMV, 1 first Gram-Schmidt sweep, 2 second
+ * sweep, 3 third sweep of the three-sweep variant, 4 first sweep of the
+ * two-sweep variant at steps j > 0) writes {launches, total_ms,
+ * total_algorithmic_bytes} to out_h[3*k ..]; launches that found their cycle
+ * already ended are not counted. */
+gmres_status gmres_set_timing(gmres_plan p, int32_t period);
 gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 15 doubles */);
 
 /* Switches the stream used by later calls. */

@@ -40,7 +40,7 @@ gmres_status fail(gmres_status s, const std::string& msg) {
 
 // Algorithmic-byte accounting and HIP-event timing of the streaming kernels.
 struct Timer {
-    bool enabled = false;
+    int period = 0;          // 0: off; k: time one restart cycle in k
     std::vector<hipEvent_t> pool;
     struct Rec { int kind; int cycle; int j; double bytes; int ev; };
     std::vector<Rec> recs;
@@ -104,7 +104,8 @@ struct gmres_plan_s {
     int slots_rb = 0;
     int *bb_ptr = nullptr, *bb_col = nullptr, *ab_ptr = nullptr, *ab_slot = nullptr;
     int* slot_pos = nullptr;
-    // single-entry row copies: Z (n rows), A Z and A^T Z (ldv rows, padded)
+    // row copies: Z single-entry (ELL-1, n rows); A Z and A^T Z two-entry
+    // (ELL-2, 2 x ldv entries interleaved per row, padded)
     int* zc1 = nullptr;
     double* zv1 = nullptr;
     int *azc1 = nullptr, *atzc1 = nullptr;
@@ -235,8 +236,8 @@ gmres_status build_az(gmres_plan_s* p, const int* rp, const int* ci, const doubl
 // Single-entry (ELL-1) copies of A Z / A^T Z for the pass-1 deflation.
 void refresh_ell1(gmres_plan_s* p) {
     if (p->R == 0 || !p->azc1) return;
-    ell1_build(p->st, p->n, p->azrp, p->azci, p->azv, p->azc1, p->azv1, p->azv1f);
-    if (p->atzc1) ell1_build(p->st, p->n, p->atzrp, p->atzci, p->atzv, p->atzc1, p->atzv1, nullptr);
+    ell2_build(p->st, p->n, p->azrp, p->azci, p->azv, p->azc1, p->azv1, p->azv1f);
+    if (p->atzc1) ell2_build(p->st, p->n, p->atzrp, p->atzci, p->atzv, p->atzc1, p->atzv1, nullptr);
 }
 
 // (Re)computes everything derived from the values of A.
@@ -332,19 +333,20 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
     CHECK(ensure_slots(p));
     if (p->R > 0) {
         // Padded to ldv rows: padding reads as "no entry" (-1) with value 0.
-        CHECK(dalloc(p, &p->azc1, p->ldv));
-        CHECK(dalloc(p, &p->azv1, p->ldv));
-        HIP_OK(hipMemsetAsync(p->azc1, 0xFF, p->ldv * sizeof(int), p->st));
-        HIP_OK(hipMemsetAsync(p->azv1, 0, p->ldv * sizeof(double), p->st));
+        // Two entries per row (ELL-2).
+        CHECK(dalloc(p, &p->azc1, 2 * p->ldv));
+        CHECK(dalloc(p, &p->azv1, 2 * p->ldv));
+        HIP_OK(hipMemsetAsync(p->azc1, 0xFF, 2 * p->ldv * sizeof(int), p->st));
+        HIP_OK(hipMemsetAsync(p->azv1, 0, 2 * p->ldv * sizeof(double), p->st));
         if (p->o.precision != GMRES_FP64) {
-            CHECK(dalloc(p, &p->azv1f, p->ldv));
-            HIP_OK(hipMemsetAsync(p->azv1f, 0, p->ldv * sizeof(float), p->st));
+            CHECK(dalloc(p, &p->azv1f, 2 * p->ldv));
+            HIP_OK(hipMemsetAsync(p->azv1f, 0, 2 * p->ldv * sizeof(float), p->st));
         }
         if (p->need_adjoint) {
-            CHECK(dalloc(p, &p->atzc1, p->ldv));
-            CHECK(dalloc(p, &p->atzv1, p->ldv));
-            HIP_OK(hipMemsetAsync(p->atzc1, 0xFF, p->ldv * sizeof(int), p->st));
-            HIP_OK(hipMemsetAsync(p->atzv1, 0, p->ldv * sizeof(double), p->st));
+            CHECK(dalloc(p, &p->atzc1, 2 * p->ldv));
+            CHECK(dalloc(p, &p->atzv1, 2 * p->ldv));
+            HIP_OK(hipMemsetAsync(p->atzc1, 0xFF, 2 * p->ldv * sizeof(int), p->st));
+            HIP_OK(hipMemsetAsync(p->atzv1, 0, 2 * p->ldv * sizeof(double), p->st));
         }
         refresh_ell1(p);
     }
@@ -374,6 +376,8 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.nscale = std::sqrt((double)p->n);
     a.L = p->L;
     a.NB = p->NB;
+    a.nbcap = p->NB_cap;
+    a.pass_grid = 1;
     a.m = p->o.m;
     a.nslot = p->o.m + 1;
     a.ldv = p->ldv;
@@ -552,12 +556,15 @@ gmres_status ensure_graph(gmres_plan_s* p, int op, int prec, const void* b) {
 // block in *out.
 gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double rtol,
                         double r0_override, int64_t max_iters, Ctrl* out, bool trust_est = false) {
-    const bool timing = p->timer.enabled;
-    const bool graph = p->o.use_graph && !timing;
+    // Timed cycles (one in timer.period) are enqueued kernel by kernel with
+    // events in their timed dispatches; the others replay the cycle graph.
+    const int period = p->timer.period;
+    const bool graph = p->o.use_graph != 0;
     EngineArgs a = make_args(p, op, prec);
     a.trust_est = trust_est ? 1 : 0;
     TimerHook hook(p, prec, op);
-    if (timing) a.timer = &hook;
+    EngineArgs at = a;
+    at.timer = &hook;
     if (graph) CHECK(ensure_graph(p, op, prec, b));
     if (prec != p->last_prec) {
         CHECK(clear_typed(p));
@@ -566,10 +573,13 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
     launch_ctrl_reset(p->st, p->ctrl, max_iters);
     launch_restart_init(a, b, rtol, r0_override);
     auto enqueue = [&](int c) -> gmres_status {
-        if (graph) {
+        const bool timed = period > 0 && c % period == 0;
+        if (timed) {
+            hook.cycle = c;
+            launch_cycle(at, b);
+        } else if (graph) {
             HIP_OK(hipGraphLaunch(p->gexec[op][prec], p->st));
         } else {
-            hook.cycle = c;
             launch_cycle(a, b);
         }
         HIP_OK(hipMemcpyAsync(&p->ctrl_h[c & 1], p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, p->st));
@@ -589,7 +599,7 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
     }
     HIP_OK(hipStreamSynchronize(p->st));
     HIP_OK(hipMemcpy(out, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
-    if (timing) collect_timer(p, out->cycles);
+    if (period > 0) collect_timer(p, out->cycles);
     if (!finished) return fail(GMRES_EDEVICE, "solve loop did not terminate");
     return GMRES_OK;
 }
@@ -1263,9 +1273,10 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
     return GMRES_OK;
 }
 
-gmres_status gmres_set_timing(gmres_plan p, int32_t enable) {
+gmres_status gmres_set_timing(gmres_plan p, int32_t period) {
     if (!p) return fail(GMRES_EINVAL, "plan is NULL");
-    p->timer.enabled = enable != 0;
+    if (period < 0) return fail(GMRES_EINVAL, "timing period must be >= 0");
+    p->timer.period = period;
     p->timer.reset();
     return GMRES_OK;
 }

@@ -45,6 +45,8 @@ struct EngineArgs {
     double nscale;          // sqrt(n): FP16 storage scale numerator
     int L;                  // SpMV lanes per row
     int NB;                 // workgroups of the streaming kernels (partial-sum count)
+    int nbcap;              // partial-sum capacity per slot (largest grid)
+    int pass_grid;          // 1: Arnoldi passes run one round of resident workgroups
     int m;
     int nslot;              // index of the norm slot in `part`
     int64_t ldv;            // basis column stride (elements)
@@ -68,8 +70,8 @@ struct EngineArgs {
     const int *bb_ptr, *bb_col, *ab_ptr, *slot_pos;   // slot_pos: slot -> column-contiguous position
     const int* zc1;         // Z single-entry rows (ELL-1)
     const double* zv1;
-    const int* azc1;        // A Z single-entry rows (ELL-1) of the operator
-    const void* azv1;       // AT
+    const int* azc1;        // A Z two-entry rows (ELL-2, 2 per row, interleaved) of the operator
+    const void* azv1;       // AT, 2 per row
     // Sliced ELL copy of the operator (used when L == kSell).
     const int *sell_off, *sell_col;
     const void* sell_val;   // AT
@@ -160,6 +162,8 @@ void sell_values(hipStream_t st, int64_t total, const int* src, const double* va
 // Single-entry row copies of a CSR (see setup.hip); c1 may be NULL (values only).
 void ell1_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const double* v, int* c1,
                 double* v1, float* v1f);
+void ell2_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const double* v, int* c2,
+                double* v2, float* v2f);
 void invperm(hipStream_t st, int64_t m, const int* perm, int* pos);
 // Per-block deflation slots for the fused Z^T y (see setup.hip).  Buffers are
 // hipMalloc'ed here; the caller owns them.

@@ -19,6 +19,11 @@
 // enqueue a whole cycle without waiting.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "internal.hpp"
 
 namespace gm {
@@ -457,12 +462,111 @@ __device__ __forceinline__ ACC raw_at(const uint4& u, int e) {
     return (ACC)ld_f(tmp + e);
 }
 
-// Sum over the T lanes of a tile group (butterfly; same value in all of them).
+// Cross-lane moves inside a row of 16 lanes (DPP): quad_perm [1,0,3,2] (0xB1),
+// quad_perm [2,3,0,1] (0x4E), half-row mirror (0x141), row mirror (0x140).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the T consecutive lanes of a tile group (T <= 16, groups aligned
+// to T); every lane of the group gets the same value (the pairings are
+// symmetric, so both partners add the same two operands).
 template <int T, typename ACC>
 __device__ __forceinline__ ACC group_sum(ACC v) {
-#pragma unroll
-    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    static_assert(T >= 1 && T <= 16 && (T & (T - 1)) == 0, "tile group of 1..16 lanes");
+    if constexpr (T >= 2) v += dpp_mov<0xB1>(v);
+    if constexpr (T >= 4) v += dpp_mov<0x4E>(v);
+    if constexpr (T >= 8) v += dpp_mov<0x141>(v);
+    if constexpr (T >= 16) v += dpp_mov<0x140>(v);
     return v;
+}
+
+// Basis tiles of one lane: tile q holds column k = sub + q*T at rows
+// i0 .. i0+R-1.  Every tile slot is filled (branch-free code): slots past the
+// last column re-read column nv-1 (an address another lane of the same wave
+// reads, so no extra memory traffic) and carry coefficient 0; their dot
+// accumulators are never stored.  Requires nv >= 1.
+template <int JT, int T, typename VT>
+__device__ __forceinline__ void load_cols(const VT* __restrict__ V, int64_t ldv, int nv, int sub,
+                                          int64_t i0, uint4 (&raw)[JT]) {
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+        const int k = min(sub + q * T, nv - 1);
+        raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
+    }
+}
+
+// Coefficients of a lane's columns, staged through LDS (c_l holds JMAX
+// entries, zero from nv on).
+template <int JMAX, int T, typename ACC>
+__device__ __forceinline__ void stage_coef(const double* __restrict__ coef, int nv, ACC* c_l,
+                                           int sub, ACC (&cr)[JMAX / T]) {
+    for (int k = threadIdx.x; k < JMAX; k += kWG) c_l[k] = k < nv ? (ACC)coef[k] : (ACC)0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < JMAX / T; ++q) cr[q] = c_l[sub + q * T];
+}
+
+// sum_q cr[q] * (row e of tile q), over the lane's columns, then over the group.
+template <int JT, int T, typename VT, typename ACC>
+__device__ __forceinline__ ACC combine_row(const uint4 (&raw)[JT], const ACC (&cr)[JT], int e) {
+    ACC u = 0;
+#pragma unroll
+    for (int q = 0; q < JT; ++q) u += raw_at<VT, ACC>(raw[q], e) * cr[q];
+    return group_sum<T>(u);
+}
+
+// acc[q] += (tile q) . x over the tile's rows.
+template <int JT, int T, int R, typename VT, typename ACC>
+__device__ __forceinline__ void accumulate_dots(const uint4 (&raw)[JT], const ACC (&x)[R],
+                                                ACC (&acc)[JT]) {
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+        ACC t = 0;
+#pragma unroll
+        for (int e = 0; e < R; ++e) t += raw_at<VT, ACC>(raw[q], e) * x[e];
+        acc[q] += t;
+    }
+}
+
+// w = y - (A Z) s for one tile, from the two-entry row copy of A Z (pairs
+// (column, value) per row, -1 / 0 where absent); rows with more entries are
+// marked -2 and fall back to the CSR copy.  The common rows are handled
+// without branches or dependent loads.
+template <int RT, typename AZT, typename ACC>
+__device__ __forceinline__ void deflate_tile(int64_t i0, const int* __restrict__ azrp,
+                                             const int* __restrict__ azci,
+                                             const AZT* __restrict__ azv,
+                                             const int* __restrict__ azc2,
+                                             const AZT* __restrict__ azv2, const ACC* s_l,
+                                             ACC (&u)[RT]) {
+    int ac[2 * RT];
+    ACC av[2 * RT];
+    load_ints<2 * RT>(azc2 + 2 * i0, ac);
+    load_tile<AZT, 2 * RT, ACC>(azv2 + 2 * i0, av);
+    bool multi = false;
+#pragma unroll
+    for (int e = 0; e < RT; ++e) {
+        u[e] -= av[2 * e] * s_l[max(ac[2 * e], 0)] + av[2 * e + 1] * s_l[max(ac[2 * e + 1], 0)];
+        multi |= ac[2 * e] == -2;
+    }
+    if (multi) {
+#pragma unroll
+        for (int e = 0; e < RT; ++e) {
+            if (ac[2 * e] == -2) {
+                const int64_t i = i0 + e;
+                for (int q = azrp[i]; q < azrp[i + 1]; ++q) u[e] -= (ACC)azv[q] * s_l[azci[q]];
+            }
+        }
+    }
 }
 
 // Writes the workgroup sums of the per-lane accumulators acc[q] (column
@@ -509,8 +613,8 @@ __global__ __launch_bounds__(kWG) void k_pass1(int n, int64_t ldv, const VT* __r
                                                const int* __restrict__ azrp,
                                                const int* __restrict__ azci,
                                                const AZT* __restrict__ azv,
-                                               const int* __restrict__ azc1,
-                                               const AZT* __restrict__ azv1,
+                                               const int* __restrict__ azc2,
+                                               const AZT* __restrict__ azv2,
                                                const double* __restrict__ s, int R,
                                                WT* __restrict__ w, double* __restrict__ part,
                                                int nslot, int NB, const Ctrl* ctrl, int gate) {
@@ -528,45 +632,17 @@ __global__ __launch_bounds__(kWG) void k_pass1(int n, int64_t ldv, const VT* __r
     ACC accn = 0;
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
-        // All basis tiles of this lane are requested before any arithmetic.
         uint4 raw[JT];
-#pragma unroll
-        for (int q = 0; q < JT; ++q) {
-            const int k = sub + q * T;
-            if (k < nv) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
-        }
+        if (nv > 0) load_cols<JT, T, VT>(V, ldv, nv, sub, i0, raw);
         ACC wv[RT];
         load_tile<WT, RT, ACC>(y + i0, wv);
-        if (R > 0) {
-            int ac[RT];
-            ACC av[RT];
-            load_ints<RT>(azc1 + i0, ac);
-            load_tile<AZT, RT, ACC>(azv1 + i0, av);
-#pragma unroll
-            for (int e = 0; e < RT; ++e) {
-                if (ac[e] >= 0) {
-                    wv[e] -= av[e] * s_l[ac[e]];
-                } else if (ac[e] == -2) {
-                    const int64_t i = i0 + e;
-                    for (int q = azrp[i]; q < azrp[i + 1]; ++q) wv[e] -= (ACC)azv[q] * s_l[azci[q]];
-                }
-            }
-        }
+        if (R > 0) deflate_tile<RT, AZT, ACC>(i0, azrp, azci, azv, azc2, azv2, s_l, wv);
         if (sub == 0) {
             store_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
             for (int e = 0; e < RT; ++e) accn += wv[e] * wv[e];
         }
-#pragma unroll
-        for (int q = 0; q < JT; ++q) {
-            const int k = sub + q * T;
-            if (k < nv) {
-                ACC t = 0;
-#pragma unroll
-                for (int e = 0; e < RT; ++e) t += raw_at<VT, ACC>(raw[q], e) * wv[e];
-                acc[q] += t;
-            }
-        }
+        if (nv > 0) accumulate_dots<JT, T, RT, VT, ACC>(raw, wv, acc);
     }
     store_partials<JMAX, T, ACC>(acc, accn, nv, red, part, nslot, NB);
 }
@@ -583,9 +659,9 @@ __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __r
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
     __shared__ ACC red[kWG / kWave][JMAX + 1];
-    for (int k = threadIdx.x; k < nv; k += kWG) c_l[k] = (ACC)coef[k];
-    __syncthreads();
     const int sub = threadIdx.x & (T - 1);
+    ACC cr[JT];
+    stage_coef<JMAX, T, ACC>(coef, nv, c_l, sub, cr);
     ACC acc[JT];
 #pragma unroll
     for (int q = 0; q < JT; ++q) acc[q] = 0;
@@ -593,38 +669,17 @@ __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __r
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-#pragma unroll
-        for (int q = 0; q < JT; ++q) {
-            const int k = sub + q * T;
-            if (k < nv) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
-        }
+        load_cols<JT, T, VT>(V, ldv, nv, sub, i0, raw);
         ACC wv[RT];
         load_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
-        for (int e = 0; e < RT; ++e) {
-            ACC u = 0;
-#pragma unroll
-            for (int q = 0; q < JT; ++q) {
-                const int k = sub + q * T;
-                if (k < nv) u += raw_at<VT, ACC>(raw[q], e) * c_l[k];
-            }
-            wv[e] -= group_sum<T>(u);
-        }
+        for (int e = 0; e < RT; ++e) wv[e] -= combine_row<JT, T, VT, ACC>(raw, cr, e);
         if (sub == 0) {
             store_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
             for (int e = 0; e < RT; ++e) accn += wv[e] * wv[e];
         }
-#pragma unroll
-        for (int q = 0; q < JT; ++q) {
-            const int k = sub + q * T;
-            if (k < nv) {
-                ACC t = 0;
-#pragma unroll
-                for (int e = 0; e < RT; ++e) t += raw_at<VT, ACC>(raw[q], e) * wv[e];
-                acc[q] += t;
-            }
-        }
+        accumulate_dots<JT, T, RT, VT, ACC>(raw, wv, acc);
     }
     store_partials<JMAX, T, ACC>(acc, accn, nv, red, part, nslot, NB);
 }
@@ -643,32 +698,20 @@ __global__ __launch_bounds__(kWG) void k_pass3(int n, int64_t ldv, VT* __restric
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
     __shared__ ACC red[kWG / kWave];
-    for (int k = threadIdx.x; k < nv; k += kWG) c_l[k] = (ACC)coef[k];
-    __syncthreads();
+    const int sub = threadIdx.x & (T - 1);
+    ACC cr[JT];
+    stage_coef<JMAX, T, ACC>(coef, nv, c_l, sub, cr);
     const ACC sg = (ACC)(*sigma);
     VT* __restrict__ vout = V + nv * ldv;
-    const int sub = threadIdx.x & (T - 1);
     ACC accn = 0;
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-#pragma unroll
-        for (int q = 0; q < JT; ++q) {
-            const int k = sub + q * T;
-            if (k < nv) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
-        }
+        load_cols<JT, T, VT>(V, ldv, nv, sub, i0, raw);
         ACC wv[RT];
         load_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
-        for (int e = 0; e < RT; ++e) {
-            ACC u = 0;
-#pragma unroll
-            for (int q = 0; q < JT; ++q) {
-                const int k = sub + q * T;
-                if (k < nv) u += raw_at<VT, ACC>(raw[q], e) * c_l[k];
-            }
-            wv[e] -= group_sum<T>(u);
-        }
+        for (int e = 0; e < RT; ++e) wv[e] -= combine_row<JT, T, VT, ACC>(raw, cr, e);
         if (sub == 0) {
             ACC ov[RT];
 #pragma unroll
@@ -703,8 +746,8 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
                                                    const int* __restrict__ azrp,
                                                    const int* __restrict__ azci,
                                                    const AZT* __restrict__ azv,
-                                                   const int* __restrict__ azc1,
-                                                   const AZT* __restrict__ azv1,
+                                                   const int* __restrict__ azc2,
+                                                   const AZT* __restrict__ azv2,
                                                    const double* __restrict__ s, int R,
                                                    const double* __restrict__ coef2,
                                                    const double* __restrict__ cc,
@@ -718,14 +761,14 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
     __shared__ ACC c2_l[JMAX], cc_l[JMAX];
     __shared__ ACC red[kWG / kWave][JMAX + 2];
     for (int a = threadIdx.x; a < R; a += kWG) s_l[a] = (ACC)s[a];
-    for (int k = threadIdx.x; k < nvr; k += kWG) {
-        c2_l[k] = (ACC)coef2[k];
-        cc_l[k] = (ACC)cc[k];
-    }
-    __syncthreads();
+    const int sub = threadIdx.x & (T - 1);
+    ACC c2r[JT], ccr[JT];
+    for (int k = threadIdx.x; k < JMAX; k += kWG) cc_l[k] = k < nvr ? (ACC)cc[k] : (ACC)0;
+    stage_coef<JMAX, T, ACC>(coef2, nvr, c2_l, sub, c2r);   // synchronises
+#pragma unroll
+    for (int q = 0; q < JT; ++q) ccr[q] = cc_l[sub + q * T];
     const ACC h2last = (ACC)lag[0], ihn = (ACC)lag[1], sg = (ACC)lag[2];
     VT* __restrict__ vout = V + nvr * ldv;
-    const int sub = threadIdx.x & (T - 1);
     ACC acc[JT];
 #pragma unroll
     for (int q = 0; q < JT; ++q) acc[q] = 0;
@@ -733,44 +776,16 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-#pragma unroll
-        for (int q = 0; q < JT; ++q) {
-            const int k = sub + q * T;
-            if (k < nvr) raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
-        }
+        load_cols<JT, T, VT>(V, ldv, nvr, sub, i0, raw);
         ACC w1[RT], u[RT];
         load_tile<WT, RT, ACC>(w + i0, w1);
         load_tile<WT, RT, ACC>(y + i0, u);
-        if (R > 0) {
-            int ac[RT];
-            ACC av[RT];
-            load_ints<RT>(azc1 + i0, ac);
-            load_tile<AZT, RT, ACC>(azv1 + i0, av);
-#pragma unroll
-            for (int e = 0; e < RT; ++e) {
-                if (ac[e] >= 0) {
-                    u[e] -= av[e] * s_l[ac[e]];
-                } else if (ac[e] == -2) {
-                    const int64_t i = i0 + e;
-                    for (int q = azrp[i]; q < azrp[i + 1]; ++q) u[e] -= (ACC)azv[q] * s_l[azci[q]];
-                }
-            }
-        }
+        if (R > 0) deflate_tile<RT, AZT, ACC>(i0, azrp, azci, azv, azc2, azv2, s_l, u);
         ACC sv[RT], wn[RT];
 #pragma unroll
         for (int e = 0; e < RT; ++e) {
-            ACC a2 = 0, a3 = 0;
-#pragma unroll
-            for (int q = 0; q < JT; ++q) {
-                const int k = sub + q * T;
-                if (k < nvr) {
-                    const ACC vk = raw_at<VT, ACC>(raw[q], e);
-                    a2 += vk * c2_l[k];
-                    a3 += vk * cc_l[k];
-                }
-            }
-            a2 = group_sum<T>(a2);
-            a3 = group_sum<T>(a3);
+            const ACC a2 = combine_row<JT, T, VT, ACC>(raw, c2r, e);
+            const ACC a3 = combine_row<JT, T, VT, ACC>(raw, ccr, e);
             const ACC w2 = w1[e] - a2;
             VT stv;
             st_v(&stv, w2 * sg);
@@ -786,16 +801,7 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
                 accd += sv[e] * wn[e];
             }
         }
-#pragma unroll
-        for (int q = 0; q < JT; ++q) {
-            const int k = sub + q * T;
-            if (k < nvr) {
-                ACC t = 0;
-#pragma unroll
-                for (int e = 0; e < RT; ++e) t += raw_at<VT, ACC>(raw[q], e) * wn[e];
-                acc[q] += t;
-            }
-        }
+        accumulate_dots<JT, T, RT, VT, ACC>(raw, wn, acc);
     }
     // Partials: columns 0..nvr-1 from acc, column nvr from accd, norm slot.
     const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
@@ -1172,6 +1178,36 @@ bool disarm_kernel_events() {
     return pending;
 }
 
+// Workgroups of one streaming pass: as many as the device holds at once
+// (a single round, so every workgroup gets the same share of rows), at most
+// cap.  Queried once per kernel and device.
+static int resident_grid(const void* k, int cap) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int g = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find({dev, k});
+        if (it != cache.end()) {
+            g = it->second;
+        } else {
+            int per_cu = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kWG, 0) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                    hipSuccess ||
+                cus < 1)
+                cus = 1;
+            g = per_cu * cus;
+            cache[{dev, k}] = g;
+        }
+    }
+    return std::max(1, std::min(g, cap));
+}
+
 template <typename... KA, typename... A>
 static inline void launch(void (*k)(KA...), dim3 g, dim3 b, uint32_t sh, hipStream_t st,
                           A... args) {
@@ -1273,9 +1309,13 @@ static void sell_launch(const EngineArgs& e, const XT* x, const double* scale, c
 static int jmax_for(int nv) {
     if (nv <= 8) return 8;
     if (nv <= 16) return 16;
+    if (nv <= 24) return 24;
     if (nv <= 32) return 32;
+    if (nv <= 40) return 40;
     if (nv <= 48) return 48;
+    if (nv <= 56) return 56;
     if (nv <= 64) return 64;
+    if (nv <= 80) return 80;
     return 96;
 }
 
@@ -1288,13 +1328,28 @@ struct LanesFor {
     static constexpr int value = sizeof(VT) == 2 ? 2 * base : base;
 };
 
-#define GM_JMAX_SWITCH(nv, VTT, CALL)                                                         \
-    switch (jmax_for(nv)) {                                                                    \
-        case 8: { constexpr int J = 8; constexpr int T = LanesFor<J, VTT>::value; CALL; } break;   \
-        case 16: { constexpr int J = 16; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
-        case 32: { constexpr int J = 32; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
-        case 48: { constexpr int J = 48; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
-        case 64: { constexpr int J = 64; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
+// The two-sweep first pass keeps two coefficient sets per lane: FP32/FP64
+// bases spread the columns over twice as many lanes to stay at >= 4 waves
+// per SIMD (FP16 tiles are already spread).
+template <int J, typename VT>
+struct LanesForLag {
+    static constexpr int value =
+        sizeof(VT) == 2 ? LanesFor<J, VT>::value : (2 * LanesFor<J, VT>::value > 16 ? 16 : 2 * LanesFor<J, VT>::value);
+};
+
+#define GM_JMAX_CASE(JV, VTT, CALL) \
+    case JV: { constexpr int J = JV; constexpr int T = LanesFor<J, VTT>::value; CALL; } break;
+#define GM_JMAX_SWITCH(nv, VTT, CALL)   \
+    switch (jmax_for(nv)) {             \
+        GM_JMAX_CASE(8, VTT, CALL)      \
+        GM_JMAX_CASE(16, VTT, CALL)     \
+        GM_JMAX_CASE(24, VTT, CALL)     \
+        GM_JMAX_CASE(32, VTT, CALL)     \
+        GM_JMAX_CASE(40, VTT, CALL)     \
+        GM_JMAX_CASE(48, VTT, CALL)     \
+        GM_JMAX_CASE(56, VTT, CALL)     \
+        GM_JMAX_CASE(64, VTT, CALL)     \
+        GM_JMAX_CASE(80, VTT, CALL)     \
         default: { constexpr int J = 96; constexpr int T = LanesFor<J, VTT>::value; CALL; } break; \
     }
 
@@ -1319,6 +1374,12 @@ struct Engine {
     static constexpr int kHalf = std::is_same<VT, __half>::value ? 1 : 0;
 
     bool fused() const { return e.R > 0 && e.fuse_rb != 0; }
+
+    // Grid of an Arnoldi pass: one full round of resident workgroups, or the
+    // plan's fixed grid when pass_grid is 0.
+    int grid_for(const void* k) const {
+        return e.pass_grid ? resident_grid(k, e.nbcap) : e.NB;
+    }
 
     void coarse_slots(double* s, int gate) const {
         k_coarse_slots<<<1, kCT, 0, e.st>>>(e.R, e.ab_ptr, e.tpart, e.Einv, e.trans, s, e.ctrl,
@@ -1375,26 +1436,37 @@ struct Engine {
         if (fused()) coarse_slots(e.s_step, 2);
         else coarse(y(), e.s_step, 2);
         if (e.timer) e.timer->begin(1, j);
-        GM_JMAX_SWITCH(nv, VT, (launch(k_pass1<J, T, VT, WT, AT, ACC>, e.NB, kWG, 0, e.st, 
-                               e.n, e.ldv, V(), nv, y(), e.azrp, e.azci, azv(), e.azc1, azv1(), e.s_step, e.R, w(),
-                               e.part, e.nslot, e.NB, e.ctrl, 2)));
+        int g1 = 0, g2 = 0, g3 = 0;
+        GM_JMAX_SWITCH(nv, VT, ({
+            auto kf = k_pass1<J, T, VT, WT, AT, ACC>;
+            g1 = grid_for((const void*)kf);
+            launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), nv, y(), e.azrp, e.azci, azv(), e.azc1,
+                   azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2);
+        }));
         if (e.timer) e.timer->end(1, j);
-        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
+        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, g1, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
         if (e.timer) e.timer->begin(2, j);
-        GM_JMAX_SWITCH(nv, VT, (launch(k_pass2<J, T, VT, WT, ACC>, e.NB, kWG, 0, e.st, 
-                               e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, e.NB, e.ctrl, 2)));
+        GM_JMAX_SWITCH(nv, VT, ({
+            auto kf = k_pass2<J, T, VT, WT, ACC>;
+            g2 = grid_for((const void*)kf);
+            launch(kf, g2, kWG, 0, e.st, e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, g2,
+                   e.ctrl, 2);
+        }));
         if (e.timer) e.timer->end(2, j);
-        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
+        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, g2, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
         if (e.timer) e.timer->begin(3, j);
-        GM_JMAX_SWITCH(nv, VT, (launch(k_pass3<J, T, VT, WT, ACC>, e.NB, kWG, 0, e.st, 
-                               e.n, e.ldv, V(), nv, w(), e.coef2, e.sigma, e.part, e.nslot, e.NB,
-                               e.ctrl, 2)));
+        GM_JMAX_SWITCH(nv, VT, ({
+            auto kf = k_pass3<J, T, VT, WT, ACC>;
+            g3 = grid_for((const void*)kf);
+            launch(kf, g3, kWG, 0, e.st, e.n, e.ldv, V(), nv, w(), e.coef2, e.sigma, e.part,
+                   e.nslot, g3, e.ctrl, 2);
+        }));
         if (e.timer) e.timer->end(3, j);
-        launch(k_givens<false>, 1, kGT, 0, e.st, j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
-                                               e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap,
-                                               e.Hraw, nullptr, nullptr, e.ctrl, 2);
+        launch(k_givens<false>, 1, kGT, 0, e.st, j, e.m, e.part, g3, e.nslot, e.h1, e.h2, e.H, e.cs,
+               e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap, e.Hraw, nullptr, nullptr, e.ctrl,
+               2);
     }
 
     // Step j of the two-pass variant (see k_pass1_lag).
@@ -1410,28 +1482,36 @@ struct Engine {
         if (fused()) coarse_slots(e.s_step, 2);
         else coarse(y(), e.s_step, 2);
         if (e.timer) e.timer->begin(1, j);
+        int g1 = 0, g2 = 0;
         if (j == 0) {
-            launch(k_pass1<8, 1, VT, WT, AT, ACC>, e.NB, kWG, 0, e.st, 
-                e.n, e.ldv, V(), 1, y(), e.azrp, e.azci, azv(), e.azc1, azv1(), e.s_step, e.R, w(),
-                e.part, e.nslot, e.NB, e.ctrl, 2);
+            auto kf = k_pass1<8, 1, VT, WT, AT, ACC>;
+            g1 = grid_for((const void*)kf);
+            launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), 1, y(), e.azrp, e.azci, azv(), e.azc1,
+                   azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2);
         } else {
-            GM_JMAX_SWITCH(j, VT, (launch(k_pass1_lag<J, T, VT, WT, AT, ACC>, e.NB, kWG, 0, e.st, 
-                                      e.n, e.ldv, V(), j, w(), y(), e.azrp, e.azci, azv(), e.azc1,
-                                      azv1(), e.s_step, e.R, e.coef2, e.cc, e.lag, e.part, e.nslot,
-                                      e.NB, e.ctrl, 2)));
+            GM_JMAX_SWITCH(j, VT, ({
+                auto kf = k_pass1_lag<J, LanesForLag<J, VT>::value, VT, WT, AT, ACC>;
+                g1 = grid_for((const void*)kf);
+                launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), j, w(), y(), e.azrp, e.azci, azv(),
+                       e.azc1, azv1(), e.s_step, e.R, e.coef2, e.cc, e.lag, e.part, e.nslot, g1,
+                       e.ctrl, 2);
+            }));
         }
         if (e.timer) e.timer->end(1, j);
-        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
+        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, g1, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
         if (e.timer) e.timer->begin(2, j);
-        GM_JMAX_SWITCH(nv, VT, (launch(k_pass2<J, T, VT, WT, ACC>, e.NB, kWG, 0, e.st, 
-                                    e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, e.NB, e.ctrl, 2)));
+        GM_JMAX_SWITCH(nv, VT, ({
+            auto kf = k_pass2<J, T, VT, WT, ACC>;
+            g2 = grid_for((const void*)kf);
+            launch(kf, g2, kWG, 0, e.st, e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, g2,
+                   e.ctrl, 2);
+        }));
         if (e.timer) e.timer->end(2, j);
-        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, e.NB, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
+        k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, g2, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
                                            kHalf, e.nscale, e.sigma, e.ctrl, 2);
-        launch(k_givens<true>, 1, kGT, 0, e.st, j, e.m, e.part, e.NB, e.nslot, e.h1, e.h2, e.H, e.cs,
-                                              e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap,
-                                              e.Hraw, e.cc, e.lag, e.ctrl, 2);
+        launch(k_givens<true>, 1, kGT, 0, e.st, j, e.m, e.part, g2, e.nslot, e.h1, e.h2, e.H, e.cs,
+               e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap, e.Hraw, e.cc, e.lag, e.ctrl, 2);
     }
 
     // y = scale * A x for the step's input vector x (type XT), with the fused

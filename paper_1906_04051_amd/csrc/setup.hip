@@ -655,6 +655,48 @@ void ell1_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const d
     if (n > 0) k_ell1<<<blocks_for(n), kWG, 0, st>>>(n, rp, ci, v, c1, v1, v1f);
 }
 
+// Two-entry row copies (ELL-2, interleaved per row): c2[2i], c2[2i+1] = the
+// columns of row i's first and second entries (-1 where absent, value 0);
+// rows with three or more entries get c2[2i] = -2 and zero values (the CSR is
+// used for those).  With an indicator deflation basis on a 2-D mesh, A Z has
+// at most two entries per row except near subdomain corners.
+__global__ void k_ell2(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
+                       const double* __restrict__ v, int* __restrict__ c2, double* __restrict__ v2,
+                       float* __restrict__ v2f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int q0 = rp[i], q1 = rp[i + 1];
+    int ca = -1, cb = -1;
+    double va = 0.0, vb = 0.0;
+    if (q1 - q0 > 2) {
+        ca = -2;
+    } else {
+        if (q1 - q0 >= 1) {
+            ca = ci[q0];
+            va = v[q0];
+        }
+        if (q1 - q0 == 2) {
+            cb = ci[q0 + 1];
+            vb = v[q0 + 1];
+        }
+    }
+    if (c2) {
+        c2[2 * i] = ca;
+        c2[2 * i + 1] = cb;
+    }
+    v2[2 * i] = va;
+    v2[2 * i + 1] = vb;
+    if (v2f) {
+        v2f[2 * i] = (float)va;
+        v2f[2 * i + 1] = (float)vb;
+    }
+}
+
+void ell2_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const double* v, int* c2,
+                double* v2, float* v2f) {
+    if (n > 0) k_ell2<<<blocks_for(n), kWG, 0, st>>>(n, rp, ci, v, c2, v2, v2f);
+}
+
 // Inverse permutation: pos[perm[q]] = q.
 __global__ void k_invperm(int64_t m, const int* __restrict__ perm, int* __restrict__ pos) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -242,8 +242,10 @@ class Plan:
         _check(self._lib.gmres_autotune(self._h, ch))
         return dict(spmv_lanes=ch[0], num_blocks=ch[1], batch_wg=ch[2], batch_lanes=ch[3])
 
-    def set_timing(self, enable: bool):
-        _check(self._lib.gmres_set_timing(self._h, int(bool(enable))))
+    def set_timing(self, period):
+        """Per-kernel timing of later solves: 0/False off, True/1 every restart
+        cycle, k > 1 one cycle in k (the others replay the cycle graph)."""
+        _check(self._lib.gmres_set_timing(self._h, int(period)))
 
     def kernel_times(self) -> dict:
         out = (C.c_double * 15)()
