@@ -280,14 +280,32 @@ __global__ __launch_bounds__(kCT) void k_coarse_slots(int R, const int* __restri
                                                       const double* __restrict__ Einv, int trans,
                                                       double* __restrict__ s, const Ctrl* ctrl,
                                                       int gate) {
-    if (gated(ctrl, gate)) return;
     __shared__ double t[kMaxR];
     __shared__ double red[kCT];
     const int G = max(1, kCT / R);
     const int grp = threadIdx.x / R, a = threadIdx.x % R;
+    // The slot ranges, this thread's E^{-1} entries and the control block are
+    // requested together; the slot sums follow.
+    int q0 = 0, q1 = 0;
+    if (grp < G) {
+        q0 = ab_ptr[a];
+        q1 = ab_ptr[a + 1];
+    }
+    constexpr int kEmax = 8;   // prefetched entries per thread (R up to about 90)
+    double ev[kEmax];
+    const int espan = (R + G - 1) / G;
+    const int ea0 = grp * espan, ea1 = (grp < G) ? min(R, ea0 + espan) : ea0;
+    const bool pre = espan <= kEmax;
+    if (pre) {
+#pragma unroll
+        for (int u = 0; u < kEmax; ++u) {
+            const int aa = ea0 + u;
+            ev[u] = (aa < ea1) ? (trans ? Einv[(int64_t)a * R + aa] : Einv[(int64_t)aa * R + a]) : 0.0;
+        }
+    }
+    if (gated(ctrl, gate)) return;
     double acc = 0;
     if (grp < G) {
-        const int q0 = ab_ptr[a], q1 = ab_ptr[a + 1];
         const int span = (q1 - q0 + G - 1) / G;
         const int b0 = q0 + grp * span, b1 = min(q1, b0 + span);
 #pragma unroll 8
@@ -301,7 +319,25 @@ __global__ __launch_bounds__(kCT) void k_coarse_slots(int R, const int* __restri
         t[threadIdx.x] = v;
     }
     __syncthreads();
-    coarse_matvec(R, Einv, trans, t, s, red);
+    if (!pre) {
+        coarse_matvec(R, Einv, trans, t, s, red);
+        return;
+    }
+    // s = E^{-1} t with the prefetched entries (same split and order as
+    // coarse_matvec).
+    double v = 0;
+    if (grp < G) {
+#pragma unroll
+        for (int u = 0; u < kEmax; ++u)
+            if (ea0 + u < ea1) v += ev[u] * t[ea0 + u];
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double r = red[threadIdx.x];
+        for (int q = 1; q < G; ++q) r += red[q * R + threadIdx.x];
+        s[threadIdx.x] = r;
+    }
 }
 
 // r = b - A x (x in FP64), plus per-workgroup partial sums of ||r||^2 into
@@ -618,13 +654,14 @@ __global__ __launch_bounds__(kWG) void k_pass1(int n, int64_t ldv, const VT* __r
                                                const double* __restrict__ s, int R,
                                                WT* __restrict__ w, double* __restrict__ part,
                                                int nslot, int NB, const Ctrl* ctrl, int gate) {
-    if (gated(ctrl, gate)) return;
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC s_l[kMaxR];
     __shared__ ACC red[kWG / kWave][JMAX + 1];
     for (int a = threadIdx.x; a < R; a += kWG) s_l[a] = (ACC)s[a];
     __syncthreads();
+    // Tested after the staging loads so the two requests overlap (uniform).
+    if (gated(ctrl, gate)) return;
     const int sub = threadIdx.x & (T - 1);
     ACC acc[JT];
 #pragma unroll
@@ -654,7 +691,6 @@ __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __r
                                                WT* __restrict__ w, const double* __restrict__ coef,
                                                double* __restrict__ part, int nslot, int NB,
                                                const Ctrl* ctrl, int gate) {
-    if (gated(ctrl, gate)) return;
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
@@ -662,6 +698,7 @@ __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __r
     const int sub = threadIdx.x & (T - 1);
     ACC cr[JT];
     stage_coef<JMAX, T, ACC>(coef, nv, c_l, sub, cr);
+    if (gated(ctrl, gate)) return;   // after the staging loads (uniform)
     ACC acc[JT];
 #pragma unroll
     for (int q = 0; q < JT; ++q) acc[q] = 0;
@@ -693,7 +730,6 @@ __global__ __launch_bounds__(kWG) void k_pass3(int n, int64_t ldv, VT* __restric
                                                const double* __restrict__ sigma,
                                                double* __restrict__ part, int nslot, int NB,
                                                const Ctrl* ctrl, int gate) {
-    if (gated(ctrl, gate)) return;
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
@@ -701,6 +737,7 @@ __global__ __launch_bounds__(kWG) void k_pass3(int n, int64_t ldv, VT* __restric
     const int sub = threadIdx.x & (T - 1);
     ACC cr[JT];
     stage_coef<JMAX, T, ACC>(coef, nv, c_l, sub, cr);
+    if (gated(ctrl, gate)) return;   // after the staging loads (uniform)
     const ACC sg = (ACC)(*sigma);
     VT* __restrict__ vout = V + nv * ldv;
     ACC accn = 0;
@@ -754,7 +791,6 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
                                                    const double* __restrict__ lag,
                                                    double* __restrict__ part, int nslot, int NB,
                                                    const Ctrl* ctrl, int gate) {
-    if (gated(ctrl, gate)) return;
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC s_l[kMaxR];
@@ -768,6 +804,7 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
 #pragma unroll
     for (int q = 0; q < JT; ++q) ccr[q] = cc_l[sub + q * T];
     const ACC h2last = (ACC)lag[0], ihn = (ACC)lag[1], sg = (ACC)lag[2];
+    if (gated(ctrl, gate)) return;   // after the staging loads (uniform)
     VT* __restrict__ vout = V + nvr * ldv;
     ACC acc[JT];
 #pragma unroll
@@ -842,18 +879,21 @@ __global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ part,
                                                 double* __restrict__ h, double* __restrict__ coef,
                                                 int mode, int half_store, double nscale,
                                                 double* __restrict__ sigma, Ctrl* ctrl, int gate) {
-    if (gated(ctrl, gate)) return;
     __shared__ double red[kWG / kWave];
     const int b = blockIdx.x;
     const int slot = (b < nv) ? b : nslot;
+    // The partials are requested before the control block is tested, so the
+    // two loads overlap (the test is uniform over the workgroup).
     double acc = 0;
     for (int q = threadIdx.x; q < NB; q += kWG) acc += part[(int64_t)slot * NB + q];
+    const double vs = (b < nv && threadIdx.x == 0) ? vscale[b] : 0.0;
+    if (gated(ctrl, gate)) return;
     acc = block_sum(acc, red);
     if (threadIdx.x != 0) return;
     if (b < nv) {
-        const double hk = vscale[b] * acc;
+        const double hk = vs * acc;
         h[b] = hk;
-        coef[b] = hk * vscale[b];
+        coef[b] = hk * vs;
     } else if (mode == 1) {
         ctrl->wpre2 = acc;
     } else if (mode == 2) {
@@ -880,50 +920,83 @@ __global__ __launch_bounds__(kGT) void k_givens(int j, int m, const double* __re
                                                   double* __restrict__ hist, int64_t hist_cap,
                                                   double* __restrict__ Hraw, double* __restrict__ cc,
                                                   double* __restrict__ lag, Ctrl* ctrl, int gate) {
-    if (gated(ctrl, gate)) return;
     __shared__ double col[kMaxM + 1], cl[kMaxM], sl[kMaxM], h2l[kMaxM + 1];
     __shared__ double red[kGT / kWave];
-    __shared__ double hb[LAG ? (kMaxM + 1) * kMaxM : 1];   // Hbar band, rows 0..j, cols 0..j-1
+    __shared__ double ccp[LAG ? kGT : 1];
+    const int tid = threadIdx.x;
+    // Every independent global load is issued before the first wait: the norm
+    // partials, this column's h1/h2, the stored rotations and (thread 0) the
+    // scalar state.  The control-block test comes after them.
     double acc = 0;
-    for (int q = threadIdx.x; q < NB; q += kGT) acc += part[(int64_t)nslot * NB + q];
-    acc = block_sum_n<kGT>(acc, red);
+    for (int q = tid; q < NB; q += kGT) acc += part[(int64_t)nslot * NB + q];
+    double h1v = 0, h2v = 0, csv = 0, snv = 0, vsv = 0;
+    if (tid <= j) {
+        h1v = h1[tid];
+        h2v = h2[tid];
+        if (LAG) vsv = vscale[tid];
+    }
+    if (tid < j) {
+        csv = cs[tid];
+        snv = sn[tid];
+    }
+    double wpre2 = 0, gj = 0, target = 0, sig = 1;
+    int64_t its0 = 0, maxit = 0;
+    if (tid == 0) {
+        wpre2 = ctrl->wpre2;
+        gj = g[j];
+        target = ctrl->target;
+        its0 = ctrl->its;
+        maxit = ctrl->max_iters;
+        sig = *sigma;
+    }
+    if (gated(ctrl, gate)) return;
+    if (tid <= j) {
+        h2l[tid] = h2v;
+        col[tid] = h1v + h2v;
+    }
+    if (tid < j) {
+        cl[tid] = csv;
+        sl[tid] = snv;
+    }
+    acc = block_sum_n<kGT>(acc, red);   // also orders the LDS writes above
     if (LAG) {
-        for (int i = threadIdx.x; i <= j; i += kGT) h2l[i] = h2[i];
-        __syncthreads();
         // acc = ||w1||^2; ||w2||^2 = ||w1||^2 - ||h2||^2 (h2 against orthonormal v's).
         double q2 = 0;
-        for (int i = threadIdx.x; i <= j; i += kGT) q2 += h2l[i] * h2l[i];
+        for (int i = tid; i <= j; i += kGT) q2 += h2l[i] * h2l[i];
         q2 = block_sum_n<kGT>(q2, red);
         acc = fmax(acc - q2, 0.0);
-        for (int q = threadIdx.x; q < (j + 1) * j; q += kGT) {
-            const int l = q / j, k = q % j;
-            hb[q] = (k >= l - 1) ? Hraw[(int64_t)l * m + k] : 0.0;
-        }
     }
-    for (int i = threadIdx.x; i <= j; i += kGT) col[i] = h1[i] + (LAG ? h2l[i] : h2[i]);
-    for (int i = threadIdx.x; i < j; i += kGT) {
-        cl[i] = cs[i];
-        sl[i] = sn[i];
-    }
-    __syncthreads();
     const double hn = sqrt(acc);
     if (Hraw) {
-        for (int i = threadIdx.x; i <= j; i += kGT) Hraw[(int64_t)i * m + j] = col[i];
-        if (threadIdx.x == 0) Hraw[(int64_t)(j + 1) * m + j] = hn;
+        for (int i = tid; i <= j; i += kGT) Hraw[(int64_t)i * m + j] = col[i];
+        if (tid == 0) Hraw[(int64_t)(j + 1) * m + j] = hn;
     }
     if (LAG) {
         // Coefficients of the next lagged step: c_l = sum_k Hbar[l][k] h2_k over
-        // the unrotated Hbar (rows l <= j, columns 0..j; column j is col[]),
-        // times vscale[l].
-        for (int l = threadIdx.x; l <= j; l += kGT) {
-            double v = 0;
-            for (int k = (l > 0 ? l - 1 : 0); k < j; ++k) v += hb[l * j + k] * h2l[k];
-            v += col[l] * h2l[j];
-            cc[l] = v * vscale[l];
+        // the unrotated Hbar (rows l <= j, columns max(l-1,0)..j; column j is
+        // col[]), times vscale[l].  Row l is split over G threads whose
+        // partial sums are added in order.
+        const int rows = j + 1;
+        const int G = max(1, kGT / rows);
+        const int l = tid % rows, grp = tid / rows;
+        double v = 0;
+        if (grp < G) {
+            const int k0 = (l > 0 ? l - 1 : 0), k1 = j;   // band columns < j
+            const int span = (k1 - k0 + G - 1) / G;
+            const int a0 = k0 + grp * span, a1 = min(k1, a0 + span);
+            for (int k = a0; k < a1; ++k) v += Hraw[(int64_t)l * m + k] * h2l[k];
+        }
+        ccp[tid] = v;
+        __syncthreads();
+        if (tid < rows) {
+            double c = ccp[tid];
+            for (int q = 1; q < G; ++q) c += ccp[q * rows + tid];
+            c += col[tid] * h2l[j];
+            cc[tid] = c * vsv;
         }
     }
-    if (threadIdx.x != 0) return;
-    const double wpre = sqrt(ctrl->wpre2);
+    if (tid != 0) return;
+    const double wpre = sqrt(wpre2);
     // The lagged norm comes from a difference of squares: its rounding error is
     // about sqrt(eps) * ||w1||, so a breakdown is declared below that level.
     const double bd_tol = LAG ? 1.4901161193847656e-08 : 2.220446049250313e-16;
@@ -949,23 +1022,22 @@ __global__ __launch_bounds__(kGT) void k_givens(int j, int m, const double* __re
     sn[j] = sj;
     H[(int64_t)j * m + j] = rho;
     H[(int64_t)(j + 1) * m + j] = 0.0;
-    const double gj = g[j];
     g[j + 1] = -sj * gj;
     g[j] = cj * gj;
-    vscale[j + 1] = bd ? 0.0 : 1.0 / ((*sigma) * hn);
+    vscale[j + 1] = bd ? 0.0 : 1.0 / (sig * hn);
     if (LAG) {
         lag[0] = h2l[j];
         lag[1] = bd ? 0.0 : 1.0 / hn;
-        lag[2] = *sigma;
+        lag[2] = sig;
     }
-    const int64_t its = ctrl->its + 1;
+    const int64_t its = its0 + 1;
     ctrl->its = its;
     if (hist && its - 1 < hist_cap) hist[its - 1] = fabs(sj * gj);
     ctrl->k = j + 1;
     ctrl->breakdown = bd;
-    const bool est = fabs(sj * gj) <= ctrl->target;
+    const bool est = fabs(sj * gj) <= target;
     if (est) ctrl->est_conv = 1;
-    if (est || bd || its >= ctrl->max_iters) ctrl->stop = 1;
+    if (est || bd || its >= maxit) ctrl->stop = 1;
 }
 
 // Back substitution R_k y = g_{1:k} (column-oriented, R staged in LDS);
