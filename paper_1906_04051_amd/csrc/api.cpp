@@ -120,12 +120,15 @@ struct gmres_plan_s {
     int64_t az_nnz = 0;
     double *E = nullptr, *Einv = nullptr;
     // sliced ELL copies (forward op / adjoint op)
-    int *sell_off = nullptr, *sell_col = nullptr, *sell_src = nullptr;
+    int *sell_off = nullptr, *sell_src = nullptr;
+    short* sell_col = nullptr;   // 16-bit column offsets (NULL: no sliced ELL copy)
     double* sell_v64 = nullptr;
     float* sell_v32 = nullptr;
     int64_t sell_total = 0;
     int sell_wmax = 0, tsell_wmax = 0;
-    int *tsell_off = nullptr, *tsell_col = nullptr, *tsell_src = nullptr;
+    int sell_wuni = 0, tsell_wuni = 0;   // uniform slice widths (0: not uniform)
+    int *tsell_off = nullptr, *tsell_src = nullptr;
+    short* tsell_col = nullptr;
     double* tsell_v64 = nullptr;
     int64_t tsell_total = 0;
     // adjoint operator
@@ -205,9 +208,9 @@ gmres_status to_status(int s, const char* what) {
 
 // SpMV variant: > 0 lanes per row; -256 / -128 LDS-staged stream with that
 // many rows per block; kSell (-64) sliced ELL (short rows: FEM stencils).
-int default_lanes(int64_t n, int64_t nnz) {
+int default_lanes(int64_t n, int64_t nnz, bool have_sell) {
     const double rho = n > 0 ? (double)nnz / (double)n : 1.0;
-    if (rho <= 40) return kSell;
+    if (rho <= 40) return have_sell ? kSell : 4;
     return 32;
 }
 
@@ -417,12 +420,14 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.fuse_rb = (p->R > 0 && rb != 0 && rb == p->slots_rb) ? rb : 0;
     if (op == 0) {
         a.sell_off = p->sell_off;
+        a.sell_wuni = p->sell_wuni;
         a.sell_col = p->sell_col;
         a.sell_val = f64 ? (const void*)p->sell_v64 : (const void*)p->sell_v32;
         a.sell_wmax = p->sell_wmax;
     } else {
         a.sell_wmax = p->tsell_wmax;
         a.sell_off = p->tsell_off;
+        a.sell_wuni = p->tsell_wuni;
         a.sell_col = p->tsell_col;
         a.sell_val = p->tsell_v64;
     }
@@ -607,14 +612,14 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
 // ||b - A x|| in FP64 (scratch: p->w, partial slot of p->part).
 void spmv_f64(gmres_plan_s* p, int L, int NB, const double* x, double* y) {
     if (L == kSell)
-        launch_spmv_sell_f64(p->st, NB, (int)p->n, p->sell_off, p->sell_col, p->sell_v64, x, y);
+        launch_spmv_sell_f64(p->st, NB, (int)p->n, p->sell_off, p->sell_wuni, p->sell_col, p->sell_v64, x, y);
     else
         launch_spmv_f64(p->st, L, NB, (int)p->n, p->rowptr, p->colind, p->vals, x, y);
 }
 
 void residual_f64(gmres_plan_s* p, const double* x, const double* b, double* r, int slot) {
     if (p->L == kSell)
-        launch_residual_sell_f64(p->st, p->NB, (int)p->n, p->sell_off, p->sell_col, p->sell_v64, x,
+        launch_residual_sell_f64(p->st, p->NB, (int)p->n, p->sell_off, p->sell_wuni, p->sell_col, p->sell_v64, x,
                                  b, r, p->part, slot);
     else
         launch_residual_f64(p->st, p->L, p->NB, (int)p->n, p->rowptr, p->colind, p->vals, x, b, r,
@@ -771,7 +776,8 @@ void gmres_destroy(gmres_plan p) {
         }
     for (void* q : p->allocs) hipFree(q);
     for (int* q : {p->bb_ptr, p->bb_col, p->ab_ptr, p->ab_slot, p->slot_pos}) hipFree(q);
-    for (int* q : {p->sell_off, p->sell_col, p->sell_src, p->tsell_off, p->tsell_col, p->tsell_src}) hipFree(q);
+    for (int* q : {p->sell_off, p->sell_src, p->tsell_off, p->tsell_src}) hipFree(q);
+    for (short* q : {p->sell_col, p->tsell_col}) hipFree(q);
     if (p->ctrl_h) hipHostFree(p->ctrl_h);
     for (auto e : {p->ev_cyc[0], p->ev_cyc[1], p->ev_in, p->ev_out})
         if (e) hipEventDestroy(e);
@@ -906,21 +912,24 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     {
         int* tmp_src = nullptr;
         CHECK(to_status(sell_build(p->st, n, p->rowptr, p->colind, &p->sell_off, &p->sell_col,
-                                   &tmp_src, &p->sell_total), "sliced ELL"));
+                                   &tmp_src, &p->sell_total, &p->sell_wuni), "sliced ELL"));
         p->sell_src = tmp_src;
         p->sell_wmax = max_row_len(p->st, n, p->rowptr, p->d_flags);
         CHECK(dalloc(p, &p->sell_v64, std::max<int64_t>(p->sell_total, 1)));
         if (p->o.precision != GMRES_FP64) CHECK(dalloc(p, &p->sell_v32, std::max<int64_t>(p->sell_total, 1)));
         if (p->need_adjoint) {
             CHECK(to_status(sell_build(p->st, n, p->trp, p->tci, &p->tsell_off, &p->tsell_col,
-                                       &p->tsell_src, &p->tsell_total), "sliced ELL (A^T)"));
+                                       &p->tsell_src, &p->tsell_total, &p->tsell_wuni),
+                            "sliced ELL (A^T)"));
             CHECK(dalloc(p, &p->tsell_v64, std::max<int64_t>(p->tsell_total, 1)));
             p->tsell_wmax = max_row_len(p->st, n, p->trp, p->d_flags);
         }
     }
     CHECK(refresh_values(p));
 
-    p->L = p->o.spmv_lanes != 0 ? p->o.spmv_lanes : default_lanes(n, nnz);
+    if (p->o.spmv_lanes == kSell && !p->sell_col)
+        return fail(GMRES_EINVAL, "spmv_lanes = -64 needs column offsets col - row within +-32767");
+    p->L = p->o.spmv_lanes != 0 ? p->o.spmv_lanes : default_lanes(n, nnz, p->sell_col != nullptr);
     p->NB = p->o.num_blocks > 0 ? p->o.num_blocks
                                 : (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 1024);
     if (nsys == 1) CHECK(alloc_krylov(p));
@@ -1211,6 +1220,7 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
         double best = 1e30;
         int bestL = p->L;
         for (int L : {kSell, -256, 2, 4, 8, 16, 32}) {
+            if (L == kSell && !p->sell_col) continue;
             const double t = time_it([&] { spmv_f64(p, L, p->NB, (double*)p->V, p->y); }, 10);
             if (t < best) { best = t; bestL = L; }
         }

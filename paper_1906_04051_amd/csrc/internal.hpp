@@ -73,7 +73,9 @@ struct EngineArgs {
     const int* azc1;        // A Z two-entry rows (ELL-2, 2 per row, interleaved) of the operator
     const void* azv1;       // AT, 2 per row
     // Sliced ELL copy of the operator (used when L == kSell).
-    const int *sell_off, *sell_col;
+    const int* sell_off;
+    int sell_wuni;          // > 0: every slice has this width (entries per row); off unused
+    const short* sell_col;  // 16-bit column offsets from the row
     const void* sell_val;   // AT
     int sell_wmax;          // widest slice (entries per row)
     double *s_step, *s_res; // coarse solutions (per step / per restart)
@@ -110,11 +112,11 @@ void launch_residual_f64(hipStream_t st, int L, int NB, int n, const int* rp, co
 void launch_sum_slot(hipStream_t st, const double* part, int NB, int slot, double* out);
 void launch_spmv_f64(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
                      const double* v, const double* x, double* y);
-void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
-                          const double* val, const double* x, double* y);
-void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
-                              const double* val, const double* x, const double* b, double* r,
-                              double* part, int slot);
+void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
+                          const short* col, const double* val, const double* x, double* y);
+void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
+                              const short* col, const double* val, const double* x,
+                              const double* b, double* r, double* part, int slot);
 void launch_spmv_f32(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
                      const float* v, const float* x, float* y);
 void launch_scale_to_f32(hipStream_t st, int NB, int n, const double* r, const double* nrm2,
@@ -156,7 +158,7 @@ void grad_vals(hipStream_t st, int64_t n, const int* rowptr, const int* colind, 
 int zt_max_row(hipStream_t st, int R, const int* ztrp, int* d_tmp);
 // Sliced ELL (64-row slices) of a CSR matrix; buffers hipMalloc'ed here.
 int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
-               int** scol, int** src, int64_t* total);
+               short** scol, int** src, int64_t* total, int* wuni);
 void sell_values(hipStream_t st, int64_t total, const int* src, const double* vals, double* v64,
                  float* v32);
 // Single-entry row copies of a CSR (see setup.hip); c1 may be NULL (values only).

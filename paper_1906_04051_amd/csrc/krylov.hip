@@ -185,8 +185,8 @@ __global__ __launch_bounds__(RB) void k_spmv_stream(int n, const int* __restrict
 // every load instruction reads 64 consecutive entries of one slice column.
 // MODE / ZT as for the stream kernel (RB = 256 row blocks for the slots).
 template <int MODE, bool ZT, int WMAX, typename AT, typename XT, typename BT, typename YT, typename ACC>
-__global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict__ off,
-                                                   const int* __restrict__ scol,
+__global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict__ off, int wuni,
+                                                   const short* __restrict__ scol,
                                                    const AT* __restrict__ sval,
                                                    const XT* __restrict__ x,
                                                    const double* __restrict__ scale_ptr,
@@ -202,29 +202,50 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
                                                    const double* __restrict__ zv1,
                                                    double* __restrict__ tpart, const Ctrl* ctrl,
                                                    int gate) {
-    if (gated(ctrl, gate)) return;
     __shared__ ACC red[kWG / kWave];
     __shared__ double sred[ZT ? kWG / kWave : 1][kBlockColsMax];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
+    // The control block is requested here and tested after the first row
+    // block's independent loads are in flight (the test is uniform).
+    const bool stopped = gated(ctrl, gate);
     const ACC scale = (MODE == 0 && scale_ptr) ? (ACC)(*scale_ptr) : (ACC)1;
     ACC nrm = 0;
     for (int64_t r0 = (int64_t)blockIdx.x * kWG; r0 < n; r0 += (int64_t)gridDim.x * kWG) {
         const int64_t row = r0 + threadIdx.x;
+        const int64_t sl = r0 / kWave + wv;
+        // Loads that do not depend on each other: slice bounds (none when every
+        // slice has the same width), the row's Z entry, b, the block's slots.
+        int q0, w;
+        if (wuni > 0) {
+            q0 = (int)(sl * wuni * kWave);
+            w = wuni;
+        } else {
+            // The slice bounds are the same in every lane of the wavefront.
+            q0 = __builtin_amdgcn_readfirstlane(off[sl]);
+            w = (__builtin_amdgcn_readfirstlane(off[sl + 1]) - q0) / kWave;
+        }
         int zc = -1;
         ACC zvv = 0;
         if (ZT && row < n) {
             zc = zc1[row];
             zvv = (ACC)zv1[row];
         }
+        ACC bv = 0;
+        if (MODE == 1 && row < n) bv = (ACC)b[row];
+        int l0 = 0, l1 = 0;
+        if (ZT) {
+            const int64_t blk = r0 / kWG;
+            l0 = bb_ptr[blk];
+            l1 = bb_ptr[blk + 1];
+        }
+        if (stopped) return;
         ACC acc = 0;
         if (row < n) {
-            const int64_t sl = r0 / kWave + wv;
-            const int q0 = off[sl];
-            const int w = (off[sl + 1] - q0) / kWave;
             const int q = q0 + lane;
+            const XT* __restrict__ xr = x + row;   // columns are stored as offsets from the row
             if (w <= WMAX) {
-                // Column indices and values of the whole row first, then the gathers.
+                // Column offsets and values of the whole row first, then the gathers.
                 int cc[WMAX];
                 AT vv[WMAX];
 #pragma unroll
@@ -236,14 +257,14 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
                 ACC xv[WMAX];
 #pragma unroll
                 for (int k = 0; k < WMAX; ++k)
-                    if (k < w) xv[k] = (ACC)ld_f(x + cc[k]);
+                    if (k < w) xv[k] = (ACC)ld_f(xr + cc[k]);
 #pragma unroll
                 for (int k = 0; k < WMAX; ++k)
                     if (k < w) acc += (ACC)vv[k] * xv[k];
             } else {
 #pragma unroll 4
                 for (int k = 0; k < w; ++k)
-                    acc += (ACC)sval[q + k * kWave] * (ACC)ld_f(x + scol[q + k * kWave]);
+                    acc += (ACC)sval[q + k * kWave] * (ACC)ld_f(xr + scol[q + k * kWave]);
             }
         }
         ACC yi = 0;
@@ -253,18 +274,17 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
                 y[row] = v;
                 yi = (ACC)v;
             } else {
-                const YT v = (YT)((ACC)b[row] - acc);
+                const YT v = (YT)(bv - acc);
                 y[row] = v;
                 yi = (ACC)v;
                 nrm += yi * yi;
             }
         }
-        if (ZT) {
-            const int64_t blk = r0 / kWG;
-            block_slots<kWG, ACC>(bb_ptr[blk], bb_ptr[blk + 1], bb_col, slot_pos, zc, zvv, yi,
-                                  row < n, row, zrp, zci, zv, tpart, sred);
-        }
+        if (ZT)
+            block_slots<kWG, ACC>(l0, l1, bb_col, slot_pos, zc, zvv, yi, row < n, row, zrp, zci,
+                                  zv, tpart, sred);
     }
+    if (stopped) return;
     if (MODE == 1) {
         const ACC t = block_sum_n<kWG>(nrm, red);
         if (threadIdx.x == 0) part[(int64_t)slot * NB + blockIdx.x] = (double)t;
@@ -1363,11 +1383,11 @@ static void sell_launch_w(const EngineArgs& e, const XT* x, const double* scale,
     const int grid = MODE == 0 ? (int)std::max<int64_t>(1, ((int64_t)e.n + kWG - 1) / kWG) : e.NB;
     if (e.R > 0 && e.fuse_rb == 256)
         launch(k_spmv_sell<MODE, true, WMAX, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st, 
-            e.n, e.sell_off, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
+            e.n, e.sell_off, e.sell_wuni, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
             e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
     else
         launch(k_spmv_sell<MODE, false, WMAX, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st, 
-            e.n, e.sell_off, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, nullptr, nullptr,
+            e.n, e.sell_off, e.sell_wuni, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, nullptr, nullptr,
             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, e.ctrl, gate);
 }
 
@@ -1679,18 +1699,18 @@ void launch_spmv_f64(hipStream_t st, int L, int NB, int n, const int* rp, const 
     spmv_dispatch<double, double, double, double>(L, NB, st, n, rp, ci, v, x, nullptr, y, nullptr, 0);
 }
 
-void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
-                          const double* val, const double* x, double* y) {
+void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
+                          const short* col, const double* val, const double* x, double* y) {
     k_spmv_sell<0, false, 32, double, double, double, double, double><<<NB, kWG, 0, st>>>(
-        n, off, col, val, x, nullptr, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr,
+        n, off, wuni, col, val, x, nullptr, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 
-void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* col,
-                              const double* val, const double* x, const double* b, double* r,
-                              double* part, int slot) {
+void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
+                              const short* col, const double* val, const double* x,
+                              const double* b, double* r, double* part, int slot) {
     k_spmv_sell<1, false, 32, double, double, double, double, double><<<NB, kWG, 0, st>>>(
-        n, off, col, val, x, nullptr, b, r, part, slot, NB, nullptr, nullptr, nullptr, nullptr,
+        n, off, wuni, col, val, x, nullptr, b, r, part, slot, NB, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 

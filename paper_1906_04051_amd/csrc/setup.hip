@@ -8,6 +8,8 @@
 // rows accumulate in CSR order, E entries in Z^T order.
 #include <hipcub/hipcub.hpp>
 
+#include <vector>
+
 #include "internal.hpp"
 
 namespace gm {
@@ -425,9 +427,12 @@ int lu_inverse(hipStream_t st, int nsys, const int64_t* d_sys_zcol_off, const in
 // --------------------------------------------------------- sliced ELL (SELL-64)
 // Rows are grouped in slices of 64 (one wavefront); slice s stores its rows'
 // entries column-major, width = longest row of the slice: entry (row, k) at
-// off[s] + k*64 + (row % 64).  Padding entries point at the row itself with a
-// zero value.  src[q] is the CSR index of entry q (-1 for padding), used to
-// refresh values.
+// off[s] + k*64 + (row % 64).  Column indices are stored as 16-bit offsets
+// from the row (col - row), which mesh orderings keep small; the copy is not
+// built (all outputs NULL, status OK) when an offset falls outside
+// [-32767, 32767].  Padding entries point
+// at the row itself (offset 0) with a zero value.  src[q] is the CSR index of
+// entry q (-1 for padding), used to refresh values.
 
 __global__ void k_sell_width(int64_t n, const int* __restrict__ rowptr, int* __restrict__ wsz) {
     const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -440,7 +445,8 @@ __global__ void k_sell_width(int64_t n, const int* __restrict__ rowptr, int* __r
 }
 
 __global__ void k_sell_fill(int64_t n, const int* __restrict__ rowptr, const int* __restrict__ colind,
-                            const int* __restrict__ off, int* __restrict__ scol, int* __restrict__ src) {
+                            const int* __restrict__ off, short* __restrict__ scol,
+                            int* __restrict__ src, int* __restrict__ overflow) {
     const int64_t sl = (int64_t)blockIdx.x;     // one block of 64 threads per slice
     const int64_t i = sl * 64 + threadIdx.x;
     const int w = (off[sl + 1] - off[sl]) / 64;
@@ -450,10 +456,13 @@ __global__ void k_sell_fill(int64_t n, const int* __restrict__ rowptr, const int
     for (int k = 0; k < w; ++k) {
         const int q = base + k * 64;
         if (k < len) {
-            scol[q] = colind[k0 + k];
+            const int64_t d = (int64_t)colind[k0 + k] - i;
+            const bool out = d < -32767 || d > 32767;   // symmetric, so A^T fits too
+            if (out) *overflow = 1;
+            scol[q] = (short)(out ? 0 : d);
             src[q] = k0 + k;
         } else {
-            scol[q] = i < n ? (int)i : 0;
+            scol[q] = 0;
             src[q] = -1;
         }
     }
@@ -470,9 +479,11 @@ __global__ void k_sell_vals(int64_t m, const int* __restrict__ src, const double
 }
 
 int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
-               int** scol, int** src, int64_t* total) {
+               short** scol, int** src, int64_t* total, int* wuni) {
     const int64_t nsl = (n + 63) / 64;
-    *off = *scol = *src = nullptr;
+    *off = *src = nullptr;
+    *scol = nullptr;
+    *wuni = 0;
     int* wsz = nullptr;
     void* tmp = nullptr;
     size_t tb = 0;
@@ -491,20 +502,38 @@ int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, 
         hipMemcpyAsync(&h, *off + nsl, sizeof(int), hipMemcpyDeviceToHost, st);
         if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
     }
-    if (status == kStatusOk && (hipMalloc(scol, std::max(h, 1) * sizeof(int)) != hipSuccess ||
+    if (status == kStatusOk && (hipMalloc(scol, std::max(h, 1) * sizeof(short)) != hipSuccess ||
                                 hipMalloc(src, std::max(h, 1) * sizeof(int)) != hipSuccess))
         status = kStatusNoMem;
+    int ovf = 0;
     if (status == kStatusOk) {
-        if (nsl > 0) k_sell_fill<<<(unsigned)nsl, 64, 0, st>>>(n, rowptr, colind, *off, *scol, *src);
+        // wsz (nsl + 1 ints) is free again: its first entry is the overflow flag.
+        hipMemsetAsync(wsz, 0, sizeof(int), st);
+        if (nsl > 0)
+            k_sell_fill<<<(unsigned)nsl, 64, 0, st>>>(n, rowptr, colind, *off, *scol, *src, wsz);
+        hipMemcpyAsync(&ovf, wsz, sizeof(int), hipMemcpyDeviceToHost, st);
         if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
     }
     hipFree(wsz);
     hipFree(tmp);
-    if (status != kStatusOk) {
+    if (status != kStatusOk || ovf) {
         hipFree(*off);
         hipFree(*scol);
         hipFree(*src);
-        *off = *scol = *src = nullptr;
+        *off = *src = nullptr;
+        *scol = nullptr;
+        h = 0;
+    }
+    if (status == kStatusOk && nsl > 0 && *off) {
+        // Uniform width (every slice as wide as the first): the kernels then
+        // compute slice offsets instead of loading them.
+        std::vector<int> ho((size_t)nsl + 1);
+        if (hipMemcpy(ho.data(), *off, (nsl + 1) * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            status = kStatusDevice;
+        const int w0 = ho[1] - ho[0];
+        bool uni = status == kStatusOk && w0 > 0 && w0 % 64 == 0;
+        for (int64_t q = 0; uni && q <= nsl; ++q) uni = (int64_t)ho[q] == q * w0;
+        if (uni) *wuni = w0 / 64;
     }
     *total = h;
     return status;

@@ -81,12 +81,38 @@ def test_spmv_integer_exact_all_lane_counts():
                  z_colind=np.zeros(0, np.int32), z_vals=np.zeros(0))
     x = rng.integers(-4, 5, size=n).astype(np.float64)
     ref = oracle.spmv(s.rowptr, s.colind, s.vals, x)
-    for L in (1, 2, 4, 8, 16, 32, 64):
+    for L in (1, 2, 4, 8, 16, 32, 64, -64, -128, -256):
         say("spmv integer L =", L)
         plan, d = G().plan_for(s, m=4, spmv_lanes=L)
         y = plan.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
         assert np.array_equal(y, ref), L
         plan.close()
+
+
+def test_spmv_far_columns_without_sliced_ell():
+    """Column offsets |col - row| > 32767 do not fit the 16-bit sliced-ELL
+    copy: the plan falls back to the CSR kernels (exact on integer data) and an
+    explicit request for the sliced-ELL kernel is rejected."""
+    n = 70001
+    rows = np.concatenate([np.arange(n), np.arange(1, n), [0, n - 1]])
+    cols = np.concatenate([np.arange(n), np.arange(n - 1), [n - 1, 0]])
+    vals = np.concatenate([np.full(n, 4.0), np.full(n - 1, -1.0), [2.0, -3.0]])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    s = W.System(n=n, rowptr=rowptr, colind=cols.astype(np.int32), vals=vals.astype(np.float64),
+                 b=np.zeros(n), r=0, z_rowptr=np.zeros(n + 1, np.int32),
+                 z_colind=np.zeros(0, np.int32), z_vals=np.zeros(0))
+    x = np.random.default_rng(13).integers(-4, 5, size=n).astype(np.float64)
+    ref = oracle.spmv(s.rowptr, s.colind, s.vals, x)
+    plan, d = G().plan_for(s, m=4)
+    assert np.array_equal(plan.spmv(torch.from_numpy(x).cuda()).cpu().numpy(), ref)
+    plan.close()
+    with pytest.raises(G().GmresError) as e:
+        G().plan_for(s, m=4, spmv_lanes=-64)
+    assert e.value.status == -1
 
 
 @pytest.mark.parametrize("cfg,mesh", [(1, 64), (2, 96), (3, 24)])
