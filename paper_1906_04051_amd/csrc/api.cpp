@@ -489,13 +489,28 @@ struct TimerHook final : KTimer {
     int open_ev = -1;
     bool lagged = false;
     TimerHook(gmres_plan_s* pp, int pr, int o) : p(pp), prec(pr), op(o), lagged(pp->o.ortho == 1) {}
+    // Algorithmic bytes of one launch: every array the kernel's scheme reads or
+    // writes, touched once (cache hits not credited).  A Z is read through its
+    // two-entry row copy (int32 column pairs and value pairs per row).
     double kernel_bytes(int kind, int j) const {
         const double n = (double)p->n, nnz = (double)p->nnz;
         const double bv = type_bytes(prec, 1), bw = type_bytes(prec, 2), ba = type_bytes(prec, 0);
         const double nv = j + 1;
-        const double az = p->R > 0 ? 4.0 * (n + 1) + (4.0 + ba) * (double)p->az_nnz + 8.0 * p->R : 0.0;
+        const double az = p->R > 0 ? (8.0 + 2.0 * ba) * n + 8.0 * p->R : 0.0;
         switch (kind) {
-            case 0: return (ba + 4.0) * nnz + 4.0 * (n + 1) + bv * n + bw * n;
+            case 0: {
+                // Input: the stored v_0 (or v_j, three-sweep variant), else the
+                // once-projected work vector.  Fused Z^T y reads Z's ELL-1 copy.
+                const double bx = (!lagged || j == 0) ? bv : bw;
+                const double zt = p->R > 0 ? 12.0 * n : 0.0;
+                const bool t = op == 1;
+                const int64_t total = t ? p->tsell_total : p->sell_total;
+                const int wuni = t ? p->tsell_wuni : p->sell_wuni;
+                if (p->L == kSell && total > 0)
+                    return (ba + 2.0) * (double)total + (wuni ? 0.0 : 4.0 * (n / 64.0 + 1.0)) +
+                           bx * n + bw * n + zt;
+                return (ba + 4.0) * nnz + 4.0 * (n + 1) + bx * n + bw * n + zt;
+            }
             case 1:
                 if (lagged && j > 0)   // reads V_0..j-1, w1, u; writes v_j, w
                     return bv * n * (nv - 1) + bv * n + 3.0 * bw * n + az;
