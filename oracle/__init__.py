@@ -5,8 +5,8 @@ CPU-baseline leg are the only callers.  The GPU solver never imports this
 package and this package never imports the solver; both take inputs from
 ``paper_1906_04051_amd.workloads`` only.
 
-Every numerical routine lives in ``oracle.c`` (plain C, FP64,
-``-ffp-contract=off``).  This module only marshals numpy arrays.
+Every numerical routine lives in ``oracle.c`` and ``dgmres.c`` (plain C,
+FP64, ``-ffp-contract=off``).  This module only marshals numpy arrays.
 
 Parity pins: see ``tests/test_oracle.py``.  Functions without an independent
 pin: none (the dense adjoint in ``dense_adjoint`` is itself the pin of the
@@ -23,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_D = os.path.join(_HERE, "dgmres.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -32,7 +33,7 @@ STATUS = {0: "OK", 1: "MAXITER", -1: "EINVAL", -2: "ESINGULAR", -3: "ENONFINITE"
 def build() -> str:
     """Compile liboracle.so (gcc, -O2, no FP contraction)."""
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           _SRC, "-o", _LIB + ".tmp", "-lm"]
+           _SRC, _SRC_D, "-o", _LIB + ".tmp", "-lm"]
     subprocess.check_call(cmd)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -68,6 +69,15 @@ def _load():
     lib.oracle_csr_transpose.restype = None
     lib.oracle_grad_vals.argtypes = [C.c_int64, i32p, i32p, f64p, f64p, f64p]
     lib.oracle_grad_vals.restype = None
+    lib.oracle_dgmres.argtypes = [C.c_int64, i32p, i32p, f64p, f64p, vp, C.c_int32, C.c_int64,
+                                  C.c_double, C.c_int32, f64p, i64p, f64p, vp, vp, vp]
+    lib.oracle_dgmres.restype = C.c_int
+    lib.oracle_power_iteration.argtypes = [C.c_int32, f64p, f64p]
+    lib.oracle_power_iteration.restype = C.c_double
+    lib.oracle_inverse_iteration.argtypes = [C.c_int32, f64p, f64p]
+    lib.oracle_inverse_iteration.restype = C.c_int
+    lib.oracle_apply_minv.argtypes = [C.c_int64, C.c_int32, f64p, f64p, C.c_double, f64p, f64p]
+    lib.oracle_apply_minv.restype = C.c_int
     _lib = lib
     return lib
 
@@ -155,6 +165,62 @@ def gmres(sysm, m: int, rtol: float, max_iters: int, x0=None, b=None, r0_norm_ov
         res["V0"] = V0
         res["H0"] = H0
     return res
+
+
+def dgmres(sysm, m: int, rtol: float, max_iters: int, rmax: int = 20, x0=None, b=None,
+           history: bool = False, export: bool = False) -> Result:
+    """GMRES(m) right-preconditioned by the paper's adaptive spectral deflation
+    (Sec. 3.3; readings in dgmres.c).  Uses A and b of System `sysm` (its Z is
+    ignored).  rmax = 0 gives plain GMRES(m)."""
+    lib = _load()
+    n = sysm.n
+    b = _f64(sysm.b if b is None else b)
+    x0a = None if x0 is None else _f64(x0)
+    x = np.zeros(n, np.float64)
+    info_i = np.zeros(4, np.int64)
+    info_d = np.zeros(4, np.float64)
+    hist = np.zeros(max(max_iters, 1), np.float64) if history else None
+    U = np.zeros((max(rmax, 1), n), np.float64) if export else None
+    T = np.zeros((max(rmax, 1), max(rmax, 1)), np.float64) if export else None
+    st = lib.oracle_dgmres(n, _i32(sysm.rowptr), _i32(sysm.colind), _f64(sysm.vals), b, _ptr(x0a),
+                           m, max_iters, rtol, rmax, x, info_i, info_d, _ptr(hist), _ptr(U), _ptr(T))
+    res = Result(x=x, iters=int(info_i[0]), cycles=int(info_i[1]), status=int(st),
+                 status_name=STATUS.get(int(st), str(st)), r=int(info_i[3]), rho0=float(info_d[0]),
+                 rel_res=float(info_d[1]), rel_res_true=float(info_d[2]), mu=float(info_d[3]))
+    if history:
+        res["history"] = hist[:res.iters].copy()
+    if export:
+        rr = res.r
+        res["U"] = U[:rr].copy()
+        res["T"] = T.ravel()[:rr * rr].reshape(rr, rr).copy()
+    return res
+
+
+def apply_minv(U, T, mu, v):
+    """M^{-1} v = v + U (|mu| T^{-1} - I) U^T v for U given as r x n rows."""
+    U = _f64(U)
+    r, n = U.shape
+    out = np.zeros(n, np.float64)
+    st = _load().oracle_apply_minv(n, r, U, _f64(T), float(mu), _f64(v), out)
+    if st != 0:
+        raise RuntimeError("oracle_apply_minv: " + STATUS.get(st, str(st)))
+    return out
+
+
+def power_iteration(M):
+    """(|mu|, z): the oracle's fixed-count power iteration on a small matrix."""
+    M = _f64(M)
+    z = np.zeros(M.shape[0], np.float64)
+    mu = _load().oracle_power_iteration(M.shape[0], M, z)
+    return mu, z
+
+
+def inverse_iteration(M):
+    """(status, z): the oracle's fixed-count inverse iteration on a small matrix."""
+    M = _f64(M)
+    z = np.zeros(M.shape[0], np.float64)
+    st = _load().oracle_inverse_iteration(M.shape[0], M, z)
+    return st, z
 
 
 def csr_transpose(rowptr, colind, vals):

@@ -404,3 +404,113 @@ def test_adjoint_against_dense_and_fd():
         Lp.append(0.5 * np.dot(xs - xt, xs - xt))
     fd = (Lp[0] - Lp[1]) / (2 * h)
     assert abs(fd - dkappa) <= 1e-5 * abs(dkappa)
+
+
+# ------------------------------------------- adaptive spectral deflation (Sec. 3.3)
+
+def _spd_with_spectrum(lam, rng):
+    n = len(lam)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return Q @ np.diag(lam) @ Q.T, Q
+
+
+def test_minv_maps_invariant_subspace_to_mu():
+    """Eq. precond2 with U an exact invariant subspace (A U = U Lambda, T = U^T A U
+    = Lambda): A M^{-1} U = |mu| U, and M^{-1} v = v for v orthogonal to U."""
+    rng = np.random.default_rng(21)
+    lam = np.array([0.01, 0.03, 0.1, 1.0, 2.0, 3.0, 5.0, 8.0, 9.0, 10.0])
+    A, Q = _spd_with_spectrum(lam, rng)
+    U = Q[:, :3]
+    T = U.T @ A @ U
+    mu = 10.0
+    for q in range(3):
+        y = A @ oracle.apply_minv(U.T, T, mu, U[:, q])
+        assert np.allclose(y, mu * U[:, q], atol=1e-10)
+    v = Q[:, 5] + 0.5 * Q[:, 8]
+    assert np.allclose(oracle.apply_minv(U.T, T, mu, v), v, atol=1e-13)
+    # The spectrum of A M^{-1}: the three smallest eigenvalues move to |mu|.
+    AM = np.stack([A @ oracle.apply_minv(U.T, T, mu, np.eye(10)[:, k]) for k in range(10)], axis=1)
+    ev = np.sort(np.linalg.eigvals(AM).real)
+    assert np.allclose(ev, np.sort(np.concatenate([lam[3:], [mu] * 3])), atol=1e-9)
+
+
+def test_power_and_inverse_iteration_against_eig():
+    """The fixed-count iterations find the dominant and the smallest eigenpair
+    of a matrix whose extreme eigenvalues are real and well separated."""
+    rng = np.random.default_rng(22)
+    n = 12
+    lam = np.array([0.05, 0.9, 1.0, 1.2, 1.5, 1.7, 2.0, 2.2, 2.5, 2.7, 3.0, 9.0])
+    S = rng.standard_normal((n, n)) + 4 * np.eye(n)
+    M = S @ np.diag(lam) @ np.linalg.inv(S)
+    mu, z = oracle.power_iteration(M)
+    assert abs(mu - 9.0) <= 1e-6 * 9.0
+    e_big = S[:, -1] / np.linalg.norm(S[:, -1])
+    assert abs(abs(z @ e_big) - 1.0) <= 1e-8
+    st, z = oracle.inverse_iteration(M)
+    assert st == 0
+    e_small = S[:, 0] / np.linalg.norm(S[:, 0])
+    assert abs(abs(z @ e_small) - 1.0) <= 1e-10
+    st, _ = oracle.inverse_iteration(np.diag([1.0, 0.0, 2.0]))
+    assert st != 0
+
+
+def test_dgmres_without_deflation_is_gmres():
+    """r_max = 0 gives M^{-1} = I: plain GMRES(m), the same trajectory as the
+    pinned deflated GMRES with an empty Z."""
+    s = _no_defl(_small_cd())
+    ref = oracle.gmres(s, 12, 1e-9, 3000, history=True)
+    res = oracle.dgmres(s, 12, 1e-9, 3000, rmax=0, history=True)
+    assert res.status_name == "OK" and res.iters == ref.iters and res.r == 0
+    assert np.allclose(res.history, ref.history, rtol=1e-8, atol=1e-14 * ref.rho0)
+    assert np.linalg.norm(res.x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_dgmres_solves_and_keeps_invariants():
+    """Adaptive deflation: the returned x meets the tolerance on the true
+    residual, U stays orthonormal with r <= r_max, T = U^T A U."""
+    s = _small_cd()
+    A = W.dense(s)
+    for rmax in (3, 20):
+        res = oracle.dgmres(s, 10, 1e-10, 5000, rmax=rmax, export=True)
+        assert res.status_name == "OK"
+        r = np.linalg.norm(s.b - A @ res.x)
+        assert r <= 1e-10 * res.rho0 * (1 + 1e-6)
+        assert abs(r / res.rho0 - res.rel_res_true) <= 1e-12
+        U = res.U.T
+        assert 1 <= res.r <= rmax
+        assert np.linalg.norm(U.T @ U - np.eye(res.r)) <= 1e-10
+        assert np.linalg.norm(res.T - U.T @ A @ U) <= 1e-10 * np.linalg.norm(A, 2)
+
+
+def test_dgmres_estimate_is_true_residual_after_one_cycle():
+    """Right preconditioning keeps |gamma_{k+1}| = ||b - A x_k|| (eq. res)."""
+    s = _small_cd()
+    res = oracle.dgmres(s, 15, 0.0, 15, rmax=5, history=True)
+    assert res.iters == 15
+    assert abs(res.history[-1] - res.rel_res_true * res.rho0) <= 1e-9 * res.rho0
+
+
+def test_dgmres_deflation_reduces_iterations():
+    """Deflating the small Ritz directions speeds up GMRES(m) on a
+    diffusion-dominated problem (Sec. 3.3, convergence figure)."""
+    s = W.make_config(1, mesh=24)
+    plain = oracle.dgmres(s, 10, 1e-8, 20000, rmax=0)
+    defl = oracle.dgmres(s, 10, 1e-8, 20000, rmax=20)
+    assert plain.status_name == "OK" and defl.status_name == "OK"
+    assert defl.iters < 0.8 * plain.iters
+
+
+def test_dgmres_removal_keeps_smallest_directions():
+    """With r_max = 2 the removal keeps U orthonormal and T consistent after
+    many restarts; the kept directions have Rayleigh quotients near the small
+    end of the spectrum."""
+    rng = np.random.default_rng(23)
+    lam = np.concatenate([[0.001, 0.002], np.linspace(1.0, 2.0, 58)])
+    A, Q = _spd_with_spectrum(lam, rng)
+    s = W.from_dense(A, rng.standard_normal(60))
+    res = oracle.dgmres(s, 6, 1e-12, 4000, rmax=2, export=True)
+    assert res.status_name == "OK" and res.r == 2
+    U = res.U.T
+    assert np.linalg.norm(U.T @ U - np.eye(2)) <= 1e-10
+    assert np.linalg.norm(res.T - U.T @ A @ U) <= 1e-10 * 2.0
+    assert np.max(np.abs(np.linalg.eigvals(res.T))) < 0.5
