@@ -58,12 +58,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sysm, m, fp64_iters, sample_iters):
+def cpu_baseline(sysm, m, fp64_iters, sample_iters, adapt_rmax=0):
     """Oracle (plain C, FP64, one thread) on `sample_iters` inner steps of the
     same system; time-to-rtol extrapolated with the solve's iteration count."""
     import oracle
     t0 = time.perf_counter()
-    res = oracle.gmres(sysm, m, 0.0, sample_iters)
+    if adapt_rmax > 0:
+        res = oracle.dgmres(sysm, m, 0.0, sample_iters, rmax=adapt_rmax)
+    else:
+        res = oracle.gmres(sysm, m, 0.0, sample_iters)
     dt = time.perf_counter() - t0
     per_iter = dt / max(res.iters, 1)
     return dict(value=per_iter * fp64_iters, unit="s", cores=1, kind="oracle",
@@ -114,6 +117,9 @@ def main():
                     help="tolerance of each inner solve (default 1e-3 for f16, 1e-5 for f32)")
     ap.add_argument("--ortho", type=int, default=1, choices=[0, 1],
                     help="0: CGS2 in three sweeps; 1: CGS2 in two sweeps (lagged normalisation)")
+    ap.add_argument("--adaptive", type=int, default=0, metavar="RMAX",
+                    help="instead of the default step: one FP64 solve right-preconditioned by "
+                         "adaptive spectral deflation with at most RMAX Ritz vectors (no fixed Z)")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short fixed-count FP64 run (two restart cycles) plus a copy of known "
                          "size, for hardware-counter collection")
@@ -130,16 +136,35 @@ def main():
     torch.cuda.set_device(0)
     cfg = W.CONFIGS[2]
     m = cfg["m"]
-    log(f"[bench] generating config 2 at mesh {args.mesh}")
-    sysm = W.make_config(2, mesh=args.mesh)
-    d = G.upload(sysm)
+    if args.adaptive == 0:
+        log(f"[bench] generating config 2 at mesh {args.mesh}")
+        sysm = W.make_config(2, mesh=args.mesh)
+        d = G.upload(sysm)
     common = dict(m=m, rtol=1e-8, max_iters=200000, ortho=args.ortho)
     inner = args.inner_rtol if args.inner_rtol else (1e-3 if args.mixed_basis == "f16" else 1e-5)
     plans = {}
-    if args.only in ("both", "fp64"):
+    if args.adaptive > 0:
+        # The paper's own preconditioner, no fixed deflation basis, on the
+        # kappa = 1 problem of the same mesh (GMRES(30)): the log-normal
+        # problem has more small eigenvalues than r_max vectors can hold.
+        import copy
+        cfg = W.CONFIGS[1]
+        m = cfg["m"]
+        common["m"] = m
+        log(f"[bench] generating the kappa = 1 problem at mesh {args.mesh}")
+        sysm = copy.copy(W.make_config(1, mesh=args.mesh))
+        sysm.r = 0
+        sysm.z_rowptr = np.zeros(sysm.n + 1, np.int32)
+        sysm.z_colind = np.zeros(0, np.int32)
+        sysm.z_vals = np.zeros(0)
+        d = G.upload(sysm)
+        plans["adaptive"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
+                                   d["z_vals"], r=0, precision="fp64", adapt_rmax=args.adaptive,
+                                   **common)
+    elif args.only in ("both", "fp64"):
         plans["fp64"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
                                d["z_vals"], r=sysm.r, precision="fp64", **common)
-    if args.only in ("both", "mixed"):
+    if args.adaptive == 0 and args.only in ("both", "mixed"):
         plans["mixed"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
                                 d["z_vals"], r=sysm.r, precision="mixed_" + args.mixed_basis,
                                 inner_rtol=inner, inner_max_iters=100000, max_refine=40, **common)
@@ -191,7 +216,7 @@ def main():
     total = time.perf_counter() - t_start
 
     med = {k: float(np.median(v)) for k, v in times.items()}
-    headline = "mixed" if "mixed" in med else "fp64"
+    headline = "mixed" if "mixed" in med else ("adaptive" if "adaptive" in med else "fp64")
     out = {
         "metric": METRIC,
         "value": med[headline],
@@ -210,6 +235,12 @@ def main():
                    "rtol": 1e-8, "step": "+".join(plans), "ortho": args.ortho,
                    "mixed_basis": args.mixed_basis, "inner_rtol": inner},
     }
+    if args.adaptive > 0:
+        out["config"].update(workload=f"q1_convection_diffusion_{args.mesh}x{args.mesh}_kappa1",
+                             deflation="adaptive spectral (Ritz vectors of H_k)",
+                             adapt_rmax=args.adaptive, deflation_vectors=0)
+        out["defl_r_adaptive"] = infos["adaptive"]["defl_r"]
+        out["mu_adaptive"] = infos["adaptive"]["mu"]
     for k in plans:
         out[f"time_to_rtol_{k}_s"] = med[k]
         out[f"iters_{k}"] = infos[k]["iters"]
@@ -225,13 +256,13 @@ def main():
                                            GBs=v["bytes"] / (v["ms"] * 1e6), total_ms=v["ms"])
         out["kernels"] = per
         # Dominant kernel: most total time in the FP64 solve (else the mixed one).
-        src = "fp64" if "fp64" in plans else "mixed"
+        src = next(k for k in ("fp64", "adaptive", "mixed") if k in plans)
         cand = {kk: v for (nm, kk), v in ktot.items() if nm == src and v["launches"] > 0}
         dom = max(cand, key=lambda kk: cand[kk]["ms"])
         v = cand[dom]
         achieved = v["bytes"] / (v["ms"] * 1e6)
         traffic = None
-        if (src == "fp64" and dom == TRAFFIC["kind"] and TRAFFIC["bytes_per_launch"]
+        if (src == "fp64" and args.adaptive == 0 and dom == TRAFFIC["kind"] and TRAFFIC["bytes_per_launch"]
                 and TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
             traffic = TRAFFIC["bytes_per_launch"]
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -243,7 +274,8 @@ def main():
     if not args.no_cpu_baseline:
         fp64_iters = infos["fp64"]["iters"] if "fp64" in infos else infos[headline]["iters"]
         log(f"[bench] cpu baseline: oracle, {args.cpu_sample_iters} steps")
-        out["cpu_baseline"] = cpu_baseline(sysm, m, fp64_iters, args.cpu_sample_iters)
+        out["cpu_baseline"] = cpu_baseline(sysm, m, fp64_iters, args.cpu_sample_iters,
+                                           adapt_rmax=args.adaptive)
     print(json.dumps(out), flush=True)
 
 

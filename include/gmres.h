@@ -81,6 +81,15 @@ typedef struct {
                                  normalisation (the SpMV of step j+1 runs on the once-projected
                                  vector; the second update is folded into the next sweep through
                                  the Arnoldi relation).  Equal in exact arithmetic. */
+    int32_t adapt_rmax;       /* > 0: right preconditioning by the paper's adaptive spectral
+                                 deflation M^{-1} = I + U (|mu| T^{-1} - I) U^T, T = U^T A U
+                                 (Sec. 3.3, eqs. precond1, precond2, tau_mat, precond3): U starts
+                                 empty at every solve, gains one Ritz vector of H_k per restart
+                                 (inverse iteration, u = V_k z) and keeps at most adapt_rmax
+                                 columns (the direction of T's largest eigenvalue is removed);
+                                 |mu| by power iteration on H_k.  1..22; needs a single-system
+                                 FP64 plan, an empty Z (the fixed deflation is not combined with
+                                 it) and no adjoint.  0 = off. */
 } gmres_opts;
 
 typedef struct {
@@ -88,16 +97,17 @@ typedef struct {
     int32_t cycles;           /* restart cycles */
     int32_t refinements;      /* mixed: refinement steps */
     int32_t status;           /* gmres_status */
-    int32_t pad;
+    int32_t defl_r;           /* adaptive deflation: columns of U at exit (else 0) */
     double  rho0;             /* ||b - A x0|| (or the override) */
     double  rel_res;          /* ||P (b - A x_hat)|| / rho0 at exit (= true relative residual of x) */
     double  rel_res_true;     /* ||b - A x|| / rho0 recomputed from the returned x (FP64) */
     double  solve_ms;         /* host wall time of the call */
+    double  mu;               /* adaptive deflation: |mu| of the last restart (else 0) */
 } gmres_info;
 
 /* Fills *o with defaults: m = 30, max_iters = 10000, rtol = 1e-8, FP64,
  * inner_rtol = 1e-3 (FP16 basis) , max_refine = 30, inner_max_iters = 20000,
- * use_graph = 1, ortho = 1, everything else 0 (auto). */
+ * use_graph = 1, ortho = 1, everything else 0 (auto / off). */
 void gmres_default_opts(gmres_opts* o);
 
 /*

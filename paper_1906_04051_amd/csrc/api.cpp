@@ -85,6 +85,7 @@ struct gmres_plan_s {
     std::vector<int64_t> row_off, zcol_off, e_off_h;
     gmres_opts o{};
     int need_adjoint = 0;
+    AdaptArgs adapt{};      // adaptive spectral deflation buffers (adapt.rmax > 0)
     std::vector<void*> allocs;
 
     // plan-owned copies of the inputs
@@ -353,6 +354,27 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
         }
         refresh_ell1(p);
     }
+    if (p->o.adapt_rmax > 0) {
+        AdaptArgs& ad = p->adapt;
+        const int rc = p->o.adapt_rmax + 1;
+        ad.rmax = p->o.adapt_rmax;
+        CHECK(dalloc(p, &ad.st, 1));
+        CHECK(dalloc(p, &ad.U, (int64_t)rc * p->ldv));
+        CHECK(dalloc(p, &ad.AU, (int64_t)rc * p->ldv));
+        CHECK(dalloc(p, &ad.T, (int64_t)rc * rc));
+        CHECK(dalloc(p, &ad.C, (int64_t)rc * rc));
+        for (double** q : {&ad.s, &ad.tcol, &ad.trow, &ad.hvec}) CHECK(dalloc(p, q, rc + 1));
+        CHECK(dalloc(p, &ad.zc, kMaxM));
+        for (double** q : {&ad.ucand, &ad.aucand, &ad.dvec}) CHECK(dalloc(p, q, p->ldv));
+        CHECK(dalloc(p, &ad.part, (int64_t)(rc + 1) * p->NB_cap));
+        // Padded rows of U, AU and the candidates stay zero.
+        HIP_OK(hipMemsetAsync(ad.U, 0, (size_t)rc * p->ldv * sizeof(double), p->st));
+        HIP_OK(hipMemsetAsync(ad.AU, 0, (size_t)rc * p->ldv * sizeof(double), p->st));
+        for (double* q : {ad.ucand, ad.aucand, ad.dvec})
+            HIP_OK(hipMemsetAsync(q, 0, (size_t)p->ldv * sizeof(double), p->st));
+        HIP_OK(hipMemsetAsync(ad.T, 0, (size_t)rc * rc * sizeof(double), p->st));
+        HIP_OK(hipMemsetAsync(ad.C, 0, (size_t)rc * rc * sizeof(double), p->st));
+    }
     CHECK(dalloc(p, &p->ctrl, 1));
     HIP_OK(hipHostMalloc((void**)&p->ctrl_h, 2 * sizeof(Ctrl), 0));
     HIP_OK(hipEventCreateWithFlags(&p->ev_cyc[0], hipEventDisableTiming));
@@ -381,6 +403,7 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.NB = p->NB;
     a.nbcap = p->NB_cap;
     a.pass_grid = 1;
+    a.adapt = (p->adapt.rmax > 0 && op == 0 && prec == kPrecF64) ? &p->adapt : nullptr;
     a.m = p->o.m;
     a.nslot = p->o.m + 1;
     a.ldv = p->ldv;
@@ -674,8 +697,16 @@ gmres_status solve_f64(gmres_plan_s* p, int op, const double* b, const double* x
     if (x0) launch_copy(p->st, x0, p->xh, n);
     else launch_fill(p->st, p->xh, n, 0.0);
     Ctrl c{};
+    if (op == 0 && p->adapt.rmax > 0) adapt_reset(p->st, p->adapt);   // U starts empty
     CHECK(run_engine(p, op, kPrecF64, p->bws, rtol, r0_override, max_iters, &c));
     launch_correct(p->st, p->NB, (int)n, p->zrp, p->zci, p->zv, p->s_res, p->R, p->xh, x);
+    if (op == 0 && p->adapt.rmax > 0) {
+        AdaptState as{};
+        HIP_OK(hipMemcpyAsync(&as, p->adapt.st, sizeof(as), hipMemcpyDeviceToHost, p->st));
+        HIP_OK(hipStreamSynchronize(p->st));
+        info->defl_r = as.r;
+        info->mu = as.mu;
+    }
     info->iters += c.its;
     info->cycles += c.cycles;
     info->status = c.status;
@@ -814,6 +845,10 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
         return fail(GMRES_EINVAL, "max_iters >= 0 and rtol >= 0 required");
     if (p->o.precision < 0 || p->o.precision > 2) return fail(GMRES_EINVAL, "unknown precision");
     if (p->o.ortho < 0 || p->o.ortho > 1) return fail(GMRES_EINVAL, "unknown orthogonalisation variant");
+    if (p->o.adapt_rmax < 0 || p->o.adapt_rmax > kAdaptMax)
+        return fail(GMRES_EINVAL, "adapt_rmax must be in [0, 22]");
+    if (p->o.adapt_rmax > 0 && (p->o.precision != GMRES_FP64 || nsys != 1 || need_adjoint))
+        return fail(GMRES_EINVAL, "adaptive deflation needs a single-system FP64 plan without adjoint");
     if (p->o.precision != GMRES_FP64 && (!(p->o.inner_rtol > 0.0) || p->o.inner_rtol >= 1.0))
         return fail(GMRES_EINVAL, "inner_rtol must be in (0, 1)");
     if (p->o.spmv_lanes != 0 && p->o.spmv_lanes != -256 && p->o.spmv_lanes != -128 &&
@@ -836,6 +871,8 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     p->n = p->row_off[nsys];
     p->nnz = nnz;
     p->R = (int)p->zcol_off[nsys];
+    if (p->o.adapt_rmax > 0 && p->R > 0)
+        return fail(GMRES_EINVAL, "adaptive deflation is not combined with a fixed deflation basis Z");
     p->znnz = p->R > 0 ? z_nnz : 0;
     if (p->n >= INT32_MAX || nnz < 0 || nnz >= INT32_MAX || p->znnz >= INT32_MAX)
         return fail(GMRES_EINVAL, "sizes exceed the int32 CSR range");

@@ -37,6 +37,13 @@ struct Ctrl {
     int64_t pad[3];
 };
 
+// A kernel returns at once when the solve (gate 1) or the current cycle
+// (gate 2) has ended; gate 0 always runs.
+__device__ __forceinline__ bool gated(const Ctrl* c, int gate) {
+    if (gate == 0 || c == nullptr) return false;
+    return c->done != 0 || (gate == 2 && c->stop != 0);
+}
+
 // ---------------------------------------------------------------- reductions
 
 template <typename T>

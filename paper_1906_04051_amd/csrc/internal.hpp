@@ -36,6 +36,31 @@ struct KTimer {
     virtual ~KTimer() = default;
 };
 
+// Adaptive spectral deflation (the paper's M^{-1} = I + U(|mu| T^{-1} - I)U^T).
+constexpr int kAdaptMax = 22;   // largest r_max
+
+// Device-resident state of the adaptive deflation space.
+struct AdaptState {
+    int32_t r;        // columns of U in use
+    int32_t ok;       // this restart's candidate is appended
+    int32_t remove;   // this restart removes a direction
+    int32_t r_old, r_new;
+    int32_t pad;
+    double mu;        // |mu| (largest Ritz value magnitude)
+    double nu;        // norm of the orthogonalised candidate
+};
+
+struct AdaptArgs {
+    int rmax;
+    AdaptState* st;
+    double *U, *AU;          // (rmax + 1) columns, stride ldv
+    double *T, *C;           // (rmax + 1)^2 row-major, leading dimension rmax + 1
+    double *s, *tcol, *trow, *hvec;   // rmax + 2 each
+    double* zc;              // kMaxM Ritz coefficients on the stored basis
+    double *ucand, *aucand, *dvec;    // ldv each
+    double* part;            // (rmax + 2) * NB_cap partial sums
+};
+
 // Everything one solve engine needs: the operator (A or A^T), the deflation
 // data, and the Krylov workspace.
 struct EngineArgs {
@@ -92,9 +117,16 @@ struct EngineArgs {
     KTimer* timer;          // optional
     int trust_est;          // inner solves of the refinement: end on the estimate
     int lagged;             // two-pass CGS2 with lagged normalisation
+    const AdaptArgs* adapt; // FP64 adaptive spectral deflation (nullptr: off)
     double* cc;             // lagged: coefficients (Hbar h2) of the next step, m + 1
     double* lag;            // lagged: h2_last, 1/hn, sigma
 };
+
+// adapt.hip
+void adapt_reset(hipStream_t st, const AdaptArgs& a);
+void adapt_pre(const EngineArgs& e, const double* x, const double* scale);
+void adapt_post(const EngineArgs& e, double* y);
+void adapt_cycle_end(const EngineArgs& e, const double* V, const double* coef);
 
 // krylov.hip
 // Timing events for the next timed launch of the engine on this thread

@@ -22,16 +22,12 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "internal.hpp"
 
 namespace gm {
-
-__device__ __forceinline__ bool gated(const Ctrl* c, int gate) {
-    if (gate == 0 || c == nullptr) return false;
-    return c->done != 0 || (gate == 2 && c->stop != 0);
-}
 
 constexpr int kCT = 1024;   // threads of the coarse-solve kernels
 __device__ void coarse_matvec(int R, const double* __restrict__ Einv, int trans, const double* t,
@@ -1513,8 +1509,24 @@ struct Engine {
         k_store_v0<VT, WT><<<e.NB, kWG, 0, e.st>>>(e.n, p(), e.sigma0, Vcol(0), e.ctrl, 1);
     }
 
+    // Adaptive deflation (FP64 only): s = C U^T x before the SpMV of input x,
+    // y += (A U) s after it, so y = A M^{-1} x.
+    void op_pre(const VT* x, const double* scale) const {
+        if constexpr (std::is_same<VT, double>::value)
+            if (e.adapt) adapt_pre(e, x, scale);
+    }
+    void op_pre_w(const WT* x) const {
+        if constexpr (std::is_same<WT, double>::value)
+            if (e.adapt) adapt_pre(e, x, nullptr);
+    }
+    void op_post() const {
+        if constexpr (std::is_same<WT, double>::value)
+            if (e.adapt) adapt_post(e, y());
+    }
+
     void step(int j) const {
         const int nv = j + 1;
+        op_pre(Vcol(j), e.vscale + j);
         if (e.timer) e.timer->begin(0, j);
         if (e.L == kSell)
             sell_launch<0, AT, VT, double, WT, ACC>(e, Vcol(j), e.vscale + j, nullptr, y(), 0, 2);
@@ -1525,6 +1537,7 @@ struct Engine {
             spmv_dispatch<AT, VT, WT, ACC>(e.L, e.NB, e.st, e.n, e.rowptr, e.colind, vals(), Vcol(j),
                                            e.vscale + j, y(), e.ctrl, 2);
         if (e.timer) e.timer->end(0, j);
+        op_post();
         if (fused()) coarse_slots(e.s_step, 2);
         else coarse(y(), e.s_step, 2);
         if (e.timer) e.timer->begin(1, j);
@@ -1564,6 +1577,8 @@ struct Engine {
     // Step j of the two-pass variant (see k_pass1_lag).
     void step_lag(int j) const {
         const int nv = j + 1;
+        if (j == 0) op_pre(Vcol(0), e.vscale);
+        else op_pre_w(w());
         if (e.timer) e.timer->begin(0, j);
         if (j == 0) {
             spmv_any<VT>(Vcol(0), e.vscale);
@@ -1571,6 +1586,7 @@ struct Engine {
             spmv_any<WT>(w(), nullptr);
         }
         if (e.timer) e.timer->end(0, j);
+        op_post();
         if (fused()) coarse_slots(e.s_step, 2);
         else coarse(y(), e.s_step, 2);
         if (e.timer) e.timer->begin(1, j);
@@ -1627,7 +1643,14 @@ struct Engine {
         }
         k_backsolve<<<1, kWG, 0, e.st>>>(e.m, e.H, e.g, e.vscale, e.coef1, e.cyc_k, e.cyc_cap,
                                          e.ctrl, 1);
-        k_xupdate<VT><<<e.NB, kWG, 0, e.st>>>(e.n, e.ldv, V(), e.coef1, e.xh, e.ctrl, 1);
+        bool adapted = false;
+        if constexpr (std::is_same<VT, double>::value) {
+            if (e.adapt) {
+                adapt_cycle_end(e, V(), e.coef1);   // x += M^{-1} V_k y_k; new U, T
+                adapted = true;
+            }
+        }
+        if (!adapted) k_xupdate<VT><<<e.NB, kWG, 0, e.st>>>(e.n, e.ldv, V(), e.coef1, e.xh, e.ctrl, 1);
         restart_block(b, false, 0.0, 0.0);
     }
 };

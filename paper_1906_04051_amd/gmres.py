@@ -35,16 +35,17 @@ class GmresOpts(C.Structure):
                 ("inner_max_iters", C.c_int64), ("use_graph", C.c_int32),
                 ("record_history", C.c_int32), ("spmv_lanes", C.c_int32),
                 ("num_blocks", C.c_int32), ("batch_wg", C.c_int32), ("batch_lanes", C.c_int32),
-                ("ortho", C.c_int32)]
+                ("ortho", C.c_int32), ("adapt_rmax", C.c_int32)]
 
 
 class GmresInfo(C.Structure):
     _fields_ = [("iters", C.c_int64), ("cycles", C.c_int32), ("refinements", C.c_int32),
-                ("status", C.c_int32), ("pad", C.c_int32), ("rho0", C.c_double),
-                ("rel_res", C.c_double), ("rel_res_true", C.c_double), ("solve_ms", C.c_double)]
+                ("status", C.c_int32), ("defl_r", C.c_int32), ("rho0", C.c_double),
+                ("rel_res", C.c_double), ("rel_res_true", C.c_double), ("solve_ms", C.c_double),
+                ("mu", C.c_double)]
 
     def to_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
         d["status_name"] = STATUS.get(self.status, str(self.status))
         return d
 
