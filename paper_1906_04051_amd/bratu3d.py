@@ -24,6 +24,7 @@ position map.
 from __future__ import annotations
 
 import dataclasses
+import sys
 import time
 from typing import Optional
 
@@ -112,7 +113,7 @@ class BratuMesh:
 
 def _log(verbose, *a):
     if verbose:
-        print("[bratu3d]", *a, flush=True)
+        print("[bratu3d]", *a, file=sys.stderr, flush=True)
 
 
 def build_mesh(n: int, verbose: bool = False) -> BratuMesh:
@@ -230,3 +231,24 @@ def newton(mesh: BratuMesh, solve, lam: float = LAMBDA, tol: float = 1e-8, max_n
         if nd <= tol * max(1.0, float(np.linalg.norm(u))):
             break
     return u, hist
+
+
+def gpu_solver(mesh: BratuMesh, lam: float = LAMBDA, **opts):
+    """A Newton linear solver on the GPU library: one plan for the mesh
+    pattern, the Jacobian values replaced at every Newton step
+    (gmres_update_values), then gmres_solve.  Returns (solve, plan)."""
+    import torch
+
+    from . import gmres as G
+
+    sys0 = system_at(mesh, np.zeros(mesh.N), lam)
+    plan, d = G.plan_for(sys0, **opts)
+
+    def solve(vals, b):
+        plan.update_values(torch.from_numpy(np.ascontiguousarray(vals)).cuda())
+        x, info = plan.solve(torch.from_numpy(np.ascontiguousarray(b)).cuda())
+        return x.cpu().numpy(), dict(iters=info["iters"], status=info["status_name"],
+                                     rel_res_true=info["rel_res_true"], solve_ms=info["solve_ms"],
+                                     defl_r=info["defl_r"])
+
+    return solve, plan
