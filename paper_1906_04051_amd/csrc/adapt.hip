@@ -537,7 +537,8 @@ void adapt_post(const EngineArgs& e, double* y) {
 
 static void spmv_into(const EngineArgs& e, const double* x, double* y) {
     if (e.L == kSell)
-        launch_spmv_sell_f64(e.st, e.NB, e.n, e.sell_off, e.sell_wuni, e.sell_col,
+        launch_spmv_sell_f64(e.st, e.NB, e.n, e.sell_off, e.sell_perm, e.sell_wuni, e.sell_wmax,
+                             e.sell_col,
                              reinterpret_cast<const double*>(e.sell_val), x, y);
     else
         launch_spmv_f64(e.st, e.L, e.NB, e.n, e.rowptr, e.colind,

@@ -122,6 +122,7 @@ struct gmres_plan_s {
     double *E = nullptr, *Einv = nullptr;
     // sliced ELL copies (forward op / adjoint op)
     int *sell_off = nullptr, *sell_src = nullptr;
+    int *sell_perm = nullptr, *tsell_perm = nullptr;   // sorted row order (NULL: unsorted)
     short* sell_col = nullptr;   // 16-bit column offsets (NULL: no sliced ELL copy)
     double* sell_v64 = nullptr;
     float* sell_v32 = nullptr;
@@ -443,6 +444,7 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.fuse_rb = (p->R > 0 && rb != 0 && rb == p->slots_rb) ? rb : 0;
     if (op == 0) {
         a.sell_off = p->sell_off;
+        a.sell_perm = p->sell_perm;
         a.sell_wuni = p->sell_wuni;
         a.sell_col = p->sell_col;
         a.sell_val = f64 ? (const void*)p->sell_v64 : (const void*)p->sell_v32;
@@ -450,6 +452,7 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     } else {
         a.sell_wmax = p->tsell_wmax;
         a.sell_off = p->tsell_off;
+        a.sell_perm = p->tsell_perm;
         a.sell_wuni = p->tsell_wuni;
         a.sell_col = p->tsell_col;
         a.sell_val = p->tsell_v64;
@@ -526,12 +529,16 @@ struct TimerHook final : KTimer {
                 // once-projected work vector.  Fused Z^T y reads Z's ELL-1 copy.
                 const double bx = (!lagged || j == 0) ? bv : bw;
                 const double zt = p->R > 0 ? 12.0 * n : 0.0;
+                // Sliced ELL: the stored entries (value + 16-bit offset; the
+                // slices' padding is not credited), slice offsets unless
+                // uniform, the row order when sorted.
                 const bool t = op == 1;
                 const int64_t total = t ? p->tsell_total : p->sell_total;
                 const int wuni = t ? p->tsell_wuni : p->sell_wuni;
+                const bool sorted = (t ? p->tsell_perm : p->sell_perm) != nullptr;
                 if (p->L == kSell && total > 0)
-                    return (ba + 2.0) * (double)total + (wuni ? 0.0 : 4.0 * (n / 64.0 + 1.0)) +
-                           bx * n + bw * n + zt;
+                    return (ba + 2.0) * nnz + (wuni ? 0.0 : 4.0 * (n / 64.0 + 1.0)) +
+                           (sorted ? 4.0 * n : 0.0) + bx * n + bw * n + zt;
                 return (ba + 4.0) * nnz + 4.0 * (n + 1) + bx * n + bw * n + zt;
             }
             case 1:
@@ -650,15 +657,16 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
 // ||b - A x|| in FP64 (scratch: p->w, partial slot of p->part).
 void spmv_f64(gmres_plan_s* p, int L, int NB, const double* x, double* y) {
     if (L == kSell)
-        launch_spmv_sell_f64(p->st, NB, (int)p->n, p->sell_off, p->sell_wuni, p->sell_col, p->sell_v64, x, y);
+        launch_spmv_sell_f64(p->st, NB, (int)p->n, p->sell_off, p->sell_perm, p->sell_wuni, p->sell_wmax,
+                             p->sell_col, p->sell_v64, x, y);
     else
         launch_spmv_f64(p->st, L, NB, (int)p->n, p->rowptr, p->colind, p->vals, x, y);
 }
 
 void residual_f64(gmres_plan_s* p, const double* x, const double* b, double* r, int slot) {
     if (p->L == kSell)
-        launch_residual_sell_f64(p->st, p->NB, (int)p->n, p->sell_off, p->sell_wuni, p->sell_col, p->sell_v64, x,
-                                 b, r, p->part, slot);
+        launch_residual_sell_f64(p->st, p->NB, (int)p->n, p->sell_off, p->sell_perm, p->sell_wuni,
+                                 p->sell_wmax, p->sell_col, p->sell_v64, x, b, r, p->part, slot);
     else
         launch_residual_f64(p->st, p->L, p->NB, (int)p->n, p->rowptr, p->colind, p->vals, x, b, r,
                             p->part, slot);
@@ -822,7 +830,8 @@ void gmres_destroy(gmres_plan p) {
         }
     for (void* q : p->allocs) hipFree(q);
     for (int* q : {p->bb_ptr, p->bb_col, p->ab_ptr, p->ab_slot, p->slot_pos}) hipFree(q);
-    for (int* q : {p->sell_off, p->sell_src, p->tsell_off, p->tsell_src}) hipFree(q);
+    for (int* q : {p->sell_off, p->sell_src, p->sell_perm, p->tsell_off, p->tsell_src, p->tsell_perm})
+        hipFree(q);
     for (short* q : {p->sell_col, p->tsell_col}) hipFree(q);
     if (p->ctrl_h) hipHostFree(p->ctrl_h);
     for (auto e : {p->ev_cyc[0], p->ev_cyc[1], p->ev_in, p->ev_out})
@@ -963,15 +972,16 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     // Sliced ELL copies for the SpMV (values filled by refresh_values).
     {
         int* tmp_src = nullptr;
-        CHECK(to_status(sell_build(p->st, n, p->rowptr, p->colind, &p->sell_off, &p->sell_col,
-                                   &tmp_src, &p->sell_total, &p->sell_wuni), "sliced ELL"));
+        CHECK(to_status(sell_build(p->st, n, p->rowptr, p->colind, &p->sell_off, &p->sell_perm,
+                                   &p->sell_col, &tmp_src, &p->sell_total, &p->sell_wuni),
+                        "sliced ELL"));
         p->sell_src = tmp_src;
         p->sell_wmax = max_row_len(p->st, n, p->rowptr, p->d_flags);
         CHECK(dalloc(p, &p->sell_v64, std::max<int64_t>(p->sell_total, 1)));
         if (p->o.precision != GMRES_FP64) CHECK(dalloc(p, &p->sell_v32, std::max<int64_t>(p->sell_total, 1)));
         if (p->need_adjoint) {
-            CHECK(to_status(sell_build(p->st, n, p->trp, p->tci, &p->tsell_off, &p->tsell_col,
-                                       &p->tsell_src, &p->tsell_total, &p->tsell_wuni),
+            CHECK(to_status(sell_build(p->st, n, p->trp, p->tci, &p->tsell_off, &p->tsell_perm,
+                                       &p->tsell_col, &p->tsell_src, &p->tsell_total, &p->tsell_wuni),
                             "sliced ELL (A^T)"));
             CHECK(dalloc(p, &p->tsell_v64, std::max<int64_t>(p->tsell_total, 1)));
             p->tsell_wmax = max_row_len(p->st, n, p->trp, p->d_flags);

@@ -15,6 +15,7 @@ constexpr int kMaxM = 96;           // largest supported restart length m
 constexpr int kMaxR = 256;          // largest deflation count per system (coarse solve in one WG)
 constexpr int kAzRowMax = 64;       // largest row length of the compact A*Z operator
 constexpr int kBlockColsMax = 64;   // deflation columns per SpMV row block (fused Z^T y)
+constexpr int kXcd = 8;             // accelerator complex dies (own L2 each); blocks go round-robin
 
 // Device-resident control block of one solve.  Every kernel of a restart
 // cycle reads it, so the host launches whole cycles without synchronising.
@@ -81,6 +82,16 @@ __device__ __forceinline__ T block_sum_n(T v, T* lds) {
     for (int i = 1; i < NT / kWave; ++i) s += lds[i];
     __syncthreads();
     return s;
+}
+
+// Workgroup b of nb runs on die b % kXcd.  Returns a bijection of [0, nb)
+// under which each die's workgroups, in dispatch order, take one contiguous
+// range of logical blocks, so neighbouring rows (and the vector entries
+// they gather) meet in the same die's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % kXcd, k = b / kXcd;
+    const int q = nb / kXcd, r = nb % kXcd;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
 // Half-precision basis storage helpers.

@@ -99,6 +99,7 @@ struct EngineArgs {
     const void* azv1;       // AT, 2 per row
     // Sliced ELL copy of the operator (used when L == kSell).
     const int* sell_off;
+    const int* sell_perm;   // row of each position (NULL: position = row)
     int sell_wuni;          // > 0: every slice has this width (entries per row); off unused
     const short* sell_col;  // 16-bit column offsets from the row
     const void* sell_val;   // AT
@@ -144,10 +145,10 @@ void launch_residual_f64(hipStream_t st, int L, int NB, int n, const int* rp, co
 void launch_sum_slot(hipStream_t st, const double* part, int NB, int slot, double* out);
 void launch_spmv_f64(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
                      const double* v, const double* x, double* y);
-void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
-                          const short* col, const double* val, const double* x, double* y);
-void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
-                              const short* col, const double* val, const double* x,
+void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* perm, int wuni,
+                          int wmax, const short* col, const double* val, const double* x, double* y);
+void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* perm,
+                              int wuni, int wmax, const short* col, const double* val, const double* x,
                               const double* b, double* r, double* part, int slot);
 void launch_spmv_f32(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,
                      const float* v, const float* x, float* y);
@@ -188,9 +189,10 @@ void to_f32(hipStream_t st, int64_t n, const double* src, float* dst);
 void grad_vals(hipStream_t st, int64_t n, const int* rowptr, const int* colind, const double* lam,
                const double* x, double* g);
 int zt_max_row(hipStream_t st, int R, const int* ztrp, int* d_tmp);
-// Sliced ELL (64-row slices) of a CSR matrix; buffers hipMalloc'ed here.
+// Sliced ELL (64-row slices, rows optionally sorted within 256-row blocks;
+// *perm NULL when not) of a CSR matrix; buffers hipMalloc'ed here.
 int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
-               short** scol, int** src, int64_t* total, int* wuni);
+               int** perm, short** scol, int** src, int64_t* total, int* wuni);
 void sell_values(hipStream_t st, int64_t total, const int* src, const double* vals, double* v64,
                  float* v32);
 // Single-entry row copies of a CSR (see setup.hip); c1 may be NULL (values only).

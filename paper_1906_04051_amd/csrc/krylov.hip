@@ -177,11 +177,15 @@ __global__ __launch_bounds__(RB) void k_spmv_stream(int n, const int* __restrict
     }
 }
 
-// Sliced-ELL SpMV: one wavefront per 64-row slice, 256 rows per block, so
-// every load instruction reads 64 consecutive entries of one slice column.
-// MODE / ZT as for the stream kernel (RB = 256 row blocks for the slots).
-template <int MODE, bool ZT, int WMAX, typename AT, typename XT, typename BT, typename YT, typename ACC>
-__global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict__ off, int wuni,
+// Sliced-ELL SpMV: one wavefront per 64-position slice, NT positions per
+// block, so every load instruction reads 64 consecutive entries of one slice
+// column; position p holds row perm[p] (rows sorted within 256-row blocks) or
+// p.  MODE / ZT as for the stream kernel (ZT needs NT = 256, the row blocks
+// of the slots: a block's positions hold the same rows in either order).
+template <int MODE, bool ZT, int WMAX, int NT, typename AT, typename XT, typename BT, typename YT,
+          typename ACC>
+__global__ __launch_bounds__(NT) void k_spmv_sell(int n, const int* __restrict__ off,
+                                                   const int* __restrict__ perm, int wuni,
                                                    const short* __restrict__ scol,
                                                    const AT* __restrict__ sval,
                                                    const XT* __restrict__ x,
@@ -198,8 +202,9 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
                                                    const double* __restrict__ zv1,
                                                    double* __restrict__ tpart, const Ctrl* ctrl,
                                                    int gate) {
-    __shared__ ACC red[kWG / kWave];
-    __shared__ double sred[ZT ? kWG / kWave : 1][kBlockColsMax];
+    static_assert(!ZT || NT == kWG, "fused slots need 256-row blocks");
+    __shared__ ACC red[NT / kWave];
+    __shared__ double sred[ZT ? NT / kWave : 1][kBlockColsMax];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     // The control block is requested here and tested after the first row
@@ -207,8 +212,12 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
     const bool stopped = gated(ctrl, gate);
     const ACC scale = (MODE == 0 && scale_ptr) ? (ACC)(*scale_ptr) : (ACC)1;
     ACC nrm = 0;
-    for (int64_t r0 = (int64_t)blockIdx.x * kWG; r0 < n; r0 += (int64_t)gridDim.x * kWG) {
-        const int64_t row = r0 + threadIdx.x;
+    // Die-contiguous row blocks: the stencil's vector entries stay in one L2.
+    const int64_t b0 = xcd_block(blockIdx.x, gridDim.x);
+    for (int64_t r0 = b0 * NT; r0 < n; r0 += (int64_t)gridDim.x * NT) {
+        const int64_t pos = r0 + threadIdx.x;
+        // Beyond n the position is its own (invalid) row.
+        const int64_t row = perm && pos < n ? (int64_t)perm[pos] : pos;
         const int64_t sl = r0 / kWave + wv;
         // Loads that do not depend on each other: slice bounds (none when every
         // slice has the same width), the row's Z entry, b, the block's slots.
@@ -240,27 +249,52 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
         if (row < n) {
             const int q = q0 + lane;
             const XT* __restrict__ xr = x + row;   // columns are stored as offsets from the row
-            if (w <= WMAX) {
-                // Column offsets and values of the whole row first, then the gathers.
-                int cc[WMAX];
-                AT vv[WMAX];
+            // Loads are branch-free (column index clamped to the slice's last
+            // column, products past the width dropped by a select), so the
+            // compiler can count outstanding loads exactly and never waits
+            // for one gather before issuing the next.
+            if (w > 0) {
+                if constexpr (WMAX > 0) {
+                    // Every slice is at most WMAX wide (the launch picks WMAX
+                    // from the longest row): offsets and values of the whole
+                    // row, then the gathers, then the products.
+                    int cc[WMAX];
+                    AT vv[WMAX];
 #pragma unroll
-                for (int k = 0; k < WMAX; ++k)
-                    if (k < w) {
-                        cc[k] = scol[q + k * kWave];
-                        vv[k] = sval[q + k * kWave];
+                    for (int k = 0; k < WMAX; ++k) {
+                        const int kk = min(k, w - 1);
+                        cc[k] = scol[q + kk * kWave];
+                        vv[k] = sval[q + kk * kWave];
                     }
-                ACC xv[WMAX];
+                    ACC xv[WMAX];
 #pragma unroll
-                for (int k = 0; k < WMAX; ++k)
-                    if (k < w) xv[k] = (ACC)ld_f(xr + cc[k]);
+                    for (int k = 0; k < WMAX; ++k) xv[k] = (ACC)ld_f(xr + cc[k]);
 #pragma unroll
-                for (int k = 0; k < WMAX; ++k)
-                    if (k < w) acc += (ACC)vv[k] * xv[k];
-            } else {
-#pragma unroll 4
-                for (int k = 0; k < w; ++k)
-                    acc += (ACC)sval[q + k * kWave] * (ACC)ld_f(xr + scol[q + k * kWave]);
+                    for (int k = 0; k < WMAX; ++k) acc += k < w ? (ACC)vv[k] * xv[k] : (ACC)0;
+                } else {
+                    // Rows of any length, in chunks of CH entries: the values
+                    // and gathers of one chunk are issued, then the column
+                    // offsets of the next, which stay in flight while the
+                    // products of the first wait.
+                    constexpr int CH = 8;
+                    int cc[CH];
+#pragma unroll
+                    for (int k = 0; k < CH; ++k) cc[k] = scol[q + min(k, w - 1) * kWave];
+                    for (int k0 = 0; k0 < w; k0 += CH) {
+                        ACC xv[CH];
+                        AT va[CH];
+#pragma unroll
+                        for (int k = 0; k < CH; ++k) {
+                            va[k] = sval[q + min(k0 + k, w - 1) * kWave];
+                            xv[k] = (ACC)ld_f(xr + cc[k]);
+                        }
+#pragma unroll
+                        for (int k = 0; k < CH; ++k) cc[k] = scol[q + min(k0 + CH + k, w - 1) * kWave];
+#pragma unroll
+                        for (int k = 0; k < CH; ++k)
+                            acc += k0 + k < w ? (ACC)va[k] * xv[k] : (ACC)0;
+                    }
+                }
             }
         }
         ACC yi = 0;
@@ -277,12 +311,12 @@ __global__ __launch_bounds__(kWG) void k_spmv_sell(int n, const int* __restrict_
             }
         }
         if (ZT)
-            block_slots<kWG, ACC>(l0, l1, bb_col, slot_pos, zc, zvv, yi, row < n, row, zrp, zci,
+            block_slots<NT, ACC>(l0, l1, bb_col, slot_pos, zc, zvv, yi, row < n, row, zrp, zci,
                                   zv, tpart, sred);
     }
     if (stopped) return;
     if (MODE == 1) {
-        const ACC t = block_sum_n<kWG>(nrm, red);
+        const ACC t = block_sum_n<NT>(nrm, red);
         if (threadIdx.x == 0) part[(int64_t)slot * NB + blockIdx.x] = (double)t;
     }
 }
@@ -1376,22 +1410,30 @@ static void sell_launch_w(const EngineArgs& e, const XT* x, const double* scale,
     const AT* sv = reinterpret_cast<const AT*>(e.sell_val);
     // MODE 0 needs no per-block partials: one block per 256-row block.  MODE 1
     // writes one norm partial per block, so it keeps the NB-block grid.
-    const int grid = MODE == 0 ? (int)std::max<int64_t>(1, ((int64_t)e.n + kWG - 1) / kWG) : e.NB;
-    if (e.R > 0 && e.fuse_rb == 256)
-        launch(k_spmv_sell<MODE, true, WMAX, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st, 
-            e.n, e.sell_off, e.sell_wuni, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
+    const int64_t n = e.n;
+    if (e.R > 0 && e.fuse_rb == 256) {
+        const int grid = MODE == 0 ? (int)std::max<int64_t>(1, (n + kWG - 1) / kWG) : e.NB;
+        launch(k_spmv_sell<MODE, true, WMAX, kWG, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st,
+            e.n, e.sell_off, e.sell_perm, e.sell_wuni, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, e.zrp, e.zci, e.zv,
             e.bb_ptr, e.bb_col, e.slot_pos, e.zc1, e.zv1, e.tpart, e.ctrl, gate);
-    else
-        launch(k_spmv_sell<MODE, false, WMAX, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st, 
-            e.n, e.sell_off, e.sell_wuni, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, nullptr, nullptr,
+    } else {
+        const int grid = MODE == 0 ? (int)std::max<int64_t>(1, (n + kWG - 1) / kWG) : e.NB;
+        launch(k_spmv_sell<MODE, false, WMAX, kWG, AT, XT, BT, YT, ACC>, grid, kWG, 0, e.st,
+            e.n, e.sell_off, e.sell_perm, e.sell_wuni, e.sell_col, sv, x, scale, b, y, e.part, slot, e.NB, nullptr, nullptr,
             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, e.ctrl, gate);
+    }
 }
 
 template <int MODE, typename AT, typename XT, typename BT, typename YT, typename ACC>
 static void sell_launch(const EngineArgs& e, const XT* x, const double* scale, const BT* b, YT* y,
                         int slot, int gate) {
-    if (e.sell_wmax <= 12) sell_launch_w<MODE, 12, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
-    else sell_launch_w<MODE, 32, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    // Fully unrolled rows up to 25 entries (the smallest instance that holds
+    // the longest row), chunked rows beyond.
+    if (e.sell_wmax <= 9) sell_launch_w<MODE, 9, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    else if (e.sell_wmax <= 12) sell_launch_w<MODE, 12, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    else if (e.sell_wmax <= 16) sell_launch_w<MODE, 16, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    else if (e.sell_wmax <= 25) sell_launch_w<MODE, 25, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    else sell_launch_w<MODE, 0, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
 }
 
 static int jmax_for(int nv) {
@@ -1722,19 +1764,37 @@ void launch_spmv_f64(hipStream_t st, int L, int NB, int n, const int* rp, const 
     spmv_dispatch<double, double, double, double>(L, NB, st, n, rp, ci, v, x, nullptr, y, nullptr, 0);
 }
 
-void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
-                          const short* col, const double* val, const double* x, double* y) {
-    k_spmv_sell<0, false, 32, double, double, double, double, double><<<NB, kWG, 0, st>>>(
-        n, off, wuni, col, val, x, nullptr, nullptr, y, nullptr, 0, NB, nullptr, nullptr, nullptr, nullptr,
-        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+// Standalone FP64 sliced-ELL products (no fused Z^T y); wmax = widest row.
+template <int MODE, int WMAX>
+static void sell_f64(hipStream_t st, int NB, int n, const int* off, const int* perm, int wuni,
+                     const short* col, const double* val, const double* x, const double* b, double* y,
+                     double* part, int slot) {
+    const int grid = MODE == 0 ? std::max(1, (n + kWG - 1) / kWG) : NB;
+    k_spmv_sell<MODE, false, WMAX, kWG, double, double, double, double, double><<<grid, kWG, 0, st>>>(
+        n, off, perm, wuni, col, val, x, nullptr, b, y, part, slot, NB, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 
-void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, int wuni,
-                              const short* col, const double* val, const double* x,
+template <int MODE>
+static void sell_f64_w(int wmax, hipStream_t st, int NB, int n, const int* off, const int* perm,
+                       int wuni, const short* col, const double* val, const double* x,
+                       const double* b, double* y, double* part, int slot) {
+    if (wmax <= 9) sell_f64<MODE, 9>(st, NB, n, off, perm, wuni, col, val, x, b, y, part, slot);
+    else if (wmax <= 12) sell_f64<MODE, 12>(st, NB, n, off, perm, wuni, col, val, x, b, y, part, slot);
+    else if (wmax <= 16) sell_f64<MODE, 16>(st, NB, n, off, perm, wuni, col, val, x, b, y, part, slot);
+    else if (wmax <= 25) sell_f64<MODE, 25>(st, NB, n, off, perm, wuni, col, val, x, b, y, part, slot);
+    else sell_f64<MODE, 0>(st, NB, n, off, perm, wuni, col, val, x, b, y, part, slot);
+}
+
+void launch_spmv_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* perm, int wuni,
+                          int wmax, const short* col, const double* val, const double* x, double* y) {
+    sell_f64_w<0>(wmax, st, NB, n, off, perm, wuni, col, val, x, nullptr, y, nullptr, 0);
+}
+
+void launch_residual_sell_f64(hipStream_t st, int NB, int n, const int* off, const int* perm,
+                              int wuni, int wmax, const short* col, const double* val, const double* x,
                               const double* b, double* r, double* part, int slot) {
-    k_spmv_sell<1, false, 32, double, double, double, double, double><<<NB, kWG, 0, st>>>(
-        n, off, wuni, col, val, x, nullptr, b, r, part, slot, NB, nullptr, nullptr, nullptr, nullptr,
-        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+    sell_f64_w<1>(wmax, st, NB, n, off, perm, wuni, col, val, x, b, r, part, slot);
 }
 
 void launch_spmv_f32(hipStream_t st, int L, int NB, int n, const int* rp, const int* ci,

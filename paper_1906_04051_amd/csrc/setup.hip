@@ -425,14 +425,19 @@ int lu_inverse(hipStream_t st, int nsys, const int64_t* d_sys_zcol_off, const in
 }
 
 // --------------------------------------------------------- sliced ELL (SELL-64)
-// Rows are grouped in slices of 64 (one wavefront); slice s stores its rows'
-// entries column-major, width = longest row of the slice: entry (row, k) at
-// off[s] + k*64 + (row % 64).  Column indices are stored as 16-bit offsets
-// from the row (col - row), which mesh orderings keep small; the copy is not
-// built (all outputs NULL, status OK) when an offset falls outside
-// [-32767, 32767].  Padding entries point
-// at the row itself (offset 0) with a zero value.  src[q] is the CSR index of
-// entry q (-1 for padding), used to refresh values.
+// Positions are grouped in slices of 64 (one wavefront); slice s stores the
+// entries of its positions column-major, width = longest row of the slice:
+// entry k of position p at off[s] + k*64 + (p % 64).  Position p holds row p,
+// or row perm[p] when the rows of every 256-row block (one SpMV workgroup)
+// are sorted by decreasing length (SELL-C-sigma, C = 64, sigma = 256); the
+// sorted order is kept only when it saves at least 1/16 of the stored
+// entries (rows of very different lengths side by side, as for tri-quadratic
+// hexahedra).  Column indices are stored as 16-bit offsets from the row
+// (col - row), which mesh orderings keep small; the copy is not built (all
+// outputs NULL, status OK) when an offset falls outside [-32767, 32767].
+// Padding entries point at the row itself (offset 0) with a zero value.
+// src[q] is the CSR index of entry q (-1 for padding), used to refresh
+// values.
 
 __global__ void k_sell_width(int64_t n, const int* __restrict__ rowptr, int* __restrict__ wsz) {
     const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -444,11 +449,35 @@ __global__ void k_sell_width(int64_t n, const int* __restrict__ rowptr, int* __r
     wsz[sl] = w * 64;
 }
 
+// Sorted row order of each 256-row block (decreasing length, ties by row) and
+// the resulting slice sizes: the first position of a slice holds its longest row.
+__global__ __launch_bounds__(kWG) void k_sell_sort(int64_t n, const int* __restrict__ rowptr,
+                                                   int* __restrict__ perm, int* __restrict__ wsz) {
+    __shared__ int len[kWG];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kWG;
+    const int64_t i = r0 + t;
+    const int li = i < n ? rowptr[i + 1] - rowptr[i] : -1;
+    len[t] = li;
+    __syncthreads();
+    int rank = 0;
+    for (int u = 0; u < kWG; ++u) {
+        const int lu = len[u];
+        rank += (lu > li) || (lu == li && u < t);
+    }
+    if (i < n) {
+        perm[r0 + rank] = (int)i;
+        if (rank % 64 == 0) wsz[(r0 + rank) / 64] = li * 64;
+    }
+}
+
 __global__ void k_sell_fill(int64_t n, const int* __restrict__ rowptr, const int* __restrict__ colind,
-                            const int* __restrict__ off, short* __restrict__ scol,
-                            int* __restrict__ src, int* __restrict__ overflow) {
+                            const int* __restrict__ off, const int* __restrict__ perm,
+                            short* __restrict__ scol, int* __restrict__ src,
+                            int* __restrict__ overflow) {
     const int64_t sl = (int64_t)blockIdx.x;     // one block of 64 threads per slice
-    const int64_t i = sl * 64 + threadIdx.x;
+    const int64_t pos = sl * 64 + threadIdx.x;
+    const int64_t i = pos < n && perm ? (int64_t)perm[pos] : pos;
     const int w = (off[sl + 1] - off[sl]) / 64;
     const int base = off[sl] + threadIdx.x;
     const int k0 = i < n ? rowptr[i] : 0;
@@ -478,15 +507,28 @@ __global__ void k_sell_vals(int64_t m, const int* __restrict__ src, const double
     if (v32) v32[q] = (float)v;
 }
 
-int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
-               short** scol, int** src, int64_t* total, int* wuni) {
-    const int64_t nsl = (n + 63) / 64;
-    *off = *src = nullptr;
-    *scol = nullptr;
-    *wuni = 0;
-    int* wsz = nullptr;
+// Exclusive scan of the nsl + 1 slice sizes in wsz into off; returns the
+// total (entries) through *h.
+static int sell_scan(hipStream_t st, int64_t nsl, const int* wsz, int* off, int* h) {
     void* tmp = nullptr;
     size_t tb = 0;
+    int status = kStatusOk;
+    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, wsz, off, (int)(nsl + 1), st);
+    if (hipMalloc(&tmp, std::max<size_t>(tb, 1)) != hipSuccess) return kStatusNoMem;
+    hipcub::DeviceScan::ExclusiveSum(tmp, tb, wsz, off, (int)(nsl + 1), st);
+    hipMemcpyAsync(h, off + nsl, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+    hipFree(tmp);
+    return status;
+}
+
+int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
+               int** perm, short** scol, int** src, int64_t* total, int* wuni) {
+    const int64_t nsl = (n + 63) / 64;
+    *off = *src = *perm = nullptr;
+    *scol = nullptr;
+    *wuni = 0;
+    int *wsz = nullptr, *off2 = nullptr;
     int status = kStatusOk;
     if (hipMalloc(off, (nsl + 1) * sizeof(int)) != hipSuccess ||
         hipMalloc(&wsz, (nsl + 1) * sizeof(int)) != hipSuccess)
@@ -494,13 +536,28 @@ int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, 
     int h = 0;
     if (status == kStatusOk) {
         k_sell_width<<<blocks_for(nsl + 1), kWG, 0, st>>>(n, rowptr, wsz);
-        hipcub::DeviceScan::ExclusiveSum(nullptr, tb, wsz, *off, (int)(nsl + 1), st);
-        if (hipMalloc(&tmp, tb) != hipSuccess) status = kStatusNoMem;
+        status = sell_scan(st, nsl, wsz, *off, &h);
     }
-    if (status == kStatusOk) {
-        hipcub::DeviceScan::ExclusiveSum(tmp, tb, wsz, *off, (int)(nsl + 1), st);
-        hipMemcpyAsync(&h, *off + nsl, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+    // Sorted order within each 256-row block; kept if it stores at least 1/16
+    // fewer entries.
+    if (status == kStatusOk && nsl > 0) {
+        int h2 = 0;
+        if (hipMalloc(perm, n * sizeof(int)) != hipSuccess ||
+            hipMalloc(&off2, (nsl + 1) * sizeof(int)) != hipSuccess)
+            status = kStatusNoMem;
+        if (status == kStatusOk) {
+            hipMemsetAsync(wsz + nsl, 0, sizeof(int), st);
+            k_sell_sort<<<(unsigned)((n + kWG - 1) / kWG), kWG, 0, st>>>(n, rowptr, *perm, wsz);
+            status = sell_scan(st, nsl, wsz, off2, &h2);
+        }
+        if (status == kStatusOk && (int64_t)h2 * 16 <= (int64_t)h * 15) {
+            std::swap(*off, off2);
+            h = h2;
+        } else {
+            hipFree(*perm);
+            *perm = nullptr;
+        }
+        hipFree(off2);
     }
     if (status == kStatusOk && (hipMalloc(scol, std::max(h, 1) * sizeof(short)) != hipSuccess ||
                                 hipMalloc(src, std::max(h, 1) * sizeof(int)) != hipSuccess))
@@ -510,21 +567,21 @@ int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, 
         // wsz (nsl + 1 ints) is free again: its first entry is the overflow flag.
         hipMemsetAsync(wsz, 0, sizeof(int), st);
         if (nsl > 0)
-            k_sell_fill<<<(unsigned)nsl, 64, 0, st>>>(n, rowptr, colind, *off, *scol, *src, wsz);
+            k_sell_fill<<<(unsigned)nsl, 64, 0, st>>>(n, rowptr, colind, *off, *perm, *scol, *src, wsz);
         hipMemcpyAsync(&ovf, wsz, sizeof(int), hipMemcpyDeviceToHost, st);
         if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
     }
     hipFree(wsz);
-    hipFree(tmp);
     if (status != kStatusOk || ovf) {
         hipFree(*off);
+        hipFree(*perm);
         hipFree(*scol);
         hipFree(*src);
-        *off = *src = nullptr;
+        *off = *src = *perm = nullptr;
         *scol = nullptr;
         h = 0;
     }
-    if (status == kStatusOk && nsl > 0 && *off) {
+    if (status == kStatusOk && nsl > 0 && *off && !*perm) {
         // Uniform width (every slice as wide as the first): the kernels then
         // compute slice offsets instead of loading them.
         std::vector<int> ho((size_t)nsl + 1);

@@ -62,10 +62,14 @@ def no_defl(s):
 
 # ---------------------------------------------------------------- SpMV
 
-def test_spmv_integer_exact_all_lane_counts():
-    rng = np.random.default_rng(11)
+@pytest.mark.parametrize("maxlen", [10, 30, 40, 130])
+def test_spmv_integer_exact_all_lane_counts(maxlen):
+    """Random row lengths (empty rows included): the sliced-ELL copy sorts the
+    rows of each 256-row block by length, and the kernel instance follows the
+    longest row (<= 12, <= 32, any)."""
+    rng = np.random.default_rng(11 + maxlen)
     n = 3001
-    dens = rng.random((n,)) * 40
+    dens = rng.random((n,)) * maxlen
     rows, cols, vals = [], [], []
     for i in range(n):
         k = int(dens[i]) + (1 if i % 7 else 0)
@@ -82,7 +86,7 @@ def test_spmv_integer_exact_all_lane_counts():
     x = rng.integers(-4, 5, size=n).astype(np.float64)
     ref = oracle.spmv(s.rowptr, s.colind, s.vals, x)
     for L in (1, 2, 4, 8, 16, 32, 64, -64, -128, -256):
-        say("spmv integer L =", L)
+        say("spmv integer maxlen", maxlen, "L =", L)
         plan, d = G().plan_for(s, m=4, spmv_lanes=L)
         y = plan.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
         assert np.array_equal(y, ref), L
