@@ -1460,11 +1460,14 @@ struct LanesFor {
 
 // The two-sweep first pass keeps two coefficient sets per lane: FP32/FP64
 // bases spread the columns over twice as many lanes to stay at >= 4 waves
-// per SIMD (FP16 tiles are already spread).
+// per SIMD (FP16 tiles are already spread), except FP64 bases of 33..64
+// columns, where 4 lanes (10-16 columns each, 3-4 waves per SIMD) measured
+// faster than 8.
 template <int J, typename VT>
 struct LanesForLag {
-    static constexpr int value =
-        sizeof(VT) == 2 ? LanesFor<J, VT>::value : (2 * LanesFor<J, VT>::value > 16 ? 16 : 2 * LanesFor<J, VT>::value);
+    static constexpr int spread = 2 * LanesFor<J, VT>::value > 16 ? 16 : 2 * LanesFor<J, VT>::value;
+    static constexpr int value = sizeof(VT) == 2 ? LanesFor<J, VT>::value
+                                 : (sizeof(VT) == 8 && J > 32 && J <= 64 ? 4 : spread);
 };
 
 #define GM_JMAX_CASE(JV, VTT, CALL) \
