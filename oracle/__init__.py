@@ -5,8 +5,8 @@ CPU-baseline leg are the only callers.  The GPU solver never imports this
 package and this package never imports the solver; both take inputs from
 ``paper_1906_04051_amd.workloads`` only.
 
-Every numerical routine lives in ``oracle.c`` and ``dgmres.c`` (plain C,
-FP64, ``-ffp-contract=off``).  This module only marshals numpy arrays.
+Every numerical routine lives in ``oracle.c``, ``dgmres.c`` and ``bgmres.c``
+(plain C, FP64, ``-ffp-contract=off``).  This module only marshals numpy arrays.
 
 Parity pins: see ``tests/test_oracle.py``.  Functions without an independent
 pin: none (the dense adjoint in ``dense_adjoint`` is itself the pin of the
@@ -24,16 +24,18 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRC_D = os.path.join(_HERE, "dgmres.c")
+_SRC_B = os.path.join(_HERE, "bgmres.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-STATUS = {0: "OK", 1: "MAXITER", -1: "EINVAL", -2: "ESINGULAR", -3: "ENONFINITE", -6: "ENOMEM"}
+STATUS = {0: "OK", 1: "MAXITER", 2: "BREAKDOWN", -1: "EINVAL", -2: "ESINGULAR", -3: "ENONFINITE",
+          -6: "ENOMEM"}
 
 
 def build() -> str:
     """Compile liboracle.so (gcc, -O2, no FP contraction)."""
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           _SRC, _SRC_D, "-o", _LIB + ".tmp", "-lm"]
+           _SRC, _SRC_D, _SRC_B, "-o", _LIB + ".tmp", "-lm"]
     subprocess.check_call(cmd)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -72,6 +74,9 @@ def _load():
     lib.oracle_dgmres.argtypes = [C.c_int64, i32p, i32p, f64p, f64p, vp, C.c_int32, C.c_int64,
                                   C.c_double, C.c_int32, f64p, i64p, f64p, vp, vp, vp]
     lib.oracle_dgmres.restype = C.c_int
+    lib.oracle_bgmres.argtypes = [C.c_int64, i32p, i32p, f64p, C.c_int32, f64p, vp, C.c_int32,
+                                  C.c_int64, C.c_double, f64p, i64p, f64p, vp]
+    lib.oracle_bgmres.restype = C.c_int
     lib.oracle_power_iteration.argtypes = [C.c_int32, f64p, f64p]
     lib.oracle_power_iteration.restype = C.c_double
     lib.oracle_inverse_iteration.argtypes = [C.c_int32, f64p, f64p]
@@ -193,6 +198,28 @@ def dgmres(sysm, m: int, rtol: float, max_iters: int, rmax: int = 20, x0=None, b
         rr = res.r
         res["U"] = U[:rr].copy()
         res["T"] = T.ravel()[:rr * rr].reshape(rr, rr).copy()
+    return res
+
+
+def bgmres(rowptr, colind, vals, B, m: int, rtol: float, max_steps: int, X0=None,
+           history: bool = False) -> Result:
+    """Block GMRES(m) for A X = B with the k columns of B (n x k) as right-hand
+    sides (definition and readings in bgmres.c).  Iterations are block steps."""
+    lib = _load()
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    n, k = B.shape
+    X = np.zeros((n, k), np.float64)
+    X0a = None if X0 is None else np.ascontiguousarray(X0, dtype=np.float64)
+    info_i = np.zeros(4, np.int64)
+    info_d = np.zeros(4, np.float64)
+    hist = np.zeros(max(max_steps, 1), np.float64) if history else None
+    st = lib.oracle_bgmres(n, _i32(rowptr), _i32(colind), _f64(vals), k, B, _ptr(X0a), m, max_steps,
+                           rtol, X, info_i, info_d, _ptr(hist))
+    res = Result(x=X, iters=int(info_i[0]), cycles=int(info_i[1]), status=int(st),
+                 status_name=STATUS.get(int(st), str(st)), rho0_max=float(info_d[0]),
+                 rel_res_est=float(info_d[1]), rel_res_true=float(info_d[2]))
+    if history:
+        res["history"] = hist[:res.iters].copy()
     return res
 
 

@@ -1,0 +1,286 @@
+/*
+ * bgmres.c -- plain FP64 CPU oracle for block GMRES(m) with k right-hand
+ * sides: A X = B, X and B n x k.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.c): only the test suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load this library.
+ *
+ * The paper solves one right-hand side at a time (Sec. 3.2); several
+ * right-hand sides sharing A are handled here by the block form of the same
+ * minimisation.  Definition written out: after j block steps of a cycle,
+ *     X = X_0 + V_j Y,   Y = argmin || B - A X ||_F,
+ * over the block Krylov space span{R_0, A R_0, ..., A^{j-1} R_0} (R_0 = B - A X_0),
+ * which splits into one least-squares problem per column over the same
+ * space.  Built as:
+ *   - V_0 S = R_0 by modified Gram-Schmidt column by column (S upper
+ *     triangular, positive diagonal);
+ *   - block step j: for each column c, w = A v_{jk+c} orthogonalised by
+ *     modified Gram-Schmidt against every basis column so far (including the
+ *     block's earlier new columns), h = coefficients, h_{(j+1)k+c, jk+c} = ||w||;
+ *     this is the block Arnoldi relation A V_j = V_{j+1} Hbar_j (the analogue
+ *     of eq. hessenberg) with a band Hessenberg Hbar of k subdiagonals;
+ *   - the least-squares problem min || G - Hbar_j Y ||_F, G = [S; 0], by a
+ *     Householder QR of Hbar_j computed from scratch after every block step;
+ *     the residual of column c is the norm of the last k entries of column c
+ *     of Q^T G (the analogue of eq. res);
+ *   - a cycle ends when every column's estimate is <= rtol * rho0_c
+ *     (rho0_c = ||b_c - A x0_c||, eq. relative per column), at m block
+ *     steps, at the step cap, or at a block breakdown; X += V Y; the solve
+ *     ends when every recomputed true residual passes.
+ *
+ * Readings (the GPU path uses the same ones):
+ *   - iterations are counted in block steps;
+ *   - block breakdown: a new column whose norm after orthogonalisation is
+ *     <= BD_TOL times its norm before (the block Krylov space has stopped
+ *     growing); the block step's columns of Hbar are kept, the cycle ends
+ *     there (its new basis block is never used); a cycle whose starting block
+ *     R_0 is rank-deficient (same test in its QR) returns BREAKDOWN;
+ *   - a column with rho0_c = 0 is rejected (EINVAL), as is k < 1 or m < 1.
+ * Build with -ffp-contract=off; sums run in index order.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define BG_OK 0
+#define BG_MAXITER 1
+#define BG_BREAKDOWN 2
+#define BG_EINVAL -1
+#define BG_ENONFINITE -3
+#define BG_ENOMEM -6
+
+#define BD_TOL 1e-10
+
+void oracle_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+                 const double *x, double *y);
+double oracle_dot(int64_t n, const double *a, const double *b);
+double oracle_nrm2(int64_t n, const double *a);
+
+/* Householder QR of the (rows x cols) column-major matrix M (rows >= cols),
+ * applied to the (rows x k) column-major right-hand side G: on return the
+ * upper triangle of M holds R and G holds Q^T G. */
+static void householder_qr(int rows, int cols, double *M, int k, double *G)
+{
+    double *v = (double *)malloc(sizeof(double) * (size_t)rows);
+    for (int c = 0; c < cols; ++c) {
+        double nrm = 0.0;
+        for (int i = c; i < rows; ++i) nrm += M[(size_t)c * rows + i] * M[(size_t)c * rows + i];
+        nrm = sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const double a0 = M[(size_t)c * rows + c];
+        const double alpha = a0 >= 0.0 ? -nrm : nrm;
+        for (int i = 0; i < rows; ++i) v[i] = 0.0;
+        v[c] = a0 - alpha;
+        for (int i = c + 1; i < rows; ++i) v[i] = M[(size_t)c * rows + i];
+        double vv = 0.0;
+        for (int i = c; i < rows; ++i) vv += v[i] * v[i];
+        if (vv == 0.0) continue;
+        /* H = I - 2 v v^T / (v^T v) applied to the remaining columns and G. */
+        for (int q = c; q < cols; ++q) {
+            double s = 0.0;
+            for (int i = c; i < rows; ++i) s += v[i] * M[(size_t)q * rows + i];
+            s = 2.0 * s / vv;
+            for (int i = c; i < rows; ++i) M[(size_t)q * rows + i] -= s * v[i];
+        }
+        for (int q = 0; q < k; ++q) {
+            double s = 0.0;
+            for (int i = c; i < rows; ++i) s += v[i] * G[(size_t)q * rows + i];
+            s = 2.0 * s / vv;
+            for (int i = c; i < rows; ++i) G[(size_t)q * rows + i] -= s * v[i];
+        }
+    }
+    free(v);
+}
+
+static int finite_all(int64_t n, const double *v)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+/* Column c of the row-major n x k matrix M into the vector out. */
+static void get_col(int64_t n, int k, const double *M, int c, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = M[i * k + c];
+}
+
+/*
+ * B, X0, X: n x k row-major.  max_steps caps the block steps over all cycles.
+ * info_i: [block steps, cycles, -, -]; info_d: [max_c rho0_c, max_c estimated
+ * relative residual at the last block step, max_c true relative residual, -].
+ * hist (nullable, max_steps entries): per block step, max_c estimate / rho0_c.
+ */
+int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+                  int32_t k, const double *B, const double *X0, int32_t m, int64_t max_steps,
+                  double rtol, double *X, int64_t *info_i, double *info_d, double *hist)
+{
+    for (int q = 0; q < 4; ++q) {
+        info_i[q] = 0;
+        info_d[q] = 0.0;
+    }
+    if (n < 1 || k < 1 || m < 1 || max_steps < 0 || !(rtol >= 0.0)) return BG_EINVAL;
+    if (!finite_all(n * (int64_t)k, B) || !finite_all(rowptr[n], vals) ||
+        (X0 && !finite_all(n * (int64_t)k, X0)))
+        return BG_ENONFINITE;
+    const int cols_max = m * k, rows_max = (m + 1) * k;
+    double *V = (double *)calloc((size_t)rows_max * (size_t)n, sizeof(double));
+    double *Hb = (double *)calloc((size_t)rows_max * (size_t)cols_max, sizeof(double)); /* col-major */
+    double *M = (double *)malloc(sizeof(double) * (size_t)rows_max * (size_t)cols_max);
+    double *G = (double *)malloc(sizeof(double) * (size_t)rows_max * (size_t)k);
+    double *S = (double *)calloc((size_t)k * (size_t)k, sizeof(double));
+    double *Y = (double *)malloc(sizeof(double) * (size_t)cols_max * (size_t)k);
+    double *rho0 = (double *)malloc(sizeof(double) * (size_t)k);
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!V || !Hb || !M || !G || !S || !Y || !rho0 || !t || !w) {
+        free(V); free(Hb); free(M); free(G); free(S); free(Y); free(rho0); free(t); free(w);
+        return BG_ENOMEM;
+    }
+    for (int64_t i = 0; i < n * (int64_t)k; ++i) X[i] = X0 ? X0[i] : 0.0;
+
+    /* R = B - A X for every column, into V's first block (column vectors). */
+#define RESIDUALS(NORMS)                                                         \
+    for (int c = 0; c < k; ++c) {                                                \
+        get_col(n, k, X, c, t);                                                  \
+        oracle_spmv(n, rowptr, colind, vals, t, w);                              \
+        for (int64_t i = 0; i < n; ++i) V[(size_t)c * n + i] = B[i * k + c] - w[i]; \
+        NORMS[c] = oracle_nrm2(n, V + (size_t)c * n);                            \
+    }
+
+    double *rn = (double *)malloc(sizeof(double) * (size_t)k);
+    RESIDUALS(rho0);
+    double rho_max = 0.0;
+    int bad = 0;
+    for (int c = 0; c < k; ++c) {
+        if (rho0[c] == 0.0) bad = 1;
+        if (rho0[c] > rho_max) rho_max = rho0[c];
+    }
+    info_d[0] = rho_max;
+    int status = BG_MAXITER;
+    int64_t steps = 0, cycles = 0;
+    double est_max = 1.0;
+    if (bad) {
+        status = BG_EINVAL;
+        goto done;
+    }
+    for (int c = 0; c < k; ++c) rn[c] = rho0[c];
+    for (;;) {
+        int all = 1;
+        for (int c = 0; c < k; ++c)
+            if (rn[c] > rtol * rho0[c]) all = 0;
+        if (all) {
+            status = BG_OK;
+            break;
+        }
+        if (steps >= max_steps) {
+            status = BG_MAXITER;
+            break;
+        }
+        /* V_0 S = R by MGS (residual columns are in V already). */
+        memset(S, 0, sizeof(double) * (size_t)k * (size_t)k);
+        int bd = 0;
+        for (int c = 0; c < k; ++c) {
+            double *vc = V + (size_t)c * n;
+            const double before = oracle_nrm2(n, vc);
+            for (int q = 0; q < c; ++q) {
+                const double h = oracle_dot(n, V + (size_t)q * n, vc);
+                S[(size_t)c * k + q] = h;
+                for (int64_t i = 0; i < n; ++i) vc[i] -= h * V[(size_t)q * n + i];
+            }
+            const double nv = oracle_nrm2(n, vc);
+            if (!(nv > BD_TOL * before)) bd = 1;
+            S[(size_t)c * k + c] = nv;
+            if (nv > 0.0)
+                for (int64_t i = 0; i < n; ++i) vc[i] /= nv;
+        }
+        if (bd) {
+            status = BG_BREAKDOWN;
+            break;
+        }
+        ++cycles;
+        memset(Hb, 0, sizeof(double) * (size_t)rows_max * (size_t)cols_max);
+        int j_done = 0;  /* block steps kept in this cycle */
+        for (int j = 0; j < m && steps < max_steps; ++j) {
+            /* Block step j: columns jk .. jk+k-1 of Hbar, basis block j+1. */
+            int brk = 0;
+            for (int c = 0; c < k; ++c) {
+                const int col = j * k + c, newq = (j + 1) * k + c;
+                oracle_spmv(n, rowptr, colind, vals, V + (size_t)col * n, w);
+                const double before = oracle_nrm2(n, w);
+                for (int q = 0; q < newq; ++q) {
+                    const double h = oracle_dot(n, V + (size_t)q * n, w);
+                    Hb[(size_t)col * rows_max + q] = h;
+                    for (int64_t i = 0; i < n; ++i) w[i] -= h * V[(size_t)q * n + i];
+                }
+                const double hn = oracle_nrm2(n, w);
+                Hb[(size_t)col * rows_max + newq] = hn;
+                if (!(hn > BD_TOL * before)) brk = 1;
+                for (int64_t i = 0; i < n; ++i) V[(size_t)newq * n + i] = hn > 0.0 ? w[i] / hn : 0.0;
+            }
+            ++steps;
+            j_done = j + 1;
+            /* Least squares from scratch over the (j+2)k x (j+1)k block. */
+            const int rows = (j + 2) * k, cols = (j + 1) * k;
+            for (int q = 0; q < cols; ++q)
+                for (int i = 0; i < rows; ++i) M[(size_t)q * rows + i] = Hb[(size_t)q * rows_max + i];
+            for (int q = 0; q < k; ++q)
+                for (int i = 0; i < rows; ++i) G[(size_t)q * rows + i] = i < k ? S[(size_t)q * k + i] : 0.0;
+            householder_qr(rows, cols, M, k, G);
+            double worst = 0.0;
+            int conv = 1;
+            for (int q = 0; q < k; ++q) {
+                double e = 0.0;
+                for (int i = cols; i < rows; ++i) e += G[(size_t)q * rows + i] * G[(size_t)q * rows + i];
+                e = sqrt(e);
+                if (e / rho0[q] > worst) worst = e / rho0[q];
+                if (e > rtol * rho0[q]) conv = 0;
+            }
+            est_max = worst;
+            if (hist) hist[steps - 1] = worst;
+            if (conv || brk) break;
+        }
+        if (j_done > 0) {
+            /* Y = R^{-1} (Q^T G)_top for the kept block steps, X += V Y. */
+            const int rows = (j_done + 1) * k, cols = j_done * k;
+            for (int q = 0; q < cols; ++q)
+                for (int i = 0; i < rows; ++i) M[(size_t)q * rows + i] = Hb[(size_t)q * rows_max + i];
+            for (int q = 0; q < k; ++q)
+                for (int i = 0; i < rows; ++i) G[(size_t)q * rows + i] = i < k ? S[(size_t)q * k + i] : 0.0;
+            householder_qr(rows, cols, M, k, G);
+            for (int q = 0; q < k; ++q)
+                for (int i = cols - 1; i >= 0; --i) {
+                    double s = G[(size_t)q * rows + i];
+                    for (int l = i + 1; l < cols; ++l) s -= M[(size_t)l * rows + i] * Y[(size_t)q * cols + l];
+                    Y[(size_t)q * cols + i] = s / M[(size_t)i * rows + i];
+                }
+            for (int64_t i = 0; i < n; ++i)
+                for (int c = 0; c < k; ++c) {
+                    double s = 0.0;
+                    for (int q = 0; q < cols; ++q) s += V[(size_t)q * n + i] * Y[(size_t)c * cols + q];
+                    X[i * k + c] += s;
+                }
+        }
+        if (!finite_all(n * (int64_t)k, X)) {
+            status = BG_ENONFINITE;
+            break;
+        }
+        RESIDUALS(rn);
+    }
+done:
+    {
+        double tr = 0.0;
+        RESIDUALS(rn);
+        for (int c = 0; c < k; ++c)
+            if (rho0[c] > 0.0 && rn[c] / rho0[c] > tr) tr = rn[c] / rho0[c];
+        info_d[2] = tr;
+    }
+    info_i[0] = steps;
+    info_i[1] = cycles;
+    info_d[1] = est_max;
+#undef RESIDUALS
+    free(V); free(Hb); free(M); free(G); free(S); free(Y); free(rho0); free(t); free(w); free(rn);
+    return status;
+}
