@@ -157,6 +157,32 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
                                  gmres_info* infos_h);
 
 /*
+ * Block GMRES(m_block) for k right-hand sides sharing the plan's A (several
+ * right-hand sides; the paper solves one at a time, Sec. 3.2, and this is
+ * the block form of the same minimisation): after j block steps of a cycle
+ * X = X0 + V Y with Y minimising ||B - A X||_F over the block Krylov space
+ * span{R0, A R0, ..., A^{j-1} R0}, R0 = B - A X0; cycles restart from X.
+ * Single-system plans without a deflation basis (R = 0) and without adaptive
+ * deflation, any precision setting (the solve is FP64).  The plan's rtol
+ * applies to every column: the solve ends when ||b_c - A x_c|| <= rtol *
+ * ||b_c - A x0_c|| for all c (true residuals); max_iters caps the block
+ * steps.  k in [1, 16]; m_block in [1, 16] block steps per cycle (block
+ * Krylov dimension m_block * k).  B, X0 (or NULL: zero), X: n x k row-major
+ * device arrays owned by the caller; X must not alias B (it may alias X0).
+ * The first call allocates a plan-owned workspace of (m_block + 4) panels of
+ * n x 16 doubles (reused by later calls with m_block no larger).  info_h:
+ * iters = block steps, cycles, rho0 = max_c ||b_c - A x0_c||, rel_res = max_c
+ * estimated relative residual at the last block step, rel_res_true = max_c
+ * true relative residual.  Each cycle runs on the columns not yet
+ * converged; a residual column that has become dependent on the others adds
+ * no basis vector (the block basis may be narrower than the number of
+ * right-hand sides).  Returns OK or MAXITER, or EINVAL (sizes, a plan with
+ * deflation, a zero column of B - A X0), ENONFINITE, ENOMEM, EDEVICE.
+ */
+gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const double* B,
+                               const double* X0, double* X, gmres_info* info_h);
+
+/*
  * Adjoint of x = A^{-1} b for a single-system plan built with need_adjoint:
  * solves A^T lambda = grad_x with the same deflated GMRES(m) in FP64 (on A^T,
  * A^T Z and E^T), then grad_b = lambda and grad_vals[k] = -lambda_i x_j for
@@ -190,14 +216,17 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h);
  * pair of HIP events in its own dispatch (kernel execution time, as a kernel
  * trace reports it); the other cycles run as usual (graph replay when
  * use_graph).  EINVAL for period < 0.
+ * gmres_solve_block times every launch of its dot, panel-product and SpMM
+ * kernels when period >= 1.
  * gmres_kernel_times: totals over the timed cycles of the last solve (or
- * adjoint): for kernel class k (0 SpMV, 1 first Gram-Schmidt sweep, 2 second
- * sweep, 3 third sweep of the three-sweep variant, 4 first sweep of the
- * two-sweep variant at steps j > 0) writes {launches, total_ms,
- * total_algorithmic_bytes} to out_h[3*k ..]; launches that found their cycle
- * already ended are not counted. */
+ * adjoint, or block solve): for kernel class k (0 SpMV, 1 first Gram-Schmidt
+ * sweep, 2 second sweep, 3 third sweep of the three-sweep variant, 4 first
+ * sweep of the two-sweep variant at steps j > 0, 5 block dot products
+ * P^T W, 6 block panel products W +/- P C, 7 block SpMM) writes {launches,
+ * total_ms, total_algorithmic_bytes} to out_h[3*k ..]; launches that found
+ * their cycle already ended are not counted. */
 gmres_status gmres_set_timing(gmres_plan p, int32_t period);
-gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 15 doubles */);
+gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 24 doubles */);
 
 /* Switches the stream used by later calls. */
 gmres_status gmres_set_stream(gmres_plan p, hipStream_t stream);

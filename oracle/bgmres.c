@@ -26,15 +26,22 @@
  *   - a cycle ends when every column's estimate is <= rtol * rho0_c
  *     (rho0_c = ||b_c - A x0_c||, eq. relative per column), at m block
  *     steps, at the step cap, or at a block breakdown; X += V Y; the solve
- *     ends when every recomputed true residual passes.
+ *     ends when every recomputed true residual passes;
+ *   - a cycle runs on the columns whose true residual has not passed yet
+ *     (the block shrinks as columns converge; converged columns keep x_c),
+ *     since converged residuals are nearly dependent on the others.
  *
  * Readings (the GPU path uses the same ones):
  *   - iterations are counted in block steps;
  *   - block breakdown: a new column whose norm after orthogonalisation is
  *     <= BD_TOL times its norm before (the block Krylov space has stopped
  *     growing); the block step's columns of Hbar are kept, the cycle ends
- *     there (its new basis block is never used); a cycle whose starting block
- *     R_0 is rank-deficient (same test in its QR) returns BREAKDOWN;
+ *     there (its new basis block is never used);
+ *   - at a restart, a residual column dependent on the earlier ones (same
+ *     test in the QR of the starting block) adds no basis vector: the cycle
+ *     runs with kb <= ka basis columns per block and ka right-hand sides
+ *     (G = [S; 0], S kb x ka), so restarted residuals that have become
+ *     nearly dependent do not stop the solve;
  *   - a column with rho0_c = 0 is rejected (EINVAL), as is k < 1 or m < 1.
  * Build with -ffp-contract=off; sums run in index order.
  */
@@ -151,6 +158,7 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
     }
 
     double *rn = (double *)malloc(sizeof(double) * (size_t)k);
+    int *act = (int *)malloc(sizeof(int) * (size_t)k);
     RESIDUALS(rho0);
     double rho_max = 0.0;
     int bad = 0;
@@ -179,64 +187,76 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
             status = BG_MAXITER;
             break;
         }
-        /* V_0 S = R by MGS (residual columns are in V already). */
-        memset(S, 0, sizeof(double) * (size_t)k * (size_t)k);
-        int bd = 0;
-        for (int c = 0; c < k; ++c) {
-            double *vc = V + (size_t)c * n;
-            const double before = oracle_nrm2(n, vc);
-            for (int q = 0; q < c; ++q) {
-                const double h = oracle_dot(n, V + (size_t)q * n, vc);
-                S[(size_t)c * k + q] = h;
-                for (int64_t i = 0; i < n; ++i) vc[i] -= h * V[(size_t)q * n + i];
+        /* Active columns: those whose residual has not passed yet; the cycle
+         * runs on their residuals only (moved to the front of V). */
+        int ka = 0;
+        for (int c = 0; c < k; ++c)
+            if (rn[c] > rtol * rho0[c]) {
+                act[ka] = c;
+                if (ka != c) memcpy(V + (size_t)ka * n, V + (size_t)c * n, sizeof(double) * (size_t)n);
+                ++ka;
             }
-            const double nv = oracle_nrm2(n, vc);
-            if (!(nv > BD_TOL * before)) bd = 1;
-            S[(size_t)c * k + c] = nv;
-            if (nv > 0.0)
-                for (int64_t i = 0; i < n; ++i) vc[i] /= nv;
+        /* V_0 S = R by MGS over the active residual columns; a column that is
+         * dependent on the accepted ones (norm after projection <= BD_TOL
+         * times before) adds no basis vector but stays a right-hand side:
+         * kb basis columns, ka right-hand sides, S kb x ka. */
+        memset(S, 0, sizeof(double) * (size_t)k * (size_t)k);
+        int kb = 0;
+        for (int c = 0; c < ka; ++c) {
+            memcpy(w, V + (size_t)c * n, sizeof(double) * (size_t)n);
+            const double before = oracle_nrm2(n, w);
+            for (int q = 0; q < kb; ++q) {
+                const double h = oracle_dot(n, V + (size_t)q * n, w);
+                S[(size_t)c * k + q] = h;
+                for (int64_t i = 0; i < n; ++i) w[i] -= h * V[(size_t)q * n + i];
+            }
+            const double nv = oracle_nrm2(n, w);
+            if (nv > BD_TOL * before) {
+                S[(size_t)c * k + kb] = nv;
+                for (int64_t i = 0; i < n; ++i) V[(size_t)kb * n + i] = w[i] / nv;
+                ++kb;
+            }
         }
-        if (bd) {
-            status = BG_BREAKDOWN;
-            break;
-        }
+        const int kk = kb;
+        const int rmax = (m + 1) * kk;
         ++cycles;
         memset(Hb, 0, sizeof(double) * (size_t)rows_max * (size_t)cols_max);
         int j_done = 0;  /* block steps kept in this cycle */
         for (int j = 0; j < m && steps < max_steps; ++j) {
-            /* Block step j: columns jk .. jk+k-1 of Hbar, basis block j+1. */
+            /* Block step j: columns j kk .. j kk + kk - 1 of Hbar, basis block j+1. */
             int brk = 0;
-            for (int c = 0; c < k; ++c) {
-                const int col = j * k + c, newq = (j + 1) * k + c;
+            for (int c = 0; c < kk; ++c) {
+                const int col = j * kk + c, newq = (j + 1) * kk + c;
                 oracle_spmv(n, rowptr, colind, vals, V + (size_t)col * n, w);
                 const double before = oracle_nrm2(n, w);
                 for (int q = 0; q < newq; ++q) {
                     const double h = oracle_dot(n, V + (size_t)q * n, w);
-                    Hb[(size_t)col * rows_max + q] = h;
+                    Hb[(size_t)col * rmax + q] = h;
                     for (int64_t i = 0; i < n; ++i) w[i] -= h * V[(size_t)q * n + i];
                 }
                 const double hn = oracle_nrm2(n, w);
-                Hb[(size_t)col * rows_max + newq] = hn;
+                Hb[(size_t)col * rmax + newq] = hn;
                 if (!(hn > BD_TOL * before)) brk = 1;
                 for (int64_t i = 0; i < n; ++i) V[(size_t)newq * n + i] = hn > 0.0 ? w[i] / hn : 0.0;
             }
             ++steps;
             j_done = j + 1;
-            /* Least squares from scratch over the (j+2)k x (j+1)k block. */
-            const int rows = (j + 2) * k, cols = (j + 1) * k;
+            /* Least squares from scratch over the (j+2)kk x (j+1)kk block. */
+            const int rows = (j + 2) * kk, cols = (j + 1) * kk;
             for (int q = 0; q < cols; ++q)
-                for (int i = 0; i < rows; ++i) M[(size_t)q * rows + i] = Hb[(size_t)q * rows_max + i];
-            for (int q = 0; q < k; ++q)
-                for (int i = 0; i < rows; ++i) G[(size_t)q * rows + i] = i < k ? S[(size_t)q * k + i] : 0.0;
-            householder_qr(rows, cols, M, k, G);
+                for (int i = 0; i < rows; ++i) M[(size_t)q * rows + i] = Hb[(size_t)q * rmax + i];
+            for (int q = 0; q < ka; ++q)
+                for (int i = 0; i < rows; ++i) G[(size_t)q * rows + i] = i < kk ? S[(size_t)q * k + i] : 0.0;
+            householder_qr(rows, cols, M, ka, G);
             double worst = 0.0;
             int conv = 1;
-            for (int q = 0; q < k; ++q) {
+            for (int q = 0; q < ka; ++q) {
                 double e = 0.0;
                 for (int i = cols; i < rows; ++i) e += G[(size_t)q * rows + i] * G[(size_t)q * rows + i];
                 e = sqrt(e);
-                if (e / rho0[q] > worst) worst = e / rho0[q];
-                if (e > rtol * rho0[q]) conv = 0;
+                const double r0q = rho0[act[q]];
+                if (e / r0q > worst) worst = e / r0q;
+                if (e > rtol * r0q) conv = 0;
             }
             est_max = worst;
             if (hist) hist[steps - 1] = worst;
@@ -244,23 +264,23 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
         }
         if (j_done > 0) {
             /* Y = R^{-1} (Q^T G)_top for the kept block steps, X += V Y. */
-            const int rows = (j_done + 1) * k, cols = j_done * k;
+            const int rows = (j_done + 1) * kk, cols = j_done * kk;
             for (int q = 0; q < cols; ++q)
-                for (int i = 0; i < rows; ++i) M[(size_t)q * rows + i] = Hb[(size_t)q * rows_max + i];
-            for (int q = 0; q < k; ++q)
-                for (int i = 0; i < rows; ++i) G[(size_t)q * rows + i] = i < k ? S[(size_t)q * k + i] : 0.0;
-            householder_qr(rows, cols, M, k, G);
-            for (int q = 0; q < k; ++q)
+                for (int i = 0; i < rows; ++i) M[(size_t)q * rows + i] = Hb[(size_t)q * rmax + i];
+            for (int q = 0; q < ka; ++q)
+                for (int i = 0; i < rows; ++i) G[(size_t)q * rows + i] = i < kk ? S[(size_t)q * k + i] : 0.0;
+            householder_qr(rows, cols, M, ka, G);
+            for (int q = 0; q < ka; ++q)
                 for (int i = cols - 1; i >= 0; --i) {
                     double s = G[(size_t)q * rows + i];
                     for (int l = i + 1; l < cols; ++l) s -= M[(size_t)l * rows + i] * Y[(size_t)q * cols + l];
                     Y[(size_t)q * cols + i] = s / M[(size_t)i * rows + i];
                 }
             for (int64_t i = 0; i < n; ++i)
-                for (int c = 0; c < k; ++c) {
+                for (int c = 0; c < ka; ++c) {
                     double s = 0.0;
                     for (int q = 0; q < cols; ++q) s += V[(size_t)q * n + i] * Y[(size_t)c * cols + q];
-                    X[i * k + c] += s;
+                    X[i * k + act[c]] += s;
                 }
         }
         if (!finite_all(n * (int64_t)k, X)) {
@@ -282,5 +302,6 @@ done:
     info_d[1] = est_max;
 #undef RESIDUALS
     free(V); free(Hb); free(M); free(G); free(S); free(Y); free(rho0); free(t); free(w); free(rn);
+    free(act);
     return status;
 }

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgmres_mi355x.so")
-SOURCES = ["krylov.hip", "adapt.hip", "setup.hip", "batched.hip", "api.cpp"]
+SOURCES = ["krylov.hip", "adapt.hip", "setup.hip", "batched.hip", "block.hip", "api.cpp"]
 ARCH = os.environ.get("GMRES_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

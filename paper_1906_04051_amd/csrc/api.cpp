@@ -47,7 +47,7 @@ struct Timer {
     int used = 0;
     // Kernel classes: 0 SpMV, 1 first sweep, 2 second sweep, 3 third sweep
     // (three-sweep CGS2), 4 first sweep of the two-sweep variant at j > 0.
-    static constexpr int kKinds = 5;
+    static constexpr int kKinds = 8;
     double launches[kKinds] = {};
     double ms[kKinds] = {};
     double bytes[kKinds] = {};
@@ -75,6 +75,8 @@ struct Plan;
 }  // namespace
 
 struct gmres_plan_s {
+    gm::BlockWork* block = nullptr;   // block GMRES workspace (allocated on first use)
+    int block_m = 0;
     int device = 0;
     hipStream_t user_stream = nullptr;
     hipStream_t st = nullptr;           // plan-owned stream (capturable)
@@ -833,6 +835,7 @@ void gmres_destroy(gmres_plan p) {
     for (int* q : {p->sell_off, p->sell_src, p->sell_perm, p->tsell_off, p->tsell_src, p->tsell_perm})
         hipFree(q);
     for (short* q : {p->sell_col, p->tsell_col}) hipFree(q);
+    gm::block_free(p->block);
     if (p->ctrl_h) hipHostFree(p->ctrl_h);
     for (auto e : {p->ev_cyc[0], p->ev_cyc[1], p->ev_in, p->ev_out})
         if (e) hipEventDestroy(e);
@@ -1072,6 +1075,77 @@ gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double
     info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info_h) *info_h = info;
     if (info.status == kStatusNonFinite) return fail(GMRES_ENONFINITE, "non-finite value in b, x0 or the iteration");
+    return (gmres_status)info.status;
+}
+
+gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const double* B,
+                               const double* X0, double* X, gmres_info* info_h) {
+    if (!p || !B || !X) return fail(GMRES_EINVAL, "plan, B and X are required");
+    if (p->nsys != 1) return fail(GMRES_EINVAL, "gmres_solve_block needs a single-system plan");
+    if (p->R > 0 || p->o.adapt_rmax > 0)
+        return fail(GMRES_EINVAL, "gmres_solve_block runs on A alone (no deflation basis, no adaptive deflation)");
+    if (k < 1 || k > 16) return fail(GMRES_EINVAL, "k must be in [1, 16]");
+    if (m_block < 1 || m_block > gm::kBlockStepsMax) return fail(GMRES_EINVAL, "m_block must be in [1, 16]");
+    if (X == B) return fail(GMRES_EINVAL, "X must not alias B");
+    const auto t0 = std::chrono::steady_clock::now();
+    CHECK(enter(p));
+    if (p->block && p->block_m < m_block) {
+        HIP_OK(hipStreamSynchronize(p->st));
+        gm::block_free(p->block);
+        p->block = nullptr;
+    }
+    if (!p->block) {
+        CHECK(to_status(gm::block_alloc(&p->block, p->st, p->n, m_block), "block workspace"));
+        p->block_m = m_block;
+    }
+    // Timing (set_timing > 0): every block kernel launch carries its events.
+    struct Hook final : gm::BlockTimer {
+        gmres_plan_s* p;
+        explicit Hook(gmres_plan_s* q) : p(q) {}
+        void begin(int kind, double bytes) override {
+            Timer& t = p->timer;
+            const int e0 = t.used++;
+            t.used++;
+            arm_kernel_events(t.ev(e0), t.ev(e0 + 1));
+            t.recs.push_back({kind, 0, 0, bytes, e0});
+        }
+        void end() override {
+            if (disarm_kernel_events()) p->timer.recs.back().cycle = -1;
+        }
+    } hook(p);
+    p->timer.reset();
+    gm::BlockArgs a{p->st, p->rowptr, p->colind, p->vals, k, m_block, p->o.rtol, p->o.max_iters, B, X0, X,
+                    p->nnz, p->timer.period > 0 ? &hook : nullptr};
+    gm::BlockResult r;
+    const int s = gm::block_solve(p->block, a, &r);
+    if (p->timer.period > 0) {
+        Timer& t = p->timer;
+        for (const auto& rec : t.recs) {
+            if (rec.cycle < 0) continue;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, t.pool[rec.ev], t.pool[rec.ev + 1]);
+            t.launches[rec.kind] += 1;
+            t.ms[rec.kind] += ms;
+            t.bytes[rec.kind] += rec.bytes;
+        }
+        t.recs.clear();
+        t.used = 0;
+    }
+    if (s == kStatusInval) {
+        leave(p);
+        return fail(GMRES_EINVAL, "a column of B - A X0 is zero (or not finite)");
+    }
+    CHECK(to_status(s, "block GMRES"));
+    CHECK(leave(p));
+    gmres_info info{};
+    info.status = r.status;
+    info.iters = r.steps;
+    info.cycles = r.cycles;
+    info.rho0 = r.rho0;
+    info.rel_res = r.rel_res_est;
+    info.rel_res_true = r.rel_res_true;
+    info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info_h) *info_h = info;
     return (gmres_status)info.status;
 }
 

@@ -1,0 +1,780 @@
+// Block GMRES(m) for k <= 16 right-hand sides sharing A (A X = B).
+//
+// The paper solves one right-hand side at a time (Sec. 3.2); with several,
+// the same minimisation over the block Krylov space span{R0, A R0, ...}
+// turns the Gram-Schmidt work into tall-skinny matrix products, which run
+// here on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+//   - vectors are 16-wide row-major panels (n_pad x 16, columns >= k zero):
+//     one row of a panel is one 128-byte line;
+//   - SpMM Y = A X: 16 lanes per row, one per column, so every gather reads
+//     one line of X;
+//   - C = [V_0 .. V_j]^T W: one 16x16 MFMA accumulator per panel, 4 rows of
+//     every panel per instruction (one coalesced 512-byte load per panel);
+//   - W -/+= sum_i V_i C_i: one 16-row tile per wavefront, the coefficients in
+//     LDS;
+//   - block Gram-Schmidt applied twice (BCGS2), then the new block by
+//     Cholesky QR applied twice (CholQR2): H_{j+1,j} = R2 R1;
+//   - the band Hessenberg least-squares problem by Householder reflections
+//     updated per block step in one workgroup (the oracle refactors it from
+//     scratch; equal in exact arithmetic), the per-column residual estimate
+//     from the transformed right-hand side (analogue of eq. res).
+// Readings shared with the oracle: iterations are block steps; a cycle runs on
+// the columns whose true residual has not passed; a new column whose norm
+// after orthogonalisation is <= 1e-10 times its norm before ends the cycle
+// after that block step (its new basis block is never used); at a restart a
+// residual column dependent on the earlier ones (same test) adds no basis
+// vector but stays a right-hand side of the least-squares problem (kb <= ka
+// basis columns per block); a zero initial residual column is rejected.
+#include <hip/hip_ext.h>
+
+#include <cmath>
+#include <new>
+
+#include "internal.hpp"
+
+namespace gm {
+
+namespace {
+
+constexpr int kBW = 16;            // panel width
+constexpr int kPan = kBW * kBW;    // entries of one 16 x 16 coefficient block
+constexpr int kDotGrid = 1024;     // workgroups of the dot kernel (partials)
+constexpr int kSplit = 16;         // first-level splits of the partial sums
+constexpr int kNormGrid = 1024;    // workgroups of the residual kernel
+constexpr int kLdH = (kBlockStepsMax + 1) * kBW;   // rows of the least-squares arrays
+constexpr double kBdTol = 1e-10;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D += A B for A 16x4, B 4x16: lane l feeds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; register r of lane l holds D[l / 16 + 4 r][l % 16].
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row-major n x k (caller layout) <-> 16-wide panel.
+__global__ __launch_bounds__(kWG) void k_bpack(int64_t n, int k, const double* __restrict__ src,
+                                               double* __restrict__ P) {
+    const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n * kBW) return;
+    const int64_t row = e / kBW;
+    const int c = (int)(e % kBW);
+    P[e] = (c < k && src) ? src[row * k + c] : 0.0;
+}
+
+__global__ __launch_bounds__(kWG) void k_bunpack(int64_t n, int k, const double* __restrict__ P,
+                                                 double* __restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n * k) return;
+    const int64_t row = e / k;
+    const int c = (int)(e % k);
+    dst[e] = P[row * kBW + c];
+}
+
+// Y = A X (MODE 0), or Y = B - A X with per-workgroup partial sums of squares
+// of every column (MODE 1).  16 lanes per row, 16 rows per workgroup.
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict__ rowptr,
+                                               const int* __restrict__ colind,
+                                               const double* __restrict__ vals,
+                                               const double* __restrict__ X,
+                                               const double* __restrict__ B, double* __restrict__ Y,
+                                               double* __restrict__ part) {
+    __shared__ double red[kWG];
+    const int c = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
+    double nrm = 0.0;
+    for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
+        const int64_t row = r0 + rl;
+        if (row < n) {
+            const int q0 = rowptr[row], q1 = rowptr[row + 1];
+            double acc = 0.0;
+            int q = q0;
+            for (; q + 4 <= q1; q += 4) {
+                const int c0 = colind[q], c1 = colind[q + 1], c2 = colind[q + 2], c3 = colind[q + 3];
+                const double a0 = vals[q], a1 = vals[q + 1], a2 = vals[q + 2], a3 = vals[q + 3];
+                const double x0 = X[(int64_t)c0 * kBW + c], x1 = X[(int64_t)c1 * kBW + c];
+                const double x2 = X[(int64_t)c2 * kBW + c], x3 = X[(int64_t)c3 * kBW + c];
+                acc += a0 * x0;
+                acc += a1 * x1;
+                acc += a2 * x2;
+                acc += a3 * x3;
+            }
+            for (; q < q1; ++q) acc += vals[q] * X[(int64_t)colind[q] * kBW + c];
+            if (MODE == 0) {
+                Y[row * kBW + c] = acc;
+            } else {
+                const double y = B[row * kBW + c] - acc;
+                Y[row * kBW + c] = y;
+                nrm += y * y;
+            }
+        }
+    }
+    if (MODE == 1) {
+        red[threadIdx.x] = nrm;
+        __syncthreads();
+        if (threadIdx.x < kBW) {
+            double s = 0.0;
+            for (int i = 0; i < kWG / kBW; ++i) s += red[i * kBW + threadIdx.x];
+            part[(int64_t)blockIdx.x * kBW + threadIdx.x] = s;
+        }
+    }
+}
+
+// Column sums of squares: out[c] = sum_b part[b * 16 + c].
+__global__ __launch_bounds__(kWG) void k_bcolsum(int nblk, const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+    __shared__ double red[kWG];
+    const int c = threadIdx.x & (kBW - 1), s = threadIdx.x / kBW;
+    double acc = 0.0;
+    for (int b = s; b < nblk; b += kWG / kBW) acc += part[(int64_t)b * kBW + c];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < kBW) {
+        double t = 0.0;
+        for (int i = 0; i < kWG / kBW; ++i) t += red[i * kBW + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+// Partial products C_i = P_i^T W (P_i = panel i of V for i < nv; with gram,
+// P_nv = W) over 4-row chunks, one MFMA accumulator per panel; per-workgroup
+// partials part[(blk * nb + i) * 256 + m * 16 + n] (fixed order).  Panels
+// beyond nb are loaded (W again) and multiplied but never stored, so the loop
+// body is branch-free.
+template <int NBMAX>
+__global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const double* __restrict__ V,
+                                               int nv, const double* __restrict__ W, int gram,
+                                               double* __restrict__ part) {
+    __shared__ double red[kWG / kWave][kPan];
+    const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int nb = nv + gram;
+    d4 acc[NBMAX];
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t e = (int64_t)(l / kBW) * kBW + (l & (kBW - 1));
+    const int64_t nw = (int64_t)gridDim.x * (kWG / kWave);
+    for (int64_t r0 = ((int64_t)blockIdx.x * (kWG / kWave) + wv) * 4; r0 < n_pad; r0 += nw * 4) {
+        const double b = W[r0 * kBW + e];
+        double a[NBMAX];
+#pragma unroll
+        for (int i = 0; i < NBMAX; ++i) {
+            const double* src = i < nv ? V + i * ps : W;
+            a[i] = src[r0 * kBW + e];
+        }
+#pragma unroll
+        for (int i = 0; i < NBMAX; ++i) acc[i] = mfma16(a[i], b, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) {
+        if (i < nb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wv][(l / kBW + 4 * r) * kBW + (l & (kBW - 1))] = acc[i][r];
+            __syncthreads();
+            const int t = threadIdx.x;
+            double s = red[0][t];
+#pragma unroll
+            for (int w = 1; w < kWG / kWave; ++w) s += red[w][t];
+            part[((int64_t)blockIdx.x * nb + i) * kPan + t] = s;
+            __syncthreads();
+        }
+    }
+}
+
+// Sum of the dot partials over the workgroups, in two fixed-order levels.
+__global__ __launch_bounds__(kWG) void k_breduce1(int nblk, int cnt, const double* __restrict__ part,
+                                                  double* __restrict__ p2) {
+    const int e = blockIdx.x * kWG + threadIdx.x, s = blockIdx.y;
+    if (e >= cnt) return;
+    double acc = 0.0;
+    for (int b = s; b < nblk; b += kSplit) acc += part[(int64_t)b * cnt + e];
+    p2[(int64_t)s * cnt + e] = acc;
+}
+
+// out = sum of the splits; with acc_into: acc_into[e] = (first ? 0 :
+// acc_into[e]) + out[e] for e < acc_cnt, and (first) the diagonal of block
+// diag_blk saved to nb2.
+__global__ __launch_bounds__(kWG) void k_breduce2(int cnt, const double* __restrict__ p2,
+                                                  double* __restrict__ out, double* acc_into,
+                                                  int acc_cnt, int first, int diag_blk,
+                                                  double* __restrict__ nb2) {
+    const int e = blockIdx.x * kWG + threadIdx.x;
+    if (e >= cnt) return;
+    double acc = 0.0;
+    for (int s = 0; s < kSplit; ++s) acc += p2[(int64_t)s * cnt + e];
+    out[e] = acc;
+    if (acc_into && e < acc_cnt) acc_into[e] = (first ? 0.0 : acc_into[e]) + acc;
+    if (nb2 && diag_blk >= 0) {
+        const int d = e - diag_blk * kPan;
+        if (d >= 0 && d < kPan && d / kBW == d % kBW) nb2[d / kBW] = acc;
+    }
+}
+
+// OUT = IN + sign * sum_{i < nb} P_i C_i (P_i = panel i of V, C_i = C[i*256 ..]
+// row-major 16x16), one 16-row tile per wavefront; IN may be NULL; IN, OUT and
+// the panels may alias (a tile is read completely before it is written, by
+// the same wavefront).
+__global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const double* V, int nb,
+                                               const double* __restrict__ C, const double* IN,
+                                               double sign, double* OUT) {
+    __shared__ double cs[(kBlockStepsMax + 1) * kPan];
+    for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
+    __syncthreads();
+    const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t ntile = n_pad / kBW;
+    for (int64_t tile = (int64_t)blockIdx.x * (kWG / kWave) + wv; tile < ntile;
+         tile += (int64_t)gridDim.x * (kWG / kWave)) {
+        const int64_t r0 = tile * kBW;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < nb; ++i) {
+            const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * kBW + l / kBW;
+            const double* Ci = cs + i * kPan + (l / kBW) * kBW + (l & (kBW - 1));
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = P[4 * q];
+                b[q] = Ci[4 * q * kBW];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = mfma16(a[q], b[q], acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t idx = (r0 + l / kBW + 4 * r) * kBW + (l & (kBW - 1));
+            OUT[idx] = (IN ? IN[idx] : 0.0) + sign * acc[r];
+        }
+    }
+}
+
+// R^T R = G for the 16x16 Gram matrix G (row-major); rows/columns >= k are
+// the identity.  Rinv = R^{-1}; Rout = R Rprev (Rprev NULL: R).  With test,
+// a pivot <= kBdTol times the column's norm before orthogonalisation
+// (sqrt(nb2[c]), else sqrt(G_cc)) sets *flag |= 2, bdmask[c] = 1, and makes
+// row c of R and of R^{-1} zero (the column counts as dependent).
+__global__ void k_bchol(int k, const double* __restrict__ G, const double* __restrict__ nb2, int test,
+                        const double* __restrict__ Rprev, double* __restrict__ Rout,
+                        double* __restrict__ Rinv, int* flag, int* __restrict__ bdmask) {
+    __shared__ double R[kPan], Ri[kPan];
+    __shared__ int bd[kBW];
+    const int t = threadIdx.x;   // 64 threads; t < 16 active
+    if (t < kBW) bd[t] = 0;
+    for (int e = t; e < kPan; e += blockDim.x) {
+        R[e] = 0.0;
+        Ri[e] = 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < kBW; ++j) {
+        if (t == 0) {
+            double d;
+            if (j >= k) {
+                d = 1.0;
+            } else {
+                double p = G[j * kBW + j];
+                for (int i = 0; i < j; ++i) p -= R[i * kBW + j] * R[i * kBW + j];
+                const double before = nb2 ? nb2[j] : G[j * kBW + j];
+                if (test && !(p > kBdTol * kBdTol * before)) bd[j] = 1;
+                // A broken column counts as dependent: zero row of R.
+                d = (p > 0.0 && !bd[j]) ? sqrt(p) : 0.0;
+            }
+            R[j * kBW + j] = d;
+        }
+        __syncthreads();
+        if (t > j && t < kBW) {
+            double s = (j < k && t < k) ? G[j * kBW + t] : 0.0;
+            for (int i = 0; i < j; ++i) s -= R[i * kBW + j] * R[i * kBW + t];
+            const double d = R[j * kBW + j];
+            R[j * kBW + t] = d > 0.0 ? s / d : 0.0;
+        }
+        __syncthreads();
+    }
+    // Column t of R^{-1} by back substitution (broken pivots give zeros).
+    if (t < kBW) {
+        for (int i = kBW - 1; i >= 0; --i) {
+            double s = i == t ? 1.0 : 0.0;
+            for (int q = i + 1; q < kBW; ++q) s -= R[i * kBW + q] * Ri[q * kBW + t];
+            const double d = R[i * kBW + i];
+            Ri[i * kBW + t] = (d > 0.0 && !bd[i]) ? s / d : 0.0;
+        }
+    }
+    __syncthreads();
+    if (t < kBW) {
+        for (int i = 0; i < kBW; ++i) {
+            double o;
+            if (Rprev) {
+                o = 0.0;
+                for (int q = i; q <= t; ++q) o += R[i * kBW + q] * Rprev[q * kBW + t];
+            } else {
+                o = R[i * kBW + t];
+            }
+            Rout[i * kBW + t] = o;
+            Rinv[i * kBW + t] = Ri[i * kBW + t];
+        }
+    }
+    __syncthreads();
+    if (t < kBW && test && bdmask) bdmask[t] = bd[t];
+    if (t == 0 && test) {
+        int any = 0;
+        for (int j = 0; j < kBW; ++j) any |= bd[j];
+        if (any) *flag |= 2;
+    }
+}
+
+// In-place column selection of a panel: column i <- column map[i] (map[i] < 0:
+// zero), one row per thread.
+__global__ __launch_bounds__(kWG) void k_bselect(int64_t n, const int* __restrict__ map, double* P) {
+    const int64_t row = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (row >= n) return;
+    double v[kBW];
+#pragma unroll
+    for (int c = 0; c < kBW; ++c) v[c] = P[row * kBW + c];
+#pragma unroll
+    for (int c = 0; c < kBW; ++c) {
+        const int q = map[c];
+        double o = 0.0;
+#pragma unroll
+        for (int s = 0; s < kBW; ++s) o = (q == s) ? v[s] : o;
+        P[row * kBW + c] = o;
+    }
+}
+
+// X[:, act[c]] += T[:, c] for c < ka.
+__global__ __launch_bounds__(kWG) void k_bscatter(int64_t n, int ka, const int* __restrict__ act,
+                                                  const double* __restrict__ T, double* __restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n * kBW) return;
+    const int64_t row = e / kBW;
+    const int c = (int)(e % kBW);
+    if (c < ka) X[row * kBW + act[c]] += T[e];
+}
+
+// Least-squares state, column-major with kLdH rows: H (transformed Hbar),
+// reflectors v (k + 1 entries per column) and beta, G (transformed [S; 0]).
+struct LsView {
+    double* H;      // kLdH * (kBlockStepsMax * kBW)
+    double* v;      // (kBlockStepsMax * kBW) * (kBW + 1)
+    double* beta;   // kBlockStepsMax * kBW
+    double* G;      // kLdH * kBW
+    double* rho0;   // kBW
+    double* est;    // kBW
+};
+
+// G = [S; 0] for the cycle's starting block (S kb x ka, row-major in 16x16).
+__global__ __launch_bounds__(kWG) void k_bls_init(int kb, int ka, const double* __restrict__ S, LsView ls) {
+    for (int e = threadIdx.x; e < kLdH * kBW; e += kWG) {
+        const int c = e / kLdH, i = e % kLdH;
+        ls.G[e] = (c < ka && i < kb) ? S[i * kBW + c] : 0.0;
+    }
+}
+
+// Block step j (k basis columns per block, ka right-hand sides): append the
+// block column (rows 0 .. (j+2)k-1) built from the accumulated projection
+// coefficients Csum (blocks 0..j) and H_{j+1,j} = Rj, apply the previous
+// reflectors, make k new ones, apply them to G, and estimate each right-hand
+// side's residual.  *flag |= 1 when every one passes.
+__global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
+                                             const double* __restrict__ Csum,
+                                             const double* __restrict__ Rj, LsView ls, int* flag) {
+    __shared__ double h[kBW][kLdH];
+    __shared__ double vs[kBW + 1];
+    __shared__ double bs;
+    const int t = threadIdx.x;
+    const int rows = (j + 2) * k, c0 = j * k;
+    for (int e = t; e < kBW * kLdH; e += kWG) {
+        const int col = e / kLdH, row = e % kLdH;
+        double val = 0.0;
+        if (col < k && row < rows) {
+            const int blk = row / k, kk = row % k;
+            if (blk <= j) val = Csum[blk * kPan + kk * kBW + col];
+            else val = kk <= col ? Rj[kk * kBW + col] : 0.0;
+        }
+        h[col][row] = val;
+    }
+    __syncthreads();
+    // Previous reflectors, in order; column t of the new block per thread.
+    if (t < k) {
+        for (int p = 0; p < c0; ++p) {
+            const double* vp = ls.v + (int64_t)p * (kBW + 1);
+            const double bp = ls.beta[p];
+            double s = 0.0;
+            for (int i = 0; i <= k; ++i) s += vp[i] * h[t][p + i];
+            s *= bp;
+            for (int i = 0; i <= k; ++i) h[t][p + i] -= s * vp[i];
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < k; ++q) {
+        const int col = c0 + q;
+        if (t == 0) {
+            double nrm = 0.0;
+            for (int i = 0; i <= k; ++i) nrm += h[q][col + i] * h[q][col + i];
+            nrm = sqrt(nrm);
+            double beta = 0.0;
+            if (nrm > 0.0) {
+                const double a0 = h[q][col];
+                const double alpha = a0 >= 0.0 ? -nrm : nrm;
+                vs[0] = a0 - alpha;
+                for (int i = 1; i <= k; ++i) vs[i] = h[q][col + i];
+                double vv = 0.0;
+                for (int i = 0; i <= k; ++i) vv += vs[i] * vs[i];
+                beta = vv > 0.0 ? 2.0 / vv : 0.0;
+            } else {
+                for (int i = 0; i <= k; ++i) vs[i] = 0.0;
+            }
+            bs = beta;
+            for (int i = 0; i <= k; ++i) ls.v[(int64_t)col * (kBW + 1) + i] = vs[i];
+            ls.beta[col] = beta;
+        }
+        __syncthreads();
+        const double beta = bs;
+        if (beta != 0.0) {
+            if (t >= q && t < k) {   // columns q.. of the block
+                double s = 0.0;
+                for (int i = 0; i <= k; ++i) s += vs[i] * h[t][col + i];
+                s *= beta;
+                for (int i = 0; i <= k; ++i) h[t][col + i] -= s * vs[i];
+            } else if (t >= kBW && t < kBW + ka) {   // right-hand sides
+                const int c = t - kBW;
+                double s = 0.0;
+                for (int i = 0; i <= k; ++i) s += vs[i] * ls.G[(int64_t)c * kLdH + col + i];
+                s *= beta;
+                for (int i = 0; i <= k; ++i) ls.G[(int64_t)c * kLdH + col + i] -= s * vs[i];
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < k * rows; e += kWG) {
+        const int col = e / rows, row = e % rows;
+        ls.H[(int64_t)(c0 + col) * kLdH + row] = h[col][row];
+    }
+    __syncthreads();
+    if (t == 0) {
+        int conv = 1;
+        for (int c = 0; c < ka; ++c) {
+            double e2 = 0.0;
+            for (int i = (j + 1) * k; i < rows; ++i) e2 += ls.G[(int64_t)c * kLdH + i] * ls.G[(int64_t)c * kLdH + i];
+            const double est = sqrt(e2);
+            ls.est[c] = est;
+            if (est > rtol * ls.rho0[c]) conv = 0;
+        }
+        if (conv) *flag |= 1;
+    }
+}
+
+// Y = R^{-1} G_top (R: leading J x J upper triangle of H, J = nblk * k; ka
+// right-hand sides), written as nblk padded 16x16 coefficient blocks
+// Cy[blk * 256 + kk * 16 + c].
+__global__ __launch_bounds__(kWG) void k_bsolve(int nblk, int k, int ka, LsView ls, double* __restrict__ Cy) {
+    __shared__ double y[kLdH][kBW];
+    __shared__ double part[kBW][kBW + 1];
+    const int J = nblk * k;
+    const int c = threadIdx.x & (kBW - 1), g = threadIdx.x / kBW;
+    for (int e = threadIdx.x; e < kLdH * kBW; e += kWG) y[e / kBW][e % kBW] = 0.0;
+    __syncthreads();
+    for (int i = J - 1; i >= 0; --i) {
+        double s = 0.0;
+        if (c < ka)
+            for (int q = i + 1 + g; q < J; q += kBW) s += ls.H[(int64_t)q * kLdH + i] * y[q][c];
+        part[g][c] = s;
+        __syncthreads();
+        if (g == 0 && c < ka) {
+            double acc = ls.G[(int64_t)c * kLdH + i];
+            for (int q = 0; q < kBW; ++q) acc -= part[q][c];
+            y[i][c] = acc / ls.H[(int64_t)i * kLdH + i];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nblk * kPan; e += kWG) {
+        const int blk = e / kPan, kk = (e % kPan) / kBW, cc = e % kBW;
+        Cy[e] = (kk < k && cc < ka) ? y[blk * k + kk][cc] : 0.0;
+    }
+}
+
+// Launch through the timing hook when there is one: the kernel carries the
+// armed start/stop events in its own dispatch.
+template <typename... KA, typename... A>
+void blaunch(BlockTimer* tm, int kind, double bytes, void (*k)(KA...), dim3 g, dim3 b, hipStream_t st,
+             A... args) {
+    hipEvent_t e0, e1;
+    if (tm) tm->begin(kind, bytes);
+    if (tm && take_kernel_events(&e0, &e1))
+        hipExtLaunchKernelGGL(k, g, b, 0, st, e0, e1, 0u, static_cast<KA>(args)...);
+    else
+        k<<<g, b, 0, st>>>(static_cast<KA>(args)...);
+    if (tm) tm->end();
+}
+
+template <int NBMAX>
+void dots_launch(BlockTimer* tm, double bytes, hipStream_t st, int64_t n_pad, int64_t ps, const double* V,
+                 int nv, const double* W, int gram, double* part) {
+    blaunch(tm, 5, bytes, k_bdots<NBMAX>, dim3(kDotGrid), dim3(kWG), st, n_pad, ps, V, nv, W, gram, part);
+}
+
+}  // namespace
+
+struct BlockWork {
+    int64_t n = 0, n_pad = 0, ps = 0;
+    int m = 0;
+    double* panels = nullptr;   // (m + 1) basis panels, W, B, X
+    double *part = nullptr, *p2 = nullptr, *C = nullptr, *Csum = nullptr;
+    double *R1 = nullptr, *R = nullptr, *Rinv = nullptr, *nb2 = nullptr, *Cy = nullptr;
+    double *npart = nullptr, *nsq = nullptr;
+    double *lsbuf = nullptr, *S = nullptr;
+    int* flag = nullptr;
+    int* imap = nullptr;   // [0,16): column map; [16,32): active columns; [32,48): broken mask
+    LsView ls{};
+    double* V() const { return panels; }
+    double* W() const { return panels + (int64_t)(m + 1) * ps; }
+    double* Bp() const { return panels + (int64_t)(m + 2) * ps; }
+    double* Xp() const { return panels + (int64_t)(m + 3) * ps; }
+};
+
+void block_free(BlockWork* w) {
+    if (!w) return;
+    for (double* q : {w->panels, w->part, w->p2, w->C, w->Csum, w->R1, w->R, w->Rinv, w->nb2, w->Cy,
+                      w->npart, w->nsq, w->lsbuf, w->S})
+        hipFree(q);
+    hipFree(w->flag);
+    hipFree(w->imap);
+    delete w;
+}
+
+int block_alloc(BlockWork** out, hipStream_t st, int64_t n, int m) {
+    BlockWork* w = new (std::nothrow) BlockWork();
+    if (!w) return kStatusNoMem;
+    w->n = n;
+    w->n_pad = (n + 63) / 64 * 64;
+    w->ps = w->n_pad * kBW;
+    w->m = m;
+    const int64_t nbmax = m + 2;
+    const int64_t lsn = (int64_t)kLdH * kBlockStepsMax * kBW + (int64_t)kBlockStepsMax * kBW * (kBW + 1) +
+                        (int64_t)kBlockStepsMax * kBW + (int64_t)kLdH * kBW + 2 * kBW;
+    bool ok = hipMalloc(&w->panels, (m + 4) * w->ps * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->part, (int64_t)kDotGrid * nbmax * kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->p2, (int64_t)kSplit * nbmax * kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->C, nbmax * kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->Csum, nbmax * kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->R1, kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->R, kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->Rinv, kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->nb2, kBW * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->Cy, (int64_t)(m + 1) * kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->npart, (int64_t)kNormGrid * kBW * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->nsq, kBW * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->lsbuf, lsn * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->S, kPan * sizeof(double)) == hipSuccess &&
+              hipMalloc(&w->flag, sizeof(int)) == hipSuccess &&
+              hipMalloc(&w->imap, 3 * kBW * sizeof(int)) == hipSuccess;
+    if (!ok) {
+        block_free(w);
+        return kStatusNoMem;
+    }
+    // Panel rows beyond n stay zero for the whole life of the plan.
+    if (hipMemsetAsync(w->panels, 0, (m + 4) * w->ps * sizeof(double), st) != hipSuccess ||
+        hipMemsetAsync(w->lsbuf, 0, lsn * sizeof(double), st) != hipSuccess) {
+        block_free(w);
+        return kStatusDevice;
+    }
+    double* q = w->lsbuf;
+    w->ls.H = q;
+    q += (int64_t)kLdH * kBlockStepsMax * kBW;
+    w->ls.v = q;
+    q += (int64_t)kBlockStepsMax * kBW * (kBW + 1);
+    w->ls.beta = q;
+    q += (int64_t)kBlockStepsMax * kBW;
+    w->ls.G = q;
+    q += (int64_t)kLdH * kBW;
+    w->ls.rho0 = q;
+    q += kBW;
+    w->ls.est = q;
+    *out = w;
+    return kStatusOk;
+}
+
+namespace {
+
+// C[0 .. nb) = P^T W (panels of V, then W itself when gram), summed.
+void dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nv, const double* W,
+          int gram, double* acc_into, int acc_blocks, int first, int diag_blk, double* nb2) {
+    const int nb = nv + gram;
+    const double bytes = (double)(nv + 1) * (double)w.n * kBW * sizeof(double);   // panels and W, once
+    if (nb <= 4) dots_launch<4>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
+    else if (nb <= 8) dots_launch<8>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
+    else if (nb <= 12) dots_launch<12>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
+    else dots_launch<kBlockStepsMax + 2>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
+    const int cnt = nb * kPan;
+    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(kDotGrid, cnt, w.part, w.p2);
+    k_breduce2<<<(cnt + kWG - 1) / kWG, kWG, 0, st>>>(cnt, w.p2, w.C, acc_into, acc_blocks * kPan, first,
+                                                      diag_blk, nb2);
+}
+
+void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, const double* C,
+          const double* IN, double sign, double* OUT) {
+    const int64_t ntile = w.n_pad / kBW;
+    const int grid = (int)std::min<int64_t>((ntile + 3) / 4, 8192);
+    const double bytes = (double)(nb + (IN ? 1 : 0) + 1) * (double)w.n * kBW * sizeof(double);
+    blaunch(tm, 6, bytes, k_bgemm, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT);
+}
+
+// Cholesky QR applied twice to the panel `src` into `dst` (may alias):
+// dst R = src, R = R2 R1 (into w.R).  test: breakdown test of the first pass
+// against nb2 (NULL: the Gram diagonal).
+void cholqr2(const BlockWork& w, BlockTimer* tm, hipStream_t st, int k, const double* src, double* dst,
+             int test, const double* nb2) {
+    dots(w, tm, st, nullptr, 0, src, 1, nullptr, 0, 0, -1, nullptr);
+    k_bchol<<<1, kWave, 0, st>>>(k, w.C, nb2, test, nullptr, w.R1, w.Rinv, w.flag, w.imap + 2 * kBW);
+    gemm(w, tm, st, src, 1, w.Rinv, nullptr, 1.0, dst);
+    dots(w, tm, st, nullptr, 0, dst, 1, nullptr, 0, 0, -1, nullptr);
+    k_bchol<<<1, kWave, 0, st>>>(k, w.C, nullptr, 0, w.R1, w.R, w.Rinv, w.flag, nullptr);
+    gemm(w, tm, st, dst, 1, w.Rinv, nullptr, 1.0, dst);
+}
+
+// Residual panel W = B - A X and the column norms on the host.
+// Algorithmic bytes of one SpMM: A (8-byte values, 4-byte indices, row
+// pointers), the input panel (one line per row), the output panel (and B).
+double spmm_bytes(const BlockWork& w, const BlockArgs& a, int mode) {
+    return 12.0 * (double)a.nnz + 4.0 * (double)(w.n + 1) + (2.0 + mode) * (double)w.n * kBW * sizeof(double);
+}
+
+int residual(const BlockWork& w, const BlockArgs& a, double* h_nrm) {
+    blaunch(a.timer, 7, spmm_bytes(w, a, 1), k_bspmm<1>, dim3(kNormGrid), dim3(kWG), a.st, w.n, a.rowptr,
+            a.colind, a.vals, (const double*)w.Xp(), (const double*)w.Bp(), w.W(), w.npart);
+    k_bcolsum<<<1, kWG, 0, a.st>>>(kNormGrid, w.npart, w.nsq);
+    double sq[kBW];
+    if (hipMemcpyAsync(sq, w.nsq, sizeof(sq), hipMemcpyDeviceToHost, a.st) != hipSuccess ||
+        hipStreamSynchronize(a.st) != hipSuccess)
+        return kStatusDevice;
+    for (int c = 0; c < kBW; ++c) h_nrm[c] = std::sqrt(sq[c]);
+    return kStatusOk;
+}
+
+int read_flag(const BlockWork& w, hipStream_t st, int* f) {
+    if (hipMemcpyAsync(f, w.flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return kStatusDevice;
+    return kStatusOk;
+}
+
+}  // namespace
+
+int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
+    const hipStream_t st = a.st;
+    const int k = a.k, m = a.m;
+    *res = BlockResult{};
+    const int64_t pe = w->n * kBW;
+    const unsigned gpe = (unsigned)((pe + kWG - 1) / kWG), grow = (unsigned)((w->n + kWG - 1) / kWG);
+    k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, a.B, w->Bp());
+    k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, a.X0, w->Xp());
+    double rho0[kBW], rn[kBW];
+    int s = residual(*w, a, rho0);
+    if (s != kStatusOk) return s;
+    double rho_max = 0.0;
+    for (int c = 0; c < k; ++c) {
+        if (!(rho0[c] > 0.0)) return kStatusInval;   // zero (or non-finite) initial residual column
+        rho_max = std::max(rho_max, rho0[c]);
+    }
+    res->rho0 = rho_max;
+    for (int c = 0; c < kBW; ++c) rn[c] = rho0[c];
+    int64_t steps = 0;
+    int cycles = 0, status = kStatusMaxIter;
+    double est_max = 1.0;
+    for (;;) {
+        // Active columns: residual not yet below rtol * rho0_c.
+        int act[kBW], ka = 0;
+        for (int c = 0; c < k; ++c)
+            if (rn[c] > a.rtol * rho0[c]) act[ka++] = c;
+        if (ka == 0) {
+            status = kStatusOk;
+            break;
+        }
+        if (steps >= a.max_steps) {
+            status = kStatusMaxIter;
+            break;
+        }
+        // Starting block from the active residual columns: V_0 S = R.
+        int hmap[3 * kBW];
+        for (int c = 0; c < kBW; ++c) {
+            hmap[c] = c < ka ? act[c] : -1;
+            hmap[kBW + c] = c < ka ? act[c] : 0;
+        }
+        if (hipMemcpyAsync(w->imap, hmap, 2 * kBW * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemsetAsync(w->flag, 0, sizeof(int), st) != hipSuccess ||
+            hipMemsetAsync(w->imap + 2 * kBW, 0, kBW * sizeof(int), st) != hipSuccess)
+            return kStatusDevice;
+        k_bselect<<<grow, kWG, 0, st>>>(w->n, w->imap, w->W());
+        cholqr2(*w, a.timer, st, ka, w->W(), w->V(), 1, nullptr);
+        // A residual column dependent on the earlier ones adds no basis
+        // vector: keep kb independent columns, S = their rows of R (kb x ka).
+        double hR[kPan];
+        if (hipMemcpyAsync(hR, w->R, sizeof(hR), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hmap + 2 * kBW, w->imap + 2 * kBW, kBW * sizeof(int), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return kStatusDevice;
+        int indep[kBW], kb = 0;
+        for (int c = 0; c < ka; ++c)
+            if (!hmap[2 * kBW + c]) indep[kb++] = c;
+        double hS[kPan] = {};
+        for (int q = 0; q < kb; ++q)
+            for (int c = 0; c < ka; ++c) hS[q * kBW + c] = hR[indep[q] * kBW + c];
+        double r0a[kBW] = {};
+        for (int c = 0; c < ka; ++c) r0a[c] = rho0[act[c]];
+        if (hipMemcpyAsync(w->S, hS, sizeof(hS), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(w->ls.rho0, r0a, sizeof(r0a), hipMemcpyHostToDevice, st) != hipSuccess)
+            return kStatusDevice;
+        if (kb < ka) {
+            int cmap[kBW];
+            for (int c = 0; c < kBW; ++c) cmap[c] = c < kb ? indep[c] : -1;
+            if (hipMemcpyAsync(w->imap, cmap, kBW * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
+                return kStatusDevice;
+            k_bselect<<<grow, kWG, 0, st>>>(w->n, w->imap, w->V());
+        }
+        if (hipMemsetAsync(w->flag, 0, sizeof(int), st) != hipSuccess) return kStatusDevice;
+        k_bls_init<<<1, kWG, 0, st>>>(kb, ka, w->S, w->ls);
+        ++cycles;
+        int jd = 0, f = 0;
+        for (int j = 0; j < m && steps < a.max_steps; ++j) {
+            double* Vj = w->V() + (int64_t)j * w->ps;
+            double* Vn = w->V() + (int64_t)(j + 1) * w->ps;
+            const unsigned g16 = (unsigned)((w->n + kWG / kBW - 1) / (kWG / kBW));
+            blaunch(a.timer, 7, spmm_bytes(*w, a, 0), k_bspmm<0>, dim3(g16), dim3(kWG), st, w->n, a.rowptr,
+                    a.colind, a.vals, (const double*)Vj, (const double*)nullptr, w->W(), (double*)nullptr);
+            // BCGS2: two projections onto V_0..V_j; the first also gives the
+            // squared column norms of A V_j (the breakdown reference).
+            dots(*w, a.timer, st, w->V(), j + 1, w->W(), 1, w->Csum, j + 1, 1, j + 1, w->nb2);
+            gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W());
+            dots(*w, a.timer, st, w->V(), j + 1, w->W(), 0, w->Csum, j + 1, 0, -1, nullptr);
+            gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W());
+            cholqr2(*w, a.timer, st, kb, w->W(), Vn, 1, w->nb2);
+            k_bls<<<1, kWG, 0, st>>>(j, kb, ka, a.rtol, w->Csum, w->R, w->ls, w->flag);
+            ++steps;
+            jd = j + 1;
+            if ((s = read_flag(*w, st, &f)) != kStatusOk) return s;
+            if (f) break;
+        }
+        double est[kBW];
+        if (hipMemcpyAsync(est, w->ls.est, sizeof(est), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return kStatusDevice;
+        est_max = 0.0;
+        for (int c = 0; c < ka; ++c) est_max = std::max(est_max, est[c] / r0a[c]);
+        // X[:, act] += V Y (through the free W panel).
+        k_bsolve<<<1, kWG, 0, st>>>(jd, kb, ka, w->ls, w->Cy);
+        gemm(*w, a.timer, st, w->V(), jd, w->Cy, nullptr, 1.0, w->W());
+        k_bscatter<<<gpe, kWG, 0, st>>>(w->n, ka, w->imap + kBW, w->W(), w->Xp());
+        if ((s = residual(*w, a, rn)) != kStatusOk) return s;
+        for (int c = 0; c < k; ++c)
+            if (!std::isfinite(rn[c])) return kStatusNonFinite;
+    }
+    const int64_t ue = w->n * k;
+    k_bunpack<<<(unsigned)((ue + kWG - 1) / kWG), kWG, 0, st>>>(w->n, k, w->Xp(), a.X);
+    if (hipStreamSynchronize(st) != hipSuccess) return kStatusDevice;
+    double tr = 0.0;
+    for (int c = 0; c < k; ++c) tr = std::max(tr, rn[c] / rho0[c]);
+    res->steps = steps;
+    res->cycles = cycles;
+    res->status = status;
+    res->rel_res_est = est_max;
+    res->rel_res_true = tr;
+    return kStatusOk;
+}
+
+}  // namespace gm

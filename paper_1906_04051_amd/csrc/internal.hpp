@@ -135,6 +135,8 @@ void adapt_cycle_end(const EngineArgs& e, const double* V, const double* coef);
 // armed pair was not consumed by a launch.
 void arm_kernel_events(hipEvent_t start, hipEvent_t stop);
 bool disarm_kernel_events();
+// Takes the armed event pair (if any) for a launch made outside krylov.hip.
+bool take_kernel_events(hipEvent_t* start, hipEvent_t* stop);
 void launch_restart_init(const EngineArgs& a, const void* b, double rtol, double r0_override);
 void launch_cycle(const EngineArgs& a, const void* b);
 void launch_correct(hipStream_t st, int NB, int n, const int* zrp, const int* zci, const double* zv,
@@ -240,5 +242,42 @@ void launch_seg_resid(hipStream_t st, int nsys, const int64_t* row_off, const in
                       double* out);
 // One launch of a pass kernel (FP64) for tuning: kind 1, 2 or 3 at nv columns.
 void launch_pass_probe(const EngineArgs& a, int kind, int nv);
+
+
+// ---------------------------------------------------------------- block GMRES
+// Block GMRES(m) for k <= 16 right-hand sides (block.hip).
+constexpr int kBlockStepsMax = 16;   // block steps per cycle
+// Per-launch timing of the block kernels: begin() may arm events that the
+// next launch carries (kinds 5 dots, 6 panel products, 7 SpMM; bytes =
+// algorithmic bytes of the launch).
+struct BlockTimer {
+    virtual void begin(int kind, double bytes) = 0;
+    virtual void end() = 0;
+    virtual ~BlockTimer() = default;
+};
+struct BlockArgs {
+    hipStream_t st;
+    const int* rowptr;
+    const int* colind;
+    const double* vals;
+    int k, m;                  // right-hand sides, block steps per cycle
+    double rtol;
+    int64_t max_steps;         // block steps over all cycles
+    const double* B;           // n x k row-major (device)
+    const double* X0;          // n x k row-major or NULL (zero)
+    double* X;                 // n x k row-major (device, output)
+    int64_t nnz;
+    BlockTimer* timer;         // NULL: untimed
+};
+struct BlockResult {
+    int64_t steps = 0;
+    int cycles = 0;
+    int status = 0;            // kStatusOk / MaxIter / Breakdown
+    double rho0 = 0.0, rel_res_est = 0.0, rel_res_true = 0.0;
+};
+struct BlockWork;
+int block_alloc(BlockWork** out, hipStream_t st, int64_t n, int m);
+void block_free(BlockWork* w);
+int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res);
 
 }  // namespace gm

@@ -1300,6 +1300,14 @@ bool disarm_kernel_events() {
     return pending;
 }
 
+bool take_kernel_events(hipEvent_t* start, hipEvent_t* stop) {
+    if (!t_ev_start) return false;
+    *start = t_ev_start;
+    *stop = t_ev_stop;
+    t_ev_start = t_ev_stop = nullptr;
+    return true;
+}
+
 // Workgroups of one streaming pass: as many as the device holds at once
 // (a single round, so every workgroup gets the same share of rows), at most
 // cap.  Queried once per kernel and device.

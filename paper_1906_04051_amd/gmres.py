@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "MAXITER", 2: "BREAKDOWN", 3: "STAGNATED", -1: "EINVAL", -
           -3: "ENONFINITE", -4: "EDEVICE", -5: "ENOMEM"}
 
 # Every symbol include/gmres.h declares.
-EXPORTS = ["gmres_default_opts", "gmres_setup", "gmres_solve", "gmres_solve_batched",
+EXPORTS = ["gmres_default_opts", "gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_solve_block",
            "gmres_adjoint", "gmres_update_values", "gmres_spmv", "gmres_history",
            "gmres_autotune", "gmres_set_timing", "gmres_kernel_times", "gmres_set_stream",
            "gmres_destroy", "gmres_last_error"]
@@ -75,6 +75,7 @@ def load_library():
     lib.gmres_solve.argtypes = [vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_solve_batched.argtypes = [vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_adjoint.argtypes = [vp, vp, vp, vp, vp, C.POINTER(GmresInfo)]
+    lib.gmres_solve_block.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_update_values.argtypes = [vp, vp]
     lib.gmres_spmv.argtypes = [vp, vp, vp]
     lib.gmres_history.argtypes = [vp, C.POINTER(dbl), i64]
@@ -87,7 +88,7 @@ def load_library():
     lib.gmres_destroy.restype = None
     lib.gmres_last_error.argtypes = []
     lib.gmres_last_error.restype = C.c_char_p
-    for name in ("gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_adjoint",
+    for name in ("gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_solve_block", "gmres_adjoint",
                  "gmres_update_values", "gmres_spmv", "gmres_autotune", "gmres_set_timing",
                  "gmres_kernel_times", "gmres_set_stream"):
         getattr(lib, name).restype = C.c_int
@@ -211,6 +212,27 @@ class Plan:
         _check(st)
         return x, [i.to_dict() for i in infos]
 
+    def solve_block(self, B, m_block: int, X0=None, out=None):
+        """Block GMRES(m_block) for the k columns of B (n x k, row-major,
+        float64, on the plan's device).  Returns (X, info dict); iters are
+        block steps."""
+        import torch
+        for t, name in ((B, "B"), (X0, "X0")):
+            if t is None:
+                continue
+            if (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2
+                    or t.shape[0] != self.n):
+                raise TypeError(f"{name} must be a contiguous float64 CUDA tensor of shape (n, k)")
+        k = int(B.shape[1])
+        if X0 is not None and tuple(X0.shape) != tuple(B.shape):
+            raise ValueError("X0 must have the shape of B")
+        X = out if out is not None else torch.empty_like(B)
+        info = GmresInfo()
+        st = self._lib.gmres_solve_block(self._h, k, int(m_block), _ptr(B), _ptr(X0), _ptr(X),
+                                         C.byref(info))
+        _check(st)
+        return X, info.to_dict()
+
     def adjoint(self, x, grad_x):
         """Returns (grad_b, grad_vals, info dict)."""
         import torch
@@ -249,9 +271,9 @@ class Plan:
         _check(self._lib.gmres_set_timing(self._h, int(period)))
 
     def kernel_times(self) -> dict:
-        out = (C.c_double * 15)()
+        out = (C.c_double * 24)()
         _check(self._lib.gmres_kernel_times(self._h, out))
-        names = ["spmv", "pass1", "pass2", "pass3", "pass1_lag"]
+        names = ["spmv", "pass1", "pass2", "pass3", "pass1_lag", "block_dots", "block_gemm", "block_spmm"]
         return {nm: dict(launches=out[3 * k], ms=out[3 * k + 1], bytes=out[3 * k + 2])
                 for k, nm in enumerate(names)}
 

@@ -13,6 +13,10 @@ against facts fixed by the mathematics, never against the oracle itself:
                     one cycle;
   * whole solve  -- to tolerance on a FEM system, every column within its
                     rtol, solution against a dense direct solve;
+  * dependent columns -- B with a repeated column and a column that is the
+                    sum of two others: the minimisation is linear in B, so
+                    X keeps the same relations (restarts keep one basis vector
+                    per independent residual direction);
   * invalid input -- a zero right-hand side column, k < 1.
 """
 import copy
@@ -147,3 +151,20 @@ def test_invalid_inputs():
     B[:, 1] = 0.0
     assert oracle.bgmres(rp, ci, v, B, 4, 1e-8, 10).status_name == "EINVAL"
     assert oracle.bgmres(rp, ci, v, np.ones((n, 2)), 0, 1e-8, 10).status_name == "EINVAL"
+
+
+def test_dependent_right_hand_sides_keep_linearity():
+    s = W.make_config(1, mesh=24)
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((s.n, 5))
+    B[:, 2] = B[:, 0]
+    B[:, 4] = B[:, 1] + B[:, 3]
+    res = oracle.bgmres(s.rowptr, s.colind, s.vals, B, 6, 1e-10, 4000)
+    assert res.status_name == "OK"
+    X = res.x
+    scale = np.abs(X).max()
+    assert np.abs(X[:, 2] - X[:, 0]).max() <= 1e-12 * scale
+    assert np.abs(X[:, 4] - X[:, 1] - X[:, 3]).max() <= 1e-8 * scale
+    for c in range(5):
+        r = B[:, c] - oracle.spmv(s.rowptr, s.colind, s.vals, X[:, c])
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(B[:, c]) * (1 + 1e-6)
