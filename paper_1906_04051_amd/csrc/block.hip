@@ -137,36 +137,38 @@ __global__ __launch_bounds__(kWG) void k_bcolsum(int nblk, const double* __restr
 }
 
 // Partial products C_i = P_i^T W (P_i = panel i of V for i < nv; with gram,
-// P_nv = W) over 4-row chunks, one MFMA accumulator per panel; per-workgroup
-// partials part[(blk * nb + i) * 256 + m * 16 + n] (fixed order).  Panels
-// beyond nb are loaded (W again) and multiplied but never stored, so the loop
-// body is branch-free.
-template <int NBMAX>
+// P_nv = W) over 4-row chunks, one MFMA accumulator per panel; workgroups
+// with blockIdx.y = g take panels [NG g, NG g + NG) (W is read once per
+// group, which keeps NG accumulators per lane and the occupancy high);
+// per-workgroup partials part[(blockIdx.x * nb + i) * 256 + m * 16 + n]
+// (fixed order).  Panels beyond nb are loaded (W again) and multiplied but
+// never stored, so the loop body is branch-free.
+template <int NG>
 __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const double* __restrict__ V,
                                                int nv, const double* __restrict__ W, int gram,
                                                double* __restrict__ part) {
     __shared__ double red[kWG / kWave][kPan];
     const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int nb = nv + gram;
-    d4 acc[NBMAX];
+    const int nb = nv + gram, i0 = blockIdx.y * NG;
+    d4 acc[NG];
 #pragma unroll
-    for (int i = 0; i < NBMAX; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < NG; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    const double* src[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) src[i] = i0 + i < nv ? V + (i0 + i) * ps : W;
     const int64_t e = (int64_t)(l / kBW) * kBW + (l & (kBW - 1));
     const int64_t nw = (int64_t)gridDim.x * (kWG / kWave);
     for (int64_t r0 = ((int64_t)blockIdx.x * (kWG / kWave) + wv) * 4; r0 < n_pad; r0 += nw * 4) {
         const double b = W[r0 * kBW + e];
-        double a[NBMAX];
+        double a[NG];
 #pragma unroll
-        for (int i = 0; i < NBMAX; ++i) {
-            const double* src = i < nv ? V + i * ps : W;
-            a[i] = src[r0 * kBW + e];
-        }
+        for (int i = 0; i < NG; ++i) a[i] = src[i][r0 * kBW + e];
 #pragma unroll
-        for (int i = 0; i < NBMAX; ++i) acc[i] = mfma16(a[i], b, acc[i]);
+        for (int i = 0; i < NG; ++i) acc[i] = mfma16(a[i], b, acc[i]);
     }
 #pragma unroll
-    for (int i = 0; i < NBMAX; ++i) {
-        if (i < nb) {
+    for (int i = 0; i < NG; ++i) {
+        if (i0 + i < nb) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) red[wv][(l / kBW + 4 * r) * kBW + (l & (kBW - 1))] = acc[i][r];
             __syncthreads();
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const 
             double s = red[0][t];
 #pragma unroll
             for (int w = 1; w < kWG / kWave; ++w) s += red[w][t];
-            part[((int64_t)blockIdx.x * nb + i) * kPan + t] = s;
+            part[((int64_t)blockIdx.x * nb + i0 + i) * kPan + t] = s;
             __syncthreads();
         }
     }
@@ -502,11 +504,7 @@ void blaunch(BlockTimer* tm, int kind, double bytes, void (*k)(KA...), dim3 g, d
     if (tm) tm->end();
 }
 
-template <int NBMAX>
-void dots_launch(BlockTimer* tm, double bytes, hipStream_t st, int64_t n_pad, int64_t ps, const double* V,
-                 int nv, const double* W, int gram, double* part) {
-    blaunch(tm, 5, bytes, k_bdots<NBMAX>, dim3(kDotGrid), dim3(kWG), st, n_pad, ps, V, nv, W, gram, part);
-}
+constexpr int kDotGroup = 4;   // panels per workgroup of the dot kernel
 
 }  // namespace
 
@@ -596,10 +594,9 @@ void dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
           int gram, double* acc_into, int acc_blocks, int first, int diag_blk, double* nb2) {
     const int nb = nv + gram;
     const double bytes = (double)(nv + 1) * (double)w.n * kBW * sizeof(double);   // panels and W, once
-    if (nb <= 4) dots_launch<4>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
-    else if (nb <= 8) dots_launch<8>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
-    else if (nb <= 12) dots_launch<12>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
-    else dots_launch<kBlockStepsMax + 2>(tm, bytes, st, w.n_pad, w.ps, V, nv, W, gram, w.part);
+    const int groups = (nb + kDotGroup - 1) / kDotGroup;
+    blaunch(tm, 5, bytes, k_bdots<kDotGroup>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv, W,
+            gram, w.part);
     const int cnt = nb * kPan;
     k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(kDotGrid, cnt, w.part, w.p2);
     k_breduce2<<<(cnt + kWG - 1) / kWG, kWG, 0, st>>>(cnt, w.p2, w.C, acc_into, acc_blocks * kPan, first,

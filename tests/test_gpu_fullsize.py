@@ -250,3 +250,27 @@ def test_poisson_1024_adaptive_to_tolerance():
     _, i0 = p0.solve(d0["b"])
     say("1024^2 kappa=1 plain GMRES(30):", i0["iters"], "iterations,", i0["status_name"])
     assert info["iters"] < i0["iters"]
+
+
+def test_block_16_rhs_fullsize_fixed_count():
+    """Block GMRES with 16 right-hand sides on the 1,050,625-unknown kappa = 1
+    system (the block benchmark's workload): two block steps in the
+    benchmark's configuration against the block oracle, element by element."""
+    import copy
+    s = copy.copy(W.make_config(1, mesh=1024))
+    s.r = 0
+    s.z_rowptr = np.zeros(s.n + 1, np.int32)
+    s.z_colind = np.zeros(0, np.int32)
+    s.z_vals = np.zeros(0)
+    B = np.random.default_rng(20190610).standard_normal((s.n, 16))
+    ref = oracle.bgmres(s.rowptr, s.colind, s.vals, B, 8, 0.0, 2)
+    plan, d = G().plan_for(s, m=50, rtol=0.0, max_iters=2)
+    X, info = plan.solve_block(torch.from_numpy(B).cuda(), 8)
+    X = X.cpu().numpy()
+    plan.close()
+    err = float(np.linalg.norm(X - ref.x) / np.linalg.norm(ref.x))
+    say(f"block 16 rhs full size: steps {info['iters']} rel diff {err:.3e} "
+        f"max rel res {info['rel_res_true']:.4e} (oracle {ref.rel_res_true:.4e})")
+    assert info["iters"] == ref.iters == 2
+    assert err <= 1e-8
+    assert abs(info["rel_res_true"] - ref.rel_res_true) <= 1e-8
