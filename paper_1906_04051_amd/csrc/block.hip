@@ -376,10 +376,14 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
                                              const double* __restrict__ Csum,
                                              const double* __restrict__ Rj, LsView ls, int* flag) {
     __shared__ double h[kBW][kLdH];
+    __shared__ double vl[(kBlockStepsMax - 1) * kBW * (kBW + 1)];   // previous reflectors
+    __shared__ double bl[(kBlockStepsMax - 1) * kBW];
     __shared__ double vs[kBW + 1];
     __shared__ double bs;
     const int t = threadIdx.x;
     const int rows = (j + 2) * k, c0 = j * k;
+    for (int e = t; e < c0 * (kBW + 1); e += kWG) vl[e] = ls.v[e];
+    for (int e = t; e < c0; e += kWG) bl[e] = ls.beta[e];
     for (int e = t; e < kBW * kLdH; e += kWG) {
         const int col = e / kLdH, row = e % kLdH;
         double val = 0.0;
@@ -394,8 +398,8 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
     // Previous reflectors, in order; column t of the new block per thread.
     if (t < k) {
         for (int p = 0; p < c0; ++p) {
-            const double* vp = ls.v + (int64_t)p * (kBW + 1);
-            const double bp = ls.beta[p];
+            const double* vp = vl + p * (kBW + 1);
+            const double bp = bl[p];
             double s = 0.0;
             for (int i = 0; i <= k; ++i) s += vp[i] * h[t][p + i];
             s *= bp;
