@@ -323,8 +323,9 @@ def main():
                     help="storage of the Krylov basis in the inner FP32 solves")
     ap.add_argument("--inner-rtol", type=float, default=None,
                     help="tolerance of each inner solve (default 1e-3 for f16, 1e-5 for f32)")
-    ap.add_argument("--ortho", type=int, default=1, choices=[0, 1],
-                    help="0: CGS2 in three sweeps; 1: CGS2 in two sweeps (lagged normalisation)")
+    ap.add_argument("--ortho", type=int, default=1, choices=[0, 1, 2],
+                    help="0: CGS2 in three sweeps; 1: CGS2 in two sweeps (lagged normalisation); "
+                         "2: CGS2 with one reduction per step (FP64 only: use with --only fp64)")
     ap.add_argument("--adaptive", type=int, default=0, metavar="RMAX",
                     help="instead of the default step: one FP64 solve right-preconditioned by "
                          "adaptive spectral deflation with at most RMAX Ritz vectors (no fixed Z)")

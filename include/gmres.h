@@ -80,7 +80,10 @@ typedef struct {
                                  (project, re-project, update); 1 = CGS2 in two sweeps with lagged
                                  normalisation (the SpMV of step j+1 runs on the once-projected
                                  vector; the second update is folded into the next sweep through
-                                 the Arnoldi relation).  Equal in exact arithmetic. */
+                                 the Arnoldi relation); 2 = CGS2 with one reduction per step
+                                 (delayed re-orthogonalisation: one dot sweep of q and A q against
+                                 the basis, one update sweep; FP64 single-system plans without
+                                 adaptive deflation).  Equal in exact arithmetic. */
     int32_t adapt_rmax;       /* > 0: right preconditioning by the paper's adaptive spectral
                                  deflation M^{-1} = I + U (|mu| T^{-1} - I) U^T, T = U^T A U
                                  (Sec. 3.3, eqs. precond1, precond2, tau_mat, precond3): U starts

@@ -149,6 +149,7 @@ struct gmres_plan_s {
     void* V = nullptr;
     double *y = nullptr, *w = nullptr, *pv = nullptr, *rv = nullptr, *xh = nullptr, *bws = nullptr;
     double *xo = nullptr, *r64 = nullptr, *dvec = nullptr;
+    double* dcs = nullptr;   // slot sums of the single-reduction CGS2 (2m + 3)
     double* part = nullptr;
     double *h1, *h2, *coef1, *coef2, *H, *Hraw, *cs, *sn, *g, *vscale, *sigma, *sigma0, *scal;
     double *cc = nullptr, *lag = nullptr;
@@ -312,7 +313,8 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
     for (double** q : {&p->xh, &p->bws, &p->xo, &p->r64, &p->dvec}) CHECK(dalloc(p, q, n));
     CHECK(clear_typed(p));
     p->NB_cap = std::max(p->NB, (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 2048));
-    CHECK(dalloc(p, &p->part, (int64_t)(m + 2) * p->NB_cap));
+    CHECK(dalloc(p, &p->part, (int64_t)(2 * m + 3) * p->NB_cap));
+    CHECK(dalloc(p, &p->dcs, 2 * m + 3));
     const int64_t small = 5 * (m + 1) + 2 * (int64_t)(m + 1) * m + 2 * m + 2 * (m + 1) + 24;
     double* s = nullptr;
     CHECK(dalloc(p, &s, small));
@@ -494,6 +496,8 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.Hraw = p->Hraw;
     a.ctrl = p->ctrl;
     a.lagged = p->o.ortho == 1 ? 1 : 0;
+    a.dcgs = p->o.ortho == 2 ? 1 : 0;
+    a.dcs = p->dcs;
     a.cc = p->cc;
     a.lag = p->lag;
     a.cyc_k = p->cyc_k;
@@ -515,8 +519,9 @@ struct TimerHook final : KTimer {
     int op;
     int cycle = 0;
     int open_ev = -1;
-    bool lagged = false;
-    TimerHook(gmres_plan_s* pp, int pr, int o) : p(pp), prec(pr), op(o), lagged(pp->o.ortho == 1) {}
+    bool lagged = false, dcgs = false;
+    TimerHook(gmres_plan_s* pp, int pr, int o)
+        : p(pp), prec(pr), op(o), lagged(pp->o.ortho == 1), dcgs(pp->o.ortho == 2) {}
     // Algorithmic bytes of one launch: every array the kernel's scheme reads or
     // writes, touched once (cache hits not credited).  A Z is read through its
     // two-entry row copy (int32 column pairs and value pairs per row).
@@ -544,10 +549,15 @@ struct TimerHook final : KTimer {
                 return (ba + 4.0) * nnz + 4.0 * (n + 1) + bx * n + bw * n + zt;
             }
             case 1:
+                if (dcgs && j > 0)     // reads V_0..j-1, q, y (and A Z); writes P u into y
+                    return bv * n * j + bw * n + 2.0 * bw * n + az;
                 if (lagged && j > 0)   // reads V_0..j-1, w1, u; writes v_j, w
                     return bv * n * (nv - 1) + bv * n + 3.0 * bw * n + az;
                 return bw * n + az + bv * n * nv + bw * n;
-            case 2: return bv * n * nv + 2.0 * bw * n;
+            case 2:
+                if (dcgs && j > 0)     // reads V_0..j-1, q, P u; writes v_j, w
+                    return bv * n * j + 2.0 * bw * n + bv * n + bw * n;
+                return bv * n * nv + 2.0 * bw * n;
             default: return bv * n * nv + bw * n + bv * n;
         }
     }
@@ -856,7 +866,9 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     if (p->o.max_iters < 0 || !(p->o.rtol >= 0.0))
         return fail(GMRES_EINVAL, "max_iters >= 0 and rtol >= 0 required");
     if (p->o.precision < 0 || p->o.precision > 2) return fail(GMRES_EINVAL, "unknown precision");
-    if (p->o.ortho < 0 || p->o.ortho > 1) return fail(GMRES_EINVAL, "unknown orthogonalisation variant");
+    if (p->o.ortho < 0 || p->o.ortho > 2) return fail(GMRES_EINVAL, "unknown orthogonalisation variant");
+    if (p->o.ortho == 2 && (p->o.precision != GMRES_FP64 || nsys != 1 || p->o.adapt_rmax > 0))
+        return fail(GMRES_EINVAL, "ortho = 2 needs a single-system FP64 plan without adaptive deflation");
     if (p->o.adapt_rmax < 0 || p->o.adapt_rmax > kAdaptMax)
         return fail(GMRES_EINVAL, "adapt_rmax must be in [0, 22]");
     if (p->o.adapt_rmax > 0 && (p->o.precision != GMRES_FP64 || nsys != 1 || need_adjoint))

@@ -924,6 +924,159 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
 // normalised v_k) and coef[k] = h[k] * vscale[k] (coefficient of stored_k).
 // The norm slot: mode 1 writes ||w||^2 to ctrl->wpre2 (breakdown reference);
 // mode 2 sets the storage scale sigma (sqrt(N)/||w|| for FP16 storage, else 1).
+// ------------------------------- CGS2 with one reduction per step (FP64)
+// Delayed re-orthogonalisation: step j >= 1 starts from q = w1_{j-1}, the
+// previous step's once-projected, unnormalised vector, and u = A q (SpMV).
+// One dot sweep over V_{0..j-1} takes s = V^T q (the second projection of q,
+// delayed by one step), t = V^T (P u), alpha = q^T q, tau = q^T (P u) and
+// ||P u||^2, and stores P u in y; one reduction; then k_dc_step finalises
+// column j-1 of Hbar (h1 + s, and beta = sqrt(alpha - ||s||^2) below) and
+// derives the coefficients of the update sweep, which forms the
+// re-orthogonalised v_j = (q - V s) / beta and the next once-projected vector
+//   w1_j = P A v_j - [V v_j] h1_j,
+// with P A v_j = (P u - V_{0..j} (Hbar s)) / beta from the Arnoldi relation
+// (eq. hessenberg) and h1_j from the dot products of this sweep.  Same bytes
+// per step as the two-sweep variant, one reduction instead of two.
+// Slots: s_l at l, t_l at nv + l (l < nv), alpha 2nv, tau 2nv + 1,
+// ||P u||^2 2nv + 2.  With U = false (the cycle's last column) only s and
+// alpha are taken and y is not touched.
+template <int JMAX, int T, bool U>
+__global__ __launch_bounds__(kWG) void k_dc_dots(int n, int64_t ldv, const double* __restrict__ V, int nv,
+                                                 const double* __restrict__ q, double* __restrict__ y,
+                                                 const int* __restrict__ azrp,
+                                                 const int* __restrict__ azci,
+                                                 const double* __restrict__ azv,
+                                                 const int* __restrict__ azc2,
+                                                 const double* __restrict__ azv2,
+                                                 const double* __restrict__ sc, int R,
+                                                 double* __restrict__ part, int NB, const Ctrl* ctrl,
+                                                 int gate) {
+    constexpr int JT = JMAX / T;
+    constexpr int RT = 2;
+    __shared__ double s_l[kMaxR];
+    __shared__ double red[kWG / kWave][2 * JMAX + 3];
+    if (U)
+        for (int a = threadIdx.x; a < R; a += kWG) s_l[a] = sc[a];
+    __syncthreads();
+    if (gated(ctrl, gate)) return;
+    const int sub = threadIdx.x & (T - 1);
+    double as[JT], at[JT];
+#pragma unroll
+    for (int k = 0; k < JT; ++k) as[k] = at[k] = 0.0;
+    double aa = 0.0, atau = 0.0, apu = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
+    for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
+        uint4 raw[JT];
+        load_cols<JT, T, double>(V, ldv, nv, sub, i0, raw);
+        double qv[RT], u[RT] = {0.0, 0.0};
+        load_tile<double, RT, double>(q + i0, qv);
+        if (U) {
+            load_tile<double, RT, double>(y + i0, u);
+            if (R > 0) deflate_tile<RT, double, double>(i0, azrp, azci, azv, azc2, azv2, s_l, u);
+        }
+        if (sub == 0) {
+            if (U) store_tile<double, RT, double>(y + i0, u);
+#pragma unroll
+            for (int e = 0; e < RT; ++e) {
+                aa += qv[e] * qv[e];
+                atau += qv[e] * u[e];
+                apu += u[e] * u[e];
+            }
+        }
+        accumulate_dots<JT, T, RT, double, double>(raw, qv, as);
+        if (U) accumulate_dots<JT, T, RT, double, double>(raw, u, at);
+    }
+    const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int k = 0; k < JT; ++k) {
+        if (k * T < nv) {
+            double t1 = as[k], t2 = at[k];
+#pragma unroll
+            for (int o = kWave / 2; o >= T; o >>= 1) {
+                t1 += __shfl_xor(t1, o, kWave);
+                t2 += __shfl_xor(t2, o, kWave);
+            }
+            const int c = sub + k * T;
+            if (ln < T && c < nv) {
+                red[wv][c] = t1;
+                red[wv][JMAX + c] = t2;
+            }
+        }
+    }
+    {
+        const double r0 = wave_sum(aa), r1 = wave_sum(atau), r2 = wave_sum(apu);
+        if (ln == 0) {
+            red[wv][2 * JMAX] = r0;
+            red[wv][2 * JMAX + 1] = r1;
+            red[wv][2 * JMAX + 2] = r2;
+        }
+    }
+    __syncthreads();
+    for (int tk = threadIdx.x; tk < 2 * JMAX + 3; tk += kWG) {
+        int slot = -1;
+        if (tk < nv) slot = tk;
+        else if (tk >= JMAX && tk < JMAX + nv) slot = nv + (tk - JMAX);
+        else if (tk >= 2 * JMAX) slot = 2 * nv + (tk - 2 * JMAX);
+        if (slot < 0) continue;
+        double t = red[0][tk];
+#pragma unroll
+        for (int w = 1; w < kWG / kWave; ++w) t += red[w][tk];
+        part[(int64_t)slot * NB + blockIdx.x] = t;
+    }
+}
+
+// Update sweep: qt = q - sum_l stored_l a_l (stored as column nv, times
+// sigma), w = P u / beta - sum_l stored_l b_l - qt e, with lag[0] = 1/beta,
+// lag[1] = e, lag[2] = sigma.  w holds q on entry (updated in place).
+template <int JMAX, int T>
+__global__ __launch_bounds__(kWG) void k_dc_update(int n, int64_t ldv, double* __restrict__ V, int nv,
+                                                   double* __restrict__ w, const double* __restrict__ y,
+                                                   const double* __restrict__ a,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ lag, const Ctrl* ctrl,
+                                                   int gate) {
+    constexpr int JT = JMAX / T;
+    constexpr int RT = 2;
+    __shared__ double a_l[JMAX], b_l[JMAX];
+    const int sub = threadIdx.x & (T - 1);
+    double ar[JT], br[JT];
+    stage_coef<JMAX, T, double>(a, nv, a_l, sub, ar);   // synchronises
+    stage_coef<JMAX, T, double>(b, nv, b_l, sub, br);
+    const double ib = lag[0], ee = lag[1], sg = lag[2];
+    if (gated(ctrl, gate)) return;
+    double* __restrict__ vout = V + nv * ldv;
+    const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
+    for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
+        uint4 raw[JT];
+        load_cols<JT, T, double>(V, ldv, nv, sub, i0, raw);
+        double qv[RT], u[RT], sv[RT], wn[RT];
+        load_tile<double, RT, double>(w + i0, qv);
+        load_tile<double, RT, double>(y + i0, u);
+#pragma unroll
+        for (int e = 0; e < RT; ++e) {
+            const double qt = qv[e] - combine_row<JT, T, double, double>(raw, ar, e);
+            sv[e] = qt * sg;
+            wn[e] = u[e] * ib - combine_row<JT, T, double, double>(raw, br, e) - qt * ee;
+        }
+        if (sub == 0) {
+            store_tile<double, RT, double>(vout + i0, sv);
+            store_tile<double, RT, double>(w + i0, wn);
+        }
+    }
+}
+
+// Sums of the dot slots: out[b] = sum over workgroups of part[b * NB ..].
+__global__ __launch_bounds__(kWG) void k_dc_sum(const double* __restrict__ part, int NB,
+                                                double* __restrict__ out, const Ctrl* ctrl, int gate) {
+    __shared__ double red[kWG / kWave];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < NB; q += kWG) acc += part[(int64_t)b * NB + q];
+    if (gated(ctrl, gate)) return;
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) out[b] = acc;
+}
+
 __global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ part, int NB, int nv,
                                                 int nslot, const double* __restrict__ vscale,
                                                 double* __restrict__ h, double* __restrict__ coef,
@@ -1092,6 +1245,151 @@ __global__ __launch_bounds__(kGT) void k_givens(int j, int m, const double* __re
 
 // Back substitution R_k y = g_{1:k} (column-oriented, R staged in LDS);
 // coef[i] = y_i * vscale[i] (coefficient of stored_i in x_hat += V_k y).
+// Single-reduction CGS2: column j-1 of Hbar from the slot sums dcs of
+// k_dc_dots (nv = j): s_l = vscale_l dcs[l], t_l = vscale_l dcs[j + l],
+// alpha, tau, ||P u||^2; beta = sqrt(alpha - ||s||^2) (Pythagoras: v_l
+// orthonormal), column = h1 + s over rows < j and beta at row j; Givens as in
+// k_givens.  Unless FINAL, the coefficients of the update sweep: c = Hbar s
+// (unrotated Hbar, band rows), h1 of column j (l < j: (t_l - c_l)/beta;
+// l = j: ((tau - s.t)/beta - c_j)/beta), d = c/beta + h1, ca = s vscale,
+// cb = d vscale (l < j), lag = {1/beta, d_j/beta, sigma}, and ||P A v_j||^2
+// for the next breakdown test.  h1 holds column j-1's first-projection
+// coefficients on entry and column j's on exit.
+template <bool FINAL>
+__global__ __launch_bounds__(kGT) void k_dc_step(int j, int m, const double* __restrict__ dcs,
+                                                 double* __restrict__ h1, double* __restrict__ H,
+                                                 double* __restrict__ cs, double* __restrict__ sn,
+                                                 double* __restrict__ g, double* __restrict__ vscale,
+                                                 const double* __restrict__ sigma,
+                                                 double* __restrict__ hist, int64_t hist_cap,
+                                                 double* __restrict__ Hraw, double* __restrict__ ca,
+                                                 double* __restrict__ cb, double* __restrict__ lag,
+                                                 Ctrl* ctrl, int gate) {
+    __shared__ double sl[kMaxM + 1], tl[kMaxM + 1], col[kMaxM + 1], cl[kMaxM], snl[kMaxM];
+    __shared__ double cc[kMaxM + 1], vsl[kMaxM + 1];
+    __shared__ double red[kGT / kWave];
+    const int tid = threadIdx.x;
+    const int jc = j - 1;
+    double sv = 0.0, tv = 0.0, h1v = 0.0, vsv = 0.0, csv = 0.0, snv = 0.0;
+    if (tid < j) {
+        vsv = vscale[tid];
+        sv = dcs[tid];
+        if (!FINAL) tv = dcs[j + tid];
+        h1v = h1[tid];
+    }
+    if (tid < jc) {
+        csv = cs[tid];
+        snv = sn[tid];
+    }
+    double alpha = 0.0, tau = 0.0, pu2 = 0.0, wpre2 = 0.0, gj = 0.0, target = 0.0, sig = 1.0;
+    int64_t its0 = 0, maxit = 0;
+    if (tid == 0) {
+        alpha = dcs[2 * j];
+        if (!FINAL) {
+            tau = dcs[2 * j + 1];
+            pu2 = dcs[2 * j + 2];
+        }
+        wpre2 = ctrl->wpre2;
+        gj = g[jc];
+        target = ctrl->target;
+        its0 = ctrl->its;
+        maxit = ctrl->max_iters;
+        sig = *sigma;
+    }
+    if (gated(ctrl, gate)) return;
+    sv *= vsv;
+    tv *= vsv;
+    if (tid < j) {
+        sl[tid] = sv;
+        tl[tid] = tv;
+        col[tid] = h1v + sv;
+        vsl[tid] = vsv;
+    }
+    if (tid < jc) {
+        cl[tid] = csv;
+        snl[tid] = snv;
+    }
+    double ss = block_sum_n<kGT>(sv * sv, red);   // also orders the LDS writes above
+    double st = block_sum_n<kGT>(sv * tv, red);
+    double beta = 0.0;
+    if (tid == 0) {
+        beta = sqrt(fmax(alpha - ss, 0.0));
+        col[j] = beta;
+    }
+    __syncthreads();
+    beta = col[j];
+    for (int i = tid; i <= j; i += kGT) Hraw[(int64_t)i * m + jc] = col[i];
+    // sqrt(eps) * ||P A v_{j-1}||: the Pythagorean norm carries about sqrt(eps)
+    // of relative rounding error.
+    const int bd = !(beta > 1.4901161193847656e-08 * sqrt(tid == 0 ? wpre2 : 0.0)) ? 1 : 0;
+    __syncthreads();
+    double ib = 0.0;
+    if (!FINAL) {
+        // c = Hbar(0:j, 0:j-1) s over the band (row i: columns i-1 .. j-1).
+        // Columns < j-1 from Hraw, column j-1 from LDS (just formed).
+        double c = 0.0;
+        if (tid <= j) {
+            for (int l = (tid > 0 ? tid - 1 : 0); l < jc; ++l) c += Hraw[(int64_t)tid * m + l] * sl[l];
+            c += col[tid] * sl[jc];
+        }
+        if (tid <= j) cc[tid] = c;
+        __syncthreads();
+        ib = beta > 0.0 ? 1.0 / beta : 0.0;
+        const double vjpu = (tau - st) * ib;   // thread 0 only (tau, st valid there)
+        if (tid < j) {
+            const double h1n = (tl[tid] - cc[tid]) * ib;
+            const double d = cc[tid] * ib + h1n;
+            ca[tid] = sl[tid] * vsl[tid];
+            cb[tid] = d * vsl[tid];
+            h1[tid] = h1n;
+        }
+        double ct = block_sum_n<kGT>(tid < j ? cc[tid] * tl[tid] : 0.0, red);
+        double c2 = block_sum_n<kGT>(tid <= j ? cc[tid] * cc[tid] : 0.0, red);
+        if (tid == 0) {
+            const double h1j = (vjpu - cc[j]) * ib;
+            const double dj = cc[j] * ib + h1j;
+            h1[j] = h1j;
+            lag[0] = bd ? 0.0 : ib;
+            lag[1] = bd ? 0.0 : dj * ib;
+            lag[2] = sig;
+            const double z2 = (pu2 - 2.0 * (ct + cc[j] * vjpu) + c2) * ib * ib;
+            ctrl->wpre2 = fmax(z2, 0.0);
+        }
+    }
+    if (tid != 0) return;
+    double a = col[0];
+    for (int i = 0; i < jc; ++i) {
+        const double c = cl[i], sv2 = snl[i], bb = col[i + 1];
+        H[(int64_t)i * m + jc] = c * a + sv2 * bb;
+        a = -sv2 * a + c * bb;
+    }
+    double rho = hypot(a, beta);
+    double cj, sj;
+    if (beta == 0.0) {
+        cj = 1.0;
+        sj = 0.0;
+        rho = a;
+    } else {
+        cj = a / rho;
+        sj = beta / rho;
+    }
+    cs[jc] = cj;
+    sn[jc] = sj;
+    H[(int64_t)jc * m + jc] = rho;
+    H[(int64_t)j * m + jc] = 0.0;
+    g[j] = -sj * gj;
+    g[jc] = cj * gj;
+    vscale[j] = bd ? 0.0 : 1.0 / (sig * beta);
+    const int64_t its = its0 + 1;
+    ctrl->its = its;
+    if (hist && its - 1 < hist_cap) hist[its - 1] = fabs(sj * gj);
+    ctrl->k = j;
+    ctrl->breakdown = bd;
+    const bool est = fabs(sj * gj) <= target;
+    if (est) ctrl->est_conv = 1;
+    if (est || bd || its >= maxit || FINAL) ctrl->stop = 1;
+}
+
 __global__ __launch_bounds__(kWG) void k_backsolve(int m, const double* __restrict__ H,
                                                    const double* __restrict__ g,
                                                    const double* __restrict__ vscale,
@@ -1675,6 +1973,69 @@ struct Engine {
                e.sn, e.g, e.vscale, e.sigma, e.hist, e.hist_cap, e.Hraw, e.cc, e.lag, e.ctrl, 2);
     }
 
+    // Single-reduction CGS2 (FP64 bases only): step 0 is the two-sweep
+    // variant's first projection; step j >= 1 is SpMV on q = w1_{j-1}, one
+    // dot sweep, one reduction, the column/coefficient kernel and the update
+    // sweep; after the last step one more dot sweep finalises column m-1.
+    void step_dc(int j) const {
+        if constexpr (std::is_same<VT, double>::value && std::is_same<WT, double>::value) {
+            if (e.timer) e.timer->begin(0, j);
+            if (j == 0) spmv_any<VT>(Vcol(0), e.vscale);
+            else spmv_any<WT>(w(), nullptr);
+            if (e.timer) e.timer->end(0, j);
+            if (fused()) coarse_slots(e.s_step, 2);
+            else coarse(y(), e.s_step, 2);
+            if (j == 0) {
+                if (e.timer) e.timer->begin(1, 0);
+                auto kf = k_pass1<8, 1, VT, WT, AT, ACC>;
+                const int g1 = grid_for((const void*)kf);
+                launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), 1, y(), e.azrp, e.azci, azv(), e.azc1,
+                       azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2);
+                if (e.timer) e.timer->end(1, 0);
+                k_finish<<<2, kWG, 0, e.st>>>(e.part, g1, 1, e.nslot, e.vscale, e.h1, e.coef1, 1, kHalf,
+                                              e.nscale, e.sigma, e.ctrl, 2);
+                if (e.timer) e.timer->begin(2, 0);
+                auto kf2 = k_pass2<8, 1, VT, WT, ACC>;
+                const int g2 = grid_for((const void*)kf2);
+                launch(kf2, g2, kWG, 0, e.st, e.n, e.ldv, V(), 1, w(), e.coef1, e.part, e.nslot, g2,
+                       e.ctrl, 2);
+                if (e.timer) e.timer->end(2, 0);
+                k_finish<<<1, kWG, 0, e.st>>>(e.part, g2, 0, e.nslot, e.vscale, e.h2, e.coef2, 2, kHalf,
+                                              e.nscale, e.sigma, e.ctrl, 2);
+                return;
+            }
+            dc_dots<true>(j);
+            GM_JMAX_SWITCH(j, VT, ({
+                auto kf = k_dc_update<J, LanesForLag<J, VT>::value>;
+                const int g = grid_for((const void*)kf);
+                if (e.timer) e.timer->begin(2, j);
+                launch(kf, g, kWG, 0, e.st, e.n, e.ldv, V(), j, w(), y(), e.coef1, e.coef2, e.lag,
+                       e.ctrl, 2);
+                if (e.timer) e.timer->end(2, j);
+            }));
+        }
+    }
+
+    // Dot sweep with nv = j, its reduction and the column kernel (U: with the
+    // SpMV output; else the cycle's last column).
+    template <bool UU>
+    void dc_dots(int j) const {
+        int g = 0;
+        GM_JMAX_SWITCH(j, VT, ({
+            auto kf = k_dc_dots<J, LanesForLag<J, VT>::value, UU>;
+            g = grid_for((const void*)kf);
+            if (e.timer) e.timer->begin(1, j);
+            launch(kf, g, kWG, 0, e.st, e.n, e.ldv, (const double*)V(), j, (const double*)w(), (double*)y(),
+                   e.azrp, e.azci, (const double*)azv(), e.azc1, (const double*)azv1(), e.s_step, e.R,
+                   e.part, g, e.ctrl, 2);
+            if (e.timer) e.timer->end(1, j);
+        }));
+        k_dc_sum<<<2 * j + 3, kWG, 0, e.st>>>(e.part, g, e.dcs, e.ctrl, 2);
+        launch(k_dc_step<!UU>, 1, kGT, 0, e.st, j, e.m, (const double*)e.dcs, e.h1, e.H, e.cs, e.sn, e.g,
+               e.vscale, (const double*)e.sigma, e.hist, e.hist_cap, e.Hraw, e.coef1, e.coef2, e.lag,
+               e.ctrl, 2);
+    }
+
     // y = scale * A x for the step's input vector x (type XT), with the fused
     // Z^T y partials when available.
     template <typename XT>
@@ -1691,9 +2052,12 @@ struct Engine {
     template <typename BT>
     void cycle(const BT* b) const {
         for (int j = 0; j < e.m; ++j) {
-            if (e.lagged) step_lag(j);
+            if (e.dcgs) step_dc(j);
+            else if (e.lagged) step_lag(j);
             else step(j);
         }
+        if constexpr (std::is_same<VT, double>::value && std::is_same<WT, double>::value)
+            if (e.dcgs) dc_dots<false>(e.m);
         k_backsolve<<<1, kWG, 0, e.st>>>(e.m, e.H, e.g, e.vscale, e.coef1, e.cyc_k, e.cyc_cap,
                                          e.ctrl, 1);
         bool adapted = false;

@@ -71,17 +71,33 @@ def cfg2():
     return W.make_config(2)
 
 
-def test_config2_fixed_count_parity(cfg2):
+@pytest.mark.parametrize("ortho", [1, 2])
+def test_config2_fixed_count_parity(cfg2, ortho):
     s = cfg2
     K = 60
-    say("config 2: oracle", K, "steps at N =", s.n)
+    say("config 2: oracle", K, "steps at N =", s.n, "ortho", ortho)
     ref = oracle.gmres(s, 50, 0.0, K)
-    plan, d = plan_like_bench(s, m=50, rtol=0.0, max_iters=K)
+    plan, d = plan_like_bench(s, m=50, rtol=0.0, max_iters=K, ortho=ortho)
     x, info = plan.solve(d["b"])
     assert info["iters"] == K
     e = rel(x.cpu().numpy(), ref.x)
     say(f"config 2 fixed-count K={K}: rel err {e:.2e}")
     assert e <= 1e-8
+
+
+def test_config2_single_reduction_cgs2_to_tolerance(cfg2):
+    """The single-reduction CGS2 (ortho = 2) on the benchmark system to rtol
+    1e-8: true residual recomputed on the host, Z^T r = 0, and the iteration
+    count of the two-sweep default within 1%."""
+    s = cfg2
+    p1, d = plan_like_bench(s, m=50, rtol=1e-8, max_iters=200000)
+    _, i1 = p1.solve(d["b"])
+    p2, d2 = plan_like_bench(s, m=50, rtol=1e-8, max_iters=200000, ortho=2)
+    x2, i2 = p2.solve(d2["b"])
+    say("config 2 ortho 2:", i2["iters"], "iterations (two-sweep:", i1["iters"], ")")
+    assert i2["status_name"] == "OK"
+    assert abs(i2["iters"] - i1["iters"]) <= max(1, i1["iters"] // 100)
+    residual_checks(s, x2.cpu().numpy(), 1e-8, i2["rho0"], "config 2 ortho 2")
 
 
 def test_config2_to_tolerance_fp64_and_mixed(cfg2):

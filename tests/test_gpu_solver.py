@@ -143,7 +143,7 @@ def _gpu_solve(s, b=None, x0=None, **opts):
     return out, info, plan
 
 
-@pytest.mark.parametrize("ortho", [0, 1])
+@pytest.mark.parametrize("ortho", [0, 1, 2])
 def test_config1_trajectory_parity(ortho):
     s = W.make_config(1)
     ref_tol = oracle.gmres(s, 30, 1e-8, 2000)
@@ -156,7 +156,7 @@ def test_config1_trajectory_parity(ortho):
     assert abs(info["rel_res"] - ref.rel_res_deflated) <= 1e-6 * ref.rel_res_deflated + 1e-14
 
 
-@pytest.mark.parametrize("use_graph,ortho", [(1, 1), (0, 1), (1, 0)])
+@pytest.mark.parametrize("use_graph,ortho", [(1, 1), (0, 1), (1, 0), (1, 2), (0, 2)])
 def test_config1_to_tolerance(use_graph, ortho):
     s = W.make_config(1)
     ref = oracle.gmres(s, 30, 1e-8, 2000)
@@ -170,7 +170,7 @@ def test_config1_to_tolerance(use_graph, ortho):
     assert abs(info["rel_res_true"] - np.linalg.norm(r) / ref.rho0) <= 1e-12
 
 
-@pytest.mark.parametrize("ortho", [0, 1])
+@pytest.mark.parametrize("ortho", [0, 1, 2])
 def test_residual_history_matches_oracle(ortho):
     s = W.make_config(1, mesh=32)
     ref = oracle.gmres(s, 30, 1e-8, 2000, history=True)
@@ -183,7 +183,7 @@ def test_residual_history_matches_oracle(ortho):
     assert relerr.max() <= 1e-6
 
 
-@pytest.mark.parametrize("ortho", [0, 1])
+@pytest.mark.parametrize("ortho", [0, 1, 2])
 @pytest.mark.parametrize("mesh,s_sub,m", [(5, 2, 7), (13, 3, 20), (37, 4, 30), (91, 8, 50), (150, 5, 80)])
 def test_ragged_sizes_and_restart_lengths(mesh, s_sub, m, ortho):
     # n = (mesh+1)^2 is never a multiple of the 256-thread workgroup.
@@ -219,7 +219,7 @@ def test_resume_from_checkpoint():
     assert rel(x2, full.x) <= 1e-8
 
 
-@pytest.mark.parametrize("ortho", [0, 1])
+@pytest.mark.parametrize("ortho", [0, 1, 2])
 def test_degenerate_cases(ortho):
     n = 300
     b = np.linspace(1.0, 2.0, n)
@@ -287,6 +287,13 @@ def test_error_statuses():
     with pytest.raises(Gm.GmresError) as e:
         Gm.plan_for(nanA, m=5)
     assert e.value.status == -3
+    # The single-reduction CGS2 (ortho = 2) is an FP64 single-system variant.
+    with pytest.raises(Gm.GmresError) as e:
+        Gm.plan_for(s, m=5, ortho=2, precision="mixed_f16")
+    assert e.value.status == -1
+    with pytest.raises(Gm.GmresError) as e:
+        Gm.plan_for(s, m=5, ortho=3)
+    assert e.value.status == -1
 
 
 def test_deterministic_reruns():
