@@ -789,11 +789,14 @@ gmres_status solve_mixed(gmres_plan_s* p, const double* b, const double* x0, dou
             status = (std::sqrt(nrm2) <= target * (1 + 1e-12)) ? GMRES_OK : GMRES_STAGNATED;
             break;
         }
-        // Inner solve of A d = r / ||r|| in reduced precision.
+        // Inner solve of A d = r / ||r|| in reduced precision, to the plan's
+        // inner tolerance, or to a quarter of the reduction still needed when
+        // that is looser (the last refinement need not overshoot the target).
+        const double inner = std::min(0.5, std::max(o.inner_rtol, 0.25 * target / rho));
         launch_scale_to_f32(p->st, p->NB, (int)n, p->r64, p->scal, reinterpret_cast<float*>(p->bws));
         launch_fill(p->st, p->xh, n, 0.0);
         Ctrl c{};
-        CHECK(run_engine(p, 0, prec, p->bws, o.inner_rtol, 0.0, o.inner_max_iters, &c, true));
+        CHECK(run_engine(p, 0, prec, p->bws, inner, 0.0, o.inner_max_iters, &c, true));
         launch_correct(p->st, p->NB, (int)n, p->zrp, p->zci, p->zv, p->s_res, p->R, p->xh, p->dvec);
         info->iters += c.its;
         info->cycles += c.cycles;
