@@ -243,6 +243,7 @@ def gpu_solver(mesh: BratuMesh, lam: float = LAMBDA, **opts):
 
     sys0 = system_at(mesh, np.zeros(mesh.N), lam)
     plan, d = G.plan_for(sys0, **opts)
+    plan.autotune()   # SpMV variant and grids for this pattern, kept for every Newton step
 
     def solve(vals, b):
         plan.update_values(torch.from_numpy(np.ascontiguousarray(vals)).cuda())

@@ -213,10 +213,13 @@ gmres_status to_status(int s, const char* what) {
 
 // SpMV variant: > 0 lanes per row; -256 / -128 LDS-staged stream with that
 // many rows per block; kSell (-64) sliced ELL (short rows: FEM stencils).
-int default_lanes(int64_t n, int64_t nnz, bool have_sell) {
+// Sliced ELL for short rows, and for long rows too when its copy stores at
+// most 25% padding (rows of similar length, or sorted within row blocks);
+// CSR with 4 or 32 lanes per row otherwise.
+int default_lanes(int64_t n, int64_t nnz, bool have_sell, int64_t sell_total) {
     const double rho = n > 0 ? (double)nnz / (double)n : 1.0;
-    if (rho <= 40) return have_sell ? kSell : 4;
-    return 32;
+    if (have_sell && (rho <= 40 || (double)sell_total <= 1.25 * (double)nnz)) return kSell;
+    return rho <= 40 ? 4 : 32;
 }
 
 int max_row_len(hipStream_t st, int64_t n, const int* rp, int* d_tmp) {
@@ -1009,7 +1012,8 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
 
     if (p->o.spmv_lanes == kSell && !p->sell_col)
         return fail(GMRES_EINVAL, "spmv_lanes = -64 needs column offsets col - row within +-32767");
-    p->L = p->o.spmv_lanes != 0 ? p->o.spmv_lanes : default_lanes(n, nnz, p->sell_col != nullptr);
+    p->L = p->o.spmv_lanes != 0 ? p->o.spmv_lanes
+                                : default_lanes(n, nnz, p->sell_col != nullptr, p->sell_total);
     p->NB = p->o.num_blocks > 0 ? p->o.num_blocks
                                 : (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 1024);
     if (nsys == 1) CHECK(alloc_krylov(p));

@@ -71,3 +71,24 @@ def test_newton_with_gpu_solves_matches_dense(mesh6):
     assert rel(u, u_ref) <= 1e-8
     _, R = B.jacobian_residual(m, u)
     assert np.linalg.norm(R) <= 1e-9
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_table1_largest_jacobian_fixed_count():
+    """The largest Table 1 size (60^3 elements, 1,771,561 unknowns, 108.6 M
+    stored entries, sorted sliced-ELL SpMV) in the launch configuration of
+    the paper-protocol benchmark: 60 steps (two restarts of GMRES(50)'s
+    adaptive deflation state) against the oracle, element by element."""
+    from paper_1906_04051_amd import gmres as G
+    mesh = B.build_mesh(60)
+    s = B.system_at(mesh, np.zeros(mesh.N))
+    K = 60
+    ref = oracle.dgmres(s, 50, 0.0, K, rmax=20)
+    plan, d = G.plan_for(s, m=50, rtol=0.0, max_iters=K, adapt_rmax=20)
+    plan.autotune()
+    x, info = plan.solve(d["b"])
+    e = rel(x.cpu().numpy(), ref.x)
+    say(f"Bratu n=60 Jacobian: rel err {e:.2e}, r {info['defl_r']} / {ref.r}, mu {info['mu']:.6e} / {ref.mu:.6e}")
+    assert info["iters"] == K and info["defl_r"] == ref.r
+    assert e <= 1e-8
