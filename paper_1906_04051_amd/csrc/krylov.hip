@@ -580,13 +580,24 @@ __device__ __forceinline__ ACC group_sum(ACC v) {
 // last column re-read column nv-1 (an address another lane of the same wave
 // reads, so no extra memory traffic) and carry coefficient 0; their dot
 // accumulators are never stored.  Requires nv >= 1.
+// An FP64 basis (8 B per entry and column) outgrows the 256 MB last-level
+// cache at a million rows, so its sweeps are issued with the non-temporal
+// hint: they stream through without displacing the matrix and the work
+// vectors that every step reads again.  FP16 and FP32 bases fit in that
+// cache and are read back from it, so they keep the default policy.
 template <int JT, int T, typename VT>
 __device__ __forceinline__ void load_cols(const VT* __restrict__ V, int64_t ldv, int nv, int sub,
                                           int64_t i0, uint4 (&raw)[JT]) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int q = 0; q < JT; ++q) {
         const int k = min(sub + q * T, nv - 1);
-        raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
+        if constexpr (sizeof(VT) == 8) {
+            const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(V + k * ldv + i0));
+            raw[q] = make_uint4(t.x, t.y, t.z, t.w);
+        } else {
+            raw[q] = *reinterpret_cast<const uint4*>(V + k * ldv + i0);
+        }
     }
 }
 
