@@ -581,18 +581,21 @@ __device__ __forceinline__ ACC group_sum(ACC v) {
 // reads, so no extra memory traffic) and carry coefficient 0; their dot
 // accumulators are never stored.  Requires nv >= 1.
 // An FP64 basis (8 B per entry and column) outgrows the 256 MB last-level
-// cache at a million rows, so its sweeps are issued with the non-temporal
-// hint: they stream through without displacing the matrix and the work
-// vectors that every step reads again.  FP16 and FP32 bases fit in that
-// cache and are read back from it, so they keep the default policy.
+// cache at a million rows.  Its first `keep` columns (as many as fit there
+// beside the matrix and the work vectors; chosen per plan) are read with
+// plain loads and stay cached for both sweeps of every step; the tile slots
+// whose columns reach past them carry the non-temporal hint, so the rest of
+// the basis streams through without displacing what the next step reads
+// again.  The test is uniform per slot q.  FP16 and FP32 bases fit in that
+// cache and keep the default policy throughout.
 template <int JT, int T, typename VT>
 __device__ __forceinline__ void load_cols(const VT* __restrict__ V, int64_t ldv, int nv, int sub,
-                                          int64_t i0, uint4 (&raw)[JT]) {
+                                          int64_t i0, int keep, uint4 (&raw)[JT]) {
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int q = 0; q < JT; ++q) {
         const int k = min(sub + q * T, nv - 1);
-        if constexpr (sizeof(VT) == 8) {
+        if (sizeof(VT) == 8 && (q + 1) * T > keep) {
             const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(V + k * ldv + i0));
             raw[q] = make_uint4(t.x, t.y, t.z, t.w);
         } else {
@@ -714,7 +717,7 @@ __global__ __launch_bounds__(kWG) void k_pass1(int n, int64_t ldv, const VT* __r
                                                const AZT* __restrict__ azv2,
                                                const double* __restrict__ s, int R,
                                                WT* __restrict__ w, double* __restrict__ part,
-                                               int nslot, int NB, const Ctrl* ctrl, int gate) {
+                                               int nslot, int NB, const Ctrl* ctrl, int gate, int keep) {
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC s_l[kMaxR];
@@ -731,7 +734,7 @@ __global__ __launch_bounds__(kWG) void k_pass1(int n, int64_t ldv, const VT* __r
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-        if (nv > 0) load_cols<JT, T, VT>(V, ldv, nv, sub, i0, raw);
+        if (nv > 0) load_cols<JT, T, VT>(V, ldv, nv, sub, i0, keep, raw);
         ACC wv[RT];
         load_tile<WT, RT, ACC>(y + i0, wv);
         if (R > 0) deflate_tile<RT, AZT, ACC>(i0, azrp, azci, azv, azc2, azv2, s_l, wv);
@@ -751,7 +754,7 @@ template <int JMAX, int T, typename VT, typename WT, typename ACC>
 __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __restrict__ V, int nv,
                                                WT* __restrict__ w, const double* __restrict__ coef,
                                                double* __restrict__ part, int nslot, int NB,
-                                               const Ctrl* ctrl, int gate) {
+                                               const Ctrl* ctrl, int gate, int keep) {
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
@@ -767,7 +770,7 @@ __global__ __launch_bounds__(kWG) void k_pass2(int n, int64_t ldv, const VT* __r
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-        load_cols<JT, T, VT>(V, ldv, nv, sub, i0, raw);
+        load_cols<JT, T, VT>(V, ldv, nv, sub, i0, keep, raw);
         ACC wv[RT];
         load_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
@@ -790,7 +793,7 @@ __global__ __launch_bounds__(kWG) void k_pass3(int n, int64_t ldv, VT* __restric
                                                const double* __restrict__ coef,
                                                const double* __restrict__ sigma,
                                                double* __restrict__ part, int nslot, int NB,
-                                               const Ctrl* ctrl, int gate) {
+                                               const Ctrl* ctrl, int gate, int keep) {
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC c_l[JMAX];
@@ -805,7 +808,7 @@ __global__ __launch_bounds__(kWG) void k_pass3(int n, int64_t ldv, VT* __restric
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-        load_cols<JT, T, VT>(V, ldv, nv, sub, i0, raw);
+        load_cols<JT, T, VT>(V, ldv, nv, sub, i0, keep, raw);
         ACC wv[RT];
         load_tile<WT, RT, ACC>(w + i0, wv);
 #pragma unroll
@@ -851,7 +854,7 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
                                                    const double* __restrict__ cc,
                                                    const double* __restrict__ lag,
                                                    double* __restrict__ part, int nslot, int NB,
-                                                   const Ctrl* ctrl, int gate) {
+                                                   const Ctrl* ctrl, int gate, int keep) {
     constexpr int JT = JMAX / T;
     constexpr int RT = 16 / sizeof(VT);
     __shared__ ACC s_l[kMaxR];
@@ -874,7 +877,7 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-        load_cols<JT, T, VT>(V, ldv, nvr, sub, i0, raw);
+        load_cols<JT, T, VT>(V, ldv, nvr, sub, i0, keep, raw);
         ACC w1[RT], u[RT];
         load_tile<WT, RT, ACC>(w + i0, w1);
         load_tile<WT, RT, ACC>(y + i0, u);
@@ -961,7 +964,7 @@ __global__ __launch_bounds__(kWG) void k_dc_dots(int n, int64_t ldv, const doubl
                                                  const double* __restrict__ azv2,
                                                  const double* __restrict__ sc, int R,
                                                  double* __restrict__ part, int NB, const Ctrl* ctrl,
-                                                 int gate) {
+                                                 int gate, int keep) {
     constexpr int JT = JMAX / T;
     constexpr int RT = 2;
     __shared__ double s_l[kMaxR];
@@ -978,7 +981,7 @@ __global__ __launch_bounds__(kWG) void k_dc_dots(int n, int64_t ldv, const doubl
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-        load_cols<JT, T, double>(V, ldv, nv, sub, i0, raw);
+        load_cols<JT, T, double>(V, ldv, nv, sub, i0, keep, raw);
         double qv[RT], u[RT] = {0.0, 0.0};
         load_tile<double, RT, double>(q + i0, qv);
         if (U) {
@@ -1045,7 +1048,7 @@ __global__ __launch_bounds__(kWG) void k_dc_update(int n, int64_t ldv, double* _
                                                    const double* __restrict__ a,
                                                    const double* __restrict__ b,
                                                    const double* __restrict__ lag, const Ctrl* ctrl,
-                                                   int gate) {
+                                                   int gate, int keep) {
     constexpr int JT = JMAX / T;
     constexpr int RT = 2;
     __shared__ double a_l[JMAX], b_l[JMAX];
@@ -1059,7 +1062,7 @@ __global__ __launch_bounds__(kWG) void k_dc_update(int n, int64_t ldv, double* _
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
-        load_cols<JT, T, double>(V, ldv, nv, sub, i0, raw);
+        load_cols<JT, T, double>(V, ldv, nv, sub, i0, keep, raw);
         double qv[RT], u[RT], sv[RT], wn[RT];
         load_tile<double, RT, double>(w + i0, qv);
         load_tile<double, RT, double>(y + i0, u);
@@ -1865,7 +1868,7 @@ struct Engine {
         }
         k_pass1<8, 1, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(e.n, e.ldv, V(), 0, r(), e.azrp, e.azci,
                                                             azv(), e.azc1, azv1(), e.s_res, e.R, p(), e.part,
-                                                            e.nslot, e.NB, e.ctrl, 1);
+                                                            e.nslot, e.NB, e.ctrl, 1, e.cache_cols);
         k_decide<<<1, kWG, 0, e.st>>>(e.part, e.NB, e.nslot, e.m, kHalf, e.nscale, e.g, e.vscale,
                                       e.sigma0, e.trust_est, e.ctrl);
         k_store_v0<VT, WT><<<e.NB, kWG, 0, e.st>>>(e.n, p(), e.sigma0, Vcol(0), e.ctrl, 1);
@@ -1908,7 +1911,7 @@ struct Engine {
             auto kf = k_pass1<J, T, VT, WT, AT, ACC>;
             g1 = grid_for((const void*)kf);
             launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), nv, y(), e.azrp, e.azci, azv(), e.azc1,
-                   azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2);
+                   azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2, e.cache_cols);
         }));
         if (e.timer) e.timer->end(1, j);
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, g1, nv, e.nslot, e.vscale, e.h1, e.coef1, 1,
@@ -1918,7 +1921,7 @@ struct Engine {
             auto kf = k_pass2<J, T, VT, WT, ACC>;
             g2 = grid_for((const void*)kf);
             launch(kf, g2, kWG, 0, e.st, e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, g2,
-                   e.ctrl, 2);
+                   e.ctrl, 2, e.cache_cols);
         }));
         if (e.timer) e.timer->end(2, j);
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, g2, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
@@ -1928,7 +1931,7 @@ struct Engine {
             auto kf = k_pass3<J, T, VT, WT, ACC>;
             g3 = grid_for((const void*)kf);
             launch(kf, g3, kWG, 0, e.st, e.n, e.ldv, V(), nv, w(), e.coef2, e.sigma, e.part,
-                   e.nslot, g3, e.ctrl, 2);
+                   e.nslot, g3, e.ctrl, 2, e.cache_cols);
         }));
         if (e.timer) e.timer->end(3, j);
         launch(k_givens<false>, 1, kGT, 0, e.st, j, e.m, e.part, g3, e.nslot, e.h1, e.h2, e.H, e.cs,
@@ -1957,14 +1960,14 @@ struct Engine {
             auto kf = k_pass1<8, 1, VT, WT, AT, ACC>;
             g1 = grid_for((const void*)kf);
             launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), 1, y(), e.azrp, e.azci, azv(), e.azc1,
-                   azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2);
+                   azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2, e.cache_cols);
         } else {
             GM_JMAX_SWITCH(j, VT, ({
                 auto kf = k_pass1_lag<J, LanesForLag<J, VT>::value, VT, WT, AT, ACC>;
                 g1 = grid_for((const void*)kf);
                 launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), j, w(), y(), e.azrp, e.azci, azv(),
                        e.azc1, azv1(), e.s_step, e.R, e.coef2, e.cc, e.lag, e.part, e.nslot, g1,
-                       e.ctrl, 2);
+                       e.ctrl, 2, e.cache_cols);
             }));
         }
         if (e.timer) e.timer->end(1, j);
@@ -1975,7 +1978,7 @@ struct Engine {
             auto kf = k_pass2<J, T, VT, WT, ACC>;
             g2 = grid_for((const void*)kf);
             launch(kf, g2, kWG, 0, e.st, e.n, e.ldv, V(), nv, w(), e.coef1, e.part, e.nslot, g2,
-                   e.ctrl, 2);
+                   e.ctrl, 2, e.cache_cols);
         }));
         if (e.timer) e.timer->end(2, j);
         k_finish<<<nv + 1, kWG, 0, e.st>>>(e.part, g2, nv, e.nslot, e.vscale, e.h2, e.coef2, 2,
@@ -2001,7 +2004,7 @@ struct Engine {
                 auto kf = k_pass1<8, 1, VT, WT, AT, ACC>;
                 const int g1 = grid_for((const void*)kf);
                 launch(kf, g1, kWG, 0, e.st, e.n, e.ldv, V(), 1, y(), e.azrp, e.azci, azv(), e.azc1,
-                       azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2);
+                       azv1(), e.s_step, e.R, w(), e.part, e.nslot, g1, e.ctrl, 2, e.cache_cols);
                 if (e.timer) e.timer->end(1, 0);
                 k_finish<<<2, kWG, 0, e.st>>>(e.part, g1, 1, e.nslot, e.vscale, e.h1, e.coef1, 1, kHalf,
                                               e.nscale, e.sigma, e.ctrl, 2);
@@ -2009,7 +2012,7 @@ struct Engine {
                 auto kf2 = k_pass2<8, 1, VT, WT, ACC>;
                 const int g2 = grid_for((const void*)kf2);
                 launch(kf2, g2, kWG, 0, e.st, e.n, e.ldv, V(), 1, w(), e.coef1, e.part, e.nslot, g2,
-                       e.ctrl, 2);
+                       e.ctrl, 2, e.cache_cols);
                 if (e.timer) e.timer->end(2, 0);
                 k_finish<<<1, kWG, 0, e.st>>>(e.part, g2, 0, e.nslot, e.vscale, e.h2, e.coef2, 2, kHalf,
                                               e.nscale, e.sigma, e.ctrl, 2);
@@ -2021,7 +2024,7 @@ struct Engine {
                 const int g = grid_for((const void*)kf);
                 if (e.timer) e.timer->begin(2, j);
                 launch(kf, g, kWG, 0, e.st, e.n, e.ldv, V(), j, w(), y(), e.coef1, e.coef2, e.lag,
-                       e.ctrl, 2);
+                       e.ctrl, 2, e.cache_cols);
                 if (e.timer) e.timer->end(2, j);
             }));
         }
@@ -2038,7 +2041,7 @@ struct Engine {
             if (e.timer) e.timer->begin(1, j);
             launch(kf, g, kWG, 0, e.st, e.n, e.ldv, (const double*)V(), j, (const double*)w(), (double*)y(),
                    e.azrp, e.azci, (const double*)azv(), e.azc1, (const double*)azv1(), e.s_step, e.R,
-                   e.part, g, e.ctrl, 2);
+                   e.part, g, e.ctrl, 2, e.cache_cols);
             if (e.timer) e.timer->end(1, j);
         }));
         k_dc_sum<<<2 * j + 3, kWG, 0, e.st>>>(e.part, g, e.dcs, e.ctrl, 2);
@@ -2109,14 +2112,15 @@ static void pass_probe(const EngineArgs& e, int kind, int nv) {
         GM_JMAX_SWITCH(nv, VT, (k_pass1<J, T, VT, WT, AT, ACC><<<e.NB, kWG, 0, e.st>>>(
                                     e.n, e.ldv, V, nv, y, e.azrp, e.azci, (const AT*)e.azv, e.azc1,
                                     (const AT*)e.azv1, e.s_step, e.R, w, e.part, e.nslot, e.NB,
-                                    nullptr, 0)));
+                                    nullptr, 0, e.cache_cols)));
     } else if (kind == 2) {
         GM_JMAX_SWITCH(nv, VT, (k_pass2<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
-                                    e.n, e.ldv, V, nv, w, e.coef1, e.part, e.nslot, e.NB, nullptr, 0)));
+                                    e.n, e.ldv, V, nv, w, e.coef1, e.part, e.nslot, e.NB, nullptr, 0,
+                                    e.cache_cols)));
     } else {
         GM_JMAX_SWITCH(nv, VT, (k_pass3<J, T, VT, WT, ACC><<<e.NB, kWG, 0, e.st>>>(
                                     e.n, e.ldv, (VT*)V, nv, w, e.coef2, e.sigma, e.part, e.nslot,
-                                    e.NB, nullptr, 0)));
+                                    e.NB, nullptr, 0, e.cache_cols)));
     }
 }
 
