@@ -65,7 +65,9 @@ typedef struct {
                                  steps (the paper's fixed-count protocol, Sec. 4) */
     double  r0_norm_override; /* > 0: use as ||b - A x0|| (resume from a checkpointed x) */
     int32_t precision;        /* gmres_precision */
-    double  inner_rtol;       /* mixed: relative tolerance of each inner solve */
+    double  inner_rtol;       /* mixed: tightest relative tolerance of an inner solve; the
+                                 reduction still needed (margin 2) is split evenly over the
+                                 fewest inner solves no tighter than this */
     int32_t max_refine;       /* mixed: cap on refinement steps */
     int64_t inner_max_iters;  /* mixed: cap on inner steps per refinement */
     int32_t use_graph;        /* 1: replay each restart cycle as a captured hipGraph */

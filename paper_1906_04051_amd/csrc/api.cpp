@@ -812,10 +812,19 @@ gmres_status solve_mixed(gmres_plan_s* p, const double* b, const double* x0, dou
             status = (std::sqrt(nrm2) <= target * (1 + 1e-12)) ? GMRES_OK : GMRES_STAGNATED;
             break;
         }
-        // Inner solve of A d = r / ||r|| in reduced precision, to the plan's
-        // inner tolerance, or to a quarter of the reduction still needed when
-        // that is looser (the last refinement need not overshoot the target).
-        const double inner = std::min(0.5, std::max(o.inner_rtol, 0.25 * target / rho));
+        // Inner solve of A d = r / ||r|| in reduced precision.  The reduction
+        // still needed, with a margin of 2 (need = target / (2 rho) < 1/2), is
+        // split evenly over the fewest refinements whose solves are no tighter
+        // than the plan's inner tolerance: k = ceil(log need / log inner_rtol)
+        // solves to need^(1/k) each.  (rtol 1e-8, inner_rtol 1e-3: three
+        // solves to about 1.7e-3, where fixed 1e-3 solves overshoot; the
+        // reduced-precision solves slow down near their accuracy floor.)
+        const double need = 0.5 * target / rho;
+        int k_left = 1;
+        if (need < o.inner_rtol)
+            k_left = (int)std::ceil(std::log(need) / std::log(o.inner_rtol) - 1e-9);
+        const double inner =
+            std::min(0.5, std::max(o.inner_rtol, std::pow(need, 1.0 / std::max(k_left, 1))));
         launch_scale_to_f32(p->st, p->NB, (int)n, p->r64, p->scal, reinterpret_cast<float*>(p->bws));
         launch_fill(p->st, p->xh, n, 0.0);
         Ctrl c{};
