@@ -33,6 +33,22 @@ constexpr int kSW = 64;              // threads of the small dense kernels (one 
 // nb columns of B (nb = st->r when use_r, else 0) and, when xtra is given, of
 // xtra . (scale * x) in slot nb.  part[slot * NB + block], fixed order.
 // Vectors are zero padded to whole 2-row tiles.
+// Column loads of the dot and update kernels: plain, or with the
+// non-temporal hint (NT) for the per-step operator when U and A U outgrow
+// the last-level cache: they are read once per step, while the leading
+// Krylov columns and the matrix kept there are read again every step.
+template <bool NT>
+__device__ __forceinline__ double2 ld_col2(const double* p) {
+    if constexpr (NT) {
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v t = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+        return make_double2(t.x, t.y);
+    } else {
+        return *reinterpret_cast<const double2*>(p);
+    }
+}
+
+template <bool NT>
 __global__ __launch_bounds__(kWG) void k_udots(int n, int64_t ldv, const double* __restrict__ B,
                                                const AdaptState* __restrict__ st, int use_r,
                                                const double* __restrict__ xtra,
@@ -55,7 +71,7 @@ __global__ __launch_bounds__(kWG) void k_udots(int n, int64_t ldv, const double*
         double2 bv[kAJ];
 #pragma unroll
         for (int q = 0; q < kAJ; ++q)
-            if (q < ns) bv[q] = *reinterpret_cast<const double2*>((q < nb ? B + q * ldv : xtra) + i0);
+            if (q < ns) bv[q] = ld_col2<NT>((q < nb ? B + q * ldv : xtra) + i0);
 #pragma unroll
         for (int q = 0; q < kAJ; ++q)
             if (q < ns) acc[q] += bv[q].x * x0 + bv[q].y * x1;
@@ -118,6 +134,7 @@ __global__ __launch_bounds__(kUC) void k_ucoef(const AdaptState* __restrict__ st
 
 // y += sign * sum_{q < r} B_q s_q  (B = A U for the operator, U for
 // Gram-Schmidt updates), two rows per thread.
+template <bool NT>
 __global__ __launch_bounds__(kWG) void k_ucorr(int n, int64_t ldv, const double* __restrict__ B,
                                                const AdaptState* __restrict__ st,
                                                const double* __restrict__ s, double sign,
@@ -132,7 +149,7 @@ __global__ __launch_bounds__(kWG) void k_ucorr(int n, int64_t ldv, const double*
         double2 bv[kAJ];
 #pragma unroll
         for (int q = 0; q < kAJ; ++q)
-            if (q < nb) bv[q] = *reinterpret_cast<const double2*>(B + q * ldv + i0);
+            if (q < nb) bv[q] = ld_col2<NT>(B + q * ldv + i0);
         double2 yv = *reinterpret_cast<const double2*>(y + i0);
 #pragma unroll
         for (int q = 0; q < kAJ; ++q)
@@ -519,20 +536,34 @@ __global__ void k_areset(AdaptState* st) {
 // ------------------------------------------------------------------ host
 static int small_grid(const EngineArgs& e) { return e.NB; }
 
+// U and A U at full size (2 (r_max + 1) columns of 8N bytes) take more than
+// half of the 256 MiB last-level cache: the per-step operator streams them.
+static bool stream_u(const EngineArgs& e) {
+    return 2.0 * (e.adapt->rmax + 1) * 8.0 * (double)e.n > 128.0 * 1024.0 * 1024.0;
+}
+
 void adapt_reset(hipStream_t st, const AdaptArgs& a) { k_areset<<<1, 1, 0, st>>>(a.st); }
 
 // s = C U^T (scale * x) for the SpMV input x of the step (gate 2).
 void adapt_pre(const EngineArgs& e, const double* x, const double* scale) {
     const AdaptArgs& a = *e.adapt;
     const int NB = small_grid(e);
-    k_udots<<<NB, kWG, 0, e.st>>>(e.n, e.ldv, a.U, a.st, 1, nullptr, x, scale, a.part, NB, e.ctrl, 2);
+    if (stream_u(e))
+        k_udots<true><<<NB, kWG, 0, e.st>>>(e.n, e.ldv, a.U, a.st, 1, nullptr, x, scale, a.part, NB,
+                                            e.ctrl, 2);
+    else
+        k_udots<false><<<NB, kWG, 0, e.st>>>(e.n, e.ldv, a.U, a.st, 1, nullptr, x, scale, a.part, NB,
+                                             e.ctrl, 2);
     k_ucoef<<<1, kUC, 0, e.st>>>(a.st, 1, 0, a.part, NB, a.C, a.rmax + 1, a.s, nullptr, e.ctrl, 2);
 }
 
 // y += (A U) s (gate 2).
 void adapt_post(const EngineArgs& e, double* y) {
     const AdaptArgs& a = *e.adapt;
-    k_ucorr<<<small_grid(e), kWG, 0, e.st>>>(e.n, e.ldv, a.AU, a.st, a.s, 1.0, y, e.ctrl, 2);
+    if (stream_u(e))
+        k_ucorr<true><<<small_grid(e), kWG, 0, e.st>>>(e.n, e.ldv, a.AU, a.st, a.s, 1.0, y, e.ctrl, 2);
+    else
+        k_ucorr<false><<<small_grid(e), kWG, 0, e.st>>>(e.n, e.ldv, a.AU, a.st, a.s, 1.0, y, e.ctrl, 2);
 }
 
 static void spmv_into(const EngineArgs& e, const double* x, double* y) {
@@ -554,7 +585,7 @@ void adapt_cycle_end(const EngineArgs& e, const double* V, const double* coef) {
     hipStream_t st = e.st;
     // x += d + U C U^T d,  d = V_k y_k
     k_vcomb<<<NB, kWG, 0, st>>>(e.n, e.ldv, V, coef, a.dvec, e.ctrl, 1);
-    k_udots<<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 1, nullptr, a.dvec, nullptr, a.part, NB, e.ctrl, 1);
+    k_udots<false><<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 1, nullptr, a.dvec, nullptr, a.part, NB, e.ctrl, 1);
     k_ucoef<<<1, kUC, 0, st>>>(a.st, 1, 0, a.part, NB, a.C, ld, a.s, nullptr, e.ctrl, 1);
     k_uaxpy<<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, a.s, a.dvec, e.xh, e.ctrl, 1);
     // Ritz vector u = V_k z of the smallest eigenvalue of H_k, |mu|.
@@ -562,18 +593,18 @@ void adapt_cycle_end(const EngineArgs& e, const double* V, const double* coef) {
     k_vcomb<<<NB, kWG, 0, st>>>(e.n, e.ldv, V, a.zc, a.ucand, e.ctrl, 1);
     // Classical Gram-Schmidt against U, twice.
     for (int pass = 0; pass < 2; ++pass) {
-        k_udots<<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 1, nullptr, a.ucand, nullptr, a.part, NB, e.ctrl, 1);
+        k_udots<false><<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 1, nullptr, a.ucand, nullptr, a.part, NB, e.ctrl, 1);
         k_ucoef<<<1, kUC, 0, st>>>(a.st, 1, 0, a.part, NB, nullptr, 0, a.s, nullptr, e.ctrl, 1);
-        k_ucorr<<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, a.s, -1.0, a.ucand, e.ctrl, 1);
+        k_ucorr<false><<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, a.s, -1.0, a.ucand, e.ctrl, 1);
     }
-    k_udots<<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 0, a.ucand, a.ucand, nullptr, a.part, NB, e.ctrl, 1);
+    k_udots<false><<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 0, a.ucand, a.ucand, nullptr, a.part, NB, e.ctrl, 1);
     k_unorm<<<1, kWG, 0, st>>>(a.part, NB, a.st, e.ctrl, 1);
     k_uscale<<<NB, kWG, 0, st>>>(e.n, a.ucand, a.st, e.ctrl, 1);
     spmv_into(e, a.ucand, a.aucand);
     // New column of T: U_q . A u (q < r) and u . A u; new row: u . A U_q.
-    k_udots<<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 1, a.ucand, a.aucand, nullptr, a.part, NB, e.ctrl, 1);
+    k_udots<false><<<NB, kWG, 0, st>>>(e.n, e.ldv, a.U, a.st, 1, a.ucand, a.aucand, nullptr, a.part, NB, e.ctrl, 1);
     k_ucoef<<<1, kUC, 0, st>>>(a.st, 1, 1, a.part, NB, nullptr, 0, a.s, a.tcol, e.ctrl, 1);
-    k_udots<<<NB, kWG, 0, st>>>(e.n, e.ldv, a.AU, a.st, 1, nullptr, a.ucand, nullptr, a.part, NB, e.ctrl, 1);
+    k_udots<false><<<NB, kWG, 0, st>>>(e.n, e.ldv, a.AU, a.st, 1, nullptr, a.ucand, nullptr, a.part, NB, e.ctrl, 1);
     k_ucoef<<<1, kUC, 0, st>>>(a.st, 1, 0, a.part, NB, nullptr, 0, a.s, a.trow, e.ctrl, 1);
     k_tupdate<<<1, kSW, 0, st>>>(a.rmax, a.T, a.C, a.tcol, a.trow, a.hvec, a.st, e.ctrl, 1);
     k_ucommit<<<NB, kWG, 0, st>>>(e.ldv, a.U, a.AU, a.ucand, a.aucand, a.st, e.ctrl, 1);
