@@ -402,22 +402,28 @@ gmres_status clear_typed(gmres_plan_s* p) {
     return GMRES_OK;
 }
 
-// Leading FP64 basis columns that the sweep kernels read with plain loads so
-// that they stay in the 256 MiB last-level cache (the rest of the basis
-// carries the non-temporal hint): what is left of 94% of that cache after the
-// work vectors one Arnoldi step touches (three N-vectors, with margin), the
-// two deflation row copies (36 B per row) and the SpMV's matrix copy, when it
-// fits as well, counted in 8N-byte columns.
-static int cache_cols_for(const gmres_plan_s* p, int op) {
+// Use of the 256 MiB last-level cache.  The matrix copy of the SpMV stays
+// in it when it fits beside the work vectors one Arnoldi step touches (three
+// N-vectors, with margin) and the two deflation row copies (36 B per row);
+// otherwise the sliced-ELL kernel streams it (`stream`).  The leading FP64
+// basis columns read with plain loads (`cols`; the rest of the basis carries
+// the non-temporal hint) are as many 8N-byte columns as fill what is left of
+// 94% of the cache.
+struct CacheUse {
+    int cols;
+    int stream;
+};
+static CacheUse cache_use_for(const gmres_plan_s* p, int op) {
     constexpr double kUsable = 0.94 * 256.0 * 1024.0 * 1024.0;
     const double n = (double)p->n, col = 8.0 * n;
     double resident = 3.0 * 8.0 * n + (p->R > 0 ? 36.0 * n : 0.0);
     const int64_t sell = op ? p->tsell_total : p->sell_total;
     const double mat = (p->L == kSell && sell > 0) ? 10.0 * (double)sell + 4.0 * n
                                                   : 12.0 * (double)p->nnz + 4.0 * (n + 1.0);
-    if (resident + mat <= kUsable) resident += mat;
+    const bool fits = resident + mat <= kUsable;
+    if (fits) resident += mat;
     const double c = std::floor((kUsable - resident) / col);
-    return (int)std::max(0.0, std::min(c, 1024.0));
+    return {(int)std::max(0.0, std::min(c, 1024.0)), fits ? 0 : 1};
 }
 
 EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
@@ -519,7 +525,9 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.ctrl = p->ctrl;
     a.lagged = p->o.ortho == 1 ? 1 : 0;
     a.dcgs = p->o.ortho == 2 ? 1 : 0;
-    a.cache_cols = cache_cols_for(p, op);
+    const CacheUse cu = cache_use_for(p, op);
+    a.cache_cols = cu.cols;
+    a.sell_stream = cu.stream;
     a.dcs = p->dcs;
     a.cc = p->cc;
     a.lag = p->lag;

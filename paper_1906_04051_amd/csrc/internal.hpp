@@ -120,6 +120,7 @@ struct EngineArgs {
     int lagged;             // two-pass CGS2 with lagged normalisation
     int dcgs;               // CGS2 with one reduction per step (delayed re-orthogonalisation)
     int cache_cols;         // FP64 basis: leading columns kept in the last-level cache
+    int sell_stream;        // the sliced-ELL matrix streams past that cache (chunked rows)
     double* dcs;            // its slot sums (2m + 3)
     const AdaptArgs* adapt; // FP64 adaptive spectral deflation (nullptr: off)
     double* cc;             // lagged: coefficients (Hbar h2) of the next step, m + 1

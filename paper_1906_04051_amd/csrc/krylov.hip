@@ -177,6 +177,13 @@ __global__ __launch_bounds__(RB) void k_spmv_stream(int n, const int* __restrict
     }
 }
 
+// One matrix entry (offset or value): plain, or with the non-temporal hint.
+template <bool STREAM, typename T>
+__device__ __forceinline__ T ld_mat(const T* p) {
+    if constexpr (STREAM) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Sliced-ELL SpMV: one wavefront per 64-position slice, NT positions per
 // block, so every load instruction reads 64 consecutive entries of one slice
 // column; position p holds row perm[p] (rows sorted within 256-row blocks) or
@@ -275,21 +282,26 @@ __global__ __launch_bounds__(NT) void k_spmv_sell(int n, const int* __restrict__
                     // Rows of any length, in chunks of CH entries: the values
                     // and gathers of one chunk are issued, then the column
                     // offsets of the next, which stay in flight while the
-                    // products of the first wait.
+                    // products of the first wait.  WMAX < 0: the matrix is
+                    // larger than the last-level cache, so its offsets and
+                    // values stream past it (non-temporal hint) and leave it
+                    // to the input vector and the Krylov basis.
                     constexpr int CH = 8;
+                    constexpr bool kStream = WMAX < 0;
                     int cc[CH];
 #pragma unroll
-                    for (int k = 0; k < CH; ++k) cc[k] = scol[q + min(k, w - 1) * kWave];
+                    for (int k = 0; k < CH; ++k) cc[k] = ld_mat<kStream>(scol + q + min(k, w - 1) * kWave);
                     for (int k0 = 0; k0 < w; k0 += CH) {
                         ACC xv[CH];
                         AT va[CH];
 #pragma unroll
                         for (int k = 0; k < CH; ++k) {
-                            va[k] = sval[q + min(k0 + k, w - 1) * kWave];
+                            va[k] = ld_mat<kStream>(sval + q + min(k0 + k, w - 1) * kWave);
                             xv[k] = (ACC)ld_f(xr + cc[k]);
                         }
 #pragma unroll
-                        for (int k = 0; k < CH; ++k) cc[k] = scol[q + min(k0 + CH + k, w - 1) * kWave];
+                        for (int k = 0; k < CH; ++k)
+                            cc[k] = ld_mat<kStream>(scol + q + min(k0 + CH + k, w - 1) * kWave);
 #pragma unroll
                         for (int k = 0; k < CH; ++k)
                             acc += k0 + k < w ? (ACC)va[k] * xv[k] : (ACC)0;
@@ -1748,11 +1760,13 @@ template <int MODE, typename AT, typename XT, typename BT, typename YT, typename
 static void sell_launch(const EngineArgs& e, const XT* x, const double* scale, const BT* b, YT* y,
                         int slot, int gate) {
     // Fully unrolled rows up to 25 entries (the smallest instance that holds
-    // the longest row), chunked rows beyond.
+    // the longest row), chunked rows beyond (streamed when the matrix does not
+    // fit in the last-level cache).
     if (e.sell_wmax <= 9) sell_launch_w<MODE, 9, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
     else if (e.sell_wmax <= 12) sell_launch_w<MODE, 12, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
     else if (e.sell_wmax <= 16) sell_launch_w<MODE, 16, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
     else if (e.sell_wmax <= 25) sell_launch_w<MODE, 25, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    else if (e.sell_stream) sell_launch_w<MODE, -1, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
     else sell_launch_w<MODE, 0, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
 }
 
