@@ -144,6 +144,25 @@ def test_lu_against_numpy():
         assert np.abs(PE - L @ U).max() <= 50 * r * EPS * np.abs(E).max()
 
 
+def test_lu_pivots_on_zero_and_tiny_leading_entries():
+    """Partial pivoting (the textbook LU the coarse solve names): a zero or
+    tiny leading pivot must be swapped away, not divided by."""
+    perm = np.eye(5)[[2, 0, 4, 1, 3]] * np.arange(1.0, 6.0)[:, None]
+    for E in (np.array([[0.0, 1.0], [1.0, 0.0]]), perm):
+        st, LU, piv = oracle.lu_factor(E)
+        assert st == 0
+        t = np.arange(1.0, E.shape[0] + 1)
+        assert np.allclose(oracle.lu_solve(LU, piv, t), np.linalg.solve(E, t), rtol=1e-14, atol=0)
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal((64, 64))
+    np.fill_diagonal(E, 1e-14)
+    st, LU, piv = oracle.lu_factor(E)
+    assert st == 0
+    t = rng.standard_normal(64)
+    x, xr = oracle.lu_solve(LU, piv, t), np.linalg.solve(E, t)
+    assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
 def test_lu_singular():
     E = np.array([[1.0, 2.0], [2.0, 4.0]])
     st, _, _ = oracle.lu_factor(E)
@@ -235,6 +254,30 @@ def test_k_distinct_eigenvalues_k_steps():
     res = oracle.gmres(s, 20, 1e-13, 100)
     assert res.iters == 4
     assert np.allclose(res.x, b / d, rtol=1e-12)
+
+
+def _closing_direction_system():
+    """diag(1, 1, 1, 1, 1 + 1e-10) with b = (1, 1, 1, 1, 1e-12): every entry of
+    v1 = b / ||b|| and of the first step's products is exact except the last,
+    so the first Arnoldi step leaves h_21 = 1e-10 * 5e-13 = 5e-23, far below
+    eps * ||A v1|| = eps: the Krylov space has (numerically) closed."""
+    d = np.array([1.0, 1.0, 1.0, 1.0, 1.0 + 1e-10])
+    b = np.array([1.0, 1.0, 1.0, 1.0, 1e-12])
+    return d, b, W.from_dense(np.diag(d), b)
+
+
+def test_lucky_breakdown_ends_the_cycle():
+    """Reading c8 (lucky breakdown): h_{j+1,j} <= eps ||P A v_j|| ends the
+    cycle at that step, and the restart picks up what rounding left.  In the
+    fixed-count protocol (rtol = 0, two steps) that is two one-step cycles;
+    without the test the cycle would go on with the normalised rounding
+    residue as its second direction."""
+    d, b, s = _closing_direction_system()
+    res = oracle.gmres(s, 4, 0.0, 2, first_cycle=True)
+    assert 0.0 < res.H0[1, 0] <= EPS * 1.0
+    assert res.iters == 2 and res.cycles == 2
+    assert np.isfinite(res.x).all()
+    assert np.allclose(res.x, b / d, rtol=1e-15, atol=0)
 
 
 def test_cyclic_shift_stagnates_then_exact():
@@ -463,6 +506,18 @@ def test_dgmres_without_deflation_is_gmres():
     assert res.status_name == "OK" and res.iters == ref.iters and res.r == 0
     assert np.allclose(res.history, ref.history, rtol=1e-8, atol=1e-14 * ref.rho0)
     assert np.linalg.norm(res.x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_dgmres_lucky_breakdown_ends_the_cycle():
+    """The same closing direction as test_lucky_breakdown_ends_the_cycle under
+    the adaptive preconditioner (U empty at the first cycle; with r_max > 0
+    the second cycle runs on A M^{-1} with the first cycle's Ritz vector)."""
+    d, b, s = _closing_direction_system()
+    for rmax in (0, 2):
+        res = oracle.dgmres(s, 4, 0.0, 2, rmax=rmax)
+        assert res.iters == 2 and res.cycles == 2
+        assert np.isfinite(res.x).all()
+        assert np.allclose(res.x, b / d, rtol=1e-15, atol=0)
 
 
 def test_dgmres_solves_and_keeps_invariants():

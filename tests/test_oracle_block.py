@@ -9,6 +9,8 @@ against facts fixed by the mathematics, never against the oracle itself:
   * k = 1        -- the block method is GMRES(m);
   * termination  -- block dimension N reached: the exact solution (dense solve);
   * A = I        -- one block step;
+  * closed space -- a block step whose new columns are rounding residue ends
+                    its cycle (few distinct eigenvalues);
   * estimate     -- the least-squares residual equals the recomputed one after
                     one cycle;
   * whole solve  -- to tolerance on a FEM system, every column within its
@@ -117,6 +119,30 @@ def test_identity_one_block_step():
     res = oracle.bgmres(rp, ci, v, B, 5, 1e-12, 50)
     assert res.status_name == "OK" and res.iters == 1
     assert np.abs(res.x - B).max() <= 1e-14
+
+
+def test_block_space_stops_growing_ends_the_cycle():
+    """Four distinct eigenvalues of multiplicity five and two right-hand
+    sides: the block Krylov space has dimension 8 (two directions per
+    eigenspace), so the fifth block step's new columns are rounding residue
+    (below 1e-10 of their norm before orthogonalisation) and that cycle ends
+    there (reading: the block space has stopped growing; the step is kept).
+    Fixed count of 8 block steps with m = 8: a 5-step cycle, then a 3-step
+    one.  With A = I the first block step already closes the space, and the
+    result stays finite and exact."""
+    n = 20
+    d = np.repeat([1.0, 2.0, 5.0, -3.0], 5)
+    rp, ci, v = _csr(sp.diags(d))
+    B = np.random.default_rng(7).standard_normal((n, 2))
+    res = oracle.bgmres(rp, ci, v, B, 8, 0.0, 8)
+    assert res.iters == 8 and res.cycles == 2
+    assert np.isfinite(res.x).all()
+    assert np.allclose(res.x, B / d[:, None], rtol=1e-12, atol=0)
+    rp, ci, v = _csr(sp.eye(10))
+    B = np.random.default_rng(8).standard_normal((10, 3))
+    res = oracle.bgmres(rp, ci, v, B, 4, 0.0, 3)
+    assert res.status_name == "OK" and np.isfinite(res.x).all()
+    assert np.abs(res.x - B).max() <= 1e-14 * np.abs(B).max()
 
 
 def test_estimate_is_true_residual_after_one_cycle():
