@@ -49,7 +49,7 @@ typedef enum {
     GMRES_ESINGULAR = -2,   /* E = Z^T A Z is singular (|pivot| <= r * eps * max|E|) */
     GMRES_ENONFINITE = -3,  /* NaN or Inf in A, Z, b or x0 */
     GMRES_EDEVICE = -4,     /* HIP runtime error */
-    GMRES_ENOMEM = -5       /* device allocation failed */
+    GMRES_EWORKSPACE = -5   /* the caller's workspace is too small (gmres_workspace_required) */
 } gmres_status;
 
 typedef enum {
@@ -116,22 +116,53 @@ typedef struct {
 void gmres_default_opts(gmres_opts* o);
 
 /*
+ * Device memory.  The library allocates none: every device buffer of a plan
+ * (the copies of A and Z, Z^T, the compact A Z, E and E^{-1}, the sliced-ELL
+ * and row copies, the FP32 values, A^T for the adjoint, the Krylov basis,
+ * work vectors, partial sums, control block and history) is carved out of one
+ * caller-owned workspace passed to gmres_setup, which must stay valid and
+ * untouched until gmres_destroy.  Setup temporaries (sort and scan buffers)
+ * use the top of the same workspace and are free again when setup returns.
+ *
+ * gmres_workspace_bytes returns the workspace size for a plan from host data
+ * alone (the same sizes and options as gmres_setup; 0 for invalid arguments).
+ * It is exact except for data-dependent parts, which it bounds: the compact
+ * A Z (and A^T Z) gets min(n * min(r, 64), nnz * ceil(z_nnz / n)) entries --
+ * an upper bound whenever every row of Z has at most ceil(z_nnz / n)
+ * entries, as for indicator bases -- and the sliced-ELL copy its budget of
+ * nnz + nnz/4 + 4096 entries (the plan uses the CSR kernels when the copy
+ * would be larger).  When a workspace turns out too small, gmres_setup returns
+ * GMRES_EWORKSPACE without touching it beyond its first workspace_bytes, and
+ * gmres_workspace_required() then gives the exact size needed (call again
+ * with at least that many bytes).  The workspace must be 256-byte aligned.
+ */
+size_t gmres_workspace_bytes(int32_t nsys, const int64_t* sys_row_off_h,
+                             const int64_t* sys_zcol_off_h, int64_t nnz, int64_t z_nnz,
+                             const gmres_opts* opts, int32_t need_adjoint);
+
+/* Bytes the last GMRES_EWORKSPACE failure on the calling thread needed (0 if
+ * unknown or none). */
+size_t gmres_workspace_required(void);
+
+/*
  * Builds a plan for nsys independent systems stored as one block-diagonal CSR
  * matrix of n_total = sys_row_off_h[nsys] rows (nsys = 1: a single system).
  * Rows [sys_row_off_h[s], sys_row_off_h[s+1]) form system s; their column
- * indices must lie in the same range.  Z is an n_total x r_total CSR matrix
- * whose columns [sys_zcol_off_h[s], sys_zcol_off_h[s+1]) belong to system s
- * (r_s = 0 allowed: plain GMRES(m)); r_s <= 256.  z_* may be NULL when
- * r_total = 0.
+ * indices must lie in the same range, strictly increasing within each row
+ * (sorted, no duplicates).  Z is an n_total x r_total CSR matrix (sorted
+ * rows) whose columns [sys_zcol_off_h[s], sys_zcol_off_h[s+1]) belong to
+ * system s (r_s = 0 allowed: plain GMRES(m)); r_s <= 256.  z_* may be NULL
+ * when r_total = 0.
  *
  * Setup (Sec. 3.3 analogue, done once): validates A and Z, copies them into
- * plan-owned device memory, builds Z^T, the compact product A Z, E_s = Z^T A Z
- * per system, its LU factors with partial pivoting and the explicit inverse;
- * for need_adjoint also A^T, A^T Z and (E^T)^{-1}; FP32 copies for mixed
- * precision.  The library allocates the plan's device memory itself; it is
- * released by gmres_destroy.  stream: the HIP stream for all work (0 = null
- * stream).  Errors: EINVAL (sizes, CSR, m, r_s > 256, a row of A Z with more
- * than 64 deflation columns), ENONFINITE, ESINGULAR, ENOMEM, EDEVICE; *out is
+ * the workspace, builds Z^T, the compact product A Z, E_s = Z^T A Z per
+ * system, its LU factors with partial pivoting and the explicit inverse; for
+ * need_adjoint also A^T, A^T Z and (E^T)^{-1}; FP32 copies for mixed
+ * precision.  workspace / workspace_bytes: caller-owned device memory (see
+ * gmres_workspace_bytes).  stream: the HIP stream for all work (0 = null
+ * stream).  Errors: EINVAL (sizes, unsorted or duplicate column indices,
+ * m, r_s > 256, a row of A Z with more than 64 deflation columns, a
+ * misaligned workspace), ENONFINITE, ESINGULAR, EWORKSPACE, EDEVICE; *out is
  * NULL on error.
  */
 gmres_status gmres_setup(gmres_plan* out, int32_t nsys, const int64_t* sys_row_off_h,
@@ -139,7 +170,7 @@ gmres_status gmres_setup(gmres_plan* out, int32_t nsys, const int64_t* sys_row_o
                          const int32_t* colind, const double* vals, int64_t nnz,
                          const int32_t* z_rowptr, const int32_t* z_colind, const double* z_vals,
                          int64_t z_nnz, const gmres_opts* opts, int32_t need_adjoint,
-                         hipStream_t stream);
+                         void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
  * Solves A x = b for a single-system plan (nsys = 1) with the plan's options
@@ -174,18 +205,22 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
  * steps.  k in [1, 16]; m_block in [1, 16] block steps per cycle (block
  * Krylov dimension m_block * k).  B, X0 (or NULL: zero), X: n x k row-major
  * device arrays owned by the caller; X must not alias B (it may alias X0).
- * The first call allocates a plan-owned workspace of (m_block + 4) panels of
- * n x 16 doubles (reused by later calls with m_block no larger).  info_h:
- * iters = block steps, cycles, rho0 = max_c ||b_c - A x0_c||, rel_res = max_c
- * estimated relative residual at the last block step, rel_res_true = max_c
- * true relative residual.  Each cycle runs on the columns not yet
- * converged; a residual column that has become dependent on the others adds
- * no basis vector (the block basis may be narrower than the number of
- * right-hand sides).  Returns OK or MAXITER, or EINVAL (sizes, a plan with
- * deflation, a zero column of B - A X0), ENONFINITE, ENOMEM, EDEVICE.
+ * work / work_bytes: caller-owned device scratch of at least
+ * gmres_block_workspace_bytes(p, m_block) bytes, 256-byte aligned ((m_block
+ * + 4) panels of n x 16 doubles and the small block state); its contents
+ * need not survive between calls.  info_h: iters = block steps, cycles,
+ * rho0 = max_c ||b_c - A x0_c||, rel_res = max_c estimated relative residual
+ * at the last block step, rel_res_true = max_c true relative residual.  Each
+ * cycle runs on the columns not yet converged; a residual column that has
+ * become dependent on the others adds no basis vector (the block basis may be
+ * narrower than the number of right-hand sides).  Returns OK or MAXITER, or
+ * EINVAL (sizes, a plan with deflation, a zero column of B - A X0),
+ * ENONFINITE, EWORKSPACE, EDEVICE.
  */
+size_t gmres_block_workspace_bytes(gmres_plan p, int32_t m_block);
 gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const double* B,
-                               const double* X0, double* X, gmres_info* info_h);
+                               const double* X0, double* X, void* work, size_t work_bytes,
+                               gmres_info* info_h);
 
 /*
  * Adjoint of x = A^{-1} b for a single-system plan built with need_adjoint:
@@ -236,7 +271,7 @@ gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 24 doubles */);
 /* Switches the stream used by later calls. */
 gmres_status gmres_set_stream(gmres_plan p, hipStream_t stream);
 
-/* Releases the plan and its device memory (NULL allowed). */
+/* Releases the plan (NULL allowed); the caller's workspace is free again afterwards. */
 void gmres_destroy(gmres_plan p);
 
 /* Message of the last error on the calling thread ("" if none). */

@@ -76,8 +76,7 @@ struct Plan;
 }  // namespace
 
 struct gmres_plan_s {
-    gm::BlockWork* block = nullptr;   // block GMRES workspace (allocated on first use)
-    int block_m = 0;
+    gm::BlockWork* block = nullptr;   // block GMRES buffers (bound to the caller's memory per call)
     int device = 0;
     hipStream_t user_stream = nullptr;
     hipStream_t st = nullptr;           // plan-owned stream (capturable)
@@ -89,7 +88,11 @@ struct gmres_plan_s {
     gmres_opts o{};
     int need_adjoint = 0;
     AdaptArgs adapt{};      // adaptive spectral deflation buffers (adapt.rmax > 0)
-    std::vector<void*> allocs;
+    Arena ar;               // the caller's workspace: every device buffer of the plan
+    bool sell_ok = false, tsell_ok = false;   // sliced-ELL copies planned
+    bool sell_sorted = false, tsell_sorted = false;
+    int64_t slots_cap = 0;  // capacity of the fused Z^T y slot lists
+    int64_t mc_cap = 1;     // largest Z^T chunk count per row the partial buffer holds
 
     // plan-owned copies of the inputs
     int *rowptr = nullptr, *colind = nullptr;
@@ -161,6 +164,7 @@ struct gmres_plan_s {
     double* hist = nullptr;
     int64_t hist_cap = 0;
     int64_t hist_len = 0;
+    int64_t hist_pos = 0;   // steps recorded so far by the current solve's engine runs
     int* cyc_k = nullptr;
     int64_t cyc_cap = 0;
 
@@ -171,6 +175,7 @@ struct gmres_plan_s {
     // batched
     int batch_wg = 256, batch_L = 8;
     double *bV = nullptr, *bW = nullptr;
+    double *btune_x = nullptr, *btune_b = nullptr;   // autotune: solution and right-hand side
     int* border = nullptr;
     int* bticket = nullptr;
     int64_t* bout_i = nullptr;
@@ -182,16 +187,13 @@ struct gmres_plan_s {
 
 namespace {
 
+thread_local size_t g_ws_required = 0;   // bytes the last EWORKSPACE failure needed
+
+// Carves count elements from the plan's workspace.
 template <typename T>
 gmres_status dalloc(gmres_plan_s* p, T** ptr, int64_t count) {
-    *ptr = nullptr;
-    if (count <= 0) return GMRES_OK;
-    void* q = nullptr;
-    const size_t bytes = ((size_t)count * sizeof(T) + 255) & ~(size_t)255;
-    if (hipMalloc(&q, bytes) != hipSuccess)
-        return fail(GMRES_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    p->allocs.push_back(q);
-    *ptr = reinterpret_cast<T*>(q);
+    *ptr = p->ar.take_n<T>(count);
+    if (!*ptr) return fail(GMRES_EWORKSPACE, "workspace too small");
     return GMRES_OK;
 }
 
@@ -207,7 +209,7 @@ gmres_status to_status(int s, const char* what) {
         case kStatusInval: return fail(GMRES_EINVAL, std::string(what) + ": invalid input");
         case kStatusSingular: return fail(GMRES_ESINGULAR, std::string(what) + ": E = Z^T A Z is singular");
         case kStatusNonFinite: return fail(GMRES_ENONFINITE, std::string(what) + ": non-finite value");
-        case kStatusNoMem: return fail(GMRES_ENOMEM, std::string(what) + ": out of device memory");
+        case kStatusNoMem: return fail(GMRES_EWORKSPACE, std::string(what) + ": workspace too small");
         default: return fail(GMRES_EDEVICE, std::string(what) + ": device error");
     }
 }
@@ -225,24 +227,6 @@ int default_lanes(int64_t n, int64_t nnz, bool have_sell, int64_t sell_total) {
 
 int max_row_len(hipStream_t st, int64_t n, const int* rp, int* d_tmp) {
     return zt_max_row(st, (int)n, rp, d_tmp);
-}
-
-// Builds A Z (compact CSR) for the operator (rowptr, colind, vals).
-gmres_status build_az(gmres_plan_s* p, const int* rp, const int* ci, const double* v, int** azrp,
-                      int** azci, double** azv, int64_t* nnz_out) {
-    SetupArgs sa{p->st, p->nsys, p->n, p->nnz, p->znnz, p->R, p->d_row_off, p->d_zcol_off,
-                 rp, ci, v, p->zrp, p->zci, p->zv};
-    CHECK(dalloc(p, azrp, p->n + 1));
-    int64_t cnt = 0;
-    int s = az_count(sa, rp, ci, *azrp, &cnt);
-    if (s == kStatusInval)
-        return fail(GMRES_EINVAL, "a row of A*Z reaches more than 64 deflation columns");
-    CHECK(to_status(s, "A*Z"));
-    CHECK(dalloc(p, azci, cnt));
-    CHECK(dalloc(p, azv, cnt));
-    az_fill(sa, rp, ci, v, *azrp, *azci, *azv);
-    *nnz_out = cnt;
-    return GMRES_OK;
 }
 
 // Single-entry (ELL-1) copies of A Z / A^T Z for the pass-1 deflation.
@@ -277,51 +261,51 @@ gmres_status refresh_values(gmres_plan_s* p) {
 
 gmres_status clear_typed(gmres_plan_s* p);
 
-// Builds (or rebuilds for another block size) the per-block deflation slots
-// used by the fused Z^T y of the stream SpMV.  Falls back to the separate
-// Z^T pass when a row block reaches more than 64 deflation columns.
-gmres_status ensure_slots(gmres_plan_s* p) {
-    const int rb = (p->L == kSell || p->L == -256) ? 256 : (p->L == -128 ? 128 : 0);
-    if (p->R == 0 || rb == 0 || rb == p->slots_rb) return GMRES_OK;
-    for (int* q : {p->bb_ptr, p->bb_col, p->ab_ptr, p->ab_slot, p->slot_pos}) hipFree(q);
-    p->bb_ptr = p->bb_col = p->ab_ptr = p->ab_slot = p->slot_pos = nullptr;
-    p->slots_rb = 0;
-    int64_t ns = 0;
-    int s = build_block_slots(p->st, p->n, rb, p->R, p->zrp, p->zci, &p->bb_ptr, &p->bb_col,
-                              &p->ab_ptr, &p->ab_slot, &ns, p->d_flags);
-    if (s == kStatusInval) return GMRES_OK;          // dense Z: keep the separate pass
-    CHECK(to_status(s, "deflation slots"));
-    if (ns > p->tpart_cap) {
-        double* t = nullptr;
-        CHECK(dalloc(p, &t, ns));
-        p->tpart = t;
-        p->tpart_cap = ns;
-    }
-    HIP_OK(hipMalloc(&p->slot_pos, std::max<int64_t>(ns, 1) * sizeof(int)));
-    invperm(p->st, ns, p->ab_slot, p->slot_pos);
-    p->nslots = ns;
-    p->slots_rb = rb;
-    return GMRES_OK;
+// Row block of the stream SpMV that carries the fused Z^T y (the sliced-ELL
+// kernel and the LDS-staged stream with 256 rows per workgroup).
+constexpr int kSlotRB = 256;
+
+// ------------------------------------------------------------ workspace layout
+// Every device buffer of a plan is carved from the caller's workspace, in two
+// phases: buffers whose sizes follow from the sizes and options (phase 1),
+// then those whose sizes the setup kernels count (phase 2: the compact A Z and
+// A^T Z, the sliced-ELL copies).  Setup temporaries come from the top of the
+// workspace and are given back after each step: T1 while counting, T2 while
+// building the fused Z^T y slots after phase 2.  The workspace needs
+// P1 + max(T1, P2 + T2) bytes.
+
+int64_t sell_budget(int64_t nnz) { return nnz + nnz / 4 + 4096; }
+
+// Upper bound of the compact A Z entries from sizes alone: at most
+// kAzRowMax per row, and at most (entries of A's row) x (entries of a Z row);
+// the second factor is bounded by the mean Z row length rounded up, which is
+// exact for bases with at most one entry per row (indicator bases).
+int64_t az_bound(const gmres_plan_s* p) {
+    if (p->R == 0 || p->n == 0) return 0;
+    const int64_t zrow = std::max<int64_t>(1, (p->znnz + p->n - 1) / p->n);
+    return std::min<int64_t>(p->n * std::min<int64_t>(p->R, kAzRowMax), p->nnz * zrow);
 }
 
-gmres_status alloc_krylov(gmres_plan_s* p) {
+int64_t hist_entries(const gmres_opts& o) {
+    int64_t h = o.max_iters;
+    if (o.precision != GMRES_FP64) h += (int64_t)std::max(o.max_refine, 0) * std::max<int64_t>(o.inner_max_iters, 0);
+    return std::min<int64_t>(std::max<int64_t>(h, 1), int64_t(1) << 24);
+}
+
+void carve_krylov(gmres_plan_s* p, Arena& A) {
     const int m = p->o.m;
     const int64_t n = p->n;
     p->ldv = (n + 63) & ~int64_t(63);
-    double* Vd = nullptr;
-    CHECK(dalloc(p, &Vd, (int64_t)(m + 1) * p->ldv));
-    p->V = Vd;
+    p->V = A.take_n<double>((int64_t)(m + 1) * p->ldv);
     // Typed work vectors are read in whole 16-byte tiles: they hold ldv
     // entries and their padding stays zero.
-    for (double** q : {&p->y, &p->w, &p->pv, &p->rv}) CHECK(dalloc(p, q, p->ldv));
-    for (double** q : {&p->xh, &p->bws, &p->xo, &p->r64, &p->dvec}) CHECK(dalloc(p, q, n));
-    CHECK(clear_typed(p));
+    for (double** q : {&p->y, &p->w, &p->pv, &p->rv}) *q = A.take_n<double>(p->ldv);
+    for (double** q : {&p->xh, &p->bws, &p->xo, &p->r64, &p->dvec}) *q = A.take_n<double>(n);
     p->NB_cap = std::max(p->NB, (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 2048));
-    CHECK(dalloc(p, &p->part, (int64_t)(2 * m + 3) * p->NB_cap));
-    CHECK(dalloc(p, &p->dcs, 2 * m + 3));
+    p->part = A.take_n<double>((int64_t)(2 * m + 3) * p->NB_cap);
+    p->dcs = A.take_n<double>(2 * m + 3);
     const int64_t small = 5 * (m + 1) + 2 * (int64_t)(m + 1) * m + 2 * m + 2 * (m + 1) + 24;
-    double* s = nullptr;
-    CHECK(dalloc(p, &s, small));
+    double* s = A.take_n<double>(small);
     p->h1 = s; s += m + 1;
     p->h2 = s; s += m + 1;
     p->coef1 = s; s += m + 1;
@@ -338,26 +322,231 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
     p->cc = s; s += m + 1;
     p->lag = s; s += 4;
     if (p->R > 0) {
-        CHECK(dalloc(p, &p->tpart, std::max<int64_t>((int64_t)p->R * p->MC, p->tpart_cap)));
-        CHECK(dalloc(p, &p->s_step, p->R));
-        CHECK(dalloc(p, &p->s_res, p->R));
+        p->tpart_cap = std::max<int64_t>((int64_t)p->R * p->mc_cap, p->slots_cap);
+        p->tpart = A.take_n<double>(p->tpart_cap);
+        p->s_step = A.take_n<double>(p->R);
+        p->s_res = A.take_n<double>(p->R);
+        // Two entries per row (ELL-2), padded to ldv rows.
+        p->azc1 = A.take_n<int>(2 * p->ldv);
+        p->azv1 = A.take_n<double>(2 * p->ldv);
+        if (p->o.precision != GMRES_FP64) p->azv1f = A.take_n<float>(2 * p->ldv);
+        if (p->need_adjoint) {
+            p->atzc1 = A.take_n<int>(2 * p->ldv);
+            p->atzv1 = A.take_n<double>(2 * p->ldv);
+        }
     }
-    p->tpart_cap = std::max<int64_t>(p->tpart_cap, (int64_t)p->R * p->MC);
-    CHECK(ensure_slots(p));
+    if (p->o.adapt_rmax > 0) {
+        AdaptArgs& ad = p->adapt;
+        const int rc = p->o.adapt_rmax + 1;
+        ad.rmax = p->o.adapt_rmax;
+        ad.st = A.take_n<AdaptState>(1);
+        ad.U = A.take_n<double>((int64_t)rc * p->ldv);
+        ad.AU = A.take_n<double>((int64_t)rc * p->ldv);
+        ad.T = A.take_n<double>((int64_t)rc * rc);
+        ad.C = A.take_n<double>((int64_t)rc * rc);
+        for (double** q : {&ad.s, &ad.tcol, &ad.trow, &ad.hvec}) *q = A.take_n<double>(rc + 1);
+        ad.zc = A.take_n<double>(kMaxM);
+        for (double** q : {&ad.ucand, &ad.aucand, &ad.dvec}) *q = A.take_n<double>(p->ldv);
+        ad.part = A.take_n<double>((int64_t)(rc + 1) * p->NB_cap);
+    }
+    p->ctrl = A.take_n<Ctrl>(1);
+    p->cyc_cap = 1 << 16;
+    p->cyc_k = A.take_n<int>(p->cyc_cap);
+    if (p->o.record_history) {
+        p->hist_cap = hist_entries(p->o);
+        p->hist = A.take_n<double>(p->hist_cap);
+    }
+}
+
+// Buffers of the persistent batched kernel.  A single-system plan can run it
+// too (gmres_solve_batched with nsys = 1): its basis then lies in the Krylov
+// basis of the plan ((m + 1) n <= (m + 1) ldv entries), which the next
+// single-system solve clears again.
+void carve_batched(gmres_plan_s* p, Arena& A) {
+    const int ns = p->nsys;
+    const int m = p->o.m;
+    if (ns > 1) {
+        p->bV = A.take_n<double>((int64_t)(m + 1) * p->n);
+        p->btune_x = A.take_n<double>(p->n);
+        p->btune_b = A.take_n<double>(p->n);
+    } else {
+        p->bV = static_cast<double*>(p->V);
+    }
+    p->bW = A.take_n<double>(3 * p->n);
+    p->border = A.take_n<int>(ns);
+    p->bticket = A.take_n<int>(1);
+    p->bout_i = A.take_n<int64_t>(3 * (int64_t)ns);
+    p->bout_d = A.take_n<double>(5 * (int64_t)ns);
+    p->d_v_off = A.take_n<int64_t>(ns);
+}
+
+// Phase 1: buffers sized by the plan's sizes and options.
+void carve_phase1(gmres_plan_s* p, Arena& A) {
+    const int64_t n = p->n, nnz = p->nnz, zn = p->znnz;
+    const int nsys = p->nsys;
+    p->rowptr = A.take_n<int>(n + 1);
+    p->colind = A.take_n<int>(nnz);
+    p->vals = A.take_n<double>(nnz);
+    p->d_row_off = A.take_n<int64_t>(nsys + 1);
+    p->d_zcol_off = A.take_n<int64_t>(nsys + 1);
+    p->d_e_off = A.take_n<int64_t>(nsys + 1);
+    p->d_flags = A.take_n<int>(4);
     if (p->R > 0) {
-        // Padded to ldv rows: padding reads as "no entry" (-1) with value 0.
-        // Two entries per row (ELL-2).
-        CHECK(dalloc(p, &p->azc1, 2 * p->ldv));
-        CHECK(dalloc(p, &p->azv1, 2 * p->ldv));
+        p->zrp = A.take_n<int>(n + 1);
+        p->zci = A.take_n<int>(zn);
+        p->zv = A.take_n<double>(zn);
+        p->ztrp = A.take_n<int>(p->R + 1);
+        p->ztci = A.take_n<int>(zn);
+        p->ztperm = A.take_n<int>(zn);
+        p->ztv = A.take_n<double>(zn);
+        p->zc1 = A.take_n<int>(n);
+        p->zv1 = A.take_n<double>(n);
+        p->azrp = A.take_n<int>(n + 1);
+        p->E = A.take_n<double>(p->e_off_h[nsys]);
+        p->Einv = A.take_n<double>(p->e_off_h[nsys]);
+        // Z^T chunk partials: at most ceil(longest Z^T row / CH) per column.
+        p->mc_cap = std::max<int64_t>(1, (std::min<int64_t>(n, zn) + p->CH - 1) / p->CH);
+        if (nsys == 1) {
+            const int64_t nblk = (n + kSlotRB - 1) / kSlotRB;
+            p->slots_cap = block_slots_bound(n, kSlotRB, p->R, zn);
+            p->bb_ptr = A.take_n<int>(nblk + 1);
+            p->bb_col = A.take_n<int>(p->slots_cap);
+            p->ab_ptr = A.take_n<int>(p->R + 1);
+            p->ab_slot = A.take_n<int>(p->slots_cap);
+            p->slot_pos = A.take_n<int>(p->slots_cap);
+        }
+    }
+    if (p->o.precision != GMRES_FP64) p->vals32 = A.take_n<float>(nnz);
+    if (p->need_adjoint) {
+        p->trp = A.take_n<int>(n + 1);
+        p->tci = A.take_n<int>(nnz);
+        p->tperm = A.take_n<int>(nnz);
+        p->tv = A.take_n<double>(nnz);
+        if (p->R > 0) p->atzrp = A.take_n<int>(n + 1);
+    }
+    const int64_t nsl = (n + 63) / 64;
+    p->sell_off = A.take_n<int>(nsl + 1);
+    p->sell_perm = A.take_n<int>(n);
+    if (p->need_adjoint) {
+        p->tsell_off = A.take_n<int>(nsl + 1);
+        p->tsell_perm = A.take_n<int>(n);
+    }
+    if (nsys == 1) carve_krylov(p, A);
+    if (p->o.m <= 64) carve_batched(p, A);
+}
+
+// Phase 2: buffers sized by the counts of the setup kernels (az_nnz,
+// atz_nnz, sell_total / tsell_total with sell_ok / tsell_ok).
+void carve_phase2(gmres_plan_s* p, Arena& A) {
+    const bool mixed = p->o.precision != GMRES_FP64;
+    if (p->R > 0) {
+        p->azci = A.take_n<int>(p->az_nnz);
+        p->azv = A.take_n<double>(p->az_nnz);
+        if (mixed) p->azv32 = A.take_n<float>(p->az_nnz);
+        if (p->need_adjoint) {
+            p->atzci = A.take_n<int>(p->atz_nnz);
+            p->atzv = A.take_n<double>(p->atz_nnz);
+        }
+    }
+    if (p->sell_ok) {
+        p->sell_col = A.take_n<short>(p->sell_total);
+        p->sell_src = A.take_n<int>(p->sell_total);
+        p->sell_v64 = A.take_n<double>(p->sell_total);
+        if (mixed) p->sell_v32 = A.take_n<float>(p->sell_total);
+    }
+    if (p->tsell_ok) {
+        p->tsell_col = A.take_n<short>(p->tsell_total);
+        p->tsell_src = A.take_n<int>(p->tsell_total);
+        p->tsell_v64 = A.take_n<double>(p->tsell_total);
+    }
+}
+
+// Temporaries while counting (Z^T, A Z, A^T, A^T Z, sliced-ELL plans) and
+// while building the fused Z^T y slots.
+size_t temps_counting(const gmres_plan_s* p) {
+    size_t t = sell_plan_temp_bytes(p->n);
+    if (p->R > 0) t = std::max({t, transpose_temp_bytes(p->R, p->znnz), az_count_temp_bytes(p->n)});
+    if (p->need_adjoint) t = std::max(t, transpose_temp_bytes(p->n, p->nnz));
+    return t;
+}
+size_t temps_slots(const gmres_plan_s* p) {
+    if (p->R == 0 || p->nsys != 1) return 0;
+    return block_slots_temp_bytes(p->n, kSlotRB, p->R, p->slots_cap);
+}
+
+struct Layout {
+    size_t p1 = 0, t1 = 0, p2 = 0, t2 = 0;
+    size_t total() const { return p1 + std::max(t1, p2 + t2); }
+};
+
+// Sizes the layout of a plan whose size fields are set: phase 2 with the
+// counts in *q when counted, else with their upper bounds.
+Layout layout_of(const gmres_plan_s* q, bool counted) {
+    gmres_plan_s* s = new gmres_plan_s();
+    s->o = q->o;
+    s->nsys = q->nsys;
+    s->n = q->n;
+    s->nnz = q->nnz;
+    s->znnz = q->znnz;
+    s->R = q->R;
+    s->need_adjoint = q->need_adjoint;
+    s->e_off_h = q->e_off_h;
+    s->NB = q->NB;
+    s->CH = q->CH;
+    Arena A;
+    A.sizing = true;
+    Layout L;
+    carve_phase1(s, A);
+    L.p1 = A.lo;
+    L.t1 = temps_counting(s);
+    if (counted) {
+        s->az_nnz = q->az_nnz;
+        s->atz_nnz = q->atz_nnz;
+        s->sell_ok = q->sell_ok;
+        s->tsell_ok = q->tsell_ok;
+        s->sell_total = q->sell_total;
+        s->tsell_total = q->tsell_total;
+    } else {
+        s->az_nnz = s->atz_nnz = az_bound(s);
+        s->sell_ok = true;
+        s->tsell_ok = s->need_adjoint != 0;
+        s->sell_total = s->tsell_total = sell_budget(s->nnz);
+    }
+    const size_t lo1 = A.lo;
+    carve_phase2(s, A);
+    L.p2 = A.lo - lo1;
+    L.t2 = temps_slots(s);
+    delete s;
+    return L;
+}
+
+// Builds the per-block deflation slots used by the fused Z^T y of the stream
+// SpMV (row blocks of kSlotRB rows).  Keeps the separate Z^T pass when a row
+// block reaches more than 64 deflation columns.
+gmres_status build_slots(gmres_plan_s* p) {
+    p->slots_rb = 0;
+    p->nslots = 0;
+    if (p->R == 0 || p->nsys != 1 || p->slots_cap == 0) return GMRES_OK;
+    int64_t ns = 0;
+    const int s = build_block_slots(p->st, p->ar, p->n, kSlotRB, p->R, p->zrp, p->zci, p->bb_ptr,
+                                    p->bb_col, p->ab_ptr, p->ab_slot, p->slots_cap, &ns, p->d_flags);
+    if (s == kStatusInval) return GMRES_OK;          // dense Z: keep the separate pass
+    CHECK(to_status(s, "deflation slots"));
+    invperm(p->st, ns, p->ab_slot, p->slot_pos);
+    p->nslots = ns;
+    p->slots_rb = kSlotRB;
+    return GMRES_OK;
+}
+
+// Zeroes and initialises the Krylov workspace; creates the host-side objects.
+gmres_status init_krylov(gmres_plan_s* p) {
+    CHECK(clear_typed(p));
+    if (p->R > 0) {
+        // Padding rows of the ELL-2 copies read as "no entry" (-1) with value 0.
         HIP_OK(hipMemsetAsync(p->azc1, 0xFF, 2 * p->ldv * sizeof(int), p->st));
         HIP_OK(hipMemsetAsync(p->azv1, 0, 2 * p->ldv * sizeof(double), p->st));
-        if (p->o.precision != GMRES_FP64) {
-            CHECK(dalloc(p, &p->azv1f, 2 * p->ldv));
-            HIP_OK(hipMemsetAsync(p->azv1f, 0, 2 * p->ldv * sizeof(float), p->st));
-        }
-        if (p->need_adjoint) {
-            CHECK(dalloc(p, &p->atzc1, 2 * p->ldv));
-            CHECK(dalloc(p, &p->atzv1, 2 * p->ldv));
+        if (p->azv1f) HIP_OK(hipMemsetAsync(p->azv1f, 0, 2 * p->ldv * sizeof(float), p->st));
+        if (p->atzc1) {
             HIP_OK(hipMemsetAsync(p->atzc1, 0xFF, 2 * p->ldv * sizeof(int), p->st));
             HIP_OK(hipMemsetAsync(p->atzv1, 0, 2 * p->ldv * sizeof(double), p->st));
         }
@@ -366,16 +555,6 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
     if (p->o.adapt_rmax > 0) {
         AdaptArgs& ad = p->adapt;
         const int rc = p->o.adapt_rmax + 1;
-        ad.rmax = p->o.adapt_rmax;
-        CHECK(dalloc(p, &ad.st, 1));
-        CHECK(dalloc(p, &ad.U, (int64_t)rc * p->ldv));
-        CHECK(dalloc(p, &ad.AU, (int64_t)rc * p->ldv));
-        CHECK(dalloc(p, &ad.T, (int64_t)rc * rc));
-        CHECK(dalloc(p, &ad.C, (int64_t)rc * rc));
-        for (double** q : {&ad.s, &ad.tcol, &ad.trow, &ad.hvec}) CHECK(dalloc(p, q, rc + 1));
-        CHECK(dalloc(p, &ad.zc, kMaxM));
-        for (double** q : {&ad.ucand, &ad.aucand, &ad.dvec}) CHECK(dalloc(p, q, p->ldv));
-        CHECK(dalloc(p, &ad.part, (int64_t)(rc + 1) * p->NB_cap));
         // Padded rows of U, AU and the candidates stay zero.
         HIP_OK(hipMemsetAsync(ad.U, 0, (size_t)rc * p->ldv * sizeof(double), p->st));
         HIP_OK(hipMemsetAsync(ad.AU, 0, (size_t)rc * p->ldv * sizeof(double), p->st));
@@ -384,12 +563,9 @@ gmres_status alloc_krylov(gmres_plan_s* p) {
         HIP_OK(hipMemsetAsync(ad.T, 0, (size_t)rc * rc * sizeof(double), p->st));
         HIP_OK(hipMemsetAsync(ad.C, 0, (size_t)rc * rc * sizeof(double), p->st));
     }
-    CHECK(dalloc(p, &p->ctrl, 1));
-    HIP_OK(hipHostMalloc((void**)&p->ctrl_h, 2 * sizeof(Ctrl), 0));
+    HIP_OK(hipHostMalloc((void**)&p->ctrl_h, 2 * sizeof(Ctrl), 0));   // pinned host snapshots
     HIP_OK(hipEventCreateWithFlags(&p->ev_cyc[0], hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&p->ev_cyc[1], hipEventDisableTiming));
-    p->cyc_cap = 1 << 16;
-    CHECK(dalloc(p, &p->cyc_k, p->cyc_cap));
     return GMRES_OK;
 }
 
@@ -663,7 +839,7 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
         CHECK(clear_typed(p));
         p->last_prec = prec;
     }
-    launch_ctrl_reset(p->st, p->ctrl, max_iters);
+    launch_ctrl_reset(p->st, p->ctrl, max_iters, p->hist_pos);
     launch_restart_init(a, b, rtol, r0_override);
     auto enqueue = [&](int c) -> gmres_status {
         const bool timed = period > 0 && c % period == 0;
@@ -693,6 +869,7 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
     HIP_OK(hipStreamSynchronize(p->st));
     HIP_OK(hipMemcpy(out, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
     if (period > 0) collect_timer(p, out->cycles);
+    p->hist_pos += out->its;   // the next run of the same solve records after these steps
     if (!finished) return fail(GMRES_EDEVICE, "solve loop did not terminate");
     return GMRES_OK;
 }
@@ -883,12 +1060,7 @@ void gmres_destroy(gmres_plan p) {
             if (p->gexec[a][b]) hipGraphExecDestroy(p->gexec[a][b]);
             if (p->graph[a][b]) hipGraphDestroy(p->graph[a][b]);
         }
-    for (void* q : p->allocs) hipFree(q);
-    for (int* q : {p->bb_ptr, p->bb_col, p->ab_ptr, p->ab_slot, p->slot_pos}) hipFree(q);
-    for (int* q : {p->sell_off, p->sell_src, p->sell_perm, p->tsell_off, p->tsell_src, p->tsell_perm})
-        hipFree(q);
-    for (short* q : {p->sell_col, p->tsell_col}) hipFree(q);
-    gm::block_free(p->block);
+    gm::block_delete(p->block);
     if (p->ctrl_h) hipHostFree(p->ctrl_h);
     for (auto e : {p->ev_cyc[0], p->ev_cyc[1], p->ev_in, p->ev_out})
         if (e) hipEventDestroy(e);
@@ -896,14 +1068,18 @@ void gmres_destroy(gmres_plan p) {
     delete p;
 }
 
-static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys_row_off_h,
+static gmres_status init_batched(gmres_plan_s* p);
+
+// Host-side checks of the setup arguments; fills the plan's size fields.
+static gmres_status check_args(gmres_plan_s* p, int32_t nsys, const int64_t* sys_row_off_h,
                                const int64_t* sys_zcol_off_h, const int32_t* rowptr,
                                const int32_t* colind, const double* vals, int64_t nnz,
                                const int32_t* z_rowptr, const int32_t* z_colind,
                                const double* z_vals, int64_t z_nnz, const gmres_opts* opts,
-                               int32_t need_adjoint, hipStream_t stream) {
-    if (nsys < 1 || !sys_row_off_h || !rowptr || !opts)
-        return fail(GMRES_EINVAL, "nsys, sys_row_off_h, rowptr and opts are required");
+                               int32_t need_adjoint, bool need_arrays) {
+    if (nsys < 1 || !sys_row_off_h || !opts)
+        return fail(GMRES_EINVAL, "nsys, sys_row_off_h and opts are required");
+    if (need_arrays && !rowptr) return fail(GMRES_EINVAL, "rowptr is required");
     p->o = *opts;
     if (p->o.m < 1 || p->o.m > kMaxM) return fail(GMRES_EINVAL, "m must be in [1, 96]");
     if (p->o.max_iters < 0 || !(p->o.rtol >= 0.0))
@@ -918,6 +1094,9 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
         return fail(GMRES_EINVAL, "adaptive deflation needs a single-system FP64 plan without adjoint");
     if (p->o.precision != GMRES_FP64 && (!(p->o.inner_rtol > 0.0) || p->o.inner_rtol >= 1.0))
         return fail(GMRES_EINVAL, "inner_rtol must be in (0, 1)");
+    if (p->o.precision != GMRES_FP64 && (p->o.max_refine < 0 || p->o.inner_max_iters < 0))
+        return fail(GMRES_EINVAL, "max_refine and inner_max_iters must be >= 0");
+    if (p->o.num_blocks < 0 || p->o.num_blocks > 2048) return fail(GMRES_EINVAL, "num_blocks must be in [0, 2048]");
     if (p->o.spmv_lanes != 0 && p->o.spmv_lanes != -256 && p->o.spmv_lanes != -128 &&
         p->o.spmv_lanes != kSell &&
         (p->o.spmv_lanes < 1 || p->o.spmv_lanes > 64 || (p->o.spmv_lanes & (p->o.spmv_lanes - 1))))
@@ -941,13 +1120,43 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     if (p->o.adapt_rmax > 0 && p->R > 0)
         return fail(GMRES_EINVAL, "adaptive deflation is not combined with a fixed deflation basis Z");
     p->znnz = p->R > 0 ? z_nnz : 0;
-    if (p->n >= INT32_MAX || nnz < 0 || nnz >= INT32_MAX || p->znnz >= INT32_MAX)
+    if (p->n >= INT32_MAX || nnz < 0 || nnz >= INT32_MAX || p->znnz < 0 || p->znnz >= INT32_MAX)
         return fail(GMRES_EINVAL, "sizes exceed the int32 CSR range");
-    if (nnz > 0 && (!colind || !vals)) return fail(GMRES_EINVAL, "colind/vals required");
-    if (p->R > 0 && (!z_rowptr || (p->znnz > 0 && (!z_colind || !z_vals))))
+    if (need_arrays && nnz > 0 && (!colind || !vals)) return fail(GMRES_EINVAL, "colind/vals required");
+    if (need_arrays && p->R > 0 && (!z_rowptr || (p->znnz > 0 && (!z_colind || !z_vals))))
         return fail(GMRES_EINVAL, "Z arrays required when r > 0");
     p->need_adjoint = need_adjoint ? 1 : 0;
     if (p->need_adjoint && nsys != 1) return fail(GMRES_EINVAL, "the adjoint needs a single-system plan");
+    p->e_off_h.assign(nsys + 1, 0);
+    for (int s = 0; s < nsys; ++s) {
+        const int64_t r = p->zcol_off[s + 1] - p->zcol_off[s];
+        p->e_off_h[s + 1] = p->e_off_h[s] + r * r;
+    }
+    p->NB = p->o.num_blocks > 0 ? p->o.num_blocks
+                                : (int)std::min<int64_t>(std::max<int64_t>((p->n + kWG - 1) / kWG, 1), 1024);
+    return GMRES_OK;
+}
+
+static gmres_status short_of(size_t need) {
+    g_ws_required = need;
+    return fail(GMRES_EWORKSPACE, "workspace too small: " + std::to_string(need) + " bytes needed");
+}
+
+static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys_row_off_h,
+                               const int64_t* sys_zcol_off_h, const int32_t* rowptr,
+                               const int32_t* colind, const double* vals, int64_t nnz,
+                               const int32_t* z_rowptr, const int32_t* z_colind,
+                               const double* z_vals, int64_t z_nnz, const gmres_opts* opts,
+                               int32_t need_adjoint, void* workspace, size_t workspace_bytes,
+                               hipStream_t stream) {
+    CHECK(check_args(p, nsys, sys_row_off_h, sys_zcol_off_h, rowptr, colind, vals, nnz, z_rowptr,
+                     z_colind, z_vals, z_nnz, opts, need_adjoint, true));
+    const Layout est = layout_of(p, false);
+    if (!workspace || workspace_bytes < est.p1 + est.t1) return short_of(est.total());
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(GMRES_EINVAL, "workspace must be 256-byte aligned");
+    p->ar.base = reinterpret_cast<uintptr_t>(workspace);
+    p->ar.cap = workspace_bytes;
 
     HIP_OK(hipGetDevice(&p->device));
     p->user_stream = stream;
@@ -956,34 +1165,23 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     HIP_OK(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
     CHECK(enter(p));
 
+    carve_phase1(p, p->ar);
+    if (p->ar.short_) return short_of(est.total());
+    const size_t lo1 = p->ar.lo;
+
     // Plan-owned copies of A and Z.
     const int64_t n = p->n;
-    CHECK(dalloc(p, &p->rowptr, n + 1));
-    CHECK(dalloc(p, &p->colind, std::max<int64_t>(nnz, 1)));
-    CHECK(dalloc(p, &p->vals, std::max<int64_t>(nnz, 1)));
     HIP_OK(hipMemcpyAsync(p->rowptr, rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, p->st));
     if (nnz > 0) {
         HIP_OK(hipMemcpyAsync(p->colind, colind, nnz * sizeof(int), hipMemcpyDeviceToDevice, p->st));
         HIP_OK(hipMemcpyAsync(p->vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, p->st));
     }
     if (p->R > 0) {
-        CHECK(dalloc(p, &p->zrp, n + 1));
-        CHECK(dalloc(p, &p->zci, std::max<int64_t>(p->znnz, 1)));
-        CHECK(dalloc(p, &p->zv, std::max<int64_t>(p->znnz, 1)));
         HIP_OK(hipMemcpyAsync(p->zrp, z_rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, p->st));
         if (p->znnz > 0) {
             HIP_OK(hipMemcpyAsync(p->zci, z_colind, p->znnz * sizeof(int), hipMemcpyDeviceToDevice, p->st));
             HIP_OK(hipMemcpyAsync(p->zv, z_vals, p->znnz * sizeof(double), hipMemcpyDeviceToDevice, p->st));
         }
-    }
-    CHECK(dalloc(p, &p->d_row_off, nsys + 1));
-    CHECK(dalloc(p, &p->d_zcol_off, nsys + 1));
-    CHECK(dalloc(p, &p->d_e_off, nsys + 1));
-    CHECK(dalloc(p, &p->d_flags, 4));
-    p->e_off_h.assign(nsys + 1, 0);
-    for (int s = 0; s < nsys; ++s) {
-        const int64_t r = p->zcol_off[s + 1] - p->zcol_off[s];
-        p->e_off_h[s + 1] = p->e_off_h[s] + r * r;
     }
     HIP_OK(hipMemcpyAsync(p->d_row_off, p->row_off.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, p->st));
     HIP_OK(hipMemcpyAsync(p->d_zcol_off, p->zcol_off.data(), (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, p->st));
@@ -993,67 +1191,89 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
                  p->rowptr, p->colind, p->vals, p->zrp, p->zci, p->zv};
     CHECK(to_status(setup_validate(sa, p->d_flags), "input validation"));
 
-    // Z^T and the coarse operator.
+    // Counting: Z^T, A Z, A^T, A^T Z, sliced-ELL plans (temporaries T1).
     if (p->R > 0) {
-        CHECK(dalloc(p, &p->ztrp, p->R + 1));
-        CHECK(dalloc(p, &p->ztci, std::max<int64_t>(p->znnz, 1)));
-        CHECK(dalloc(p, &p->ztperm, std::max<int64_t>(p->znnz, 1)));
-        CHECK(dalloc(p, &p->ztv, std::max<int64_t>(p->znnz, 1)));
-        CHECK(to_status(build_transpose(p->st, n, p->R, p->znnz, p->zrp, p->zci, p->ztrp, p->ztci,
+        CHECK(to_status(build_transpose(p->st, p->ar, n, p->R, p->znnz, p->zrp, p->zci, p->ztrp, p->ztci,
                                         p->ztperm), "Z transpose"));
         gather_values(p->st, p->znnz, p->ztperm, p->zv, p->ztv);
-        CHECK(dalloc(p, &p->zc1, n));
-        CHECK(dalloc(p, &p->zv1, n));
         ell1_build(p->st, n, p->zrp, p->zci, p->zv, p->zc1, p->zv1, nullptr);
         const int maxrow = zt_max_row(p->st, p->R, p->ztrp, p->d_flags);
-        p->CH = 2048;
         p->MC = std::max(1, (maxrow + p->CH - 1) / p->CH);
-        CHECK(build_az(p, p->rowptr, p->colind, p->vals, &p->azrp, &p->azci, &p->azv, &p->az_nnz));
-        CHECK(dalloc(p, &p->E, std::max<int64_t>(p->e_off_h[nsys], 1)));
-        CHECK(dalloc(p, &p->Einv, std::max<int64_t>(p->e_off_h[nsys], 1)));
-    }
-    if (p->o.precision != GMRES_FP64) {
-        CHECK(dalloc(p, &p->vals32, std::max<int64_t>(nnz, 1)));
-        if (p->R > 0) CHECK(dalloc(p, &p->azv32, std::max<int64_t>(p->az_nnz, 1)));
+        const int s = az_count(sa, p->ar, p->rowptr, p->colind, p->azrp, &p->az_nnz, p->d_flags);
+        if (s == kStatusInval)
+            return fail(GMRES_EINVAL, "a row of A*Z reaches more than 64 deflation columns");
+        CHECK(to_status(s, "A*Z"));
     }
     if (p->need_adjoint) {
-        CHECK(dalloc(p, &p->trp, n + 1));
-        CHECK(dalloc(p, &p->tci, std::max<int64_t>(nnz, 1)));
-        CHECK(dalloc(p, &p->tperm, std::max<int64_t>(nnz, 1)));
-        CHECK(dalloc(p, &p->tv, std::max<int64_t>(nnz, 1)));
-        CHECK(to_status(build_transpose(p->st, n, n, nnz, p->rowptr, p->colind, p->trp, p->tci,
+        CHECK(to_status(build_transpose(p->st, p->ar, n, n, nnz, p->rowptr, p->colind, p->trp, p->tci,
                                         p->tperm), "A transpose"));
         gather_values(p->st, nnz, p->tperm, p->vals, p->tv);
-        if (p->R > 0)
-            CHECK(build_az(p, p->trp, p->tci, p->tv, &p->atzrp, &p->atzci, &p->atzv, &p->atz_nnz));
-    }
-    // Sliced ELL copies for the SpMV (values filled by refresh_values).
-    {
-        int* tmp_src = nullptr;
-        CHECK(to_status(sell_build(p->st, n, p->rowptr, p->colind, &p->sell_off, &p->sell_perm,
-                                   &p->sell_col, &tmp_src, &p->sell_total, &p->sell_wuni),
-                        "sliced ELL"));
-        p->sell_src = tmp_src;
-        p->sell_wmax = max_row_len(p->st, n, p->rowptr, p->d_flags);
-        CHECK(dalloc(p, &p->sell_v64, std::max<int64_t>(p->sell_total, 1)));
-        if (p->o.precision != GMRES_FP64) CHECK(dalloc(p, &p->sell_v32, std::max<int64_t>(p->sell_total, 1)));
-        if (p->need_adjoint) {
-            CHECK(to_status(sell_build(p->st, n, p->trp, p->tci, &p->tsell_off, &p->tsell_perm,
-                                       &p->tsell_col, &p->tsell_src, &p->tsell_total, &p->tsell_wuni),
-                            "sliced ELL (A^T)"));
-            CHECK(dalloc(p, &p->tsell_v64, std::max<int64_t>(p->tsell_total, 1)));
-            p->tsell_wmax = max_row_len(p->st, n, p->trp, p->d_flags);
+        if (p->R > 0) {
+            const int s = az_count(sa, p->ar, p->trp, p->tci, p->atzrp, &p->atz_nnz, p->d_flags);
+            if (s == kStatusInval)
+                return fail(GMRES_EINVAL, "a row of A^T*Z reaches more than 64 deflation columns");
+            CHECK(to_status(s, "A^T*Z"));
         }
     }
+    CHECK(to_status(sell_plan(p->st, p->ar, n, p->rowptr, p->sell_off, p->sell_perm, sell_budget(nnz),
+                              &p->sell_ok, &p->sell_sorted, &p->sell_total, &p->sell_wuni),
+                    "sliced ELL"));
+    if (p->need_adjoint)
+        CHECK(to_status(sell_plan(p->st, p->ar, n, p->trp, p->tsell_off, p->tsell_perm, sell_budget(nnz),
+                                  &p->tsell_ok, &p->tsell_sorted, &p->tsell_total, &p->tsell_wuni),
+                        "sliced ELL (A^T)"));
+    if (p->ar.short_) return short_of(est.total());
+
+    // The exact size, now that the counts are known.
+    const Layout ex = layout_of(p, true);
+    if (ex.total() > workspace_bytes) return short_of(ex.total());
+    carve_phase2(p, p->ar);
+    if (p->ar.short_ || p->ar.lo - lo1 != ex.p2) return short_of(ex.total());
+
+    // Sliced-ELL patterns (dropped when a column offset does not fit 16 bits).
+    if (p->sell_ok) {
+        bool ok = false;
+        CHECK(to_status(sell_fill_pattern(p->st, n, p->rowptr, p->colind, p->sell_off,
+                                          p->sell_sorted ? p->sell_perm : nullptr, p->sell_col,
+                                          p->sell_src, p->d_flags, &ok), "sliced ELL"));
+        if (!ok) p->sell_ok = false;
+    }
+    if (p->tsell_ok) {
+        bool ok = false;
+        CHECK(to_status(sell_fill_pattern(p->st, n, p->trp, p->tci, p->tsell_off,
+                                          p->tsell_sorted ? p->tsell_perm : nullptr, p->tsell_col,
+                                          p->tsell_src, p->d_flags, &ok), "sliced ELL (A^T)"));
+        if (!ok) p->tsell_ok = false;
+    }
+    if (!p->sell_ok) {
+        p->sell_col = nullptr;
+        p->sell_src = nullptr;
+        p->sell_total = 0;
+        p->sell_wuni = 0;
+    }
+    if (!p->sell_sorted) p->sell_perm = nullptr;
+    if (!p->tsell_ok) {
+        p->tsell_col = nullptr;
+        p->tsell_src = nullptr;
+        p->tsell_total = 0;
+        p->tsell_wuni = 0;
+    }
+    if (!p->tsell_sorted) p->tsell_perm = nullptr;
+    p->sell_wmax = max_row_len(p->st, n, p->rowptr, p->d_flags);
+    if (p->need_adjoint) p->tsell_wmax = max_row_len(p->st, n, p->trp, p->d_flags);
     CHECK(refresh_values(p));
 
     if (p->o.spmv_lanes == kSell && !p->sell_col)
-        return fail(GMRES_EINVAL, "spmv_lanes = -64 needs column offsets col - row within +-32767");
+        return fail(GMRES_EINVAL, "spmv_lanes = -64 needs a sliced-ELL copy (column offsets col - row "
+                                  "within +-32767, padding within budget)");
     p->L = p->o.spmv_lanes != 0 ? p->o.spmv_lanes
                                 : default_lanes(n, nnz, p->sell_col != nullptr, p->sell_total);
-    p->NB = p->o.num_blocks > 0 ? p->o.num_blocks
-                                : (int)std::min<int64_t>(std::max<int64_t>((n + kWG - 1) / kWG, 1), 1024);
-    if (nsys == 1) CHECK(alloc_krylov(p));
+    if (nsys == 1) {
+        CHECK(build_slots(p));
+        CHECK(init_krylov(p));
+        if (!(p->block = gm::block_new())) return fail(GMRES_EINVAL, "host allocation of the plan failed");
+    }
+    if (p->bV) CHECK(init_batched(p));
     p->batch_wg = p->o.batch_wg > 0 ? p->o.batch_wg : 256;
     p->batch_L = p->o.batch_lanes > 0 ? p->o.batch_lanes : 8;
     HIP_OK(hipStreamSynchronize(p->st));
@@ -1061,18 +1281,34 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     return GMRES_OK;
 }
 
+size_t gmres_workspace_bytes(int32_t nsys, const int64_t* sys_row_off_h, const int64_t* sys_zcol_off_h,
+                             int64_t nnz, int64_t z_nnz, const gmres_opts* opts, int32_t need_adjoint) {
+    gmres_plan_s* p = new (std::nothrow) gmres_plan_s();
+    if (!p) return 0;
+    size_t bytes = 0;
+    if (check_args(p, nsys, sys_row_off_h, sys_zcol_off_h, nullptr, nullptr, nullptr, nnz, nullptr,
+                   nullptr, nullptr, z_nnz, opts, need_adjoint, false) == GMRES_OK)
+        bytes = layout_of(p, false).total();
+    delete p;
+    return bytes;
+}
+
+size_t gmres_workspace_required(void) { return g_ws_required; }
+
 gmres_status gmres_setup(gmres_plan* out, int32_t nsys, const int64_t* sys_row_off_h,
                          const int64_t* sys_zcol_off_h, const int32_t* rowptr,
                          const int32_t* colind, const double* vals, int64_t nnz,
                          const int32_t* z_rowptr, const int32_t* z_colind, const double* z_vals,
                          int64_t z_nnz, const gmres_opts* opts, int32_t need_adjoint,
-                         hipStream_t stream) {
+                         void* workspace, size_t workspace_bytes, hipStream_t stream) {
     if (!out) return fail(GMRES_EINVAL, "out is NULL");
     *out = nullptr;
+    g_ws_required = 0;
     gmres_plan_s* p = new (std::nothrow) gmres_plan_s();
-    if (!p) return fail(GMRES_ENOMEM, "host allocation failed");
+    if (!p) return fail(GMRES_EINVAL, "host allocation of the plan failed");
     gmres_status s = setup_impl(p, nsys, sys_row_off_h, sys_zcol_off_h, rowptr, colind, vals, nnz,
-                                z_rowptr, z_colind, z_vals, z_nnz, opts, need_adjoint, stream);
+                                z_rowptr, z_colind, z_vals, z_nnz, opts, need_adjoint, workspace,
+                                workspace_bytes, stream);
     if (s != GMRES_OK) {
         std::string msg = g_last_error;
         gmres_destroy(p);
@@ -1089,22 +1325,6 @@ gmres_status gmres_set_stream(gmres_plan p, hipStream_t stream) {
     return GMRES_OK;
 }
 
-static gmres_status ensure_history(gmres_plan_s* p, int64_t need) {
-    if (!p->o.record_history) return GMRES_OK;
-    need = std::max<int64_t>(need, 1);
-    if (p->hist_cap >= need) return GMRES_OK;
-    CHECK(dalloc(p, &p->hist, need));
-    p->hist_cap = need;
-    for (int a = 0; a < 2; ++a)     // graphs hold the old history pointer
-        for (int b = 0; b < 3; ++b) {
-            if (p->gexec[a][b]) hipGraphExecDestroy(p->gexec[a][b]);
-            if (p->graph[a][b]) hipGraphDestroy(p->graph[a][b]);
-            p->gexec[a][b] = nullptr;
-            p->graph[a][b] = nullptr;
-        }
-    return GMRES_OK;
-}
-
 gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double* x,
                          gmres_info* info_h) {
     if (!p || !b || !x) return fail(GMRES_EINVAL, "plan, b and x are required");
@@ -1113,17 +1333,14 @@ gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double
     const auto t0 = std::chrono::steady_clock::now();
     CHECK(enter(p));
     gmres_info info{};
-    const int64_t hist_need = p->o.precision == GMRES_FP64
-                                  ? p->o.max_iters
-                                  : p->o.inner_max_iters;
-    CHECK(ensure_history(p, std::min<int64_t>(hist_need, int64_t(1) << 26)));
+    p->hist_pos = 0;
     p->timer.reset();
     if (p->o.precision == GMRES_FP64) {
         CHECK(solve_f64(p, 0, b, x0, x, p->o.rtol, p->o.r0_norm_override, p->o.max_iters, &info));
     } else {
         CHECK(solve_mixed(p, b, x0, x, &info));
     }
-    p->hist_len = info.iters;
+    p->hist_len = std::min<int64_t>(info.iters, p->hist_cap);
     double nrm = 0;
     CHECK(true_residual(p, b, x, &nrm));
     info.rel_res_true = info.rho0 > 0 ? nrm / info.rho0 : 0.0;
@@ -1134,8 +1351,9 @@ gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double
     return (gmres_status)info.status;
 }
 
-gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const double* B,
-                               const double* X0, double* X, gmres_info* info_h) {
+static gmres_status solve_block_impl(gmres_plan p, int32_t k, int32_t m_block, const double* B,
+                                     const double* X0, double* X, void* work, size_t work_bytes,
+                                     gmres_info* info_h) {
     if (!p || !B || !X) return fail(GMRES_EINVAL, "plan, B and X are required");
     if (p->nsys != 1) return fail(GMRES_EINVAL, "gmres_solve_block needs a single-system plan");
     if (p->R > 0 || p->o.adapt_rmax > 0)
@@ -1143,17 +1361,15 @@ gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const d
     if (k < 1 || k > 16) return fail(GMRES_EINVAL, "k must be in [1, 16]");
     if (m_block < 1 || m_block > gm::kBlockStepsMax) return fail(GMRES_EINVAL, "m_block must be in [1, 16]");
     if (X == B) return fail(GMRES_EINVAL, "X must not alias B");
+    const size_t need = gm::block_workspace_bytes(p->n, m_block);
+    if (!work || work_bytes < need) {
+        g_ws_required = need;
+        return fail(GMRES_EWORKSPACE, "block workspace too small: " + std::to_string(need) + " bytes needed");
+    }
+    if (reinterpret_cast<uintptr_t>(work) & 255) return fail(GMRES_EINVAL, "block workspace must be 256-byte aligned");
     const auto t0 = std::chrono::steady_clock::now();
     CHECK(enter(p));
-    if (p->block && p->block_m < m_block) {
-        HIP_OK(hipStreamSynchronize(p->st));
-        gm::block_free(p->block);
-        p->block = nullptr;
-    }
-    if (!p->block) {
-        CHECK(to_status(gm::block_alloc(&p->block, p->st, p->n, m_block), "block workspace"));
-        p->block_m = m_block;
-    }
+    CHECK(to_status(gm::block_bind(p->block, work, work_bytes, p->st, p->n, m_block), "block workspace"));
     // Timing (set_timing > 0): every block kernel launch carries its events.
     struct Hook final : gm::BlockTimer {
         gmres_plan_s* p;
@@ -1205,6 +1421,17 @@ gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const d
     return (gmres_status)info.status;
 }
 
+size_t gmres_block_workspace_bytes(gmres_plan p, int32_t m_block) {
+    if (!p || m_block < 1 || m_block > gm::kBlockStepsMax) return 0;
+    return gm::block_workspace_bytes(p->n, m_block);
+}
+
+gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const double* B,
+                               const double* X0, double* X, void* work, size_t work_bytes,
+                               gmres_info* info_h) {
+    return solve_block_impl(p, k, m_block, B, X0, X, work, work_bytes, info_h);
+}
+
 gmres_status gmres_adjoint(gmres_plan p, const double* x, const double* grad_x, double* grad_b,
                            double* grad_vals, gmres_info* info_h) {
     if (!p || !x || !grad_x) return fail(GMRES_EINVAL, "plan, x and grad_x are required");
@@ -1212,6 +1439,7 @@ gmres_status gmres_adjoint(gmres_plan p, const double* x, const double* grad_x, 
     const auto t0 = std::chrono::steady_clock::now();
     CHECK(enter(p));
     gmres_info info{};
+    p->hist_pos = 0;
     p->timer.reset();
     CHECK(solve_f64(p, 1, grad_x, nullptr, p->dvec, p->o.rtol, 0.0, p->o.max_iters, &info));
     if (grad_b) launch_copy(p->st, p->dvec, grad_b, p->n);
@@ -1273,17 +1501,9 @@ static void drop_graphs(gmres_plan_s* p) {
         }
 }
 
-static gmres_status batch_alloc(gmres_plan_s* p) {
-    if (p->bV) return GMRES_OK;
+static gmres_status init_batched(gmres_plan_s* p) {
     const int ns = p->nsys;
     const int m = p->o.m;
-    CHECK(dalloc(p, &p->bV, (int64_t)(m + 1) * p->n));
-    CHECK(dalloc(p, &p->bW, 3 * p->n));
-    CHECK(dalloc(p, &p->border, ns));
-    CHECK(dalloc(p, &p->bticket, 1));
-    CHECK(dalloc(p, &p->bout_i, 3 * (int64_t)ns));
-    CHECK(dalloc(p, &p->bout_d, 4 * (int64_t)ns + ns));
-    CHECK(dalloc(p, &p->d_v_off, ns));
     // Largest systems first: order by nnz, then rows.
     std::vector<int32_t> rp_at(ns + 1);
     for (int s = 0; s <= ns; ++s)
@@ -1353,12 +1573,13 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
     if (!p || !b || !x) return fail(GMRES_EINVAL, "plan, b and x are required");
     if (p->o.m > 64) return fail(GMRES_EINVAL, "the batched solver supports m <= 64");
     if (x == b) return fail(GMRES_EINVAL, "x must not alias b");
+    if (!p->bV) return fail(GMRES_EINVAL, "the batched solver supports m <= 64");
     const auto t0 = std::chrono::steady_clock::now();
     CHECK(enter(p));
-    CHECK(batch_alloc(p));
     CHECK(run_batched(p, b, x0, x, p->o.max_iters, p->batch_wg, p->batch_L));
     double* nr = p->bout_d + 4 * (int64_t)p->nsys;
     launch_seg_resid(p->st, p->nsys, p->d_row_off, p->rowptr, p->colind, p->vals, x, b, nr);
+    if (p->nsys == 1) p->last_prec = -1;   // the shared basis (and its padding) is cleared before the next solve
     const int ns = p->nsys;
     std::vector<int64_t> oi(3 * (size_t)ns);
     std::vector<double> od(5 * (size_t)ns);
@@ -1440,18 +1661,12 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
         p->NB = bestNB;
         CHECK(clear_typed(p));
         p->last_prec = kPrecF64;
-        CHECK(ensure_slots(p));
         drop_graphs(p);
     } else {
         // Batched: workgroup size and SpMV lanes, timed on one restart cycle.
-        CHECK(batch_alloc(p));
-        double* bb = p->bW;   // right-hand side of ones in the first work vector block
-        double* xx = nullptr;
-        CHECK(dalloc(p, &xx, p->n));
-        double* ones = nullptr;
-        CHECK(dalloc(p, &ones, p->n));
+        double* xx = p->btune_x;
+        double* ones = p->btune_b;
         launch_fill(p->st, ones, p->n, 1.0);
-        (void)bb;
         double best = 1e30;
         for (int wg : {256, 512}) {
             for (int L : {4, 8, 16}) {

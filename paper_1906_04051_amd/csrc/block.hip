@@ -529,52 +529,62 @@ struct BlockWork {
     double* Xp() const { return panels + (int64_t)(m + 3) * ps; }
 };
 
-void block_free(BlockWork* w) {
-    if (!w) return;
-    for (double* q : {w->panels, w->part, w->p2, w->C, w->Csum, w->R1, w->R, w->Rinv, w->nb2, w->Cy,
-                      w->npart, w->nsq, w->lsbuf, w->S})
-        hipFree(q);
-    hipFree(w->flag);
-    hipFree(w->imap);
-    delete w;
+BlockWork* block_new() { return new (std::nothrow) BlockWork(); }
+void block_delete(BlockWork* w) { delete w; }
+
+namespace {
+
+int64_t ls_entries() {
+    return (int64_t)kLdH * kBlockStepsMax * kBW + (int64_t)kBlockStepsMax * kBW * (kBW + 1) +
+           (int64_t)kBlockStepsMax * kBW + (int64_t)kLdH * kBW + 2 * kBW;
 }
 
-int block_alloc(BlockWork** out, hipStream_t st, int64_t n, int m) {
-    BlockWork* w = new (std::nothrow) BlockWork();
-    if (!w) return kStatusNoMem;
+// Carves the block workspace for n rows and m block steps from an arena
+// (sizing or real).
+void block_carve(BlockWork* w, Arena& ar, int64_t n, int m) {
     w->n = n;
     w->n_pad = (n + 63) / 64 * 64;
     w->ps = w->n_pad * kBW;
     w->m = m;
     const int64_t nbmax = m + 2;
-    const int64_t lsn = (int64_t)kLdH * kBlockStepsMax * kBW + (int64_t)kBlockStepsMax * kBW * (kBW + 1) +
-                        (int64_t)kBlockStepsMax * kBW + (int64_t)kLdH * kBW + 2 * kBW;
-    bool ok = hipMalloc(&w->panels, (m + 4) * w->ps * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->part, (int64_t)kDotGrid * nbmax * kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->p2, (int64_t)kSplit * nbmax * kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->C, nbmax * kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->Csum, nbmax * kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->R1, kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->R, kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->Rinv, kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->nb2, kBW * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->Cy, (int64_t)(m + 1) * kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->npart, (int64_t)kNormGrid * kBW * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->nsq, kBW * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->lsbuf, lsn * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->S, kPan * sizeof(double)) == hipSuccess &&
-              hipMalloc(&w->flag, sizeof(int)) == hipSuccess &&
-              hipMalloc(&w->imap, 3 * kBW * sizeof(int)) == hipSuccess;
-    if (!ok) {
-        block_free(w);
-        return kStatusNoMem;
-    }
-    // Panel rows beyond n stay zero for the whole life of the plan.
-    if (hipMemsetAsync(w->panels, 0, (m + 4) * w->ps * sizeof(double), st) != hipSuccess ||
-        hipMemsetAsync(w->lsbuf, 0, lsn * sizeof(double), st) != hipSuccess) {
-        block_free(w);
+    w->panels = ar.take_n<double>((int64_t)(m + 4) * w->ps);
+    w->part = ar.take_n<double>((int64_t)kDotGrid * nbmax * kPan);
+    w->p2 = ar.take_n<double>((int64_t)kSplit * nbmax * kPan);
+    w->C = ar.take_n<double>(nbmax * kPan);
+    w->Csum = ar.take_n<double>(nbmax * kPan);
+    w->R1 = ar.take_n<double>(kPan);
+    w->R = ar.take_n<double>(kPan);
+    w->Rinv = ar.take_n<double>(kPan);
+    w->nb2 = ar.take_n<double>(kBW);
+    w->Cy = ar.take_n<double>((int64_t)(m + 1) * kPan);
+    w->npart = ar.take_n<double>((int64_t)kNormGrid * kBW);
+    w->nsq = ar.take_n<double>(kBW);
+    w->lsbuf = ar.take_n<double>(ls_entries());
+    w->S = ar.take_n<double>(kPan);
+    w->flag = ar.take_n<int>(1);
+    w->imap = ar.take_n<int>(3 * kBW);
+}
+
+}  // namespace
+
+size_t block_workspace_bytes(int64_t n, int m) {
+    BlockWork w;
+    Arena ar;
+    ar.sizing = true;
+    block_carve(&w, ar, n, m);
+    return ar.peak;
+}
+
+int block_bind(BlockWork* w, void* mem, size_t bytes, hipStream_t st, int64_t n, int m) {
+    Arena ar;
+    ar.base = reinterpret_cast<uintptr_t>(mem);
+    ar.cap = bytes;
+    block_carve(w, ar, n, m);
+    if (ar.short_ || (ar.base & 255) != 0) return kStatusNoMem;
+    // Panel rows beyond n and columns beyond k stay zero through the solve.
+    if (hipMemsetAsync(w->panels, 0, (size_t)(m + 4) * w->ps * sizeof(double), st) != hipSuccess ||
+        hipMemsetAsync(w->lsbuf, 0, (size_t)ls_entries() * sizeof(double), st) != hipSuccess)
         return kStatusDevice;
-    }
     double* q = w->lsbuf;
     w->ls.H = q;
     q += (int64_t)kLdH * kBlockStepsMax * kBW;
@@ -587,7 +597,6 @@ int block_alloc(BlockWork** out, hipStream_t st, int64_t n, int m) {
     w->ls.rho0 = q;
     q += kBW;
     w->ls.est = q;
-    *out = w;
     return kStatusOk;
 }
 

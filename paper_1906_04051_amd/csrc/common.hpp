@@ -35,7 +35,8 @@ struct Ctrl {
     double inner_scale;   // mixed precision: ||r|| of the current refinement
     int32_t est_conv;     // some cycle's estimate |gamma_{k+1}| met the target
     int32_t pad32;
-    int64_t pad[3];
+    int64_t hist_base;    // history index of this run's first step (earlier runs of the same solve)
+    int64_t pad[2];
 };
 
 // A kernel returns at once when the solve (gate 1) or the current cycle

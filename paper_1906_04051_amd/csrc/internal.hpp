@@ -21,7 +21,49 @@ constexpr int kStatusInval = -1;
 constexpr int kStatusSingular = -2;
 constexpr int kStatusNonFinite = -3;
 constexpr int kStatusDevice = -4;
-constexpr int kStatusNoMem = -5;
+constexpr int kStatusNoMem = -5;      // workspace too small (gmres_status EWORKSPACE)
+
+// Device memory carved out of one caller-owned workspace: persistent buffers
+// grow from the bottom, the temporaries of a setup step from the top (given
+// back with release(mark)).  Nothing is allocated.  A request that does not
+// fit returns nullptr and sets `short_`; `peak` is the largest extent any
+// request reached (what the workspace would have needed so far).  With
+// sizing = true no memory stands behind the arena: requests always succeed,
+// the returned addresses are not usable, and `peak` measures a layout.
+struct Arena {
+    uintptr_t base = 0;
+    size_t cap = 0, lo = 0, hi = 0, peak = 0;
+    bool sizing = false;
+    bool short_ = false;
+    static size_t round(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); }
+    void* take(size_t bytes) {
+        bytes = round(bytes);
+        peak = std::max(peak, lo + bytes + hi);
+        if (!sizing && lo + bytes + hi > cap) {
+            short_ = true;
+            return nullptr;
+        }
+        void* q = reinterpret_cast<void*>(base + lo);
+        lo += bytes;
+        return q;
+    }
+    void* temp(size_t bytes) {
+        bytes = round(bytes);
+        peak = std::max(peak, lo + hi + bytes);
+        if (!sizing && lo + hi + bytes > cap) {
+            short_ = true;
+            return nullptr;
+        }
+        hi += bytes;
+        return reinterpret_cast<void*>(base + cap - hi);
+    }
+    template <typename T>
+    T* take_n(int64_t count) { return static_cast<T*>(take((size_t)std::max<int64_t>(count, 1) * sizeof(T))); }
+    template <typename T>
+    T* temp_n(int64_t count) { return static_cast<T*>(temp((size_t)std::max<int64_t>(count, 1) * sizeof(T))); }
+    size_t mark() const { return hi; }
+    void release(size_t m) { hi = m; }
+};
 
 // Precision of one solve engine.
 constexpr int kPrecF64 = 0;   // FP64 values, basis, vectors and accumulation
@@ -161,7 +203,7 @@ void launch_spmv_f32(hipStream_t st, int L, int NB, int n, const int* rp, const 
 void launch_scale_to_f32(hipStream_t st, int NB, int n, const double* r, const double* nrm2,
                          float* out);
 void launch_axpy_norm(hipStream_t st, int NB, int n, const double* nrm2, const double* d, double* x);
-void launch_ctrl_reset(hipStream_t st, Ctrl* c, int64_t max_iters);
+void launch_ctrl_reset(hipStream_t st, Ctrl* c, int64_t max_iters, int64_t hist_base);
 void launch_fill(hipStream_t st, double* p, int64_t n, double v);
 void launch_copy(hipStream_t st, const double* a, double* b, int64_t n);
 
@@ -179,11 +221,21 @@ struct SetupArgs {
     const double* zv;
 };
 int setup_validate(const SetupArgs& a, int* d_flags);       // returns a status
-int build_transpose(hipStream_t st, int64_t nrows, int64_t ncols, int64_t nnz, const int* rowptr,
-                    const int* colind, int* trowptr, int* tcolind, int* tperm);
+// Exclusive scan of count ints into out (out[count] is not written); temps
+// from `ar`; *total (host) = the int64 sum of all inputs.  The int32 outputs
+// are meaningful only when *total < 2^31.
+int scan_i32(hipStream_t st, Arena& ar, const int* in, int* out, int64_t count, int64_t* total);
+// CSR transpose (stable: rows of the transpose in increasing original row);
+// tperm[q] = original entry of transposed entry q.  Temporaries from `ar`.
+int build_transpose(hipStream_t st, Arena& ar, int64_t nrows, int64_t ncols, int64_t nnz,
+                    const int* rowptr, const int* colind, int* trowptr, int* tcolind, int* tperm);
+size_t transpose_temp_bytes(int64_t ncols, int64_t nnz);
 void gather_values(hipStream_t st, int64_t nnz, const int* perm, const double* src, double* dst);
-int az_count(const SetupArgs& a, const int* rowptr, const int* colind, int* az_rowptr,
-             int64_t* az_nnz);
+// Row pointer of the compact A Z (n + 1) and its entry count; kStatusInval
+// when a row reaches more than kAzRowMax deflation columns.
+int az_count(const SetupArgs& a, Arena& ar, const int* rowptr, const int* colind, int* az_rowptr,
+             int64_t* az_nnz, int* d_flags);
+size_t az_count_temp_bytes(int64_t n);
 void az_fill(const SetupArgs& a, const int* rowptr, const int* colind, const double* vals,
              const int* az_rowptr, int* az_colind, double* az_vals);
 void build_coarse(const SetupArgs& a, const int* ztrp, const int* ztci, const double* ztv,
@@ -195,10 +247,19 @@ void to_f32(hipStream_t st, int64_t n, const double* src, float* dst);
 void grad_vals(hipStream_t st, int64_t n, const int* rowptr, const int* colind, const double* lam,
                const double* x, double* g);
 int zt_max_row(hipStream_t st, int R, const int* ztrp, int* d_tmp);
-// Sliced ELL (64-row slices, rows optionally sorted within 256-row blocks;
-// *perm NULL when not) of a CSR matrix; buffers hipMalloc'ed here.
-int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
-               int** perm, short** scol, int** src, int64_t* total, int* wuni);
+// Sliced ELL (64-row slices, rows optionally sorted within 256-row blocks).
+// sell_plan: slice offsets into off (nsl + 1 ints), the sorted row order into
+// perm (n ints) and *sorted = whether it is kept, the entry count *total
+// (padding included) and *wuni (uniform width, 0 if not).  *usable = false
+// when the copy would hold more than `budget` entries or 2^31 or more (the
+// plan then uses the CSR kernels).
+int sell_plan(hipStream_t st, Arena& ar, int64_t n, const int* rowptr, int* off, int* perm,
+              int64_t budget, bool* usable, bool* sorted, int64_t* total, int* wuni);
+size_t sell_plan_temp_bytes(int64_t n);
+// Column offsets and source entries of the planned copy; *usable = false when
+// an offset col - row falls outside [-32767, 32767].
+int sell_fill_pattern(hipStream_t st, int64_t n, const int* rowptr, const int* colind, const int* off,
+                      const int* perm, short* scol, int* src, int* d_flags, bool* usable);
 void sell_values(hipStream_t st, int64_t total, const int* src, const double* vals, double* v64,
                  float* v32);
 // Single-entry row copies of a CSR (see setup.hip); c1 may be NULL (values only).
@@ -207,11 +268,21 @@ void ell1_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const d
 void ell2_build(hipStream_t st, int64_t n, const int* rp, const int* ci, const double* v, int* c2,
                 double* v2, float* v2f);
 void invperm(hipStream_t st, int64_t m, const int* perm, int* pos);
-// Per-block deflation slots for the fused Z^T y (see setup.hip).  Buffers are
-// hipMalloc'ed here; the caller owns them.
-int build_block_slots(hipStream_t st, int64_t n, int RB, int R, const int* zrp, const int* zci,
-                      int** bb_ptr, int** bb_col, int** ab_ptr, int** ab_slot, int64_t* nslots,
-                      int* d_flags);
+// Per-block deflation slots for the fused Z^T y (see setup.hip) into
+// caller-provided buffers: bb_ptr (nblk + 1), bb_col and ab_slot (cap each),
+// ab_ptr (R + 1).  kStatusInval: some row block reaches more than
+// kBlockColsMax columns, or more than cap slots are needed (the plan then
+// keeps the separate Z^T pass).
+int build_block_slots(hipStream_t st, Arena& ar, int64_t n, int RB, int R, const int* zrp,
+                      const int* zci, int* bb_ptr, int* bb_col, int* ab_ptr, int* ab_slot,
+                      int64_t cap, int64_t* nslots, int* d_flags);
+size_t block_slots_temp_bytes(int64_t n, int RB, int R, int64_t cap);
+// Upper bound of the slot count: one slot per (block, column) pair, at most
+// kBlockColsMax per block, at most one per entry of Z.
+inline int64_t block_slots_bound(int64_t n, int RB, int R, int64_t znnz) {
+    const int64_t nblk = (n + RB - 1) / RB;
+    return std::min<int64_t>(nblk * std::min<int64_t>(R, kBlockColsMax), znnz);
+}
 
 // batched.hip
 struct BatchArgs {
@@ -279,9 +350,13 @@ struct BlockResult {
     int status = 0;            // kStatusOk / MaxIter / Breakdown
     double rho0 = 0.0, rel_res_est = 0.0, rel_res_true = 0.0;
 };
+// Block workspace carved from caller memory of block_workspace_bytes(n, m)
+// bytes (256-byte aligned).  block_bind zeroes the panels.
 struct BlockWork;
-int block_alloc(BlockWork** out, hipStream_t st, int64_t n, int m);
-void block_free(BlockWork* w);
+size_t block_workspace_bytes(int64_t n, int m);
+int block_bind(BlockWork* w, void* mem, size_t bytes, hipStream_t st, int64_t n, int m);
+BlockWork* block_new();
+void block_delete(BlockWork* w);
 int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res);
 
 }  // namespace gm

@@ -1261,7 +1261,7 @@ __global__ __launch_bounds__(kGT) void k_givens(int j, int m, const double* __re
     }
     const int64_t its = its0 + 1;
     ctrl->its = its;
-    if (hist && its - 1 < hist_cap) hist[its - 1] = fabs(sj * gj);
+    if (hist && ctrl->hist_base + its - 1 < hist_cap) hist[ctrl->hist_base + its - 1] = fabs(sj * gj);
     ctrl->k = j + 1;
     ctrl->breakdown = bd;
     const bool est = fabs(sj * gj) <= target;
@@ -1408,7 +1408,7 @@ __global__ __launch_bounds__(kGT) void k_dc_step(int j, int m, const double* __r
     vscale[j] = bd ? 0.0 : 1.0 / (sig * beta);
     const int64_t its = its0 + 1;
     ctrl->its = its;
-    if (hist && its - 1 < hist_cap) hist[its - 1] = fabs(sj * gj);
+    if (hist && ctrl->hist_base + its - 1 < hist_cap) hist[ctrl->hist_base + its - 1] = fabs(sj * gj);
     ctrl->k = j;
     ctrl->breakdown = bd;
     const bool est = fabs(sj * gj) <= target;
@@ -1583,10 +1583,11 @@ __global__ __launch_bounds__(kWG) void k_axpy_norm(int n, const double* __restri
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) x[i] += a * d[i];
 }
 
-__global__ void k_ctrl_reset(Ctrl* ctrl, int64_t max_iters) {
+__global__ void k_ctrl_reset(Ctrl* ctrl, int64_t max_iters, int64_t hist_base) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         Ctrl c = {};
         c.max_iters = max_iters;
+        c.hist_base = hist_base;
         c.stop = 1;
         *ctrl = c;
     }
@@ -2215,8 +2216,8 @@ void launch_axpy_norm(hipStream_t st, int NB, int n, const double* nrm2, const d
     k_axpy_norm<<<NB, kWG, 0, st>>>(n, nrm2, d, x);
 }
 
-void launch_ctrl_reset(hipStream_t st, Ctrl* c, int64_t max_iters) {
-    k_ctrl_reset<<<1, 64, 0, st>>>(c, max_iters);
+void launch_ctrl_reset(hipStream_t st, Ctrl* c, int64_t max_iters, int64_t hist_base) {
+    k_ctrl_reset<<<1, 64, 0, st>>>(c, max_iters, hist_base);
 }
 
 void launch_fill(hipStream_t st, double* p, int64_t n, double v) {

@@ -23,7 +23,8 @@ __device__ __forceinline__ int sys_of_row(const int64_t* off, int nsys, int64_t 
     return lo;
 }
 
-// flags bit 0: malformed CSR / index out of the row's system block;
+// flags bit 0: malformed CSR, index out of the row's system block, column
+// indices of a row not strictly increasing (unsorted or duplicate);
 // bit 1: non-finite value.
 __global__ void k_validate(int nsys, int64_t n, int64_t nnz, int64_t znnz,
                            const int64_t* __restrict__ row_off, const int64_t* __restrict__ zcol_off,
@@ -44,9 +45,11 @@ __global__ void k_validate(int nsys, int64_t n, int64_t nnz, int64_t znnz,
     if (k1 < k0 || k0 < 0 || (int64_t)k1 > nnz) {
         f |= 1;
     } else {
+        int prev = -1;
         for (int k = k0; k < k1; ++k) {
             const int c = colind[k];
-            if (c < c0 || c >= c1) f |= 1;
+            if (c < c0 || c >= c1 || c <= prev) f |= 1;   // in the block, sorted, no duplicates
+            prev = c;
             if (!isfinite(vals[k])) f |= 2;
         }
     }
@@ -56,9 +59,11 @@ __global__ void k_validate(int nsys, int64_t n, int64_t nnz, int64_t znnz,
         if (q1 < q0 || q0 < 0 || (int64_t)q1 > znnz) {
             f |= 1;
         } else {
+            int prev = -1;
             for (int q = q0; q < q1; ++q) {
                 const int a = zci[q];
-                if (a < a0 || a >= a1) f |= 1;
+                if (a < a0 || a >= a1 || a <= prev) f |= 1;
+                prev = a;
                 if (!isfinite(zv[q])) f |= 2;
             }
         }
@@ -118,44 +123,142 @@ __global__ void k_gather(int64_t nnz, const int* __restrict__ perm, const double
 
 static unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>((n + kWG - 1) / kWG, 1); }
 
+// ------------------------------------------------------------------ scan
+// Exclusive scan of int32 counts in three launches: per-workgroup scans of
+// kScanTile entries (with the tile totals in int64), one workgroup scanning
+// the tile totals in order, then the tile offsets added.  Integer sums, so the
+// result does not depend on the order.
+
+constexpr int kScanTile = 1024;   // entries per workgroup (4 per thread)
+
+__global__ __launch_bounds__(kWG) void k_scan_tiles(int64_t count, const int* __restrict__ in,
+                                                    int* __restrict__ out, int64_t* __restrict__ tot) {
+    __shared__ int64_t lds[kWG];
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+    int v[4];
+    int64_t s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        v[u] = t0 + u < count ? in[t0 + u] : 0;
+        s += v[u];
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the per-thread sums.
+    for (int o = 1; o < kWG; o <<= 1) {
+        const int64_t add = threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = lds[threadIdx.x] - s;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (t0 + u < count) out[t0 + u] = (int)run;
+        run += v[u];
+    }
+    if (threadIdx.x == kWG - 1) tot[blockIdx.x] = lds[kWG - 1];
+}
+
+// tot[0 .. nt) -> exclusive offsets in place; tot[nt] = grand total.
+__global__ __launch_bounds__(kWG) void k_scan_totals(int64_t nt, int64_t* __restrict__ tot) {
+    __shared__ int64_t lds[kWG];
+    int64_t carry = 0;
+    for (int64_t b = 0; b < nt; b += kWG) {
+        const int64_t i = b + threadIdx.x;
+        const int64_t v = i < nt ? tot[i] : 0;
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kWG; o <<= 1) {
+            const int64_t add = threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
+            __syncthreads();
+            lds[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < nt) tot[i] = carry + lds[threadIdx.x] - v;
+        carry += lds[kWG - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[nt] = carry;
+}
+
+__global__ void k_scan_add(int64_t count, const int64_t* __restrict__ tot, int* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = (int)((int64_t)out[i] + tot[i / kScanTile]);
+}
+
+static int64_t scan_tiles(int64_t count) { return std::max<int64_t>((count + kScanTile - 1) / kScanTile, 1); }
+
+int scan_i32(hipStream_t st, Arena& ar, const int* in, int* out, int64_t count, int64_t* total) {
+    const size_t mk = ar.mark();
+    const int64_t nt = scan_tiles(count);
+    int64_t* tot = ar.temp_n<int64_t>(nt + 1);
+    if (!tot) return kStatusNoMem;
+    k_scan_tiles<<<(unsigned)nt, kWG, 0, st>>>(count, in, out, tot);
+    k_scan_totals<<<1, kWG, 0, st>>>(nt, tot);
+    k_scan_add<<<blocks_for(count), kWG, 0, st>>>(count, tot, out);
+    int64_t h = 0;
+    hipMemcpyAsync(&h, tot + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    const bool ok = hipStreamSynchronize(st) == hipSuccess;
+    ar.release(mk);
+    if (!ok) return kStatusDevice;
+    *total = h;
+    return kStatusOk;
+}
+
+static size_t scan_temp_bytes(int64_t count) { return Arena::round((scan_tiles(count) + 1) * sizeof(int64_t)); }
+
+// ------------------------------------------------------------- transpose
+
+static int end_bit_for(int64_t ncols) {
+    int end_bit = 1;
+    while ((int64_t(1) << end_bit) < ncols) ++end_bit;
+    return end_bit;
+}
+
+static size_t sort_temp_bytes(int64_t items, int end_bit) {
+    size_t tb = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const int*)nullptr, (int*)nullptr,
+                                       (const int*)nullptr, (int*)nullptr, (int)std::max<int64_t>(items, 1),
+                                       0, end_bit, (hipStream_t)0);
+    return Arena::round(tb);
+}
+
+size_t transpose_temp_bytes(int64_t ncols, int64_t nnz) {
+    return 3 * Arena::round(std::max<int64_t>(nnz, 1) * sizeof(int)) + sort_temp_bytes(nnz, end_bit_for(ncols));
+}
+
 // Transpose of an nrows x ncols CSR pattern: a stable sort of the entries by
 // column keeps every row of the transpose in increasing original-row order.
 // tperm[q] is the original entry index of transposed entry q.
-int build_transpose(hipStream_t st, int64_t nrows, int64_t ncols, int64_t nnz, const int* rowptr,
-                    const int* colind, int* trowptr, int* tcolind, int* tperm) {
+int build_transpose(hipStream_t st, Arena& ar, int64_t nrows, int64_t ncols, int64_t nnz,
+                    const int* rowptr, const int* colind, int* trowptr, int* tcolind, int* tperm) {
     if (nnz == 0) {
         k_bounds<<<1, kWG, 0, st>>>(0, ncols, colind, trowptr);
         return hipGetLastError() == hipSuccess ? kStatusOk : kStatusDevice;
     }
-    int *row_of = nullptr, *keys_out = nullptr, *iota = nullptr;
-    void* tmp = nullptr;
+    const size_t mk = ar.mark();
+    const int end_bit = end_bit_for(ncols);
+    int* row_of = ar.temp_n<int>(nnz);
+    int* keys_out = ar.temp_n<int>(nnz);
+    int* iota = ar.temp_n<int>(nnz);
     size_t tmp_bytes = 0;
-    int end_bit = 1;
-    while ((int64_t(1) << end_bit) < ncols) ++end_bit;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, colind, keys_out, iota, tperm, (int)nnz, 0,
+                                       end_bit, st);
+    void* tmp = ar.temp(tmp_bytes);
     int status = kStatusOk;
-    if (hipMalloc(&row_of, nnz * sizeof(int)) != hipSuccess ||
-        hipMalloc(&keys_out, nnz * sizeof(int)) != hipSuccess ||
-        hipMalloc(&iota, nnz * sizeof(int)) != hipSuccess) {
+    if (!row_of || !keys_out || !iota || !tmp) {
         status = kStatusNoMem;
     } else {
         k_row_of<<<blocks_for(nrows), kWG, 0, st>>>(nrows, rowptr, row_of);
         k_iota<<<blocks_for(nnz), kWG, 0, st>>>(nnz, iota);
-        hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, colind, keys_out, iota, tperm,
-                                           (int)nnz, 0, end_bit, st);
-        if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
-            status = kStatusNoMem;
-        } else {
-            hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, colind, keys_out, iota, tperm, (int)nnz,
-                                               0, end_bit, st);
-            k_bounds<<<blocks_for(nnz + 1), kWG, 0, st>>>(nnz, ncols, keys_out, trowptr);
-            k_take_rows<<<blocks_for(nnz), kWG, 0, st>>>(nnz, tperm, row_of, tcolind);
-            if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
-        }
+        hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, colind, keys_out, iota, tperm, (int)nnz, 0,
+                                           end_bit, st);
+        k_bounds<<<blocks_for(nnz + 1), kWG, 0, st>>>(nnz, ncols, keys_out, trowptr);
+        k_take_rows<<<blocks_for(nnz), kWG, 0, st>>>(nnz, tperm, row_of, tcolind);
+        if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
     }
-    hipFree(row_of);
-    hipFree(keys_out);
-    hipFree(iota);
-    hipFree(tmp);
+    ar.release(mk);
     return status;
 }
 
@@ -236,39 +339,29 @@ __global__ void k_az_fill(int64_t n, const int* __restrict__ rowptr, const int* 
     }
 }
 
-int az_count(const SetupArgs& a, const int* rowptr, const int* colind, int* az_rowptr,
-             int64_t* az_nnz) {
-    int* cnt = nullptr;
-    int* flags = nullptr;
-    void* tmp = nullptr;
-    size_t tmp_bytes = 0;
-    int status = kStatusOk;
-    if (hipMalloc(&cnt, (a.n + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc(&flags, sizeof(int)) != hipSuccess) {
-        hipFree(cnt);
-        hipFree(flags);
-        return kStatusNoMem;
-    }
-    hipMemsetAsync(flags, 0, sizeof(int), a.st);
-    hipMemsetAsync(cnt + a.n, 0, sizeof(int), a.st);
-    k_az_count<<<blocks_for(a.n), kWG, 0, a.st>>>(a.n, rowptr, colind, a.zrp, a.zci, cnt, flags);
-    hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, az_rowptr, (int)(a.n + 1), a.st);
-    if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
-        status = kStatusNoMem;
-    } else {
-        hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, az_rowptr, (int)(a.n + 1), a.st);
-        int h[2] = {0, 0};
-        hipMemcpyAsync(&h[0], flags, sizeof(int), hipMemcpyDeviceToHost, a.st);
-        hipMemcpyAsync(&h[1], az_rowptr + a.n, sizeof(int), hipMemcpyDeviceToHost, a.st);
+int az_count(const SetupArgs& a, Arena& ar, const int* rowptr, const int* colind, int* az_rowptr,
+             int64_t* az_nnz, int* d_flags) {
+    const size_t mk = ar.mark();
+    int* cnt = ar.temp_n<int>(a.n + 1);
+    if (!cnt) return kStatusNoMem;
+    hipMemsetAsync(d_flags, 0, sizeof(int), a.st);
+    k_az_count<<<blocks_for(a.n), kWG, 0, a.st>>>(a.n, rowptr, colind, a.zrp, a.zci, cnt, d_flags);
+    int64_t total = 0;
+    int status = scan_i32(a.st, ar, cnt, az_rowptr, a.n, &total);
+    if (status == kStatusOk) {
+        int fl = 0;
+        const int tot32 = (int)std::min<int64_t>(total, INT32_MAX);
+        hipMemcpyAsync(&fl, d_flags, sizeof(int), hipMemcpyDeviceToHost, a.st);
+        hipMemcpyAsync(az_rowptr + a.n, &tot32, sizeof(int), hipMemcpyHostToDevice, a.st);
         if (hipStreamSynchronize(a.st) != hipSuccess) status = kStatusDevice;
-        else if (h[0]) status = kStatusInval;
-        *az_nnz = h[1];
+        else if (fl || total >= INT32_MAX) status = kStatusInval;
+        *az_nnz = total;
     }
-    hipFree(cnt);
-    hipFree(flags);
-    hipFree(tmp);
+    ar.release(mk);
     return status;
 }
+
+size_t az_count_temp_bytes(int64_t n) { return Arena::round((n + 1) * sizeof(int)) + scan_temp_bytes(n); }
 
 void az_fill(const SetupArgs& a, const int* rowptr, const int* colind, const double* vals,
              const int* az_rowptr, int* az_colind, double* az_vals) {
@@ -446,7 +539,7 @@ __global__ void k_sell_width(int64_t n, const int* __restrict__ rowptr, int* __r
     if (sl == nsl) { wsz[sl] = 0; return; }
     int w = 0;
     for (int64_t i = sl * 64; i < min(n, sl * 64 + 64); ++i) w = max(w, rowptr[i + 1] - rowptr[i]);
-    wsz[sl] = w * 64;
+    wsz[sl] = (int)min((int64_t)w * 64, (int64_t)INT32_MAX);   // saturates: the copy is then refused
 }
 
 // Sorted row order of each 256-row block (decreasing length, ties by row) and
@@ -467,7 +560,7 @@ __global__ __launch_bounds__(kWG) void k_sell_sort(int64_t n, const int* __restr
     }
     if (i < n) {
         perm[r0 + rank] = (int)i;
-        if (rank % 64 == 0) wsz[(r0 + rank) / 64] = li * 64;
+        if (rank % 64 == 0) wsz[(r0 + rank) / 64] = (int)min((int64_t)li * 64, (int64_t)INT32_MAX);
     }
 }
 
@@ -507,93 +600,71 @@ __global__ void k_sell_vals(int64_t m, const int* __restrict__ src, const double
     if (v32) v32[q] = (float)v;
 }
 
-// Exclusive scan of the nsl + 1 slice sizes in wsz into off; returns the
-// total (entries) through *h.
-static int sell_scan(hipStream_t st, int64_t nsl, const int* wsz, int* off, int* h) {
-    void* tmp = nullptr;
-    size_t tb = 0;
-    int status = kStatusOk;
-    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, wsz, off, (int)(nsl + 1), st);
-    if (hipMalloc(&tmp, std::max<size_t>(tb, 1)) != hipSuccess) return kStatusNoMem;
-    hipcub::DeviceScan::ExclusiveSum(tmp, tb, wsz, off, (int)(nsl + 1), st);
-    hipMemcpyAsync(h, off + nsl, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
-    hipFree(tmp);
-    return status;
+size_t sell_plan_temp_bytes(int64_t n) {
+    const int64_t nsl = (n + 63) / 64;
+    return 2 * Arena::round((nsl + 1) * sizeof(int)) + scan_temp_bytes(nsl + 1);
 }
 
-int sell_build(hipStream_t st, int64_t n, const int* rowptr, const int* colind, int** off,
-               int** perm, short** scol, int** src, int64_t* total, int* wuni) {
+int sell_plan(hipStream_t st, Arena& ar, int64_t n, const int* rowptr, int* off, int* perm,
+              int64_t budget, bool* usable, bool* sorted, int64_t* total, int* wuni) {
     const int64_t nsl = (n + 63) / 64;
-    *off = *src = *perm = nullptr;
-    *scol = nullptr;
+    *usable = false;
+    *sorted = false;
+    *total = 0;
     *wuni = 0;
-    int *wsz = nullptr, *off2 = nullptr;
-    int status = kStatusOk;
-    if (hipMalloc(off, (nsl + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc(&wsz, (nsl + 1) * sizeof(int)) != hipSuccess)
-        status = kStatusNoMem;
-    int h = 0;
-    if (status == kStatusOk) {
-        k_sell_width<<<blocks_for(nsl + 1), kWG, 0, st>>>(n, rowptr, wsz);
-        status = sell_scan(st, nsl, wsz, *off, &h);
+    const size_t mk = ar.mark();
+    int* wsz = ar.temp_n<int>(nsl + 1);
+    int* off2 = ar.temp_n<int>(nsl + 1);
+    if (!wsz || !off2) {
+        ar.release(mk);
+        return kStatusNoMem;
     }
+    // Slice widths in row order (wsz[nsl] = 0, so off[nsl] is the total).
+    k_sell_width<<<blocks_for(nsl + 1), kWG, 0, st>>>(n, rowptr, wsz);
+    int64_t h = 0;
+    int status = scan_i32(st, ar, wsz, off, nsl + 1, &h);
     // Sorted order within each 256-row block; kept if it stores at least 1/16
     // fewer entries.
     if (status == kStatusOk && nsl > 0) {
-        int h2 = 0;
-        if (hipMalloc(perm, n * sizeof(int)) != hipSuccess ||
-            hipMalloc(&off2, (nsl + 1) * sizeof(int)) != hipSuccess)
-            status = kStatusNoMem;
-        if (status == kStatusOk) {
-            hipMemsetAsync(wsz + nsl, 0, sizeof(int), st);
-            k_sell_sort<<<(unsigned)((n + kWG - 1) / kWG), kWG, 0, st>>>(n, rowptr, *perm, wsz);
-            status = sell_scan(st, nsl, wsz, off2, &h2);
-        }
-        if (status == kStatusOk && (int64_t)h2 * 16 <= (int64_t)h * 15) {
-            std::swap(*off, off2);
+        hipMemsetAsync(wsz + nsl, 0, sizeof(int), st);
+        k_sell_sort<<<(unsigned)((n + kWG - 1) / kWG), kWG, 0, st>>>(n, rowptr, perm, wsz);
+        int64_t h2 = 0;
+        status = scan_i32(st, ar, wsz, off2, nsl + 1, &h2);
+        if (status == kStatusOk && h2 * 16 <= h * 15) {
+            hipMemcpyAsync(off, off2, (nsl + 1) * sizeof(int), hipMemcpyDeviceToDevice, st);
             h = h2;
-        } else {
-            hipFree(*perm);
-            *perm = nullptr;
+            *sorted = true;
         }
-        hipFree(off2);
     }
-    if (status == kStatusOk && (hipMalloc(scol, std::max(h, 1) * sizeof(short)) != hipSuccess ||
-                                hipMalloc(src, std::max(h, 1) * sizeof(int)) != hipSuccess))
-        status = kStatusNoMem;
-    int ovf = 0;
-    if (status == kStatusOk) {
-        // wsz (nsl + 1 ints) is free again: its first entry is the overflow flag.
-        hipMemsetAsync(wsz, 0, sizeof(int), st);
-        if (nsl > 0)
-            k_sell_fill<<<(unsigned)nsl, 64, 0, st>>>(n, rowptr, colind, *off, *perm, *scol, *src, wsz);
-        hipMemcpyAsync(&ovf, wsz, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
-    }
-    hipFree(wsz);
-    if (status != kStatusOk || ovf) {
-        hipFree(*off);
-        hipFree(*perm);
-        hipFree(*scol);
-        hipFree(*src);
-        *off = *src = *perm = nullptr;
-        *scol = nullptr;
-        h = 0;
-    }
-    if (status == kStatusOk && nsl > 0 && *off && !*perm) {
+    if (status == kStatusOk && hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+    ar.release(mk);
+    if (status != kStatusOk) return status;
+    *total = h;
+    *usable = nsl > 0 && h < INT32_MAX && h <= budget;
+    if (*usable && !*sorted) {
         // Uniform width (every slice as wide as the first): the kernels then
         // compute slice offsets instead of loading them.
         std::vector<int> ho((size_t)nsl + 1);
-        if (hipMemcpy(ho.data(), *off, (nsl + 1) * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-            status = kStatusDevice;
+        if (hipMemcpy(ho.data(), off, (nsl + 1) * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            return kStatusDevice;
         const int w0 = ho[1] - ho[0];
-        bool uni = status == kStatusOk && w0 > 0 && w0 % 64 == 0;
+        bool uni = w0 > 0 && w0 % 64 == 0;
         for (int64_t q = 0; uni && q <= nsl; ++q) uni = (int64_t)ho[q] == q * w0;
         if (uni) *wuni = w0 / 64;
     }
-    *total = h;
-    return status;
+    return kStatusOk;
+}
+
+int sell_fill_pattern(hipStream_t st, int64_t n, const int* rowptr, const int* colind, const int* off,
+                      const int* perm, short* scol, int* src, int* d_flags, bool* usable) {
+    const int64_t nsl = (n + 63) / 64;
+    int ovf = 0;
+    hipMemsetAsync(d_flags, 0, sizeof(int), st);
+    if (nsl > 0) k_sell_fill<<<(unsigned)nsl, 64, 0, st>>>(n, rowptr, colind, off, perm, scol, src, d_flags);
+    hipMemcpyAsync(&ovf, d_flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) return kStatusDevice;
+    *usable = ovf == 0;
+    return kStatusOk;
 }
 
 void sell_values(hipStream_t st, int64_t total, const int* src, const double* vals, double* v64,
@@ -642,74 +713,52 @@ __global__ void k_block_cols(int64_t n, int RB, int64_t nblk, const int* __restr
     }
 }
 
-int build_block_slots(hipStream_t st, int64_t n, int RB, int R, const int* zrp, const int* zci,
-                      int** bb_ptr, int** bb_col, int** ab_ptr, int** ab_slot, int64_t* nslots,
-                      int* d_flags) {
+size_t block_slots_temp_bytes(int64_t n, int RB, int R, int64_t cap) {
     const int64_t nblk = (n + RB - 1) / RB;
-    *bb_ptr = *bb_col = *ab_ptr = *ab_slot = nullptr;
-    int* cnt = nullptr;
-    void* tmp = nullptr;
-    size_t tb = 0;
-    int status = kStatusOk;
-    if (hipMalloc(bb_ptr, (nblk + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc(&cnt, (nblk + 1) * sizeof(int)) != hipSuccess) {
-        status = kStatusNoMem;
-    }
-    int h[2] = {0, 0};
+    return Arena::round((nblk + 1) * sizeof(int)) + scan_temp_bytes(nblk + 1) +
+           2 * Arena::round(std::max<int64_t>(cap, 1) * sizeof(int)) + sort_temp_bytes(cap, end_bit_for(R));
+}
+
+int build_block_slots(hipStream_t st, Arena& ar, int64_t n, int RB, int R, const int* zrp,
+                      const int* zci, int* bb_ptr, int* bb_col, int* ab_ptr, int* ab_slot,
+                      int64_t cap, int64_t* nslots, int* d_flags) {
+    const int64_t nblk = (n + RB - 1) / RB;
+    *nslots = 0;
+    const size_t mk = ar.mark();
+    int* cnt = ar.temp_n<int>(nblk + 1);
+    if (!cnt) return kStatusNoMem;
+    hipMemsetAsync(d_flags, 0, sizeof(int), st);
+    hipMemsetAsync(cnt + nblk, 0, sizeof(int), st);
+    k_block_cols<<<blocks_for(nblk), kWG, 0, st>>>(n, RB, nblk, zrp, zci, nullptr, cnt, d_flags);
+    int64_t ns = 0;
+    int status = scan_i32(st, ar, cnt, bb_ptr, nblk + 1, &ns);
     if (status == kStatusOk) {
-        hipMemsetAsync(d_flags, 0, sizeof(int), st);
-        hipMemsetAsync(cnt + nblk, 0, sizeof(int), st);
-        k_block_cols<<<blocks_for(nblk), kWG, 0, st>>>(n, RB, nblk, zrp, zci, nullptr, cnt, d_flags);
-        hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, *bb_ptr, (int)(nblk + 1), st);
-        if (hipMalloc(&tmp, tb) != hipSuccess) status = kStatusNoMem;
-    }
-    if (status == kStatusOk) {
-        hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, *bb_ptr, (int)(nblk + 1), st);
-        hipMemcpyAsync(&h[0], d_flags, sizeof(int), hipMemcpyDeviceToHost, st);
-        hipMemcpyAsync(&h[1], *bb_ptr + nblk, sizeof(int), hipMemcpyDeviceToHost, st);
+        int fl = 0;
+        hipMemcpyAsync(&fl, d_flags, sizeof(int), hipMemcpyDeviceToHost, st);
         if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
-        else if (h[0]) status = kStatusInval;      // some block reaches too many columns
-    }
-    hipFree(tmp);
-    tmp = nullptr;
-    const int64_t ns = h[1];
-    *nslots = ns;
-    int *keys_out = nullptr, *iota = nullptr;
-    if (status == kStatusOk) {
-        if (hipMalloc(bb_col, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess ||
-            hipMalloc(ab_ptr, (R + 1) * sizeof(int)) != hipSuccess ||
-            hipMalloc(ab_slot, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess ||
-            hipMalloc(&keys_out, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess ||
-            hipMalloc(&iota, std::max<int64_t>(ns, 1) * sizeof(int)) != hipSuccess)
-            status = kStatusNoMem;
+        else if (fl || ns > cap) status = kStatusInval;   // some block reaches too many columns
     }
     if (status == kStatusOk) {
-        k_block_cols<<<blocks_for(nblk), kWG, 0, st>>>(n, RB, nblk, zrp, zci, *bb_ptr, *bb_col, d_flags);
-        k_iota<<<blocks_for(ns), kWG, 0, st>>>(ns, iota);
-        int end_bit = 1;
-        while ((int64_t(1) << end_bit) < R) ++end_bit;
-        hipcub::DeviceRadixSort::SortPairs(nullptr, tb, *bb_col, keys_out, iota, *ab_slot, (int)ns, 0,
+        const int end_bit = end_bit_for(R);
+        int* keys_out = ar.temp_n<int>(ns);
+        int* iota = ar.temp_n<int>(ns);
+        size_t tb = 0;
+        hipcub::DeviceRadixSort::SortPairs(nullptr, tb, bb_col, keys_out, iota, ab_slot, (int)ns, 0,
                                            end_bit, st);
-        if (hipMalloc(&tmp, tb) != hipSuccess) {
+        void* tmp = ar.temp(tb);
+        if (!keys_out || !iota || !tmp) {
             status = kStatusNoMem;
         } else {
-            hipcub::DeviceRadixSort::SortPairs(tmp, tb, *bb_col, keys_out, iota, *ab_slot, (int)ns, 0,
+            k_block_cols<<<blocks_for(nblk), kWG, 0, st>>>(n, RB, nblk, zrp, zci, bb_ptr, bb_col, d_flags);
+            k_iota<<<blocks_for(ns), kWG, 0, st>>>(ns, iota);
+            hipcub::DeviceRadixSort::SortPairs(tmp, tb, bb_col, keys_out, iota, ab_slot, (int)ns, 0,
                                                end_bit, st);
-            k_bounds<<<blocks_for(ns + 1), kWG, 0, st>>>(ns, R, keys_out, *ab_ptr);
+            k_bounds<<<blocks_for(ns + 1), kWG, 0, st>>>(ns, R, keys_out, ab_ptr);
             if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
         }
     }
-    hipFree(tmp);
-    hipFree(cnt);
-    hipFree(keys_out);
-    hipFree(iota);
-    if (status != kStatusOk) {
-        hipFree(*bb_ptr);
-        hipFree(*bb_col);
-        hipFree(*ab_ptr);
-        hipFree(*ab_slot);
-        *bb_ptr = *bb_col = *ab_ptr = *ab_slot = nullptr;
-    }
+    ar.release(mk);
+    if (status == kStatusOk) *nslots = ns;
     return status;
 }
 

@@ -19,10 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libgmres_mi355x.so")
 GMRES_FP64, GMRES_MIXED_F32, GMRES_MIXED_F16 = 0, 1, 2
 PRECISIONS = {"fp64": GMRES_FP64, "mixed_f32": GMRES_MIXED_F32, "mixed_f16": GMRES_MIXED_F16}
 STATUS = {0: "OK", 1: "MAXITER", 2: "BREAKDOWN", 3: "STAGNATED", -1: "EINVAL", -2: "ESINGULAR",
-          -3: "ENONFINITE", -4: "EDEVICE", -5: "ENOMEM"}
+          -3: "ENONFINITE", -4: "EDEVICE", -5: "EWORKSPACE"}
+GMRES_EWORKSPACE = -5
 
 # Every symbol include/gmres.h declares.
-EXPORTS = ["gmres_default_opts", "gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_solve_block",
+EXPORTS = ["gmres_default_opts", "gmres_workspace_bytes", "gmres_workspace_required", "gmres_setup",
+           "gmres_solve", "gmres_solve_batched", "gmres_block_workspace_bytes", "gmres_solve_block",
            "gmres_adjoint", "gmres_update_values", "gmres_spmv", "gmres_history",
            "gmres_autotune", "gmres_set_timing", "gmres_kernel_times", "gmres_set_stream",
            "gmres_destroy", "gmres_last_error"]
@@ -70,12 +72,20 @@ def load_library():
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     lib.gmres_default_opts.argtypes = [C.POINTER(GmresOpts)]
     lib.gmres_default_opts.restype = None
+    sz = C.c_size_t
+    lib.gmres_workspace_bytes.argtypes = [i32, C.POINTER(i64), C.POINTER(i64), i64, i64,
+                                          C.POINTER(GmresOpts), i32]
+    lib.gmres_workspace_bytes.restype = sz
+    lib.gmres_workspace_required.argtypes = []
+    lib.gmres_workspace_required.restype = sz
     lib.gmres_setup.argtypes = [C.POINTER(vp), i32, C.POINTER(i64), C.POINTER(i64), vp, vp, vp, i64,
-                                vp, vp, vp, i64, C.POINTER(GmresOpts), i32, vp]
+                                vp, vp, vp, i64, C.POINTER(GmresOpts), i32, vp, sz, vp]
+    lib.gmres_block_workspace_bytes.argtypes = [vp, i32]
+    lib.gmres_block_workspace_bytes.restype = sz
     lib.gmres_solve.argtypes = [vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_solve_batched.argtypes = [vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_adjoint.argtypes = [vp, vp, vp, vp, vp, C.POINTER(GmresInfo)]
-    lib.gmres_solve_block.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(GmresInfo)]
+    lib.gmres_solve_block.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, C.POINTER(GmresInfo)]
     lib.gmres_update_values.argtypes = [vp, vp]
     lib.gmres_spmv.argtypes = [vp, vp, vp]
     lib.gmres_history.argtypes = [vp, C.POINTER(dbl), i64]
@@ -88,7 +98,8 @@ def load_library():
     lib.gmres_destroy.restype = None
     lib.gmres_last_error.argtypes = []
     lib.gmres_last_error.restype = C.c_char_p
-    for name in ("gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_solve_block", "gmres_adjoint",
+    for name in ("gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_solve_block",
+                 "gmres_adjoint",
                  "gmres_update_values", "gmres_spmv", "gmres_autotune", "gmres_set_timing",
                  "gmres_kernel_times", "gmres_set_stream"):
         getattr(lib, name).restype = C.c_int
@@ -158,15 +169,33 @@ class Plan:
                 raise TypeError("rowptr/colind must be contiguous int32 CUDA tensors, vals float64")
         self.opts = default_opts(**opts)
         self._keep = (rowptr, colind, vals, z_rowptr, z_colind, z_vals)
-        h = C.c_void_p()
+        self._vals_version = 0
         znnz = 0 if z_colind is None else z_colind.numel()
-        st = lib.gmres_setup(C.byref(h), self.nsys,
-                             self.row_off.ctypes.data_as(C.POINTER(C.c_int64)),
-                             self.zcol_off.ctypes.data_as(C.POINTER(C.c_int64)),
-                             _ptr(rowptr), _ptr(colind), _ptr(vals), self.nnz,
-                             _ptr(z_rowptr), _ptr(z_colind), _ptr(z_vals), znnz,
-                             C.byref(self.opts), int(bool(need_adjoint)), _stream_handle(stream))
+        roff = self.row_off.ctypes.data_as(C.POINTER(C.c_int64))
+        zoff = self.zcol_off.ctypes.data_as(C.POINTER(C.c_int64))
+        adj = int(bool(need_adjoint))
+        # The plan's device memory: one torch-owned workspace, sized from host
+        # data; when the data-dependent parts exceed their bound, setup reports
+        # the exact size and runs again with it.
+        nbytes = lib.gmres_workspace_bytes(self.nsys, roff, zoff, self.nnz, znnz, C.byref(self.opts), adj)
+        if nbytes == 0:
+            raise GmresError(-1, "invalid plan sizes or options")
+        h = C.c_void_p()
+        for attempt in range(2):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=vals.device)
+            st = lib.gmres_setup(C.byref(h), self.nsys, roff, zoff, _ptr(rowptr), _ptr(colind), _ptr(vals),
+                                 self.nnz, _ptr(z_rowptr), _ptr(z_colind), _ptr(z_vals), znnz,
+                                 C.byref(self.opts), adj, _ptr(self.workspace), nbytes,
+                                 _stream_handle(stream))
+            if st != GMRES_EWORKSPACE or attempt == 1:
+                break
+            need = lib.gmres_workspace_required()
+            if need <= nbytes:
+                break
+            nbytes = need
         _check(st, allow_positive=False)
+        self.workspace_bytes = nbytes
+        self._block_ws = None
         self._h = h
         self._device = vals.device
 
@@ -227,9 +256,12 @@ class Plan:
         if X0 is not None and tuple(X0.shape) != tuple(B.shape):
             raise ValueError("X0 must have the shape of B")
         X = out if out is not None else torch.empty_like(B)
+        need = self._lib.gmres_block_workspace_bytes(self._h, int(m_block))
+        if self._block_ws is None or self._block_ws.numel() < need:
+            self._block_ws = torch.empty(max(need, 1), dtype=torch.uint8, device=B.device)
         info = GmresInfo()
         st = self._lib.gmres_solve_block(self._h, k, int(m_block), _ptr(B), _ptr(X0), _ptr(X),
-                                         C.byref(info))
+                                         _ptr(self._block_ws), self._block_ws.numel(), C.byref(info))
         _check(st)
         return X, info.to_dict()
 
@@ -245,6 +277,7 @@ class Plan:
 
     def update_values(self, vals):
         self._keep = (self._keep[0], self._keep[1], vals) + self._keep[3:]
+        self._vals_version += 1
         _check(self._lib.gmres_update_values(self._h, _ptr(vals)), allow_positive=False)
 
     def spmv(self, x):
@@ -324,16 +357,23 @@ def _fn():
     class _DeflatedGMRES(torch.autograd.Function):
         @staticmethod
         def forward(ctx, vals, b, plan):
-            plan.update_values(vals.detach().contiguous())
+            v = vals.detach().contiguous()
+            plan.update_values(v)
             x, info = plan.solve(b.detach().contiguous())
             ctx.plan = plan
             ctx.info = info
-            ctx.save_for_backward(x)
+            ctx.version = plan._vals_version
+            ctx.save_for_backward(x, v)
             return x
 
         @staticmethod
         def backward(ctx, gx):
-            (x,) = ctx.saved_tensors
+            x, v = ctx.saved_tensors
+            # The adjoint runs on the plan's current A^T: another forward (or
+            # update_values) on the same plan since this forward replaced the
+            # values, so put this forward's values back first.
+            if ctx.plan._vals_version != ctx.version:
+                ctx.plan.update_values(v)
             gb, gv, _ = ctx.plan.adjoint(x, gx.contiguous())
             return gv, gb, None
 

@@ -53,7 +53,10 @@ def no_defl(s):
 
 
 def relF(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    """Larger of the Frobenius ||a - b||_F / ||b||_F and the elementwise
+    max|a - b| / max|b| relative differences."""
+    d = a - b
+    return max(float(np.linalg.norm(d) / np.linalg.norm(b)), float(np.abs(d).max() / np.abs(b).max()))
 
 
 def gpu_block(s, B, m_block, rtol, max_steps, X0=None, timing=0):
@@ -100,9 +103,17 @@ def test_to_tolerance_config1(k):
     for c in range(k):
         r = B[:, c] - oracle.spmv(s.rowptr, s.colind, s.vals, X[:, c])
         assert np.linalg.norm(r) <= rtol * np.linalg.norm(B[:, c]) * (1 + 1e-6), c
-    assert relF(X, ref.x) <= 1e-6
     assert kt["block_dots"]["launches"] > 0 and kt["block_gemm"]["launches"] > 0
     assert kt["block_spmm"]["launches"] >= info["iters"]
+    # Two solutions that each meet rtol = 1e-8 differ by up to ||A^-1|| times
+    # their residuals (about 1e-6 relative here), so the FP64 parity gate of
+    # 1e-8 is taken on solves to rtol = 1e-12.
+    ref12 = oracle.bgmres(s.rowptr, s.colind, s.vals, B, 8, 1e-12, 6000)
+    X12, info12, _ = gpu_block(s, B, 8, 1e-12, 6000)
+    say("block to 1e-12 k", k, "gpu steps", info12["iters"], "oracle", ref12.iters,
+        "rel diff %.2e" % relF(X12, ref12.x))
+    assert ref12.status_name == "OK" and info12["status_name"] == "OK"
+    assert relF(X12, ref12.x) <= 1e-8
 
 
 def test_block_dimension_n_is_exact():
@@ -173,7 +184,12 @@ def test_dependent_right_hand_sides():
     scale = np.abs(X).max()
     assert np.abs(X[:, 2] - X[:, 0]).max() <= 1e-12 * scale
     assert np.abs(X[:, 4] - X[:, 1] - X[:, 3]).max() <= 1e-8 * scale
+    # Both solutions meet rtol = 1e-10, so column by column they differ by at
+    # most ||A^-1||_2 (||r_gpu|| + ||r_oracle||).
+    ainv = 1.0 / np.linalg.svd(W.dense(s), compute_uv=False)[-1]
     for c in range(5):
         r = B[:, c] - oracle.spmv(s.rowptr, s.colind, s.vals, X[:, c])
+        r_ref = B[:, c] - oracle.spmv(s.rowptr, s.colind, s.vals, ref.x[:, c])
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(B[:, c]) * (1 + 1e-6)
-    assert relF(X, ref.x) <= 1e-6
+        bound = ainv * (np.linalg.norm(r) + np.linalg.norm(r_ref))
+        assert np.linalg.norm(X[:, c] - ref.x[:, c]) <= bound * (1 + 1e-6), c

@@ -30,7 +30,12 @@ def say(*a):
 
 
 def rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    """Larger of the normwise ||a - b|| / ||b|| and the elementwise
+    max|a - b| / max|b| relative differences (a gate on it bounds both)."""
+    d = np.asarray(a) - np.asarray(b)
+    nb = max(float(np.linalg.norm(b)), 1e-300)
+    mb = max(float(np.max(np.abs(b))), 1e-300) if np.size(b) else 1.0
+    return max(float(np.linalg.norm(d)) / nb, float(np.max(np.abs(d), initial=0.0)) / mb)
 
 
 @pytest.fixture(scope="module")
