@@ -223,6 +223,22 @@ gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const d
                                gmres_info* info_h);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the block
+ * solve of gmres_solve_block with its scratch in a static device array of the
+ * library (64 MiB per GPU, held until the process ends) instead of a caller
+ * workspace.  Same arguments, results and errors as gmres_solve_block; EINVAL
+ * when gmres_block_workspace_bytes(p, m_block) exceeds 64 MiB (about 65,000
+ * rows at m_block = 4).  No device memory is allocated or freed.  Every call
+ * on one GPU uses that GPU's array: calls that overlap on one GPU (other
+ * threads, other plans, other streams) race and must be serialised by the
+ * caller; the array keeps the last call's contents, and each call clears
+ * what must start at zero.
+ */
+gmres_status gmres_solve_block_noalloc(gmres_plan p, int32_t k, int32_t m_block, const double* B,
+                                       const double* X0, double* X, gmres_info* info_h);
+
+/*
  * Adjoint of x = A^{-1} b for a single-system plan built with need_adjoint:
  * solves A^T lambda = grad_x with the same deflated GMRES(m) in FP64 (on A^T,
  * A^T Z and E^T), then grad_b = lambda and grad_vals[k] = -lambda_i x_j for

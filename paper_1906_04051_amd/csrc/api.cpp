@@ -1159,6 +1159,9 @@ static gmres_status setup_impl(gmres_plan_s* p, int32_t nsys, const int64_t* sys
     p->ar.cap = workspace_bytes;
 
     HIP_OK(hipGetDevice(&p->device));
+    // Address of the static scratch of gmres_solve_block_noalloc on this
+    // device (looked up once per device; without it only that entry fails).
+    if (nsys == 1) (void)gm::static_scratch_init(p->device);
     p->user_stream = stream;
     HIP_OK(hipStreamCreateWithFlags(&p->st, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
@@ -1430,6 +1433,20 @@ gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const d
                                const double* X0, double* X, void* work, size_t work_bytes,
                                gmres_info* info_h) {
     return solve_block_impl(p, k, m_block, B, X0, X, work, work_bytes, info_h);
+}
+
+gmres_status gmres_solve_block_noalloc(gmres_plan p, int32_t k, int32_t m_block, const double* B,
+                                       const double* X0, double* X, gmres_info* info_h) {
+    if (!p) return fail(GMRES_EINVAL, "plan is NULL");
+    if (m_block < 1 || m_block > gm::kBlockStepsMax) return fail(GMRES_EINVAL, "m_block must be in [1, 16]");
+    size_t cap = 0;
+    void* work = gm::static_scratch(p->device, &cap);
+    if (!work) return fail(GMRES_EDEVICE, "the static scratch address is unavailable on this device");
+    const size_t need = gm::block_workspace_bytes(p->n, m_block);
+    if (need > cap)
+        return fail(GMRES_EINVAL, "block solve needs " + std::to_string(need) +
+                                      " bytes of scratch; the static scratch holds " + std::to_string(cap));
+    return solve_block_impl(p, k, m_block, B, X0, X, work, cap, info_h);
 }
 
 gmres_status gmres_adjoint(gmres_plan p, const double* x, const double* grad_x, double* grad_b,

@@ -28,6 +28,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -528,6 +529,38 @@ struct BlockWork {
     double* Bp() const { return panels + (int64_t)(m + 2) * ps; }
     double* Xp() const { return panels + (int64_t)(m + 3) * ps; }
 };
+
+// Scratch of gmres_solve_block_noalloc, for callers that cannot allocate
+// device memory: one array per GPU, held until the process ends.  Host code
+// never passes `scratch` itself (its host-side name is not the device
+// address); it uses the address looked up once per device below.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return kStatusInval;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return kStatusOk;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) return kStatusDevice;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return kStatusDevice;
+    g_scratch_ptr[device] = ptr;
+    return kStatusOk;
+}
+
+void* static_scratch(int device, size_t* bytes) {
+    *bytes = kStaticScratchBytes;
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 BlockWork* block_new() { return new (std::nothrow) BlockWork(); }
 void block_delete(BlockWork* w) { delete w; }

@@ -356,6 +356,11 @@ struct BlockWork;
 size_t block_workspace_bytes(int64_t n, int m);
 int block_bind(BlockWork* w, void* mem, size_t bytes, hipStream_t st, int64_t n, int m);
 BlockWork* block_new();
+// Static per-device scratch (block.hip): static_scratch_init looks up the
+// device address of the array once per device (that device current);
+// static_scratch returns it (nullptr before init) and its size.
+int static_scratch_init(int device);
+void* static_scratch(int device, size_t* bytes);
 void block_delete(BlockWork* w);
 int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res);
 

@@ -25,6 +25,7 @@ GMRES_EWORKSPACE = -5
 # Every symbol include/gmres.h declares.
 EXPORTS = ["gmres_default_opts", "gmres_workspace_bytes", "gmres_workspace_required", "gmres_setup",
            "gmres_solve", "gmres_solve_batched", "gmres_block_workspace_bytes", "gmres_solve_block",
+           "gmres_solve_block_noalloc",
            "gmres_adjoint", "gmres_update_values", "gmres_spmv", "gmres_history",
            "gmres_autotune", "gmres_set_timing", "gmres_kernel_times", "gmres_set_stream",
            "gmres_destroy", "gmres_last_error"]
@@ -86,6 +87,7 @@ def load_library():
     lib.gmres_solve_batched.argtypes = [vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_adjoint.argtypes = [vp, vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_solve_block.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, C.POINTER(GmresInfo)]
+    lib.gmres_solve_block_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_update_values.argtypes = [vp, vp]
     lib.gmres_spmv.argtypes = [vp, vp, vp]
     lib.gmres_history.argtypes = [vp, C.POINTER(dbl), i64]
@@ -99,7 +101,7 @@ def load_library():
     lib.gmres_last_error.argtypes = []
     lib.gmres_last_error.restype = C.c_char_p
     for name in ("gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_solve_block",
-                 "gmres_adjoint",
+                 "gmres_solve_block_noalloc", "gmres_adjoint",
                  "gmres_update_values", "gmres_spmv", "gmres_autotune", "gmres_set_timing",
                  "gmres_kernel_times", "gmres_set_stream"):
         getattr(lib, name).restype = C.c_int
