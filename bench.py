@@ -1,15 +1,18 @@
 """Benchmark: time-to-rtol of deflated GMRES(50) on one MI355X.
 
-Workload: 1024 x 1024 Q1 convection-diffusion (1,050,625 unknowns, 9,443,329
-stored entries), per-element log-normal diffusion (sigma = 1), beta = (100, 0),
-b ~ U[-1, 1], 64 subdomain-indicator deflation vectors, GMRES(50), rtol 1e-8,
-zero initial guess.  Synthetic, seeded inputs, resident in HBM before timing.
+Default workload (--config 5): the 2048 x 2048 Q1 convection-diffusion system
+of the differentiable-solve configuration (4,198,401 unknowns, 37,761,025
+stored entries), diffusion kappa = 1, beta = (10, 10), manufactured load,
+64 subdomain-indicator deflation vectors, GMRES(50), rtol 1e-8, zero initial
+guess.  Synthetic, seeded inputs, resident in HBM before timing.
 
 One step = the plain FP64 solve followed by the mixed-precision solve (FP32
 inner GMRES with an FP16-stored basis inside FP64 iterative refinement) of the
 same system, both to a true FP64 relative residual <= 1e-8.  `value` is the
 median time-to-rtol of the mixed solve; the FP64 time and the ratio are
-reported beside it.
+reported beside it, and (outside the timed steps) the adjoint solve of the
+same plan.  --config 2 / 3 run the other single-system workloads the same
+way; --config 4 solves the 512-system batch (solves/s, p50/p99).
 
 Prints one JSON line.  `roofline` covers the dominant Arnoldi kernel (timed
 with HIP events on the solver's stream during the timed steps);
@@ -30,16 +33,13 @@ if ROOT not in sys.path:
 METRIC = "time-to-rtol 1e-8 (s) + SpMV/Arnoldi HBM GB/s; mixed vs FP64 GMRES"
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the dominant kernel (FP64 first Gram-Schmidt sweep of the
-# two-sweep variant, steps j = 1..49 of GMRES(50)) from FETCH_SIZE and
-# WRITE_SIZE counter runs of `bench.py --pmc-sample`, each scaled by what the
-# same counter reads for a 512 MiB device copy (FETCH_SIZE reads 262,162 KiB
-# for the 524,288 KiB read: x2.0; WRITE_SIZE reads 524,288 KiB: x1.0).
-# Valid only while the kernel sources hash to `sources_sha256`.
+# HBM traffic of the dominant kernel per workload (FP64 first Gram-Schmidt
+# sweep of the two-sweep variant over a restart cycle of GMRES(50)) from
+# FETCH_SIZE and WRITE_SIZE counter runs of `bench.py --pmc-sample`, each
+# scaled by what the same counter reads for a 512 MiB device copy.  Valid only
+# while the kernel sources hash to `sources_sha256`; None until measured.
 TRAFFIC = {
-    "kind": "pass1_lag",
-    "sources_sha256": "5a0707cb5dcbb2713a39b8d00d8c57eb17b223c4f174c34eb814ada4a9a977df",
-    "bytes_per_launch": 269939483.0,   # 252,482,043 read + 17,457,440 written (98 launches)
+    5: {"kind": "pass1_lag", "sources_sha256": None, "bytes_per_launch": None},
 }
 KERNEL_SOURCES = ("paper_1906_04051_amd/csrc/krylov.hip", "paper_1906_04051_amd/csrc/common.hpp",
                   "paper_1906_04051_amd/csrc/internal.hpp")
@@ -58,22 +58,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info():
+    """CPU model, logical CPUs and OpenMP setting of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count(), omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
+
+
 def cpu_baseline(sysm, m, fp64_iters, sample_iters, adapt_rmax=0):
-    """Oracle (plain C, FP64, one thread) on `sample_iters` inner steps of the
-    same system; time-to-rtol extrapolated with the solve's iteration count."""
+    """Oracle (plain C, FP64, one thread) on the same system: its setup (copy
+    of A and Z, A Z, E and its LU, the initial residual) timed alone with a
+    zero-step run, then `sample_iters` inner steps; the per-step time is
+    scaled to the FP64 solve's iteration count (setup excluded, as on the
+    GPU)."""
     import oracle
+    run = (lambda k: oracle.dgmres(sysm, m, 0.0, k, rmax=adapt_rmax)) if adapt_rmax > 0 else \
+          (lambda k: oracle.gmres(sysm, m, 0.0, k))
     t0 = time.perf_counter()
-    if adapt_rmax > 0:
-        res = oracle.dgmres(sysm, m, 0.0, sample_iters, rmax=adapt_rmax)
-    else:
-        res = oracle.gmres(sysm, m, 0.0, sample_iters)
+    run(0)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = run(sample_iters)
     dt = time.perf_counter() - t0
-    per_iter = dt / max(res.iters, 1)
+    per_iter = max(dt - setup, 1e-9) / max(res.iters, 1)
     return dict(value=per_iter * fp64_iters, unit="s", cores=1, kind="oracle",
                 sample=(f"{res.iters} fixed-count deflated GMRES({m}) steps of the same "
-                        f"1,050,625-unknown system incl. setup ({dt:.1f} s), scaled to the "
-                        f"{fp64_iters} steps the FP64 solve needs to reach rtol 1e-8"),
-                seconds_per_iter=per_iter, sample_seconds=dt)
+                        f"{sysm.n:,}-unknown system ({dt:.1f} s incl. {setup:.1f} s setup); the "
+                        f"per-step time scaled to the {fp64_iters} steps the FP64 solve needs "
+                        f"to reach the tolerance (extrapolated; setup excluded)"),
+                seconds_per_iter=per_iter, sample_seconds=dt, setup_seconds=setup,
+                threads=1, **host_info())
 
 
 def pmc_sample(sysm, d, m, tuned):
@@ -306,21 +327,298 @@ def block_rhs(args):
     print(json.dumps(out), flush=True)
 
 
+def batched_config4(args):
+    """Config 4: 512 independent Q1 systems (meshes 32^2 .. 256^2, own seeded
+    coefficients, beta and rhs) solved by one call of the batched solver
+    (GMRES(30), 16 deflation vectors each, rtol 1e-8).  Reports solves/s over
+    the whole call and p50/p99 of the per-system device solve times."""
+    import numpy as np
+    import torch
+    from paper_1906_04051_amd import gmres as G
+    from paper_1906_04051_amd import workloads as W
+    t0 = time.perf_counter()
+    batch = W.make_batch(512)
+    log(f"[bench] batch: {batch.nsys} systems, {batch.rowptr.size - 1} rows, {int(batch.rowptr[-1])} "
+        f"stored entries ({time.perf_counter() - t0:.1f} s)")
+    plan, d = G.plan_for(batch, m=30, rtol=1e-8, max_iters=200000)
+    tuned = plan.autotune()
+    log(f"[bench] autotune: {tuned}")
+    b = d["b"]
+    x = torch.empty_like(b)
+    for _ in range(args.warmup):
+        _, infos = plan.solve_batched(b, out=x)
+    walls, per_sys = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for step in range(args.steps):
+        t1 = time.perf_counter()
+        _, infos = plan.solve_batched(b, out=x)
+        walls.append(time.perf_counter() - t1)
+        per_sys = [i["solve_ms"] / 1000.0 for i in infos]
+        bad = [i for i in infos if i["status_name"] != "OK"]
+        log(f"[bench] step {step}: {walls[-1]:.3f} s, max rel res "
+            f"{max(i['rel_res_true'] for i in infos):.3e}, not converged {len(bad)}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    med = float(np.median(walls))
+    its = np.array([i["iters"] for i in infos])
+    out = {
+        "metric": "batched deflated GMRES(30): 512 systems to rtol 1e-8, solves/s",
+        "value": batch.nsys / med, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * total / max(args.steps, 1),
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "q1_convection_diffusion_batch_512_mesh32to256", "systems": batch.nsys,
+                   "unknowns_total": int(batch.rowptr.size - 1), "nnz_total": int(batch.rowptr[-1]),
+                   "restart_m": 30, "deflation_vectors_each": 16, "rtol": 1e-8,
+                   "batch_wg": tuned["batch_wg"], "batch_lanes": tuned["batch_lanes"]},
+        "call_s": med,
+        "solve_s_p50": float(np.percentile(per_sys, 50)), "solve_s_p99": float(np.percentile(per_sys, 99)),
+        "solve_s_max": float(np.max(per_sys)),
+        "iters_p50": float(np.percentile(its, 50)), "iters_max": int(its.max()),
+        "max_rel_res_true": max(i["rel_res_true"] for i in infos),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # The oracle on the first systems (largest work is random, so a prefix
+        # is a fair sample), scaled to all 512.
+        t1 = time.perf_counter()
+        k = 0
+        while k < batch.nsys and time.perf_counter() - t1 < 15.0:
+            oracle.gmres(batch.systems[k], 30, 1e-8, 200000)
+            k += 1
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = dict(value=k / dt, unit="solves/s", cores=1, kind="oracle",
+                                   sample=f"the first {k} systems of the batch solved to rtol 1e-8 one "
+                                          f"after another ({dt:.1f} s)", sample_seconds=dt,
+                                   threads=1, **host_info())
+    print(json.dumps(out), flush=True)
+
+
+def single_config(args):
+    """Configs 2, 3 and 5: FP64 and mixed-precision solves of one system to
+    its tolerance (one step = both), kernel times, roofline, CPU baseline."""
+    import numpy as np
+    import torch
+    from paper_1906_04051_amd import gmres as G
+    from paper_1906_04051_amd import workloads as W
+    k = args.config
+    cfg = W.CONFIGS[k]
+    m, rtol = cfg["m"], cfg["rtol"]
+    mixed_basis = args.mixed_basis or ("f32" if k == 3 else "f16")
+    inner = args.inner_rtol if args.inner_rtol else (1e-3 if mixed_basis == "f16" else 1e-5)
+    t0 = time.perf_counter()
+    log(f"[bench] generating config {k}" + (f" at mesh {args.mesh}" if args.mesh else ""))
+    sysm = W.make_config(k, mesh=args.mesh)
+    d = G.upload(sysm)
+    log(f"[bench] {sysm.n} unknowns, {sysm.nnz} stored entries ({time.perf_counter() - t0:.1f} s)")
+    common = dict(m=m, rtol=rtol, max_iters=200000, ortho=args.ortho)
+    plans = {}
+    if args.only in ("both", "fp64"):
+        plans["fp64"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
+                               d["z_vals"], r=sysm.r, precision="fp64", **common)
+    if args.only in ("both", "mixed"):
+        plans["mixed"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
+                                d["z_vals"], r=sysm.r, precision="mixed_" + mixed_basis,
+                                need_adjoint=(k == 5 and not args.no_adjoint),
+                                inner_rtol=inner, inner_max_iters=100000, max_refine=40, **common)
+    tuned = {}
+    for name, p in plans.items():
+        tuned[name] = p.autotune()
+        log(f"[bench] autotune {name}: {tuned[name]}")
+    b = d["b"]
+    if args.pmc_sample:
+        pmc_sample(sysm, d, m, tuned["fp64"])
+        return
+    x = torch.empty_like(b)
+
+    def run(name, timing):
+        p = plans[name]
+        p.set_timing(timing)
+        t1 = time.perf_counter()
+        _, info = p.solve(b, out=x)
+        dt = time.perf_counter() - t1
+        kt = p.kernel_times() if timing else None
+        return dt, info, kt
+
+    for _ in range(args.warmup):
+        for name in plans:
+            dt, info, _ = run(name, False)
+            log(f"[bench] warmup {name}: {dt:.3f} s iters {info['iters']} status {info['status_name']} "
+                f"rel_res_true {info['rel_res_true']:.3e}")
+    timing = 0 if args.no_timing else max(args.timing_period, 1)
+    times = {kk: [] for kk in plans}
+    infos, ktot = {}, {}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for step in range(args.steps):
+        for name in plans:
+            dt, info, kt = run(name, timing)
+            times[name].append(dt)
+            infos[name] = info
+            for kk, v in (kt or {}).items():
+                a = ktot.setdefault((name, kk), dict(launches=0.0, ms=0.0, bytes=0.0))
+                for fld in ("launches", "ms", "bytes"):
+                    a[fld] += v[fld]
+            log(f"[bench] step {step} {name}: {dt:.3f} s iters {info['iters']} "
+                f"refinements {info['refinements']} status {info['status_name']} "
+                f"rel_res_true {info['rel_res_true']:.3e}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    med = {kk: float(np.median(v)) for kk, v in times.items()}
+    headline = "mixed" if "mixed" in med else "fp64"
+    names = {2: f"q1_convection_diffusion_{args.mesh or 1024}x{args.mesh or 1024}_lognormal",
+             3: f"q2_bratu_jacobian_{args.mesh or 512}x{args.mesh or 512}",
+             5: f"q1_convection_diffusion_{args.mesh or 2048}x{args.mesh or 2048}_kappa1_manufactured"}
+    out = {
+        "metric": METRIC, "value": med[headline], "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * total / max(args.steps, 1),
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": (f"f32/{mixed_basis}+f64" if headline == "mixed" else "f64"), "data": "synthetic",
+        "config": {"workload": names[k], "unknowns": sysm.n, "nnz": sysm.nnz, "restart_m": m,
+                   "deflation_vectors": sysm.r, "rtol": rtol, "step": "+".join(plans),
+                   "ortho": args.ortho, "mixed_basis": mixed_basis, "inner_rtol": inner},
+    }
+    for kk in plans:
+        out[f"time_to_rtol_{kk}_s"] = med[kk]
+        out[f"iters_{kk}"] = infos[kk]["iters"]
+        out[f"rel_res_true_{kk}"] = infos[kk]["rel_res_true"]
+        out[f"us_per_iter_{kk}"] = 1e6 * med[kk] / max(infos[kk]["iters"], 1)
+    if "mixed" in med and "fp64" in med:
+        out["mixed_speedup_vs_fp64"] = med["fp64"] / med["mixed"]
+        out["refinements_mixed"] = infos["mixed"]["refinements"]
+    if ktot:
+        per = {}
+        for (name, kk), v in ktot.items():
+            if v["launches"] > 0:
+                per[f"{name}.{kk}"] = dict(launches=int(v["launches"]), avg_us=1000 * v["ms"] / v["launches"],
+                                           GBs=v["bytes"] / (v["ms"] * 1e6), total_ms=v["ms"])
+        out["kernels"] = per
+        # Dominant kernel: most total time in the FP64 solve (else the mixed one).
+        src = "fp64" if "fp64" in plans else "mixed"
+        cand = {kk: v for (nm, kk), v in ktot.items() if nm == src and v["launches"] > 0}
+        dom = max(cand, key=lambda kk: cand[kk]["ms"])
+        v = cand[dom]
+        achieved = v["bytes"] / (v["ms"] * 1e6)
+        traffic = None
+        tr = TRAFFIC.get(k)
+        if (tr and tr["bytes_per_launch"] and src == "fp64" and dom == tr["kind"]
+                and tr["sources_sha256"] == kernel_sources_sha256() and args.mesh is None):
+            traffic = tr["bytes_per_launch"]
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "traffic_unit": "bytes/launch",
+                           "kernel": f"{src}.{dom}", "launches": int(v["launches"]),
+                           "avg_launch_us": 1000 * v["ms"] / v["launches"],
+                           "bytes_per_launch_avg": v["bytes"] / v["launches"]}
+    if k == 5 and "mixed" in plans and not args.no_adjoint:
+        # Backward of the differentiable solve (outside the timed steps):
+        # L = 1/2 ||x - x_target||^2, adjoint FP64 GMRES on A^T.
+        p = plans["mixed"]
+        p.set_timing(0)
+        xs, _ = p.solve(b, out=x)
+        gx = xs - torch.from_numpy(sysm.meta["x_target"]).cuda() if "x_target" in sysm.meta else xs.clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gb, gv, ainfo = p.adjoint(xs, gx)
+        torch.cuda.synchronize()
+        out["adjoint_s"] = time.perf_counter() - t1
+        out["adjoint_iters"] = ainfo["iters"]
+        out["adjoint_rel_res_true"] = ainfo["rel_res_true"]
+    if not args.no_cpu_baseline:
+        fp64_iters = infos["fp64"]["iters"] if "fp64" in infos else infos[headline]["iters"]
+        log(f"[bench] cpu baseline: oracle, {args.cpu_sample_iters} steps")
+        out["cpu_baseline"] = cpu_baseline(sysm, m, fp64_iters, args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
+def adaptive_mode(args):
+    """The paper's own preconditioner (adaptive spectral deflation, no fixed
+    Z) on the kappa = 1 problem of a 1024^2 mesh, GMRES(30), FP64."""
+    import copy
+    import numpy as np
+    import torch
+    from paper_1906_04051_amd import gmres as G
+    from paper_1906_04051_amd import workloads as W
+    mesh = args.mesh or 1024
+    m = W.CONFIGS[1]["m"]
+    log(f"[bench] generating the kappa = 1 problem at mesh {mesh}")
+    sysm = copy.copy(W.make_config(1, mesh=mesh))
+    sysm.r = 0
+    sysm.z_rowptr = np.zeros(sysm.n + 1, np.int32)
+    sysm.z_colind = np.zeros(0, np.int32)
+    sysm.z_vals = np.zeros(0)
+    d = G.upload(sysm)
+    plan = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"], d["z_vals"], r=0,
+                  precision="fp64", adapt_rmax=args.adaptive, m=m, rtol=1e-8, max_iters=200000,
+                  ortho=args.ortho)
+    tuned = plan.autotune()
+    b = d["b"]
+    x = torch.empty_like(b)
+    for _ in range(args.warmup):
+        plan.set_timing(0)
+        plan.solve(b, out=x)
+    timing = 0 if args.no_timing else max(args.timing_period, 1)
+    times, ktot = [], {}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for step in range(args.steps):
+        plan.set_timing(timing)
+        t1 = time.perf_counter()
+        _, info = plan.solve(b, out=x)
+        times.append(time.perf_counter() - t1)
+        for kk, v in (plan.kernel_times() if timing else {}).items():
+            a = ktot.setdefault(kk, dict(launches=0.0, ms=0.0, bytes=0.0))
+            for fld in ("launches", "ms", "bytes"):
+                a[fld] += v[fld]
+        log(f"[bench] step {step}: {times[-1]:.3f} s iters {info['iters']} r {info['defl_r']} "
+            f"rel_res_true {info['rel_res_true']:.3e}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    med = float(np.median(times))
+    out = {
+        "metric": "time-to-rtol 1e-8 (s), GMRES(30) with adaptive spectral deflation",
+        "value": med, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * total / max(args.steps, 1), "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"q1_convection_diffusion_{mesh}x{mesh}_kappa1", "unknowns": sysm.n,
+                   "nnz": sysm.nnz, "restart_m": m, "deflation": "adaptive spectral (Ritz vectors of H_k)",
+                   "adapt_rmax": args.adaptive, "rtol": 1e-8, "spmv_lanes": tuned["spmv_lanes"],
+                   "num_blocks": tuned["num_blocks"]},
+        "iters": info["iters"], "defl_r": info["defl_r"], "mu": info["mu"],
+        "rel_res_true": info["rel_res_true"],
+    }
+    if ktot:
+        per = {kk: dict(launches=int(v["launches"]), avg_us=1000 * v["ms"] / v["launches"],
+                        GBs=v["bytes"] / (v["ms"] * 1e6), total_ms=v["ms"])
+               for kk, v in ktot.items() if v["launches"] > 0}
+        out["kernels"] = per
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysm, m, info["iters"], args.cpu_sample_iters,
+                                           adapt_rmax=args.adaptive)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mesh", type=int, default=1024)
-    ap.add_argument("--cpu-sample-iters", type=int, default=100)
+    ap.add_argument("--config", type=int, default=5, choices=[2, 3, 4, 5],
+                    help="workload: 5 (default) 2048^2 Q1, 4.2 M unknowns; 2 1024^2 Q1 log-normal; "
+                         "3 512^2 Q2 Bratu Jacobian; 4 the 512-system batch")
+    ap.add_argument("--mesh", type=int, default=None, help="override the config's mesh size")
+    ap.add_argument("--cpu-sample-iters", type=int, default=50,
+                    help="oracle steps of the CPU baseline (default: one restart cycle of GMRES(50))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="config 5: skip the adjoint measurement")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--timing-period", type=int, default=8,
                     help="time the kernels of one restart cycle in this many (the others "
                          "replay the captured cycle graph)")
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
-    ap.add_argument("--mixed-basis", choices=["f16", "f32"], default="f16",
-                    help="storage of the Krylov basis in the inner FP32 solves")
+    ap.add_argument("--mixed-basis", choices=["f16", "f32"], default=None,
+                    help="storage of the Krylov basis in the inner FP32 solves (default f16; f32 for config 3)")
     ap.add_argument("--inner-rtol", type=float, default=None,
                     help="tolerance of each inner solve (default 1e-3 for f16, 1e-5 for f32)")
     ap.add_argument("--ortho", type=int, default=1, choices=[0, 1, 2],
@@ -350,167 +648,26 @@ def main():
                          "size, for hardware-counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is not built)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_1906_04051_amd import gmres as G
-    from paper_1906_04051_amd import workloads as W
-
     torch.cuda.set_device(0)
     if args.bratu > 0:
         bratu_newton(args)
-        return
-    if args.bratu_fixed > 0:
+    elif args.bratu_fixed > 0:
         bratu_fixed(args)
-        return
-    if args.block > 0:
+    elif args.block > 0:
+        if args.mesh is None:
+            args.mesh = 1024
         block_rhs(args)
-        return
-    cfg = W.CONFIGS[2]
-    m = cfg["m"]
-    if args.adaptive == 0:
-        log(f"[bench] generating config 2 at mesh {args.mesh}")
-        sysm = W.make_config(2, mesh=args.mesh)
-        d = G.upload(sysm)
-    common = dict(m=m, rtol=1e-8, max_iters=200000, ortho=args.ortho)
-    inner = args.inner_rtol if args.inner_rtol else (1e-3 if args.mixed_basis == "f16" else 1e-5)
-    plans = {}
-    if args.adaptive > 0:
-        # The paper's own preconditioner, no fixed deflation basis, on the
-        # kappa = 1 problem of the same mesh (GMRES(30)): the log-normal
-        # problem has more small eigenvalues than r_max vectors can hold.
-        import copy
-        cfg = W.CONFIGS[1]
-        m = cfg["m"]
-        common["m"] = m
-        log(f"[bench] generating the kappa = 1 problem at mesh {args.mesh}")
-        sysm = copy.copy(W.make_config(1, mesh=args.mesh))
-        sysm.r = 0
-        sysm.z_rowptr = np.zeros(sysm.n + 1, np.int32)
-        sysm.z_colind = np.zeros(0, np.int32)
-        sysm.z_vals = np.zeros(0)
-        d = G.upload(sysm)
-        plans["adaptive"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
-                                   d["z_vals"], r=0, precision="fp64", adapt_rmax=args.adaptive,
-                                   **common)
-    elif args.only in ("both", "fp64"):
-        plans["fp64"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
-                               d["z_vals"], r=sysm.r, precision="fp64", **common)
-    if args.adaptive == 0 and args.only in ("both", "mixed"):
-        plans["mixed"] = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"],
-                                d["z_vals"], r=sysm.r, precision="mixed_" + args.mixed_basis,
-                                inner_rtol=inner, inner_max_iters=100000, max_refine=40, **common)
-    tuned = {}
-    for k, p in plans.items():
-        tuned[k] = p.autotune()
-        log(f"[bench] autotune {k}: {tuned[k]}")
-    b = d["b"]
-    if args.pmc_sample:
-        pmc_sample(sysm, d, m, tuned["fp64"])
-        return
-    x = torch.empty_like(b)
-
-    def run(name, timing):
-        p = plans[name]
-        p.set_timing(timing)
-        t0 = time.perf_counter()
-        _, info = p.solve(b, out=x)
-        dt = time.perf_counter() - t0
-        kt = p.kernel_times() if timing else None
-        return dt, info, kt
-
-    for w in range(args.warmup):
-        for name in plans:
-            dt, info, _ = run(name, False)
-            log(f"[bench] warmup {name}: {dt:.3f} s iters {info['iters']} status {info['status_name']} "
-                f"rel_res_true {info['rel_res_true']:.3e}")
-
-    timing = 0 if args.no_timing else max(args.timing_period, 1)
-    times = {k: [] for k in plans}
-    infos = {}
-    ktot = {}
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for step in range(args.steps):
-        for name in plans:
-            dt, info, kt = run(name, timing)
-            times[name].append(dt)
-            infos[name] = info
-            if kt:
-                for kk, v in kt.items():
-                    a = ktot.setdefault((name, kk), dict(launches=0.0, ms=0.0, bytes=0.0))
-                    for f in ("launches", "ms", "bytes"):
-                        a[f] += v[f]
-            log(f"[bench] step {step} {name}: {dt:.3f} s iters {info['iters']} "
-                f"refinements {info['refinements']} status {info['status_name']} "
-                f"rel_res_true {info['rel_res_true']:.3e}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-
-    med = {k: float(np.median(v)) for k, v in times.items()}
-    headline = "mixed" if "mixed" in med else ("adaptive" if "adaptive" in med else "fp64")
-    out = {
-        "metric": METRIC,
-        "value": med[headline],
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 * total / max(args.steps, 1),
-        "higher_is_better": False,
-        "scaling": "strong",
-        "vs_baseline": None,
-        "dtype": (f"f32/{args.mixed_basis}+f64" if headline == "mixed" else "f64"),
-        "data": "synthetic",
-        "config": {"workload": f"q1_convection_diffusion_{args.mesh}x{args.mesh}_lognormal",
-                   "unknowns": sysm.n, "nnz": sysm.nnz, "restart_m": m, "deflation_vectors": sysm.r,
-                   "rtol": 1e-8, "step": "+".join(plans), "ortho": args.ortho,
-                   "mixed_basis": args.mixed_basis, "inner_rtol": inner},
-    }
-    if args.adaptive > 0:
-        out["config"].update(workload=f"q1_convection_diffusion_{args.mesh}x{args.mesh}_kappa1",
-                             deflation="adaptive spectral (Ritz vectors of H_k)",
-                             adapt_rmax=args.adaptive, deflation_vectors=0)
-        out["defl_r_adaptive"] = infos["adaptive"]["defl_r"]
-        out["mu_adaptive"] = infos["adaptive"]["mu"]
-    for k in plans:
-        out[f"time_to_rtol_{k}_s"] = med[k]
-        out[f"iters_{k}"] = infos[k]["iters"]
-        out[f"rel_res_true_{k}"] = infos[k]["rel_res_true"]
-    if "mixed" in med and "fp64" in med:
-        out["mixed_speedup_vs_fp64"] = med["fp64"] / med["mixed"]
-        out["refinements_mixed"] = infos["mixed"]["refinements"]
-    if ktot:
-        per = {}
-        for (name, kk), v in ktot.items():
-            if v["launches"] > 0:
-                per[f"{name}.{kk}"] = dict(launches=int(v["launches"]), avg_us=1000 * v["ms"] / v["launches"],
-                                           GBs=v["bytes"] / (v["ms"] * 1e6), total_ms=v["ms"])
-        out["kernels"] = per
-        # Dominant kernel: most total time in the FP64 solve (else the mixed one).
-        src = next(k for k in ("fp64", "adaptive", "mixed") if k in plans)
-        cand = {kk: v for (nm, kk), v in ktot.items() if nm == src and v["launches"] > 0}
-        dom = max(cand, key=lambda kk: cand[kk]["ms"])
-        v = cand[dom]
-        achieved = v["bytes"] / (v["ms"] * 1e6)
-        traffic = None
-        if (src == "fp64" and args.adaptive == 0 and dom == TRAFFIC["kind"] and TRAFFIC["bytes_per_launch"]
-                and TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
-            traffic = TRAFFIC["bytes_per_launch"]
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "traffic_unit": "bytes/launch",
-                           "kernel": f"{src}.{dom}", "launches": int(v["launches"]),
-                           "avg_launch_us": 1000 * v["ms"] / v["launches"],
-                           "bytes_per_launch_avg": v["bytes"] / v["launches"]}
-    if not args.no_cpu_baseline:
-        fp64_iters = infos["fp64"]["iters"] if "fp64" in infos else infos[headline]["iters"]
-        log(f"[bench] cpu baseline: oracle, {args.cpu_sample_iters} steps")
-        out["cpu_baseline"] = cpu_baseline(sysm, m, fp64_iters, args.cpu_sample_iters,
-                                           adapt_rmax=args.adaptive)
-    print(json.dumps(out), flush=True)
+    elif args.adaptive > 0:
+        adaptive_mode(args)
+    elif args.config == 4:
+        batched_config4(args)
+    else:
+        single_config(args)
 
 
 if __name__ == "__main__":
