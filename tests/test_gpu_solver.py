@@ -452,3 +452,100 @@ def test_autograd_kappa_gradient_finite_difference():
               - float(loss(torch.tensor(1.0 - h, dtype=torch.float64, device="cuda")))) / (2 * h)
     say("dL/dkappa adjoint %.10e fd %.10e" % (g, fd))
     assert abs(g - fd) <= 1e-5 * abs(g)
+
+
+def _fd_directions(s, k, seed):
+    """k seeded unit directions jointly over (b, the stored entries of the
+    non-Dirichlet rows of A, kappa): arrays (db, dv, dk)."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    drows = np.nonzero(s.meta["D_vals"] != 0)[0]
+    dirichlet_row = np.zeros(s.n, bool)
+    dirichlet_row[rows[drows]] = True
+    free = ~dirichlet_row[rows]
+    out = []
+    for _ in range(k):
+        db = rng.standard_normal(s.n)
+        db[dirichlet_row] = 0.0
+        dv = np.where(free, rng.standard_normal(s.nnz), 0.0)
+        dk = rng.standard_normal()
+        nrm = np.sqrt(np.dot(db, db) + np.dot(dv, dv) + dk * dk)
+        out.append((db / nrm, dv / nrm, dk / nrm))
+    return out
+
+
+def test_adjoint_32_directions_central_differences():
+    """dL along 32 seeded unit directions over (b, non-Dirichlet values of A,
+    kappa) from one adjoint solve, against central differences (h = 1e-6) of
+    L = 1/2 ||x - x_target||^2 with FP64 solves started from the unperturbed
+    solution (so the solver error scales with h); gate 1e-5 of ||g||."""
+    s = W.make_config(5, mesh=32)
+    plan, d = G().plan_for(s, need_adjoint=True, m=50, rtol=1e-13, max_iters=20000)
+    x, info = plan.solve(d["b"])
+    assert info["status_name"] == "OK"
+    xt = s.meta["x_target"]
+    xn = x.cpu().numpy()
+    gx = torch.from_numpy(xn - xt).cuda()
+    gb, gv, ainfo = plan.adjoint(x, gx)
+    gb, gv = gb.cpu().numpy(), gv.cpu().numpy()
+    Kv = s.meta["K_vals"]
+    gk = float(np.dot(gv, Kv))
+    gnorm = np.sqrt(np.dot(gb, gb) + np.dot(gv, gv) + gk * gk)
+    # Warm-started FD solves: the initial residual is O(h), so rtol = 1e-7 puts
+    # the solver error at O(1e-7 h) (above the FP64 floor) and the FD error
+    # does not grow as h shrinks.
+    fdp, fdd = G().plan_for(s, m=50, rtol=1e-7, max_iters=20000)
+    x0 = torch.from_numpy(xn).cuda()
+    h = 1e-6
+    worst = 0.0
+    for i, (db, dv, dk) in enumerate(_fd_directions(s, 32, 20190610 + 5)):
+        adj = float(np.dot(gb, db) + np.dot(gv, dv) + gk * dk)
+        L = []
+        for sg in (1.0, -1.0):
+            fdp.update_values(torch.from_numpy(s.vals + sg * h * (dv + dk * Kv)).cuda())
+            xs, si = fdp.solve(torch.from_numpy(s.b + sg * h * db).cuda(), x0)
+            assert si["status_name"] == "OK"
+            xs = xs.cpu().numpy()
+            L.append(0.5 * np.dot(xs - xt, xs - xt))
+        fd = (L[0] - L[1]) / (2 * h)
+        err = abs(adj - fd) / gnorm
+        worst = max(worst, err)
+        if i < 4 or err > 1e-6:
+            say(f"direction {i}: adjoint {adj:.10e} central difference {fd:.10e} (|diff|/||g|| {err:.1e})")
+    say(f"32 directions: largest |adjoint - FD| / ||g|| = {worst:.2e}")
+    assert worst <= 1e-5
+
+
+def test_mixed_refinement_escalation_and_stagnation():
+    """Inner solves capped at two steps cannot halve the FP64 residual, so the
+    refinement raises the inner precision: FP16 basis (first refinement),
+    FP32 basis (second: the first did not contract), then an FP64 solve to the
+    final tolerance (third).  With max_refine = 2 the same stall ends in
+    STAGNATED with the refined iterate.  The FP64-accurate result is compared
+    with the oracle's solution through the forward-error bound."""
+    s = W.make_config(2, mesh=48)
+    m = 50
+    ref = oracle.gmres(s, m, 1e-8, 20000)
+    assert ref.status_name == "OK"
+    x, info, plan = _gpu_solve(s, m=m, rtol=1e-8, max_iters=20000, precision="mixed_f16",
+                               inner_rtol=1e-3, inner_max_iters=2, max_refine=10, record_history=1)
+    say("escalation: refinements", info["refinements"], "iterations", info["iters"],
+        "status", info["status_name"], "rel_res_true %.2e" % info["rel_res_true"])
+    assert info["status_name"] == "OK" and info["refinements"] == 3
+    assert info["iters"] > 4                      # 2 + 2 reduced-precision steps, then the FP64 solve
+    r = host_residual(s, x)
+    assert np.linalg.norm(r) <= 1e-8 * ref.rho0 * (1 + 1e-6)
+    assert np.linalg.norm(x - ref.x) <= _forward_error_bound(s, x, ref.x, ref.rho0, 1e-8) * (1 + 1e-6)
+    # The history holds every inner step of all three solves, in order.
+    h = plan.history()
+    assert h.size == info["iters"]
+    assert np.all(np.isfinite(h)) and h[-1] <= 1e-8 * ref.rho0 * 1.01
+    # Stagnation: two refinements allowed, both stall.
+    xs, infs, _ = _gpu_solve(s, m=m, rtol=1e-8, max_iters=20000, precision="mixed_f16",
+                             inner_rtol=1e-3, inner_max_iters=2, max_refine=2)
+    say("stagnation: refinements", infs["refinements"], "status", infs["status_name"],
+        "rel_res_true %.2e" % infs["rel_res_true"])
+    assert infs["status_name"] == "STAGNATED" and infs["refinements"] == 2 and infs["iters"] == 4
+    rs = host_residual(s, xs)
+    assert abs(np.linalg.norm(rs) / ref.rho0 - infs["rel_res_true"]) <= 1e-10
+    assert infs["rel_res_true"] > 1e-8
