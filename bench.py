@@ -39,7 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counter reads for a 512 MiB device copy.  Valid only
 # while the kernel sources hash to `sources_sha256`; None until measured.
 TRAFFIC = {
-    5: {"kind": "pass1_lag", "sources_sha256": None, "bytes_per_launch": None},
+    5: {"kind": "pass1_lag",
+        "sources_sha256": "ecd2d004bf3733e2ba362091fd4f880e8ddf0c7a6bfa46de303f9cc6b91f5bd8",
+        "bytes_per_launch": 1076.5e6},   # 1,008.7 MB read + 67.8 MB written (98 launches)
 }
 KERNEL_SOURCES = ("paper_1906_04051_amd/csrc/krylov.hip", "paper_1906_04051_amd/csrc/common.hpp",
                   "paper_1906_04051_amd/csrc/internal.hpp")
@@ -97,10 +99,10 @@ def cpu_baseline(sysm, m, fp64_iters, sample_iters, adapt_rmax=0):
                 threads=1, **host_info())
 
 
-def pmc_sample(sysm, d, m, tuned):
-    """Two fixed-count restart cycles of the FP64 solve (the timed launch
-    configuration) and one 512 MiB device copy (512 MiB read + 512 MiB
-    written), for FETCH_SIZE / WRITE_SIZE counter runs."""
+def pmc_sample(sysm, d, m, tuned, tuned_mixed=None):
+    """Two fixed-count restart cycles of the FP64 solve and two of the FP16-
+    basis inner solve (the timed launch configuration) and one 512 MiB device
+    copy (512 MiB read + 512 MiB written), for hardware-counter runs."""
     import torch
     from paper_1906_04051_amd import gmres as G
     q = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"], d["z_vals"],
@@ -109,12 +111,25 @@ def pmc_sample(sysm, d, m, tuned):
     q.set_timing(True)
     _, info = q.solve(d["b"])
     kt = q.kernel_times()
+    q.close()
+    per = {"fp64." + k: dict(launches=int(v["launches"]), bytes_per_launch=v["bytes"] / max(v["launches"], 1),
+                             avg_us=1000 * v["ms"] / max(v["launches"], 1)) for k, v in kt.items()}
+    if tuned_mixed:
+        # One refinement whose inner FP16-basis solve runs exactly two cycles.
+        qm = G.Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"], d["z_vals"],
+                    r=sysm.r, precision="mixed_f16", m=m, rtol=1e-30, max_iters=2 * m, inner_rtol=1e-30,
+                    inner_max_iters=2 * m, max_refine=1, spmv_lanes=tuned_mixed["spmv_lanes"],
+                    num_blocks=tuned_mixed["num_blocks"])
+        qm.set_timing(True)
+        qm.solve(d["b"])
+        for k, v in qm.kernel_times().items():
+            per["mixed." + k] = dict(launches=int(v["launches"]), bytes_per_launch=v["bytes"] / max(v["launches"], 1),
+                                     avg_us=1000 * v["ms"] / max(v["launches"], 1))
+        qm.close()
     src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    per = {k: dict(launches=int(v["launches"]), bytes_per_launch=v["bytes"] / max(v["launches"], 1),
-                   avg_us=1000 * v["ms"] / max(v["launches"], 1)) for k, v in kt.items()}
     print(json.dumps({"pmc_sample": per, "iters": info["iters"], "copy_bytes_each_way": 512 << 20,
                       "kernel_sources_sha256": kernel_sources_sha256()}), flush=True)
 
@@ -428,7 +443,7 @@ def single_config(args):
         log(f"[bench] autotune {name}: {tuned[name]}")
     b = d["b"]
     if args.pmc_sample:
-        pmc_sample(sysm, d, m, tuned["fp64"])
+        pmc_sample(sysm, d, m, tuned["fp64"], tuned.get("mixed"))
         return
     x = torch.empty_like(b)
 
