@@ -181,6 +181,7 @@ struct gmres_plan_s {
     int64_t* bout_i = nullptr;
     double* bout_d = nullptr;
     int64_t* d_v_off = nullptr;
+    int64_t* d_w_off = nullptr;
 
     Timer timer;
 };
@@ -365,14 +366,23 @@ void carve_krylov(gmres_plan_s* p, Arena& A) {
 void carve_batched(gmres_plan_s* p, Arena& A) {
     const int ns = p->nsys;
     const int m = p->o.m;
+    // Per-system regions with a leading dimension rounded up to even (16-byte
+    // row pairs): at most one padding row per system.
+    const int64_t padded = p->n + ns;
     if (ns > 1) {
-        p->bV = A.take_n<double>((int64_t)(m + 1) * p->n);
+        p->bV = A.take_n<double>((int64_t)(m + 1) * padded);
         p->btune_x = A.take_n<double>(p->n);
         p->btune_b = A.take_n<double>(p->n);
+        if (p->R > 0) {
+            // Two-entry row copy of A Z over the global rows.
+            p->azc1 = A.take_n<int>(2 * p->n);
+            p->azv1 = A.take_n<double>(2 * p->n);
+        }
     } else {
         p->bV = static_cast<double*>(p->V);
     }
-    p->bW = A.take_n<double>(3 * p->n);
+    p->bW = A.take_n<double>(3 * padded);
+    p->d_w_off = A.take_n<int64_t>(ns);
     p->border = A.take_n<int>(ns);
     p->bticket = A.take_n<int>(1);
     p->bout_i = A.take_n<int64_t>(3 * (int64_t)ns);
@@ -1532,16 +1542,36 @@ static gmres_status init_batched(gmres_plan_s* p) {
         const int64_t wb = (int64_t)(rp_at[b + 1] - rp_at[b]) + (p->row_off[b + 1] - p->row_off[b]);
         return wa > wb;
     });
-    std::vector<int64_t> voff(ns);
-    for (int s = 0; s < ns; ++s) voff[s] = (int64_t)(m + 1) * p->row_off[s];
+    std::vector<int64_t> voff(ns), woff(ns);
+    int64_t acc = 0;
+    for (int s = 0; s < ns; ++s) {
+        const int64_t ld = (p->row_off[s + 1] - p->row_off[s] + 1) & ~int64_t(1);
+        voff[s] = (int64_t)(m + 1) * acc;
+        woff[s] = 3 * acc;
+        acc += ld;
+    }
     HIP_OK(hipMemcpy(p->border, order.data(), ns * sizeof(int), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(p->d_v_off, voff.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->d_w_off, woff.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice));
+    // Padding rows of the work vectors (and, for batches, of the basis) read as zero.
+    HIP_OK(hipMemsetAsync(p->bW, 0, 3 * (size_t)(p->n + ns) * sizeof(double), p->st));
+    if (ns > 1) {
+        HIP_OK(hipMemsetAsync(p->bV, 0, (size_t)(m + 1) * (p->n + ns) * sizeof(double), p->st));
+        if (p->R > 0) {
+            HIP_OK(hipMemsetAsync(p->azc1, 0xFF, 2 * (size_t)p->n * sizeof(int), p->st));
+            refresh_ell1(p);
+        }
+    }
     return GMRES_OK;
 }
 
 static gmres_status run_batched(gmres_plan_s* p, const double* b, const double* x0, double* x,
                                 int64_t max_iters, int wg, int lanes) {
     HIP_OK(hipMemsetAsync(p->bticket, 0, sizeof(int), p->st));
+    // A single-system plan lends its Krylov basis: clear it so that the padding
+    // row of the batched layout reads as zero.
+    if (p->nsys == 1)
+        HIP_OK(hipMemsetAsync(p->bV, 0, (size_t)(p->o.m + 1) * (p->n + 1) * sizeof(double), p->st));
     BatchArgs a{};
     a.st = p->st;
     a.nsys = p->nsys;
@@ -1554,6 +1584,17 @@ static gmres_status run_batched(gmres_plan_s* p, const double* b, const double* 
     a.zcol_off = p->d_zcol_off;
     a.e_off = p->d_e_off;
     a.v_off = p->d_v_off;
+    a.w_off = p->d_w_off;
+    a.zc1 = p->zc1;
+    a.zv1 = p->zv1;
+    a.az2c = p->azc1;
+    a.az2v = p->azv1;
+    if (p->sell_col && !p->sell_perm) {     // rows in order: a system's rows are a range of positions
+        a.sell_off = p->sell_off;
+        a.sell_wuni = p->sell_wuni;
+        a.sell_col = p->sell_col;
+        a.sell_val = p->sell_v64;
+    }
     a.order = p->border;
     a.rowptr = p->rowptr;
     a.colind = p->colind;

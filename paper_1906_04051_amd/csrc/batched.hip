@@ -74,15 +74,24 @@ __device__ __forceinline__ void bsum_cols(const double (&acc)[MB / T], double ac
     __syncthreads();
 }
 
+// 16-byte loads and stores of row pairs (the per-system regions start at even
+// offsets and have an even leading dimension).
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ __forceinline__ void st2(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+
+constexpr int kZf = 16;   // deflation columns per system that the SpMV's fused Z^T y holds per lane
+
 template <int WGS, int L, int MB>
 __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
     constexpr int NW = WGS / kWave;
-    constexpr int kRows = WGS / L;
-    constexpr int T = MB / 8;            // lanes per row in the passes (8 columns per lane)
+    constexpr int kRows = WGS / L;       // rows per SpMV round (L lanes per row)
+    constexpr int T = MB / 8;            // lanes per row pair in the sweeps (8 columns per lane)
     constexpr int JT = MB / T;
-    constexpr int PR = WGS / T;          // rows per pass iteration
+    constexpr int PR = WGS / T;          // row pairs per sweep round
+    constexpr int U = 2;                 // sweep rounds whose loads are in flight together
     __shared__ double red[NW][MB + 1];
     __shared__ double sred[NW];
+    __shared__ double zred[NW][kZf];
     __shared__ double Hs[(MB + 1) * MB];
     __shared__ double cs[MB], sn[MB], g[MB + 1], vscale[MB + 1];
     __shared__ double h1[MB + 1], h2[MB + 1], coef[MB + 1], tvec[kMaxR], svec[kMaxR];
@@ -91,6 +100,8 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
 
     const int m = a.m;
     const int lane = threadIdx.x & (L - 1);
+    const int sub = threadIdx.x & (T - 1);
+    const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
     for (;;) {
         if (threadIdx.x == 0) {
             const int t = atomicAdd(a.ticket, 1);
@@ -103,41 +114,31 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
 
         const int64_t r0 = a.row_off[sys];
         const int n = (int)(a.row_off[sys + 1] - r0);
+        const int np = (n + 1) / 2;              // row pairs
+        const int64_t ld = 2 * (int64_t)np;      // leading dimension of the system's regions
         const int64_t c0 = a.zcol_off[sys];
         const int R = (int)(a.zcol_off[sys + 1] - c0);
+        const bool fz = R > 0 && R <= kZf;       // Z^T y fused into the SpMV
         const double* Einv = a.Einv + a.e_off[sys];
         double* V = a.V + a.v_off[sys];
-        const int64_t ldv = n;
-        double* y = a.W + 3 * r0;
-        double* w = y + n;
-        double* rr = w + n;
+        double* y = a.W + a.w_off[sys];
+        double* w = y + ld;
+        double* rr = w + ld;
         double* x = a.x + r0;
         const double* b = a.b + r0;
         uint64_t t_start = wall_clock64();
 
-        // Residual r = b - A x of the current x (global row/col indices).
-        auto residual = [&](double* out) -> double {
-            double acc = 0;
-            for (int row = threadIdx.x / L; row < n; row += kRows) {
-                const int64_t gi = r0 + row;
-                const int k0 = a.rowptr[gi], k1 = a.rowptr[gi + 1];
+        // svec = E^{-1} tvec (tvec = Z^T vec, local deflation columns).
+        auto coarse_solve = [&]() {
+            for (int i = threadIdx.x; i < R; i += WGS) {
                 double s = 0;
-                for (int k = k0 + lane; k < k1; k += L) s += a.vals[k] * x[a.colind[k] - r0];
-#pragma unroll
-                for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
-                if (lane == 0) {
-                    const double ri = b[row] - s;
-                    out[row] = ri;
-                    acc += ri * ri;
-                }
+                for (int c = 0; c < R; ++c) s += Einv[(int64_t)c * R + i] * tvec[c];
+                svec[i] = s;
             }
             __syncthreads();
-            return bsum<WGS>(acc, sred);
         };
-        // svec = E^{-1} Z^T vec  (one wave per row of Z^T, then a small matvec).
-        auto coarse = [&](const double* vec) {
-            if (R == 0) return;
-            const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
+        // tvec = Z^T vec one wavefront per row of Z^T (when not fused).
+        auto zt_waves = [&](const double* vec) {
             for (int c = wv; c < R; c += NW) {
                 const int q0 = a.ztrp[c0 + c], q1 = a.ztrp[c0 + c + 1];
                 double s = 0;
@@ -146,22 +147,153 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 if (ln == 0) tvec[c] = s;
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < R; i += WGS) {
-                double s = 0;
-                for (int c = 0; c < R; ++c) s += Einv[(int64_t)c * R + i] * tvec[c];
-                svec[i] = s;
+        };
+        // Per-lane Z^T partials of one row value, summed over the workgroup
+        // in fixed order by zt_finish.
+        auto zt_add = [&](double (&zacc)[kZf], int64_t gi, double v) {
+            const int zc = a.zc1[gi];
+            if (zc >= 0) {
+                const double t = a.zv1[gi] * v;
+#pragma unroll
+                for (int c = 0; c < kZf; ++c) zacc[c] += (zc - (int)c0 == c) ? t : 0.0;
+            } else if (zc == -2) {
+                for (int q = a.zrp[gi]; q < a.zrp[gi + 1]; ++q) {
+                    const int cz = a.zci[q] - (int)c0;
+                    const double t = a.zv[q] * v;
+#pragma unroll
+                    for (int c = 0; c < kZf; ++c) zacc[c] += (cz == c) ? t : 0.0;
+                }
+            }
+        };
+        auto zt_finish = [&](double (&zacc)[kZf]) {
+#pragma unroll
+            for (int c = 0; c < kZf; ++c) {
+                const double t = wave_sum(zacc[c]);
+                if (ln == 0) zred[wv][c] = t;
+            }
+            __syncthreads();
+            if (threadIdx.x < R) {
+                double t = zred[0][threadIdx.x];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) t += zred[q][threadIdx.x];
+                tvec[threadIdx.x] = t;
             }
             __syncthreads();
         };
-        auto deflate_row = [&](int64_t gi, double v) -> double {
-            for (int q = a.azrp[gi]; q < a.azrp[gi + 1]; ++q) v -= a.azv[q] * svec[a.azci[q] - c0];
+        // out = scale * A xin (mode 0) or out = b - A xin (residual), two rows
+        // per lane group in flight; with fz also tvec = Z^T out.  Returns the
+        // workgroup sum of out^2 (residual mode).
+        auto spmv = [&](const double* xin, double scale, bool resid, double* out) -> double {
+            double zacc[kZf];
+#pragma unroll
+            for (int c = 0; c < kZf; ++c) zacc[c] = 0.0;
+            double acc = 0;
+            if (a.sell_col) {
+                // Sliced ELL: one wavefront per 64-row slice overlapping the
+                // system (rows of other systems in an edge slice are skipped);
+                // the entries of a chunk are loaded before any gather.
+                constexpr int CH = 16;
+                const int64_t sl0 = r0 / kWave, sl1 = (r0 + n + kWave - 1) / kWave;
+                for (int64_t sl = sl0 + wv; sl < sl1; sl += NW) {
+                    const int64_t gi = sl * kWave + ln;
+                    const bool ok = gi >= r0 && gi < r0 + n;
+                    int q0, w;
+                    if (a.sell_wuni > 0) {
+                        q0 = (int)(sl * a.sell_wuni * kWave);
+                        w = a.sell_wuni;
+                    } else {
+                        q0 = __builtin_amdgcn_readfirstlane(a.sell_off[sl]);
+                        w = (__builtin_amdgcn_readfirstlane(a.sell_off[sl + 1]) - q0) / kWave;
+                    }
+                    const double bvv = (resid && ok) ? b[gi - r0] : 0.0;
+                    // Rows outside the system gather from the system's own first row.
+                    const double* xr = xin + (ok ? gi - r0 : 0);
+                    double s = 0;
+                    for (int k0 = 0; k0 < w; k0 += CH) {
+                        short cc[CH];
+                        double vv[CH];
+#pragma unroll
+                        for (int k = 0; k < CH; ++k) {
+                            const int qk = q0 + min(k0 + k, w - 1) * kWave + ln;
+                            cc[k] = a.sell_col[qk];
+                            vv[k] = a.sell_val[qk];
+                        }
+                        double xv[CH];
+#pragma unroll
+                        for (int k = 0; k < CH; ++k) xv[k] = xr[ok ? (int)cc[k] : 0];
+#pragma unroll
+                        for (int k = 0; k < CH; ++k) s += (ok && k0 + k < w) ? vv[k] * xv[k] : 0.0;
+                    }
+                    if (ok) {
+                        const double v = resid ? bvv - s : s * scale;
+                        out[gi - r0] = v;
+                        if (resid) acc += v * v;
+                        if (fz) zt_add(zacc, gi, v);
+                    }
+                }
+                __syncthreads();
+                if (fz) zt_finish(zacc);
+                else if (R > 0) zt_waves(out);
+                return resid ? bsum<WGS>(acc, sred) : 0.0;
+            }
+            for (int row0 = threadIdx.x / L; row0 < n; row0 += 2 * kRows) {
+                int k0[2], k1[2];
+                double bv[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int row = row0 + u * kRows;
+                    const bool ok = row < n;
+                    k0[u] = ok ? a.rowptr[r0 + row] : 0;
+                    k1[u] = ok ? a.rowptr[r0 + row + 1] : 0;
+                    bv[u] = (resid && ok) ? b[row] : 0.0;
+                }
+                double sacc[2] = {0.0, 0.0};
+                for (int e = lane;; e += L) {
+                    const bool ok0 = k0[0] + e < k1[0], ok1 = k0[1] + e < k1[1];
+                    if (!ok0 && !ok1) break;
+                    const int col0 = ok0 ? a.colind[k0[0] + e] : (int)r0;
+                    const int col1 = ok1 ? a.colind[k0[1] + e] : (int)r0;
+                    const double v0 = ok0 ? a.vals[k0[0] + e] : 0.0;
+                    const double v1 = ok1 ? a.vals[k0[1] + e] : 0.0;
+                    sacc[0] += v0 * xin[col0 - r0];
+                    sacc[1] += v1 * xin[col1 - r0];
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                    for (int o = L / 2; o > 0; o >>= 1) sacc[u] += __shfl_xor(sacc[u], o, L);
+                    const int row = row0 + u * kRows;
+                    if (lane == 0 && row < n) {
+                        const double v = resid ? bv[u] - sacc[u] : sacc[u] * scale;
+                        out[row] = v;
+                        if (resid) acc += v * v;
+                        if (fz) zt_add(zacc, r0 + row, v);
+                    }
+                }
+            }
+            __syncthreads();
+            if (fz) zt_finish(zacc);
+            else if (R > 0) zt_waves(out);
+            return resid ? bsum<WGS>(acc, sred) : 0.0;
+        };
+        // v - (A Z)_row svec for local row i < n (two-entry row copy, else CSR).
+        auto deflate_row = [&](int i, double v) -> double {
+            const int64_t gi = r0 + i;
+            const int2 c2 = *reinterpret_cast<const int2*>(a.az2c + 2 * gi);
+            if (c2.x >= 0) {
+                const double2 v2 = ld2(a.az2v + 2 * gi);
+                v -= v2.x * svec[c2.x - c0];
+                if (c2.y >= 0) v -= v2.y * svec[c2.y - c0];
+            } else if (c2.x == -2) {
+                for (int q = a.azrp[gi]; q < a.azrp[gi + 1]; ++q) v -= a.azv[q] * svec[a.azci[q] - c0];
+            }
             return v;
         };
 
         // x0
         for (int i = threadIdx.x; i < n; i += WGS) x[i] = a.x0 ? a.x0[r0 + i] : 0.0;
         __syncthreads();
-        const double rho0 = sqrt(residual(rr));
+        const double rho0 = sqrt(spmv(x, 1.0, true, rr));
         const double target = a.rtol * rho0;
         int64_t its = 0;
         int cycles = 0;
@@ -169,15 +301,13 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
         double beta = 0.0;
         bool first = true;
         for (;;) {
-            if (!first) {
-                residual(rr);
-            }
+            if (!first) spmv(x, 1.0, true, rr);
             first = false;
             if (rho0 == 0.0) { beta = 0.0; break; }
-            coarse(rr);
+            if (R > 0) coarse_solve();
             double accn = 0;
             for (int i = threadIdx.x; i < n; i += WGS) {
-                const double p = deflate_row(r0 + i, rr[i]);
+                const double p = R > 0 ? deflate_row(i, rr[i]) : rr[i];
                 V[i] = p;
                 accn += p * p;
             }
@@ -195,39 +325,44 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
             int kk = 0;
             for (int j = 0; j < m && its < a.max_iters; ++j) {
                 const int nv = j + 1;
-                const double* vj = V + (int64_t)j * ldv;
-                const double sj = vscale[j];
-                // y = A v_j (normalised)
-                for (int row = threadIdx.x / L; row < n; row += kRows) {
-                    const int64_t gi = r0 + row;
-                    const int k0 = a.rowptr[gi], k1 = a.rowptr[gi + 1];
-                    double s = 0;
-                    for (int k = k0 + lane; k < k1; k += L) s += a.vals[k] * vj[a.colind[k] - r0];
-#pragma unroll
-                    for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
-                    if (lane == 0) y[row] = s * sj;
-                }
-                __syncthreads();
-                coarse(y);
-                // pass 1: w = P y; dots with stored basis; ||w||^2
-                const int sub = threadIdx.x & (T - 1);
+                // y = A v_j (normalised); tvec = Z^T y
+                spmv(V + (int64_t)j * ld, vscale[j], false, y);
+                if (R > 0) coarse_solve();
+                // pass 1: w = P y; dots with the stored basis; ||w||^2
                 double acc[JT];
 #pragma unroll
                 for (int q = 0; q < JT; ++q) acc[q] = 0;
                 accn = 0;
-                for (int i = threadIdx.x / T; i < n; i += PR) {
-                    double vv[JT];
+                for (int p0 = threadIdx.x / T; p0 < np; p0 += U * PR) {
+                    double2 vv[U][JT], yy[U];
 #pragma unroll
-                    for (int q = 0; q < JT; ++q)
-                        if (sub + q * T < nv) vv[q] = V[(int64_t)(sub + q * T) * ldv + i];
-                    const double wi = (R > 0) ? deflate_row(r0 + i, y[i]) : y[i];
-                    if (sub == 0) {
-                        w[i] = wi;
-                        accn += wi * wi;
+                    for (int u = 0; u < U; ++u) {
+                        const int pp = p0 + u * PR;
+                        const bool ok = pp < np;
+#pragma unroll
+                        for (int q = 0; q < JT; ++q) {
+                            const int k = sub + q * T;
+                            vv[u][q] = (ok && k < nv) ? ld2(V + (int64_t)k * ld + 2 * pp) : make_double2(0.0, 0.0);
+                        }
+                        yy[u] = ok ? ld2(y + 2 * pp) : make_double2(0.0, 0.0);
                     }
 #pragma unroll
-                    for (int q = 0; q < JT; ++q)
-                        if (sub + q * T < nv) acc[q] += vv[q] * wi;
+                    for (int u = 0; u < U; ++u) {
+                        const int pp = p0 + u * PR;
+                        if (pp >= np) continue;
+                        const int i = 2 * pp;
+                        double2 wv2 = yy[u];
+                        if (R > 0) {
+                            wv2.x = deflate_row(i, wv2.x);
+                            wv2.y = (i + 1 < n) ? deflate_row(i + 1, wv2.y) : 0.0;
+                        }
+                        if (sub == 0) {
+                            st2(w + i, wv2);
+                            accn += wv2.x * wv2.x + wv2.y * wv2.y;
+                        }
+#pragma unroll
+                        for (int q = 0; q < JT; ++q) acc[q] += vv[u][q].x * wv2.x + vv[u][q].y * wv2.y;
+                    }
                 }
                 bsum_cols<WGS, MB, T>(acc, accn, nv, red, h1);
                 const double wpre2 = h1[nv];
@@ -236,27 +371,48 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                     coef[k] = h1[k] * vscale[k];
                 }
                 __syncthreads();
-                // pass 2
+                // pass 2: w -= V coef; dots; ||w||^2
+                double cr[JT];
 #pragma unroll
-                for (int q = 0; q < JT; ++q) acc[q] = 0;
+                for (int q = 0; q < JT; ++q) {
+                    const int k = sub + q * T;
+                    cr[q] = k < nv ? coef[k] : 0.0;
+                    acc[q] = 0;
+                }
                 accn = 0;
-                for (int i = threadIdx.x / T; i < n; i += PR) {
-                    double vv[JT];
+                for (int p0 = threadIdx.x / T; p0 < np; p0 += U * PR) {
+                    double2 vv[U][JT], ww[U];
 #pragma unroll
-                    for (int q = 0; q < JT; ++q)
-                        if (sub + q * T < nv) vv[q] = V[(int64_t)(sub + q * T) * ldv + i];
-                    double u = 0;
+                    for (int u = 0; u < U; ++u) {
+                        const int pp = p0 + u * PR;
+                        const bool ok = pp < np;
 #pragma unroll
-                    for (int q = 0; q < JT; ++q)
-                        if (sub + q * T < nv) u += vv[q] * coef[sub + q * T];
-                    const double wi = w[i] - gsum<T>(u);
-                    if (sub == 0) {
-                        w[i] = wi;
-                        accn += wi * wi;
+                        for (int q = 0; q < JT; ++q) {
+                            const int k = sub + q * T;
+                            vv[u][q] = (ok && k < nv) ? ld2(V + (int64_t)k * ld + 2 * pp) : make_double2(0.0, 0.0);
+                        }
+                        ww[u] = ok ? ld2(w + 2 * pp) : make_double2(0.0, 0.0);
                     }
 #pragma unroll
-                    for (int q = 0; q < JT; ++q)
-                        if (sub + q * T < nv) acc[q] += vv[q] * wi;
+                    for (int u = 0; u < U; ++u) {
+                        const int pp = p0 + u * PR;
+                        double ux = 0, uy = 0;
+#pragma unroll
+                        for (int q = 0; q < JT; ++q) {
+                            ux += vv[u][q].x * cr[q];
+                            uy += vv[u][q].y * cr[q];
+                        }
+                        ux = gsum<T>(ux);
+                        uy = gsum<T>(uy);
+                        if (pp >= np) continue;
+                        const double2 wv2 = make_double2(ww[u].x - ux, ww[u].y - uy);
+                        if (sub == 0) {
+                            st2(w + 2 * pp, wv2);
+                            accn += wv2.x * wv2.x + wv2.y * wv2.y;
+                        }
+#pragma unroll
+                        for (int q = 0; q < JT; ++q) acc[q] += vv[u][q].x * wv2.x + vv[u][q].y * wv2.y;
+                    }
                 }
                 bsum_cols<WGS, MB, T>(acc, accn, nv, red, h2);
                 for (int k = threadIdx.x; k < nv; k += WGS) {
@@ -265,17 +421,41 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 }
                 __syncthreads();
                 // pass 3: new basis column
-                double* vout = V + (int64_t)nv * ldv;
-                accn = 0;
-                for (int i = threadIdx.x / T; i < n; i += PR) {
-                    double u = 0;
 #pragma unroll
-                    for (int q = 0; q < JT; ++q)
-                        if (sub + q * T < nv) u += V[(int64_t)(sub + q * T) * ldv + i] * coef[sub + q * T];
-                    const double wi = w[i] - gsum<T>(u);
-                    if (sub == 0) {
-                        vout[i] = wi;
-                        accn += wi * wi;
+                for (int q = 0; q < JT; ++q) {
+                    const int k = sub + q * T;
+                    cr[q] = k < nv ? coef[k] : 0.0;
+                }
+                double* vout = V + (int64_t)nv * ld;
+                accn = 0;
+                for (int p0 = threadIdx.x / T; p0 < np; p0 += U * PR) {
+                    double2 vv[U][JT], ww[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int pp = p0 + u * PR;
+                        const bool ok = pp < np;
+#pragma unroll
+                        for (int q = 0; q < JT; ++q) {
+                            const int k = sub + q * T;
+                            vv[u][q] = (ok && k < nv) ? ld2(V + (int64_t)k * ld + 2 * pp) : make_double2(0.0, 0.0);
+                        }
+                        ww[u] = ok ? ld2(w + 2 * pp) : make_double2(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int pp = p0 + u * PR;
+                        double ux = 0, uy = 0;
+#pragma unroll
+                        for (int q = 0; q < JT; ++q) {
+                            ux += vv[u][q].x * cr[q];
+                            uy += vv[u][q].y * cr[q];
+                        }
+                        ux = gsum<T>(ux);
+                        uy = gsum<T>(uy);
+                        if (pp >= np || sub != 0) continue;
+                        const double2 wv2 = make_double2(ww[u].x - ux, ww[u].y - uy);
+                        st2(vout + 2 * pp, wv2);
+                        accn += wv2.x * wv2.x + wv2.y * wv2.y;
                     }
                 }
                 const double hn = sqrt(bsum<WGS>(accn, sred));
@@ -312,12 +492,13 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
             }
             for (int i = threadIdx.x; i < n; i += WGS) {
                 double acc = 0;
-                for (int t = 0; t < kk; ++t) acc += V[(int64_t)t * ldv + i] * coef[t];
+                for (int t = 0; t < kk; ++t) acc += V[(int64_t)t * ld + i] * coef[t];
                 x[i] += acc;
             }
             __syncthreads();
         }
-        // Final coarse correction x = x_hat + Z E^{-1} Z^T (b - A x_hat).
+        // Final coarse correction x = x_hat + Z E^{-1} Z^T (b - A x_hat)
+        // (svec holds E^{-1} Z^T r of the last restart).
         if (rho0 > 0.0 && R > 0) {
             for (int i = threadIdx.x; i < n; i += WGS) {
                 double v = x[i];

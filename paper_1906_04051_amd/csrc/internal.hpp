@@ -291,6 +291,7 @@ struct BatchArgs {
     int64_t max_iters;
     double rtol;
     const int64_t *row_off, *zcol_off, *e_off, *v_off;   // device
+    const int64_t* w_off;                                 // per-system work-vector regions
     const int* order;                                     // systems by decreasing work
     const int *rowptr, *colind;
     const double* vals;
@@ -300,11 +301,21 @@ struct BatchArgs {
     const double* zv;
     const int *ztrp, *ztci;
     const double* ztv;
+    const int* zc1;          // Z single-entry rows (ELL-1, global rows; -2: several entries)
+    const double* zv1;
+    const int* az2c;         // A Z two-entry rows (ELL-2, global rows; -2: three or more)
+    const double* az2v;
+    // Sliced-ELL copy of the whole block-diagonal matrix in row order (NULL:
+    // CSR rows): slice s holds rows 64s .. 64s + 63, column offsets col - row.
+    const int* sell_off;
+    int sell_wuni;           // > 0: every slice this wide (offsets computed)
+    const short* sell_col;
+    const double* sell_val;
     const double* Einv;
     const double *b, *x0;
     double* x;
-    double* V;               // per-system basis regions
-    double* W;               // per-system work vectors (3 per row)
+    double* V;               // per-system basis regions ((m + 1) columns of ld = n_s rounded to even)
+    double* W;               // per-system work vectors (3 of ld entries each, padding zero)
     double* small;           // per-system small state
     int64_t small_stride;
     int* ticket;
