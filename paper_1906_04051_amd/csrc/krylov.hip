@@ -334,9 +334,14 @@ __global__ __launch_bounds__(NT) void k_spmv_sell(int n, const int* __restrict__
 }
 
 // s = E^{-1} t with t_a = sum of the slots of deflation column a, which are
-// stored contiguously (tpart[ab_ptr[a] .. ab_ptr[a+1]), increasing row blocks);
-// each column's range is split over G = kCT / R threads whose partial sums
-// are added in order.
+// stored contiguously (tpart[ab_ptr[a] .. ab_ptr[a+1]), increasing row blocks).
+// Column a goes to a run of SG consecutive threads (SG = the largest power of
+// two with R * SG <= kCT); member g reads slots q0 + g, q0 + g + SG, ..., so
+// neighbouring lanes read neighbouring slots and up to kSU loads per thread
+// are in flight at once.  Each thread adds its loads in order, the run adds
+// its members by butterfly (within a wavefront) and then by wavefront in
+// order.  The slot ranges, this thread's E^{-1} entries and the control
+// block are requested together before any slot is read.
 __global__ __launch_bounds__(kCT) void k_coarse_slots(int R, const int* __restrict__ ab_ptr,
                                                       const double* __restrict__ tpart,
                                                       const double* __restrict__ Einv, int trans,
@@ -344,15 +349,17 @@ __global__ __launch_bounds__(kCT) void k_coarse_slots(int R, const int* __restri
                                                       int gate) {
     __shared__ double t[kMaxR];
     __shared__ double red[kCT];
+    int SG = kCT;
+    while (SG * R > kCT) SG >>= 1;
+    const int col = threadIdx.x / SG, g = threadIdx.x % SG;
+    int q0 = 0, q1 = 0;
+    if (col < R) {
+        q0 = ab_ptr[col];
+        q1 = ab_ptr[col + 1];
+    }
+    // E^{-1} entries of this thread (same split as coarse_matvec).
     const int G = max(1, kCT / R);
     const int grp = threadIdx.x / R, a = threadIdx.x % R;
-    // The slot ranges, this thread's E^{-1} entries and the control block are
-    // requested together; the slot sums follow.
-    int q0 = 0, q1 = 0;
-    if (grp < G) {
-        q0 = ab_ptr[a];
-        q1 = ab_ptr[a + 1];
-    }
     constexpr int kEmax = 8;   // prefetched entries per thread (R up to about 90)
     double ev[kEmax];
     const int espan = (R + G - 1) / G;
@@ -366,19 +373,33 @@ __global__ __launch_bounds__(kCT) void k_coarse_slots(int R, const int* __restri
         }
     }
     if (gated(ctrl, gate)) return;
+    constexpr int kSU = 16;
     double acc = 0;
-    if (grp < G) {
-        const int span = (q1 - q0 + G - 1) / G;
-        const int b0 = q0 + grp * span, b1 = min(q1, b0 + span);
-#pragma unroll 8
-        for (int q = b0; q < b1; ++q) acc += tpart[q];
+    for (int qb = q0 + g; qb < q1; qb += kSU * SG) {
+        double v[kSU];
+#pragma unroll
+        for (int u = 0; u < kSU; ++u) {
+            const int q = qb + u * SG;
+            v[u] = q < q1 ? tpart[q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSU; ++u) acc += v[u];
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x < R) {
-        double v = red[threadIdx.x];
-        for (int q = 1; q < G; ++q) v += red[q * R + threadIdx.x];
-        t[threadIdx.x] = v;
+    // Runs of SG <= kWave lanes are aligned inside a wavefront, so xor
+    // partners below SG stay in the run.
+    const int lw = min(SG, kWave);
+    for (int o = lw / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if (SG <= kWave) {
+        if (g == 0 && col < R) t[col] = acc;
+    } else {
+        const int wv = threadIdx.x / kWave;
+        if ((threadIdx.x & (kWave - 1)) == 0) red[wv] = acc;
+        __syncthreads();
+        if (g == 0 && col < R) {
+            double v = red[wv];
+            for (int q = 1; q < SG / kWave; ++q) v += red[wv + q];
+            t[col] = v;
+        }
     }
     __syncthreads();
     if (!pre) {
