@@ -599,13 +599,16 @@ struct CacheUse {
     int cols;
     int stream;
 };
-static CacheUse cache_use_for(const gmres_plan_s* p, int op) {
+static CacheUse cache_use_for(const gmres_plan_s* p, int op, int prec) {
     constexpr double kUsable = 0.94 * 256.0 * 1024.0 * 1024.0;
-    const double n = (double)p->n, col = 8.0 * n;
-    double resident = 3.0 * 8.0 * n + (p->R > 0 ? 36.0 * n : 0.0);
+    // Bytes per row of a work vector and of a basis column, per matrix entry.
+    const double wb = (prec == kPrecF64) ? 8.0 : 4.0;
+    const double vb = (prec == kPrecF64) ? 8.0 : (prec == kPrecF32 ? 4.0 : 2.0);
+    const double n = (double)p->n, col = vb * n;
+    double resident = 3.0 * wb * n + (p->R > 0 ? (12.0 + 3.0 * wb) * n : 0.0);
     const int64_t sell = op ? p->tsell_total : p->sell_total;
-    const double mat = (p->L == kSell && sell > 0) ? 10.0 * (double)sell + 4.0 * n
-                                                  : 12.0 * (double)p->nnz + 4.0 * (n + 1.0);
+    const double mat = (p->L == kSell && sell > 0) ? (2.0 + wb) * (double)sell + 4.0 * n
+                                                  : (4.0 + wb) * (double)p->nnz + 4.0 * (n + 1.0);
     const bool fits = resident + mat <= kUsable;
     if (fits) resident += mat;
     const double c = std::floor((kUsable - resident) / col);
@@ -711,7 +714,7 @@ EngineArgs make_args(gmres_plan_s* p, int op, int prec) {
     a.ctrl = p->ctrl;
     a.lagged = p->o.ortho == 1 ? 1 : 0;
     a.dcgs = p->o.ortho == 2 ? 1 : 0;
-    const CacheUse cu = cache_use_for(p, op);
+    const CacheUse cu = cache_use_for(p, op, prec);
     a.cache_cols = cu.cols;
     a.sell_stream = cu.stream;
     a.dcs = p->dcs;
