@@ -45,9 +45,13 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build()
-    lib = C.CDLL(_LIB)
+    override = os.environ.get("ORACLE_LIB")   # another build of the same sources (sanitizers)
+    if override:
+        lib = C.CDLL(override)
+    else:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
     i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
     i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
     f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")

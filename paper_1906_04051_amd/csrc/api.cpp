@@ -14,12 +14,15 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "../../include/gmres.h"
 #include "internal.hpp"
+#include "trace.hpp"
 
 using namespace gm;
 
@@ -854,7 +857,12 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
     }
     launch_ctrl_reset(p->st, p->ctrl, max_iters, p->hist_pos);
     launch_restart_init(a, b, rtol, r0_override);
+    static const char* const kCycleName[2][3] = {{"cycle fp64", "cycle fp32", "cycle fp16-basis"},
+                                                 {"cycle adjoint fp64", "cycle adjoint fp32",
+                                                  "cycle adjoint fp16-basis"}};
+    TraceSpan span[2];
     auto enqueue = [&](int c) -> gmres_status {
+        span[c & 1].start(kCycleName[op ? 1 : 0][prec]);
         const bool timed = period > 0 && c % period == 0;
         if (timed) {
             hook.cycle = c;
@@ -874,12 +882,15 @@ gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double
     for (int64_t c = 1; c <= cap + 1; ++c) {
         if (c <= cap) CHECK(enqueue((int)c));
         HIP_OK(hipEventSynchronize(p->ev_cyc[(c - 1) & 1]));
+        span[(c - 1) & 1].stop();
         if (p->ctrl_h[(c - 1) & 1].done) {
             finished = true;
             break;
         }
     }
     HIP_OK(hipStreamSynchronize(p->st));
+    span[0].stop();
+    span[1].stop();
     HIP_OK(hipMemcpy(out, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
     if (period > 0) collect_timer(p, out->cycles);
     p->hist_pos += out->its;   // the next run of the same solve records after these steps
@@ -982,6 +993,7 @@ gmres_status solve_mixed(gmres_plan_s* p, const double* b, const double* x0, dou
     int status = GMRES_MAXITER;
     int stalls = 0;
     for (int ref = 0;; ++ref) {
+        TraceRange tr_ref("refinement");
         const double rho = std::sqrt(nrm2);
         if (rho <= target) {
             status = GMRES_OK;
@@ -1317,6 +1329,7 @@ gmres_status gmres_setup(gmres_plan* out, int32_t nsys, const int64_t* sys_row_o
                          const int32_t* z_rowptr, const int32_t* z_colind, const double* z_vals,
                          int64_t z_nnz, const gmres_opts* opts, int32_t need_adjoint,
                          void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    TraceRange tr_("gmres_setup");
     if (!out) return fail(GMRES_EINVAL, "out is NULL");
     *out = nullptr;
     g_ws_required = 0;
@@ -1343,6 +1356,7 @@ gmres_status gmres_set_stream(gmres_plan p, hipStream_t stream) {
 
 gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double* x,
                          gmres_info* info_h) {
+    TraceRange tr_("gmres_solve");
     if (!p || !b || !x) return fail(GMRES_EINVAL, "plan, b and x are required");
     if (p->nsys != 1) return fail(GMRES_EINVAL, "gmres_solve needs a single-system plan");
     if (x == b) return fail(GMRES_EINVAL, "x must not alias b");
@@ -1370,6 +1384,7 @@ gmres_status gmres_solve(gmres_plan p, const double* b, const double* x0, double
 static gmres_status solve_block_impl(gmres_plan p, int32_t k, int32_t m_block, const double* B,
                                      const double* X0, double* X, void* work, size_t work_bytes,
                                      gmres_info* info_h) {
+    TraceRange tr_("gmres_solve_block");
     if (!p || !B || !X) return fail(GMRES_EINVAL, "plan, B and X are required");
     if (p->nsys != 1) return fail(GMRES_EINVAL, "gmres_solve_block needs a single-system plan");
     if (p->R > 0 || p->o.adapt_rmax > 0)
@@ -1464,6 +1479,7 @@ gmres_status gmres_solve_block_noalloc(gmres_plan p, int32_t k, int32_t m_block,
 
 gmres_status gmres_adjoint(gmres_plan p, const double* x, const double* grad_x, double* grad_b,
                            double* grad_vals, gmres_info* info_h) {
+    TraceRange tr_("gmres_adjoint");
     if (!p || !x || !grad_x) return fail(GMRES_EINVAL, "plan, x and grad_x are required");
     if (!p->need_adjoint) return fail(GMRES_EINVAL, "plan was built without need_adjoint");
     const auto t0 = std::chrono::steady_clock::now();
@@ -1491,6 +1507,7 @@ gmres_status gmres_adjoint(gmres_plan p, const double* x, const double* grad_x, 
 }
 
 gmres_status gmres_update_values(gmres_plan p, const double* vals) {
+    TraceRange tr_("gmres_update_values");
     if (!p || (!vals && p->nnz > 0)) return fail(GMRES_EINVAL, "plan and vals are required");
     CHECK(enter(p));
     if (p->nnz > 0)
@@ -1631,6 +1648,7 @@ static gmres_status run_batched(gmres_plan_s* p, const double* b, const double* 
 
 gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0, double* x,
                                  gmres_info* infos_h) {
+    TraceRange tr_("gmres_solve_batched");
     if (!p || !b || !x) return fail(GMRES_EINVAL, "plan, b and x are required");
     if (p->o.m > 64) return fail(GMRES_EINVAL, "the batched solver supports m <= 64");
     if (x == b) return fail(GMRES_EINVAL, "x must not alias b");
@@ -1668,8 +1686,71 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
     return worst;
 }
 
+// Autotune cache (GMRES_TUNE_CACHE names a text file): one line per tuned
+// plan shape, "<key>\t<lanes> <grid> <batch workgroup> <batch lanes>"; the
+// key holds the device (architecture, compute units) and everything the
+// choices depend on.  The last line with a matching key wins; a choice the
+// plan cannot run (sliced ELL not built, grid above the resident cap) is
+// ignored and the plan is tuned again.  Appends are not locked against other
+// processes writing the same file.
+static std::string tune_key(const gmres_plan_s* p) {
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return std::string();
+    std::ostringstream k;
+    k << "v1 arch=" << prop.gcnArchName << " cu=" << prop.multiProcessorCount << " nsys=" << p->nsys
+      << " n=" << p->n << " nnz=" << p->nnz << " R=" << p->R << " m=" << p->o.m
+      << " prec=" << p->o.precision << " ortho=" << p->o.ortho << " sell=" << (p->sell_col ? p->sell_total : -1);
+    return k.str();
+}
+
+static bool tune_cache_read(const char* path, const std::string& key, int32_t (&v)[4]) {
+    std::ifstream in(path);
+    if (!in) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
+        std::istringstream vs(line.substr(tab + 1));
+        int32_t t[4];
+        if (vs >> t[0] >> t[1] >> t[2] >> t[3]) {
+            for (int i = 0; i < 4; ++i) v[i] = t[i];
+            found = true;
+        }
+    }
+    return found;
+}
+
+static void tune_cache_append(const char* path, const std::string& key, const gmres_plan_s* p) {
+    std::ofstream out(path, std::ios::app);
+    if (out) out << key << '\t' << p->L << ' ' << p->NB << ' ' << p->batch_wg << ' ' << p->batch_L << '\n';
+}
+
+static bool tune_choice_valid(const gmres_plan_s* p, const int32_t (&v)[4]) {
+    const bool lanes_ok = (v[0] == kSell && p->sell_col) ||
+                          (v[0] == -256 || v[0] == 2 || v[0] == 4 || v[0] == 8 || v[0] == 16 || v[0] == 32);
+    const bool nb_ok = v[1] >= 1 && v[1] <= p->NB_cap;
+    const bool batch_ok = (v[2] == 256 || v[2] == 512 || v[2] == 1024) &&
+                          (v[3] == 4 || v[3] == 8 || v[3] == 16 || v[3] == 32);
+    return lanes_ok && nb_ok && batch_ok;
+}
+
 gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
+    TraceRange tr_("gmres_autotune");
     if (!p) return fail(GMRES_EINVAL, "plan is NULL");
+    const char* cache = std::getenv("GMRES_TUNE_CACHE");
+    const std::string key = (cache && cache[0]) ? tune_key(p) : std::string();
+    int32_t cached[4];
+    if (!key.empty() && tune_cache_read(cache, key, cached) && tune_choice_valid(p, cached)) {
+        p->L = cached[0];
+        p->NB = cached[1];
+        p->batch_wg = cached[2];
+        p->batch_L = cached[3];
+        drop_graphs(p);
+        if (chosen_h)
+            for (int i = 0; i < 4; ++i) chosen_h[i] = cached[i];
+        return GMRES_OK;
+    }
     CHECK(enter(p));
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
@@ -1742,6 +1823,7 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h) {
     hipEventDestroy(e1);
     HIP_OK(hipStreamSynchronize(p->st));
     CHECK(leave(p));
+    if (!key.empty()) tune_cache_append(cache, key, p);
     if (chosen_h) {
         chosen_h[0] = p->L;
         chosen_h[1] = p->NB;

@@ -67,9 +67,12 @@ def load_library():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1906_04051_amd.build`")
-    lib = C.CDLL(LIB_PATH)
+    # GMRES_LIB: another build of the same sources (the host-sanitizer or the
+    # bounds-checking build); the release build otherwise.
+    path = os.environ.get("GMRES_LIB") or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1906_04051_amd.build`")
+    lib = C.CDLL(path)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     lib.gmres_default_opts.argtypes = [C.POINTER(GmresOpts)]
     lib.gmres_default_opts.restype = None
