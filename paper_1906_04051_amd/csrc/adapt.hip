@@ -612,4 +612,6 @@ void adapt_cycle_end(const EngineArgs& e, const double* V, const double* coef) {
     k_afinal<<<1, 1, 0, st>>>(a.st, e.ctrl, 1);
 }
 
+GM_DEBUG_ACCESSOR(dbg_take_adapt)
+
 }  // namespace gm

@@ -934,7 +934,26 @@ gmres_status enter(gmres_plan_s* p) {
     return GMRES_OK;
 }
 
+// Bounds-checking build: waits for the plan's stream and turns any failed
+// device check into GMRES_EDEVICE.
+gmres_status debug_checks(gmres_plan_s* p) {
+#ifdef GMRES_DEBUG
+    HIP_OK(hipStreamSynchronize(p->st));
+    const unsigned int bits = dbg_take_krylov() | dbg_take_batched() | dbg_take_block() |
+                              dbg_take_setup() | dbg_take_adapt();
+    if (bits) {
+        char msg[96];
+        std::snprintf(msg, sizeof msg, "device bounds check failed (bits 0x%x)", bits);
+        return fail(GMRES_EDEVICE, msg);
+    }
+#else
+    (void)p;
+#endif
+    return GMRES_OK;
+}
+
 gmres_status leave(gmres_plan_s* p) {
+    CHECK(debug_checks(p));
     HIP_OK(hipEventRecord(p->ev_out, p->st));
     HIP_OK(hipStreamWaitEvent(p->user_stream, p->ev_out, 0));
     return GMRES_OK;

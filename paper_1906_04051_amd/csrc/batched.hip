@@ -220,7 +220,11 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                         }
                         double xv[CH];
 #pragma unroll
-                        for (int k = 0; k < CH; ++k) xv[k] = xr[ok ? (int)cc[k] : 0];
+                        for (int k = 0; k < CH; ++k) {
+                            GM_DCHECK(!ok || k0 + k >= w || (gi - r0 + cc[k] >= 0 && gi - r0 + cc[k] < n),
+                                      kDbgBatchCol);
+                            xv[k] = xr[ok ? (int)cc[k] : 0];
+                        }
 #pragma unroll
                         for (int k = 0; k < CH; ++k) s += (ok && k0 + k < w) ? vv[k] * xv[k] : 0.0;
                     }
@@ -255,6 +259,7 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                     const int col1 = ok1 ? a.colind[k0[1] + e] : (int)r0;
                     const double v0 = ok0 ? a.vals[k0[0] + e] : 0.0;
                     const double v1 = ok1 ? a.vals[k0[1] + e] : 0.0;
+                    GM_DCHECK(col0 - r0 >= 0 && col0 - r0 < n && col1 - r0 >= 0 && col1 - r0 < n, kDbgBatchCol);
                     sacc[0] += v0 * xin[col0 - r0];
                     sacc[1] += v1 * xin[col1 - r0];
                 }
@@ -571,5 +576,7 @@ void launch_batched(const BatchArgs& a, int nwg) {
             break;
     }
 }
+
+GM_DEBUG_ACCESSOR(dbg_take_batched)
 
 }  // namespace gm

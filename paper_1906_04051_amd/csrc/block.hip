@@ -92,6 +92,8 @@ __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict_
             int q = q0;
             for (; q + 4 <= q1; q += 4) {
                 const int c0 = colind[q], c1 = colind[q + 1], c2 = colind[q + 2], c3 = colind[q + 3];
+                GM_DCHECK(min(min(c0, c1), min(c2, c3)) >= 0 && max(max(c0, c1), max(c2, c3)) < n,
+                          kDbgBlockCol);
                 const double a0 = vals[q], a1 = vals[q + 1], a2 = vals[q + 2], a3 = vals[q + 3];
                 const double x0 = X[(int64_t)c0 * kBW + c], x1 = X[(int64_t)c1 * kBW + c];
                 const double x2 = X[(int64_t)c2 * kBW + c], x3 = X[(int64_t)c3 * kBW + c];
@@ -100,7 +102,10 @@ __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict_
                 acc += a2 * x2;
                 acc += a3 * x3;
             }
-            for (; q < q1; ++q) acc += vals[q] * X[(int64_t)colind[q] * kBW + c];
+            for (; q < q1; ++q) {
+                GM_DCHECK(colind[q] >= 0 && colind[q] < n, kDbgBlockCol);
+                acc += vals[q] * X[(int64_t)colind[q] * kBW + c];
+            }
             if (MODE == 0) {
                 Y[row * kBW + c] = acc;
             } else {
@@ -819,5 +824,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
     res->rel_res_true = tr;
     return kStatusOk;
 }
+
+GM_DEBUG_ACCESSOR(dbg_take_block)
 
 }  // namespace gm

@@ -17,6 +17,40 @@ constexpr int kAzRowMax = 64;       // largest row length of the compact A*Z ope
 constexpr int kBlockColsMax = 64;   // deflation columns per SpMV row block (fused Z^T y)
 constexpr int kXcd = 8;             // accelerator complex dies (own L2 each); blocks go round-robin
 
+// ------------------------------------------------------ bounds-checking build
+// Built with -DGMRES_DEBUG (`python -m paper_1906_04051_amd.build --debug`),
+// GM_DCHECK(cond, bit) ORs `bit` into this translation unit's device flag word
+// when cond fails and lets the kernel go on; after every API call the host
+// waits for the plan's stream, reads and clears the words of every unit and
+// returns GMRES_EDEVICE naming the bits.  Release builds compile the checks
+// away.  Bits: column index of a CSR row, of a sliced-ELL row, deflation
+// column of a Z or A Z entry, slot range of the fused Z^T y partials, column
+// of a batched system's row outside its system, column of the block SpMM.
+constexpr unsigned kDbgCsrCol = 1u, kDbgSellCol = 2u, kDbgDeflCol = 4u, kDbgSlot = 8u,
+                   kDbgBatchCol = 16u, kDbgBlockCol = 32u;
+#ifdef GMRES_DEBUG
+static __device__ unsigned int g_dbg_flags;
+#define GM_DCHECK(cond, bit)                                   \
+    do {                                                       \
+        if (!(cond)) atomicOr(&::gm::g_dbg_flags, (bit));      \
+    } while (0)
+#define GM_DEBUG_ACCESSOR(fn)                                                              \
+    unsigned int fn() {                                                                    \
+        unsigned int v = 0, z = 0;                                                         \
+        if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(::gm::g_dbg_flags), sizeof v) != hipSuccess) \
+            return 0x80000000u;                                                            \
+        if (v && hipMemcpyToSymbol(HIP_SYMBOL(::gm::g_dbg_flags), &z, sizeof z) != hipSuccess) \
+            return v | 0x80000000u;                                                        \
+        return v;                                                                          \
+    }
+#else
+#define GM_DCHECK(cond, bit) \
+    do {                     \
+    } while (0)
+#define GM_DEBUG_ACCESSOR(fn) \
+    unsigned int fn() { return 0; }
+#endif
+
 // Device-resident control block of one solve.  Every kernel of a restart
 // cycle reads it, so the host launches whole cycles without synchronising.
 struct Ctrl {

@@ -375,4 +375,12 @@ void* static_scratch(int device, size_t* bytes);
 void block_delete(BlockWork* w);
 int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res);
 
+// Flag words of the bounds-checking build, one per translation unit (read
+// and cleared; 0 in release builds).
+unsigned int dbg_take_krylov();
+unsigned int dbg_take_batched();
+unsigned int dbg_take_block();
+unsigned int dbg_take_setup();
+unsigned int dbg_take_adapt();
+
 }  // namespace gm

@@ -47,6 +47,7 @@ __device__ __forceinline__ void block_slots(int l0, int l1, const int* __restric
     const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
     for (int l = l0; l < l1; ++l) {
         const int col = bb_col[l];
+        GM_DCHECK(l1 - l0 <= kBlockColsMax, kDbgSlot);
         ACC c = 0;
         if (valid) {
             if (zc >= 0) {
@@ -54,6 +55,7 @@ __device__ __forceinline__ void block_slots(int l0, int l1, const int* __restric
             } else if (zc == -2) {
                 for (int q = zrp[row]; q < zrp[row + 1]; ++q)
                     if (zci[q] == col) c += (ACC)zv[q] * yi;
+                GM_DCHECK(zrp[row] <= zrp[row + 1], kDbgDeflCol);
             }
         }
         c = wave_sum(c);
@@ -85,7 +87,10 @@ __global__ __launch_bounds__(kWG) void k_spmv(int n, const int* __restrict__ row
     for (int row = blockIdx.x * kRows + threadIdx.x / L; row < n; row += gridDim.x * kRows) {
         const int k0 = rowptr[row], k1 = rowptr[row + 1];
         ACC s = 0;
-        for (int k = k0 + lane; k < k1; k += L) s += (ACC)vals[k] * (ACC)ld_f(x + colind[k]);
+        for (int k = k0 + lane; k < k1; k += L) {
+            GM_DCHECK(colind[k] >= 0 && colind[k] < n, kDbgCsrCol);
+            s += (ACC)vals[k] * (ACC)ld_f(x + colind[k]);
+        }
 #pragma unroll
         for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
         if (lane == 0) y[row] = (YT)(s * scale);
@@ -146,11 +151,17 @@ __global__ __launch_bounds__(RB) void k_spmv_stream(int n, const int* __restrict
             __syncthreads();
             if (row < rend) {
                 const int a = rowptr[row] - k0, e = rowptr[row + 1] - k0;
-                for (int q = a; q < e; ++q) acc += (ACC)sv[q] * (ACC)ld_f(x + sc[q]);
+                for (int q = a; q < e; ++q) {
+                    GM_DCHECK(sc[q] >= 0 && sc[q] < n, kDbgCsrCol);
+                    acc += (ACC)sv[q] * (ACC)ld_f(x + sc[q]);
+                }
             }
             __syncthreads();
         } else if (row < rend) {
-            for (int k = rowptr[row]; k < rowptr[row + 1]; ++k) acc += (ACC)vals[k] * (ACC)ld_f(x + colind[k]);
+            for (int k = rowptr[row]; k < rowptr[row + 1]; ++k) {
+                GM_DCHECK(colind[k] >= 0 && colind[k] < n, kDbgCsrCol);
+                acc += (ACC)vals[k] * (ACC)ld_f(x + colind[k]);
+            }
         }
         ACC yi = 0;
         if (row < rend) {
@@ -275,7 +286,10 @@ __global__ __launch_bounds__(NT) void k_spmv_sell(int n, const int* __restrict__
                     }
                     ACC xv[WMAX];
 #pragma unroll
-                    for (int k = 0; k < WMAX; ++k) xv[k] = (ACC)ld_f(xr + cc[k]);
+                    for (int k = 0; k < WMAX; ++k) {
+                        GM_DCHECK(row + cc[k] >= 0 && row + cc[k] < n, kDbgSellCol);
+                        xv[k] = (ACC)ld_f(xr + cc[k]);
+                    }
 #pragma unroll
                     for (int k = 0; k < WMAX; ++k) acc += k < w ? (ACC)vv[k] * xv[k] : (ACC)0;
                 } else {
@@ -296,6 +310,7 @@ __global__ __launch_bounds__(NT) void k_spmv_sell(int n, const int* __restrict__
                         AT va[CH];
 #pragma unroll
                         for (int k = 0; k < CH; ++k) {
+                            GM_DCHECK(row + cc[k] >= 0 && row + cc[k] < n, kDbgSellCol);
                             va[k] = ld_mat<kStream>(sval + q + min(k0 + k, w - 1) * kWave);
                             xv[k] = (ACC)ld_f(xr + cc[k]);
                         }
@@ -356,6 +371,7 @@ __global__ __launch_bounds__(kCT) void k_coarse_slots(int R, const int* __restri
     if (col < R) {
         q0 = ab_ptr[col];
         q1 = ab_ptr[col + 1];
+        GM_DCHECK(0 <= q0 && q0 <= q1, kDbgSlot);
     }
     // E^{-1} entries of this thread (same split as coarse_matvec).
     const int G = max(1, kCT / R);
@@ -689,6 +705,8 @@ __device__ __forceinline__ void deflate_tile(int64_t i0, const int* __restrict__
     bool multi = false;
 #pragma unroll
     for (int e = 0; e < RT; ++e) {
+        GM_DCHECK(ac[2 * e] >= -2 && ac[2 * e] < kMaxR && ac[2 * e + 1] >= -1 && ac[2 * e + 1] < kMaxR,
+                  kDbgDeflCol);
         u[e] -= av[2 * e] * s_l[max(ac[2 * e], 0)] + av[2 * e + 1] * s_l[max(ac[2 * e + 1], 0)];
         multi |= ac[2 * e] == -2;
     }
@@ -697,7 +715,10 @@ __device__ __forceinline__ void deflate_tile(int64_t i0, const int* __restrict__
         for (int e = 0; e < RT; ++e) {
             if (ac[2 * e] == -2) {
                 const int64_t i = i0 + e;
-                for (int q = azrp[i]; q < azrp[i + 1]; ++q) u[e] -= (ACC)azv[q] * s_l[azci[q]];
+                for (int q = azrp[i]; q < azrp[i + 1]; ++q) {
+                    GM_DCHECK(azci[q] >= 0 && azci[q] < kMaxR, kDbgDeflCol);
+                    u[e] -= (ACC)azv[q] * s_l[azci[q]];
+                }
             }
         }
     }
@@ -2251,5 +2272,7 @@ void launch_copy(hipStream_t st, const double* a, double* b, int64_t n) {
     const int64_t nb = std::min<int64_t>((n + kWG - 1) / kWG, 2048);
     if (nb > 0) k_copy_f64<<<(int)nb, kWG, 0, st>>>(a, b, n);
 }
+
+GM_DEBUG_ACCESSOR(dbg_take_krylov)
 
 }  // namespace gm

@@ -882,4 +882,6 @@ int zt_max_row(hipStream_t st, int R, const int* ztrp, int* d_tmp) {
     return h;
 }
 
+GM_DEBUG_ACCESSOR(dbg_take_setup)
+
 }  // namespace gm

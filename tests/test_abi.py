@@ -22,10 +22,13 @@ def test_header_declares_binding_exports():
     assert _declared() == sorted(G.EXPORTS)
 
 
-def test_library_exports_every_declared_symbol():
-    if not os.path.exists(G.LIB_PATH):
-        pytest.fail("libgmres_mi355x.so is not built (run __graft_entry__.build())")
-    lib = ctypes.CDLL(G.LIB_PATH)
+@pytest.mark.parametrize("variant", ["release", "bounds-checking"])
+def test_library_exports_every_declared_symbol(variant):
+    from paper_1906_04051_amd import build as B
+    path = G.LIB_PATH if variant == "release" else B.LIB_DEBUG
+    if not os.path.exists(path):
+        pytest.fail(f"{os.path.basename(path)} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
     for name in _declared():
         assert hasattr(lib, name), name
 
