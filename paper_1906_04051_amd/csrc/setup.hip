@@ -4,10 +4,9 @@
 // with partial pivoting (the coarse matrix is the analogue of the paper's
 // T_r = U^T A U, arXiv 1906.04051 Sec. 3.3, eq. tau_mat).
 //
-// All pattern work is deterministic: transposes use a stable radix sort, A Z
-// rows accumulate in CSR order, E entries in Z^T order.
-#include <hipcub/hipcub.hpp>
-
+// All pattern work is deterministic: transposes use a stable radix sort (its
+// own kernels below), A Z rows accumulate in CSR order, E entries in Z^T
+// order.
 #include <vector>
 
 #include "internal.hpp"
@@ -92,11 +91,6 @@ __global__ void k_row_of(int64_t n, const int* __restrict__ rowptr, int* __restr
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) row_of[k] = (int)i;
-}
-
-__global__ void k_iota(int64_t n, int* __restrict__ p) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = (int)i;
 }
 
 // trowptr[c] = first position q with key[q] >= c (keys sorted).
@@ -216,16 +210,139 @@ static int end_bit_for(int64_t ncols) {
     return end_bit;
 }
 
-static size_t sort_temp_bytes(int64_t items, int end_bit) {
-    size_t tb = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const int*)nullptr, (int*)nullptr,
-                                       (const int*)nullptr, (int*)nullptr, (int)std::max<int64_t>(items, 1),
-                                       0, end_bit, (hipStream_t)0);
-    return Arena::round(tb);
+// ------------------------------------------------------------ radix sort
+// Stable LSD radix sort of (key, input position) pairs, 8 bits of the key
+// per pass.  Each pass: a digit histogram per tile of kRadixTile consecutive
+// items; an exclusive scan of the histogram table in digit-major order, so
+// digit d of tile t starts after every smaller digit and after digit d of
+// the tiles before t; then a scatter in which each item takes its tile's
+// next position for its digit plus its rank among the tile's earlier items
+// of that digit.  A tile is read in rounds of kWG items; within a round the
+// rank is the count of lower lanes of the wavefront with the same digit
+// (eight ballots, one per digit bit), plus the counts of the lower
+// wavefronts, kept in LDS; the next positions advance by each round's
+// totals.  Equal keys therefore keep their input order, and the output does
+// not depend on scheduling.
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixRounds = 8;
+constexpr int kRadixTile = kWG * kRadixRounds;
+static_assert(kRadixBins == kWG, "one thread per digit");
+
+__global__ __launch_bounds__(kWG) void k_radix_hist(int64_t N, const int* __restrict__ keys, int shift,
+                                                    int64_t ntiles, int* __restrict__ hist) {
+    __shared__ int cnt[kRadixBins];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = blockIdx.x;
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = t * kRadixTile + r * kWG + threadIdx.x;
+        if (i < N) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + t] = cnt[threadIdx.x];
+}
+
+// vals_in == nullptr: the values are the input positions (first pass).
+__global__ __launch_bounds__(kWG) void k_radix_scatter(int64_t N, const int* __restrict__ keys_in,
+                                                       const int* __restrict__ vals_in, int shift,
+                                                       int64_t ntiles, const int* __restrict__ offs,
+                                                       int* __restrict__ keys_out,
+                                                       int* __restrict__ vals_out) {
+    constexpr int NW = kWG / kWave;
+    __shared__ int next[kRadixBins];          // next output position of each digit in this tile
+    __shared__ int wcnt[NW][kRadixBins];      // this round's count per wavefront and digit
+    const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
+    const int64_t t = blockIdx.x;
+    next[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + t];
+    const unsigned long long below = (1ull << ln) - 1ull;
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = t * kRadixTile + r * kWG + threadIdx.x;
+        const bool ok = i < N;
+        const int key = ok ? keys_in[i] : 0;
+        const int val = ok ? (vals_in ? vals_in[i] : (int)i) : 0;
+        const int d = (key >> shift) & (kRadixBins - 1);
+        unsigned long long m = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1;
+            const unsigned long long bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        for (int q = threadIdx.x; q < NW * kRadixBins; q += kWG) (&wcnt[0][0])[q] = 0;
+        __syncthreads();
+        const int rank = __popcll(m & below);
+        if (ok && rank == 0) wcnt[wv][d] = __popcll(m);
+        __syncthreads();
+        int pos = 0;
+        if (ok) {
+            pos = next[d] + rank;
+            for (int w = 0; w < wv; ++w) pos += wcnt[w][d];
+        }
+        __syncthreads();   // every lane has read next[] for this round
+        {
+            int tot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) tot += wcnt[w][threadIdx.x];
+            next[threadIdx.x] += tot;
+        }
+        if (ok) {
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();   // before the next round clears wcnt
+    }
+}
+
+static int radix_passes(int end_bit) { return std::max(1, (end_bit + kRadixBits - 1) / kRadixBits); }
+static int64_t radix_tiles(int64_t N) { return std::max<int64_t>((N + kRadixTile - 1) / kRadixTile, 1); }
+
+static size_t radix_temp_bytes(int64_t N, int end_bit) {
+    const int64_t table = kRadixBins * radix_tiles(N);
+    const size_t pong =
+        radix_passes(end_bit) > 1 ? 2 * Arena::round(std::max<int64_t>(N, 1) * sizeof(int)) : 0;
+    return 2 * Arena::round(table * sizeof(int)) + pong + scan_temp_bytes(table);
+}
+
+// keys_out / perm_out (N entries each): the keys sorted stably and the input
+// position of each.  Keys must lie in [0, 2^end_bit).
+static int radix_sort_pairs(hipStream_t st, Arena& ar, int64_t N, const int* keys_in, int end_bit,
+                            int* keys_out, int* perm_out) {
+    if (N == 0) return kStatusOk;
+    const size_t mk = ar.mark();
+    const int P = radix_passes(end_bit);
+    const int64_t ntiles = radix_tiles(N);
+    const int64_t table = kRadixBins * ntiles;
+    int* hist = ar.temp_n<int>(table);
+    int* offs = ar.temp_n<int>(table);
+    int* kt = P > 1 ? ar.temp_n<int>(N) : nullptr;
+    int* vt = P > 1 ? ar.temp_n<int>(N) : nullptr;
+    int status = (!hist || !offs || (P > 1 && (!kt || !vt))) ? kStatusNoMem : kStatusOk;
+    const int* kin = keys_in;
+    const int* vin = nullptr;
+    for (int p = 0; p < P && status == kStatusOk; ++p) {
+        // The last pass writes the caller's buffers; earlier ones alternate.
+        const bool to_out = ((P - 1 - p) % 2) == 0;
+        int* ko = to_out ? keys_out : kt;
+        int* vo = to_out ? perm_out : vt;
+        const int shift = p * kRadixBits;
+        k_radix_hist<<<(unsigned)ntiles, kWG, 0, st>>>(N, kin, shift, ntiles, hist);
+        int64_t total = 0;
+        status = scan_i32(st, ar, hist, offs, table, &total);
+        if (status == kStatusOk && total != N) status = kStatusDevice;
+        if (status != kStatusOk) break;
+        k_radix_scatter<<<(unsigned)ntiles, kWG, 0, st>>>(N, kin, vin, shift, ntiles, offs, ko, vo);
+        kin = ko;
+        vin = vo;
+    }
+    if (status == kStatusOk && hipGetLastError() != hipSuccess) status = kStatusDevice;
+    ar.release(mk);
+    return status;
 }
 
 size_t transpose_temp_bytes(int64_t ncols, int64_t nnz) {
-    return 3 * Arena::round(std::max<int64_t>(nnz, 1) * sizeof(int)) + sort_temp_bytes(nnz, end_bit_for(ncols));
+    return 2 * Arena::round(std::max<int64_t>(nnz, 1) * sizeof(int)) + radix_temp_bytes(nnz, end_bit_for(ncols));
 }
 
 // Transpose of an nrows x ncols CSR pattern: a stable sort of the entries by
@@ -238,25 +355,19 @@ int build_transpose(hipStream_t st, Arena& ar, int64_t nrows, int64_t ncols, int
         return hipGetLastError() == hipSuccess ? kStatusOk : kStatusDevice;
     }
     const size_t mk = ar.mark();
-    const int end_bit = end_bit_for(ncols);
     int* row_of = ar.temp_n<int>(nnz);
     int* keys_out = ar.temp_n<int>(nnz);
-    int* iota = ar.temp_n<int>(nnz);
-    size_t tmp_bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, colind, keys_out, iota, tperm, (int)nnz, 0,
-                                       end_bit, st);
-    void* tmp = ar.temp(tmp_bytes);
     int status = kStatusOk;
-    if (!row_of || !keys_out || !iota || !tmp) {
+    if (!row_of || !keys_out) {
         status = kStatusNoMem;
     } else {
         k_row_of<<<blocks_for(nrows), kWG, 0, st>>>(nrows, rowptr, row_of);
-        k_iota<<<blocks_for(nnz), kWG, 0, st>>>(nnz, iota);
-        hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, colind, keys_out, iota, tperm, (int)nnz, 0,
-                                           end_bit, st);
-        k_bounds<<<blocks_for(nnz + 1), kWG, 0, st>>>(nnz, ncols, keys_out, trowptr);
-        k_take_rows<<<blocks_for(nnz), kWG, 0, st>>>(nnz, tperm, row_of, tcolind);
-        if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+        status = radix_sort_pairs(st, ar, nnz, colind, end_bit_for(ncols), keys_out, tperm);
+        if (status == kStatusOk) {
+            k_bounds<<<blocks_for(nnz + 1), kWG, 0, st>>>(nnz, ncols, keys_out, trowptr);
+            k_take_rows<<<blocks_for(nnz), kWG, 0, st>>>(nnz, tperm, row_of, tcolind);
+            if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+        }
     }
     ar.release(mk);
     return status;
@@ -716,7 +827,7 @@ __global__ void k_block_cols(int64_t n, int RB, int64_t nblk, const int* __restr
 size_t block_slots_temp_bytes(int64_t n, int RB, int R, int64_t cap) {
     const int64_t nblk = (n + RB - 1) / RB;
     return Arena::round((nblk + 1) * sizeof(int)) + scan_temp_bytes(nblk + 1) +
-           2 * Arena::round(std::max<int64_t>(cap, 1) * sizeof(int)) + sort_temp_bytes(cap, end_bit_for(R));
+           Arena::round(std::max<int64_t>(cap, 1) * sizeof(int)) + radix_temp_bytes(cap, end_bit_for(R));
 }
 
 int build_block_slots(hipStream_t st, Arena& ar, int64_t n, int RB, int R, const int* zrp,
@@ -739,22 +850,16 @@ int build_block_slots(hipStream_t st, Arena& ar, int64_t n, int RB, int R, const
         else if (fl || ns > cap) status = kStatusInval;   // some block reaches too many columns
     }
     if (status == kStatusOk) {
-        const int end_bit = end_bit_for(R);
         int* keys_out = ar.temp_n<int>(ns);
-        int* iota = ar.temp_n<int>(ns);
-        size_t tb = 0;
-        hipcub::DeviceRadixSort::SortPairs(nullptr, tb, bb_col, keys_out, iota, ab_slot, (int)ns, 0,
-                                           end_bit, st);
-        void* tmp = ar.temp(tb);
-        if (!keys_out || !iota || !tmp) {
+        if (!keys_out) {
             status = kStatusNoMem;
         } else {
             k_block_cols<<<blocks_for(nblk), kWG, 0, st>>>(n, RB, nblk, zrp, zci, bb_ptr, bb_col, d_flags);
-            k_iota<<<blocks_for(ns), kWG, 0, st>>>(ns, iota);
-            hipcub::DeviceRadixSort::SortPairs(tmp, tb, bb_col, keys_out, iota, ab_slot, (int)ns, 0,
-                                               end_bit, st);
-            k_bounds<<<blocks_for(ns + 1), kWG, 0, st>>>(ns, R, keys_out, ab_ptr);
-            if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+            status = radix_sort_pairs(st, ar, ns, bb_col, end_bit_for(R), keys_out, ab_slot);
+            if (status == kStatusOk) {
+                k_bounds<<<blocks_for(ns + 1), kWG, 0, st>>>(ns, R, keys_out, ab_ptr);
+                if (hipStreamSynchronize(st) != hipSuccess) status = kStatusDevice;
+            }
         }
     }
     ar.release(mk);
