@@ -572,6 +572,66 @@ __device__ __forceinline__ void store_tile(T* __restrict__ p, const ACC (&in)[R]
     }
 }
 
+// Exactly R consecutive entries (R * sizeof(T) = 2, 4, 8 or a multiple of 16
+// bytes, at an address aligned to that size or to 16 bytes).
+template <typename T, int R>
+struct RowBytes {
+    static constexpr int B = R * (int)sizeof(T);
+    static_assert(B == 2 || B == 4 || B == 8 || B % 16 == 0, "row group of 2, 4, 8 or 16k bytes");
+};
+
+template <typename T, int R, typename ACC>
+__device__ __forceinline__ void load_rows(const T* __restrict__ p, ACC (&out)[R]) {
+    constexpr int B = RowBytes<T, R>::B;
+    T tmp[R];
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 16; ++c) {
+            const uint4 u = reinterpret_cast<const uint4*>(p)[c];
+            __builtin_memcpy(reinterpret_cast<char*>(tmp) + 16 * c, &u, 16);
+        }
+    } else if constexpr (B == 8) {
+        const uint2 u = *reinterpret_cast<const uint2*>(p);
+        __builtin_memcpy(tmp, &u, 8);
+    } else if constexpr (B == 4) {
+        const unsigned int u = *reinterpret_cast<const unsigned int*>(p);
+        __builtin_memcpy(tmp, &u, 4);
+    } else {
+        const unsigned short u = *reinterpret_cast<const unsigned short*>(p);
+        __builtin_memcpy(tmp, &u, 2);
+    }
+#pragma unroll
+    for (int e = 0; e < R; ++e) out[e] = (ACC)ld_f(tmp + e);
+}
+
+template <typename T, int R, typename ACC>
+__device__ __forceinline__ void store_rows(T* __restrict__ p, const ACC (&in)[R]) {
+    constexpr int B = RowBytes<T, R>::B;
+    T tmp[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) st_v(tmp + e, in[e]);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 16; ++c) {
+            uint4 u;
+            __builtin_memcpy(&u, reinterpret_cast<const char*>(tmp) + 16 * c, 16);
+            reinterpret_cast<uint4*>(p)[c] = u;
+        }
+    } else if constexpr (B == 8) {
+        uint2 u;
+        __builtin_memcpy(&u, tmp, 8);
+        *reinterpret_cast<uint2*>(p) = u;
+    } else if constexpr (B == 4) {
+        unsigned int u;
+        __builtin_memcpy(&u, tmp, 4);
+        *reinterpret_cast<unsigned int*>(p) = u;
+    } else {
+        unsigned short u;
+        __builtin_memcpy(&u, tmp, 2);
+        *reinterpret_cast<unsigned short*>(p) = u;
+    }
+}
+
 template <int R>
 __device__ __forceinline__ void load_ints(const int* __restrict__ p, int (&out)[R]) {
     if constexpr (R == 2) {
@@ -701,7 +761,7 @@ __device__ __forceinline__ void deflate_tile(int64_t i0, const int* __restrict__
     int ac[2 * RT];
     ACC av[2 * RT];
     load_ints<2 * RT>(azc2 + 2 * i0, ac);
-    load_tile<AZT, 2 * RT, ACC>(azv2 + 2 * i0, av);
+    load_rows<AZT, 2 * RT, ACC>(azv2 + 2 * i0, av);
     bool multi = false;
 #pragma unroll
     for (int e = 0; e < RT; ++e) {
@@ -930,9 +990,66 @@ __global__ __launch_bounds__(kWG) void k_pass1_lag(int n, int64_t ldv, VT* __res
     for (int q = 0; q < JT; ++q) acc[q] = 0;
     ACC accn = 0, accd = 0;
     const int64_t stride = (int64_t)gridDim.x * (kWG / T) * RT;
+    // With T > 1 lanes per tile, the first TS = min(T, RT) lanes of a tile
+    // group each own RS = RT / TS of its rows: the owner alone loads their
+    // w1, A w1 and A Z entries, deflates, forms and stores them and adds
+    // them to the norms; the group then shares the new w rows (lane
+    // shuffles) for the dot products.  With one lane per tile that lane
+    // handles all RT rows.
+    constexpr bool kSplit = T > 1;
+    constexpr int TS = T < RT ? T : RT;
+    constexpr int RS = kSplit ? RT / TS : RT;
+    const bool owner = sub < TS;
+    const int e0 = (kSplit && owner) ? sub * RS : 0;
+    const int gbase = (threadIdx.x & (kWave - 1)) & ~(T - 1);
     for (int64_t i0 = (((int64_t)blockIdx.x * kWG + threadIdx.x) / T) * RT; i0 < n; i0 += stride) {
         uint4 raw[JT];
         load_cols<JT, T, VT>(V, ldv, nvr, sub, i0, keep, raw);
+        if constexpr (kSplit) {
+            ACC w1[RS], u[RS];
+#pragma unroll
+            for (int r = 0; r < RS; ++r) w1[r] = u[r] = (ACC)0;
+            if (owner) {
+                load_rows<WT, RS, ACC>(w + i0 + e0, w1);
+                load_rows<WT, RS, ACC>(y + i0 + e0, u);
+                if (R > 0) deflate_tile<RS, AZT, ACC>(i0 + e0, azrp, azci, azv, azc2, azv2, s_l, u);
+            }
+            // Group sums for every row of the tile (all lanes take part), then
+            // this lane's rows picked out with compile-time register indices.
+            ACC a2o[RS], a3o[RS];
+#pragma unroll
+            for (int r = 0; r < RS; ++r) a2o[r] = a3o[r] = (ACC)0;
+#pragma unroll
+            for (int e = 0; e < RT; ++e) {
+                const ACC a2 = combine_row<JT, T, VT, ACC>(raw, c2r, e);
+                const ACC a3 = combine_row<JT, T, VT, ACC>(raw, ccr, e);
+                const bool mine = (e / RS) == sub;
+                a2o[e % RS] = mine ? a2 : a2o[e % RS];
+                a3o[e % RS] = mine ? a3 : a3o[e % RS];
+            }
+            ACC svo[RS], wno[RS];
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                const ACC w2 = w1[r] - a2o[r];
+                VT stv;
+                st_v(&stv, w2 * sg);
+                svo[r] = (ACC)ld_f(&stv);
+                wno[r] = (u[r] - a3o[r] - w2 * h2last) * ihn;
+                if (owner) {
+                    accn += wno[r] * wno[r];
+                    accd += svo[r] * wno[r];
+                }
+            }
+            if (owner) {
+                store_rows<VT, RS, ACC>(vout + i0 + e0, svo);
+                store_rows<WT, RS, ACC>(w + i0 + e0, wno);
+            }
+            ACC wn[RT];
+#pragma unroll
+            for (int e = 0; e < RT; ++e) wn[e] = __shfl(wno[e % RS], gbase + e / RS, kWave);
+            accumulate_dots<JT, T, RT, VT, ACC>(raw, wn, acc);
+            continue;
+        }
         ACC w1[RT], u[RT];
         load_tile<WT, RT, ACC>(w + i0, w1);
         load_tile<WT, RT, ACC>(y + i0, u);
