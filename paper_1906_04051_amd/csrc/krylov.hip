@@ -195,6 +195,10 @@ __device__ __forceinline__ T ld_mat(const T* p) {
     else return *p;
 }
 
+// WMAX of a fixed-width instance whose matrix entries carry the non-temporal
+// hint (the matrix does not fit in the last-level cache): kSellStreamW + width.
+constexpr int kSellStreamW = 1000;
+
 // Sliced-ELL SpMV: one wavefront per 64-position slice, NT positions per
 // block, so every load instruction reads 64 consecutive entries of one slice
 // column; position p holds row perm[p] (rows sorted within 256-row blocks) or
@@ -272,26 +276,28 @@ __global__ __launch_bounds__(NT) void k_spmv_sell(int n, const int* __restrict__
             // compiler can count outstanding loads exactly and never waits
             // for one gather before issuing the next.
             if (w > 0) {
-                if constexpr (WMAX > 0) {
+                constexpr bool kFixStream = WMAX > kSellStreamW;
+                constexpr int WF = kFixStream ? WMAX - kSellStreamW : WMAX;
+                if constexpr (WF > 0) {
                     // Every slice is at most WMAX wide (the launch picks WMAX
                     // from the longest row): offsets and values of the whole
                     // row, then the gathers, then the products.
-                    int cc[WMAX];
-                    AT vv[WMAX];
+                    int cc[WF];
+                    AT vv[WF];
 #pragma unroll
-                    for (int k = 0; k < WMAX; ++k) {
+                    for (int k = 0; k < WF; ++k) {
                         const int kk = min(k, w - 1);
-                        cc[k] = scol[q + kk * kWave];
-                        vv[k] = sval[q + kk * kWave];
+                        cc[k] = ld_mat<kFixStream>(scol + q + kk * kWave);
+                        vv[k] = ld_mat<kFixStream>(sval + q + kk * kWave);
                     }
-                    ACC xv[WMAX];
+                    ACC xv[WF];
 #pragma unroll
-                    for (int k = 0; k < WMAX; ++k) {
+                    for (int k = 0; k < WF; ++k) {
                         GM_DCHECK(row + cc[k] >= 0 && row + cc[k] < n, kDbgSellCol);
                         xv[k] = (ACC)ld_f(xr + cc[k]);
                     }
 #pragma unroll
-                    for (int k = 0; k < WMAX; ++k) acc += k < w ? (ACC)vv[k] * xv[k] : (ACC)0;
+                    for (int k = 0; k < WF; ++k) acc += k < w ? (ACC)vv[k] * xv[k] : (ACC)0;
                 } else {
                     // Rows of any length, in chunks of CH entries: the values
                     // and gathers of one chunk are issued, then the column
@@ -1923,7 +1929,9 @@ static void sell_launch(const EngineArgs& e, const XT* x, const double* scale, c
     // Fully unrolled rows up to 25 entries (the smallest instance that holds
     // the longest row), chunked rows beyond (streamed when the matrix does not
     // fit in the last-level cache).
-    if (e.sell_wmax <= 9) sell_launch_w<MODE, 9, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    if (e.sell_stream && e.sell_wmax <= 9)
+        sell_launch_w<MODE, kSellStreamW + 9, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
+    else if (e.sell_wmax <= 9) sell_launch_w<MODE, 9, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
     else if (e.sell_wmax <= 12) sell_launch_w<MODE, 12, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
     else if (e.sell_wmax <= 16) sell_launch_w<MODE, 16, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
     else if (e.sell_wmax <= 25) sell_launch_w<MODE, 25, AT, XT, BT, YT, ACC>(e, x, scale, b, y, slot, gate);
