@@ -30,12 +30,12 @@ __device__ __forceinline__ double bsum(double v, double* red) {
     return s;
 }
 
-// Lane layout of the passes: T consecutive lanes share one row; lane `sub`
-// owns basis columns k = sub, sub + T, ... (JT = MB / T of them), so each lane
-// keeps JT basis values and dot accumulators in registers.
-template <int T>
-__device__ __forceinline__ double gsum(double v) {
-#pragma unroll
+// Lane layout of the passes: T consecutive lanes share one row pair; lane
+// `sub` owns basis columns k = sub, sub + T, ... (JT = 8 of them), so each
+// lane keeps JT basis values and dot accumulators in registers.  T is chosen
+// per Arnoldi step (the smallest power of two with 8 T >= nv) and is the same
+// in every lane, so the shuffles below stay inside aligned groups of T lanes.
+__device__ __forceinline__ double gsum(double v, int T) {
     for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
 }
@@ -43,11 +43,10 @@ __device__ __forceinline__ double gsum(double v) {
 // Workgroup sums of acc[q] (column sub + q*T) into out[k] for k < nv and of
 // accn into out[nv].  Fixed order: butterfly over lanes of equal `sub`, then
 // waves in order.
-template <int WGS, int MB, int T>
-__device__ __forceinline__ void bsum_cols(const double (&acc)[MB / T], double accn, int nv,
+template <int WGS, int MB, int JT>
+__device__ __forceinline__ void bsum_cols(const double (&acc)[JT], double accn, int nv, int T,
                                           double (*red)[MB + 1], double* out) {
     constexpr int NW = WGS / kWave;
-    constexpr int JT = MB / T;
     const int w = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
     const int sub = ln & (T - 1);
 #pragma unroll
@@ -85,9 +84,7 @@ template <int WGS, int L, int MB>
 __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
     constexpr int NW = WGS / kWave;
     constexpr int kRows = WGS / L;       // rows per SpMV round (L lanes per row)
-    constexpr int T = MB / 8;            // lanes per row pair in the sweeps (8 columns per lane)
-    constexpr int JT = MB / T;
-    constexpr int PR = WGS / T;          // row pairs per sweep round
+    constexpr int JT = 8;                // basis columns per lane in the sweeps
     constexpr int U = 2;                 // sweep rounds whose loads are in flight together
     __shared__ double red[NW][MB + 1];
     __shared__ double sred[NW];
@@ -100,7 +97,6 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
 
     const int m = a.m;
     const int lane = threadIdx.x & (L - 1);
-    const int sub = threadIdx.x & (T - 1);
     const int wv = threadIdx.x / kWave, ln = threadIdx.x & (kWave - 1);
     for (;;) {
         if (threadIdx.x == 0) {
@@ -330,6 +326,11 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
             int kk = 0;
             for (int j = 0; j < m && its < a.max_iters; ++j) {
                 const int nv = j + 1;
+                // Lanes per row pair of this step's sweeps (more row pairs in
+                // flight while the basis is short) and row pairs per round.
+                const int T = nv <= 8 ? 1 : (nv <= 16 ? 2 : (nv <= 32 ? 4 : 8));
+                const int PR = WGS / T;
+                const int sub = threadIdx.x & (T - 1);
                 // y = A v_j (normalised); tvec = Z^T y
                 spmv(V + (int64_t)j * ld, vscale[j], false, y);
                 if (R > 0) coarse_solve();
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                         for (int q = 0; q < JT; ++q) acc[q] += vv[u][q].x * wv2.x + vv[u][q].y * wv2.y;
                     }
                 }
-                bsum_cols<WGS, MB, T>(acc, accn, nv, red, h1);
+                bsum_cols<WGS, MB, JT>(acc, accn, nv, T, red, h1);
                 const double wpre2 = h1[nv];
                 for (int k = threadIdx.x; k < nv; k += WGS) {
                     h1[k] *= vscale[k];
@@ -407,8 +408,8 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                             ux += vv[u][q].x * cr[q];
                             uy += vv[u][q].y * cr[q];
                         }
-                        ux = gsum<T>(ux);
-                        uy = gsum<T>(uy);
+                        ux = gsum(ux, T);
+                        uy = gsum(uy, T);
                         if (pp >= np) continue;
                         const double2 wv2 = make_double2(ww[u].x - ux, ww[u].y - uy);
                         if (sub == 0) {
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                         for (int q = 0; q < JT; ++q) acc[q] += vv[u][q].x * wv2.x + vv[u][q].y * wv2.y;
                     }
                 }
-                bsum_cols<WGS, MB, T>(acc, accn, nv, red, h2);
+                bsum_cols<WGS, MB, JT>(acc, accn, nv, T, red, h2);
                 for (int k = threadIdx.x; k < nv; k += WGS) {
                     h2[k] *= vscale[k];
                     coef[k] = h2[k] * vscale[k];
@@ -455,8 +456,8 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                             ux += vv[u][q].x * cr[q];
                             uy += vv[u][q].y * cr[q];
                         }
-                        ux = gsum<T>(ux);
-                        uy = gsum<T>(uy);
+                        ux = gsum(ux, T);
+                        uy = gsum(uy, T);
                         if (pp >= np || sub != 0) continue;
                         const double2 wv2 = make_double2(ww[u].x - ux, ww[u].y - uy);
                         st2(vout + 2 * pp, wv2);
