@@ -92,6 +92,9 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
     __shared__ double Hs[(MB + 1) * MB];
     __shared__ double cs[MB], sn[MB], g[MB + 1], vscale[MB + 1];
     __shared__ double h1[MB + 1], h2[MB + 1], coef[MB + 1], tvec[kMaxR], svec[kMaxR];
+    __shared__ double Hr[(MB + 1) * MB];   // unrotated Hessenberg of the cycle
+    __shared__ double cc[MB + 1];          // next step's (H h2) coefficients of the stored columns
+    __shared__ double lag[2];              // h2 of the last column, 1 / hn
     __shared__ int s_sys;
     __shared__ int s_flag;
 
@@ -331,54 +334,140 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 const int T = nv <= 8 ? 1 : (nv <= 16 ? 2 : (nv <= 32 ? 4 : 8));
                 const int PR = WGS / T;
                 const int sub = threadIdx.x & (T - 1);
-                // y = A v_j (normalised); tvec = Z^T y
-                spmv(V + (int64_t)j * ld, vscale[j], false, y);
-                if (R > 0) coarse_solve();
-                // pass 1: w = P y; dots with the stored basis; ||w||^2
-                double acc[JT];
+                // Two sweeps per step (CGS2 with lagged normalisation): step j
+                // >= 1 runs the SpMV on the previous step's once-projected w1
+                // (unnormalised) and sweep A forms, in one pass over v_0..v_{j-1},
+                //   w2 = w1 - V h2          (second projection; stored as v_j),
+                //   w  = (P A w1 - V c - w2 h2_{j-1}) / hn = P A v_j,
+                // with c = H h2 (the Arnoldi relation P A V = V H, rows < j) and
+                // hn = ||w2|| estimated as sqrt(||w1||^2 - ||h2||^2); then its
+                // dots with v_0..v_j.  Sweep B (pass 2) projects once more.
+                // Step 0: y = A v_0 and pass 1 as usual.
+                double wpre2;
+                if (j == 0) {
+                    spmv(V, vscale[0], false, y);
+                    if (R > 0) coarse_solve();
+                    // pass 1: w = P y; dots with v_0; ||w||^2
+                    double acc[JT];
 #pragma unroll
-                for (int q = 0; q < JT; ++q) acc[q] = 0;
-                accn = 0;
-                for (int p0 = threadIdx.x / T; p0 < np; p0 += U * PR) {
-                    double2 vv[U][JT], yy[U];
+                    for (int q = 0; q < JT; ++q) acc[q] = 0;
+                    accn = 0;
+                    for (int p0 = threadIdx.x / T; p0 < np; p0 += U * PR) {
+                        double2 vv[U][JT], yy[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int pp = p0 + u * PR;
-                        const bool ok = pp < np;
+                        for (int u = 0; u < U; ++u) {
+                            const int pp = p0 + u * PR;
+                            const bool ok = pp < np;
 #pragma unroll
-                        for (int q = 0; q < JT; ++q) {
-                            const int k = sub + q * T;
-                            vv[u][q] = (ok && k < nv) ? ld2(V + (int64_t)k * ld + 2 * pp) : make_double2(0.0, 0.0);
+                            for (int q = 0; q < JT; ++q) {
+                                const int k = sub + q * T;
+                                vv[u][q] = (ok && k < nv) ? ld2(V + (int64_t)k * ld + 2 * pp) : make_double2(0.0, 0.0);
+                            }
+                            yy[u] = ok ? ld2(y + 2 * pp) : make_double2(0.0, 0.0);
                         }
-                        yy[u] = ok ? ld2(y + 2 * pp) : make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int pp = p0 + u * PR;
+                            if (pp >= np) continue;
+                            const int i = 2 * pp;
+                            double2 wv2 = yy[u];
+                            if (R > 0) {
+                                wv2.x = deflate_row(i, wv2.x);
+                                wv2.y = (i + 1 < n) ? deflate_row(i + 1, wv2.y) : 0.0;
+                            }
+                            if (sub == 0) {
+                                st2(w + i, wv2);
+                                accn += wv2.x * wv2.x + wv2.y * wv2.y;
+                            }
+#pragma unroll
+                            for (int q = 0; q < JT; ++q) acc[q] += vv[u][q].x * wv2.x + vv[u][q].y * wv2.y;
+                        }
                     }
+                    bsum_cols<WGS, MB, JT>(acc, accn, nv, T, red, h1);
+                    wpre2 = h1[nv];
+                } else {
+                    spmv(w, 1.0, false, y);
+                    if (R > 0) coarse_solve();
+                    // sweep A over the j stored columns (lanes chosen for j).
+                    const int nvr = j;
+                    const int TA = nvr <= 8 ? 1 : (nvr <= 16 ? 2 : (nvr <= 32 ? 4 : 8));
+                    const int PRA = WGS / TA;
+                    const int sa = threadIdx.x & (TA - 1);
+                    double c2r[JT], ccr[JT], acc[JT];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int pp = p0 + u * PR;
-                        if (pp >= np) continue;
-                        const int i = 2 * pp;
-                        double2 wv2 = yy[u];
-                        if (R > 0) {
-                            wv2.x = deflate_row(i, wv2.x);
-                            wv2.y = (i + 1 < n) ? deflate_row(i + 1, wv2.y) : 0.0;
-                        }
-                        if (sub == 0) {
-                            st2(w + i, wv2);
-                            accn += wv2.x * wv2.x + wv2.y * wv2.y;
-                        }
-#pragma unroll
-                        for (int q = 0; q < JT; ++q) acc[q] += vv[u][q].x * wv2.x + vv[u][q].y * wv2.y;
+                    for (int q = 0; q < JT; ++q) {
+                        const int k = sa + q * TA;
+                        c2r[q] = k < nvr ? coef[k] : 0.0;
+                        ccr[q] = k < nvr ? cc[k] : 0.0;
+                        acc[q] = 0;
                     }
+                    const double h2l = lag[0], ihn = lag[1];
+                    double* vout = V + (int64_t)j * ld;
+                    accn = 0;
+                    double accd = 0;
+                    for (int p0 = threadIdx.x / TA; p0 < np; p0 += U * PRA) {
+                        double2 vv[U][JT], ww[U], yy[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int pp = p0 + u * PRA;
+                            const bool ok = pp < np;
+#pragma unroll
+                            for (int q = 0; q < JT; ++q) {
+                                const int k = sa + q * TA;
+                                vv[u][q] = (ok && k < nvr) ? ld2(V + (int64_t)k * ld + 2 * pp) : make_double2(0.0, 0.0);
+                            }
+                            ww[u] = ok ? ld2(w + 2 * pp) : make_double2(0.0, 0.0);
+                            yy[u] = ok ? ld2(y + 2 * pp) : make_double2(0.0, 0.0);
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int pp = p0 + u * PRA;
+                            double a2x = 0, a2y = 0, a3x = 0, a3y = 0;
+#pragma unroll
+                            for (int q = 0; q < JT; ++q) {
+                                a2x += vv[u][q].x * c2r[q];
+                                a2y += vv[u][q].y * c2r[q];
+                                a3x += vv[u][q].x * ccr[q];
+                                a3y += vv[u][q].y * ccr[q];
+                            }
+                            a2x = gsum(a2x, TA);
+                            a2y = gsum(a2y, TA);
+                            a3x = gsum(a3x, TA);
+                            a3y = gsum(a3y, TA);
+                            if (pp >= np) continue;
+                            const int i = 2 * pp;
+                            double2 u2 = yy[u];
+                            if (R > 0) {
+                                u2.x = deflate_row(i, u2.x);
+                                u2.y = (i + 1 < n) ? deflate_row(i + 1, u2.y) : 0.0;
+                            }
+                            const double2 w2 = make_double2(ww[u].x - a2x, ww[u].y - a2y);
+                            double2 wn = make_double2((u2.x - a3x - w2.x * h2l) * ihn,
+                                                      (u2.y - a3y - w2.y * h2l) * ihn);
+                            if (i + 1 >= n) wn.y = 0.0;
+                            if (sa == 0) {
+                                st2(vout + i, w2);
+                                st2(w + i, wn);
+                                accn += wn.x * wn.x + wn.y * wn.y;
+                                accd += w2.x * wn.x + w2.y * wn.y;
+                            }
+#pragma unroll
+                            for (int q = 0; q < JT; ++q) acc[q] += vv[u][q].x * wn.x + vv[u][q].y * wn.y;
+                        }
+                    }
+                    bsum_cols<WGS, MB, JT>(acc, accn, nvr, TA, red, h1);
+                    const double dj = bsum<WGS>(accd, sred);
+                    wpre2 = h1[nvr];
+                    if (threadIdx.x == 0) h1[nvr] = dj;
+                    __syncthreads();
                 }
-                bsum_cols<WGS, MB, JT>(acc, accn, nv, T, red, h1);
-                const double wpre2 = h1[nv];
                 for (int k = threadIdx.x; k < nv; k += WGS) {
                     h1[k] *= vscale[k];
                     coef[k] = h1[k] * vscale[k];
                 }
                 __syncthreads();
-                // pass 2: w -= V coef; dots; ||w||^2
-                double cr[JT];
+                // pass 2 (sweep B): w -= V coef; dots; ||w||^2
+                double cr[JT], acc[JT];
 #pragma unroll
                 for (int q = 0; q < JT; ++q) {
                     const int k = sub + q * T;
@@ -426,47 +515,16 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                     coef[k] = h2[k] * vscale[k];
                 }
                 __syncthreads();
-                // pass 3: new basis column
-#pragma unroll
-                for (int q = 0; q < JT; ++q) {
-                    const int k = sub + q * T;
-                    cr[q] = k < nv ? coef[k] : 0.0;
-                }
-                double* vout = V + (int64_t)nv * ld;
-                accn = 0;
-                for (int p0 = threadIdx.x / T; p0 < np; p0 += U * PR) {
-                    double2 vv[U][JT], ww[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int pp = p0 + u * PR;
-                        const bool ok = pp < np;
-#pragma unroll
-                        for (int q = 0; q < JT; ++q) {
-                            const int k = sub + q * T;
-                            vv[u][q] = (ok && k < nv) ? ld2(V + (int64_t)k * ld + 2 * pp) : make_double2(0.0, 0.0);
-                        }
-                        ww[u] = ok ? ld2(w + 2 * pp) : make_double2(0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int pp = p0 + u * PR;
-                        double ux = 0, uy = 0;
-#pragma unroll
-                        for (int q = 0; q < JT; ++q) {
-                            ux += vv[u][q].x * cr[q];
-                            uy += vv[u][q].y * cr[q];
-                        }
-                        ux = gsum(ux, T);
-                        uy = gsum(uy, T);
-                        if (pp >= np || sub != 0) continue;
-                        const double2 wv2 = make_double2(ww[u].x - ux, ww[u].y - uy);
-                        st2(vout + 2 * pp, wv2);
-                        accn += wv2.x * wv2.x + wv2.y * wv2.y;
-                    }
-                }
-                const double hn = sqrt(bsum<WGS>(accn, sred));
+                // Givens step of column j: H[:, j] = h1 + h2, h_{j+1,j} = hn with
+                // hn^2 = ||w1||^2 - ||h2||^2 (the rounding of that difference is
+                // about sqrt(eps) ||w|| -- the breakdown threshold).
                 if (threadIdx.x == 0) {
-                    const int bd = !(hn > 2.220446049250313e-16 * sqrt(wpre2));
+                    double q2 = 0;
+                    for (int i = 0; i <= j; ++i) q2 += h2[i] * h2[i];
+                    const double hn = sqrt(fmax(h2[nv] - q2, 0.0));
+                    const int bd = !(hn > 1.4901161193847656e-08 * sqrt(wpre2));
+                    for (int i = 0; i <= j; ++i) Hr[i * MB + j] = h1[i] + h2[i];
+                    Hr[(j + 1) * MB + j] = hn;
                     double a0 = h1[0] + h2[0];
                     for (int i = 0; i < j; ++i) {
                         const double c = cs[i], sv = sn[i], bb = h1[i + 1] + h2[i + 1];
@@ -480,7 +538,17 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                     g[j + 1] = -sn[j] * g[j];
                     g[j] = cs[j] * g[j];
                     vscale[nv] = bd ? 0.0 : 1.0 / hn;
+                    lag[0] = h2[j];
+                    lag[1] = bd ? 0.0 : 1.0 / hn;
                     s_flag = (fabs(g[j + 1]) <= target || bd) ? 1 : 0;
+                }
+                __syncthreads();
+                // Next step's c = H h2 on rows l <= j (band: columns l-1 .. j),
+                // times vscale[l] (coefficients of the stored columns).
+                for (int l = threadIdx.x; l <= j; l += WGS) {
+                    double c = 0;
+                    for (int k = (l > 0 ? l - 1 : 0); k <= j; ++k) c += Hr[l * MB + k] * h2[k];
+                    cc[l] = c * vscale[l];
                 }
                 __syncthreads();
                 ++its;
