@@ -194,6 +194,7 @@ __global__ __launch_bounds__(kWG) void k_breduce1(int nblk, int cnt, const doubl
     const int e = blockIdx.x * kWG + threadIdx.x, s = blockIdx.y;
     if (e >= cnt) return;
     double acc = 0.0;
+#pragma unroll 8
     for (int b = s; b < nblk; b += kSplit) acc += part[(int64_t)b * cnt + e];
     p2[(int64_t)s * cnt + e] = acc;
 }
@@ -253,6 +254,82 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
     }
 }
 
+// First projection and second dot pass of BCGS2 in one sweep over the basis:
+// OUT = IN - sum_{i < nb} P_i C_i (as k_bgemm with sign -1), then the partial
+// dots P_i^T OUT of this workgroup's tiles (as k_bdots, no Gram block).  One
+// 16-row tile per wavefront; the product reads each panel's tile with lane l
+// holding row r0 + l%16, columns l/16 + 4q (MFMA A operand), and the new tile
+// comes out with lane l holding rows r0 + l/16 + 4r, column l%16 -- the B
+// operand layout of the dot products -- so only the panels' tiles are read a
+// second time for the dots, in that layout, right after the first read
+// (from the caches).  nb <= NBMAX accumulators per lane.
+template <int NBMAX>
+__global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, const double* V, int nb,
+                                                    const double* __restrict__ C, const double* IN,
+                                                    double* OUT, double* __restrict__ part) {
+    __shared__ double cs[NBMAX * kPan];
+    __shared__ double red[kWG / kWave][kPan];
+    for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
+    __syncthreads();
+    const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    d4 dacc[NBMAX];
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) dacc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ntile = n_pad / kBW;
+    for (int64_t tile = (int64_t)blockIdx.x * (kWG / kWave) + wv; tile < ntile;
+         tile += (int64_t)gridDim.x * (kWG / kWave)) {
+        const int64_t r0 = tile * kBW;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < NBMAX; ++i) {
+            if (i < nb) {
+                const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * kBW + l / kBW;
+                const double* Ci = cs + i * kPan + (l / kBW) * kBW + (l & (kBW - 1));
+                double a[4], b[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a[q] = P[4 * q];
+                    b[q] = Ci[4 * q * kBW];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc = mfma16(a[q], b[q], acc);
+            }
+        }
+        double wn[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t idx = (r0 + l / kBW + 4 * r) * kBW + (l & (kBW - 1));
+            wn[r] = IN[idx] - acc[r];
+            OUT[idx] = wn[r];
+        }
+#pragma unroll
+        for (int i = 0; i < NBMAX; ++i) {
+            if (i < nb) {
+                const double* P = V + i * ps + (r0 + l / kBW) * kBW + (l & (kBW - 1));
+                double a[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r] = P[4 * r * kBW];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dacc[i] = mfma16(a[r], wn[r], dacc[i]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) {
+        if (i < nb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wv][(l / kBW + 4 * r) * kBW + (l & (kBW - 1))] = dacc[i][r];
+            __syncthreads();
+            const int t = threadIdx.x;
+            double s = red[0][t];
+#pragma unroll
+            for (int w = 1; w < kWG / kWave; ++w) s += red[w][t];
+            part[((int64_t)blockIdx.x * nb + i) * kPan + t] = s;
+            __syncthreads();
+        }
+    }
+}
+
 // R^T R = G for the 16x16 Gram matrix G (row-major); rows/columns >= k are
 // the identity.  Rinv = R^{-1}; Rout = R Rprev (Rprev NULL: R).  With test,
 // a pivot <= kBdTol times the column's norm before orthogonalisation
@@ -261,13 +338,19 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
 __global__ void k_bchol(int k, const double* __restrict__ G, const double* __restrict__ nb2, int test,
                         const double* __restrict__ Rprev, double* __restrict__ Rout,
                         double* __restrict__ Rinv, int* flag, int* __restrict__ bdmask) {
-    __shared__ double R[kPan], Ri[kPan];
+    __shared__ double R[kPan], Ri[kPan], Gs[kPan], Rp[kPan], nbs[kBW];
     __shared__ int bd[kBW];
-    const int t = threadIdx.x;   // 64 threads; t < 16 active
-    if (t < kBW) bd[t] = 0;
+    const int t = threadIdx.x;   // 64 threads; t < 16 active in the triangular loops
+    // Every input is read into LDS once, before the dependent loops.
+    if (t < kBW) {
+        bd[t] = 0;
+        nbs[t] = nb2 ? nb2[t] : 0.0;
+    }
     for (int e = t; e < kPan; e += blockDim.x) {
         R[e] = 0.0;
         Ri[e] = 0.0;
+        Gs[e] = G[e];
+        Rp[e] = Rprev ? Rprev[e] : 0.0;
     }
     __syncthreads();
     for (int j = 0; j < kBW; ++j) {
@@ -276,9 +359,9 @@ __global__ void k_bchol(int k, const double* __restrict__ G, const double* __res
             if (j >= k) {
                 d = 1.0;
             } else {
-                double p = G[j * kBW + j];
+                double p = Gs[j * kBW + j];
                 for (int i = 0; i < j; ++i) p -= R[i * kBW + j] * R[i * kBW + j];
-                const double before = nb2 ? nb2[j] : G[j * kBW + j];
+                const double before = nb2 ? nbs[j] : Gs[j * kBW + j];
                 if (test && !(p > kBdTol * kBdTol * before)) bd[j] = 1;
                 // A broken column counts as dependent: zero row of R.
                 d = (p > 0.0 && !bd[j]) ? sqrt(p) : 0.0;
@@ -287,7 +370,7 @@ __global__ void k_bchol(int k, const double* __restrict__ G, const double* __res
         }
         __syncthreads();
         if (t > j && t < kBW) {
-            double s = (j < k && t < k) ? G[j * kBW + t] : 0.0;
+            double s = (j < k && t < k) ? Gs[j * kBW + t] : 0.0;
             for (int i = 0; i < j; ++i) s -= R[i * kBW + j] * R[i * kBW + t];
             const double d = R[j * kBW + j];
             R[j * kBW + t] = d > 0.0 ? s / d : 0.0;
@@ -309,7 +392,7 @@ __global__ void k_bchol(int k, const double* __restrict__ G, const double* __res
             double o;
             if (Rprev) {
                 o = 0.0;
-                for (int q = i; q <= t; ++q) o += R[i * kBW + q] * Rprev[q * kBW + t];
+                for (int q = i; q <= t; ++q) o += R[i * kBW + q] * Rp[q * kBW + t];
             } else {
                 o = R[i * kBW + t];
             }
@@ -386,8 +469,16 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
     __shared__ double bl[(kBlockStepsMax - 1) * kBW];
     __shared__ double vs[kBW + 1];
     __shared__ double bs;
+    // Rows c0 .. c0 + 2k - 1 of the right-hand sides' columns of G: the only
+    // rows this step's reflectors touch, kept in LDS until the end.
+    __shared__ double gl[kBW][2 * kBW];
+    __shared__ double est2[kBW];
     const int t = threadIdx.x;
     const int rows = (j + 2) * k, c0 = j * k;
+    for (int e = t; e < kBW * 2 * kBW; e += kWG) {
+        const int c = e / (2 * kBW), r = e % (2 * kBW);
+        gl[c][r] = (c < ka && r < 2 * k) ? ls.G[(int64_t)c * kLdH + c0 + r] : 0.0;
+    }
     for (int e = t; e < c0 * (kBW + 1); e += kWG) vl[e] = ls.v[e];
     for (int e = t; e < c0; e += kWG) bl[e] = ls.beta[e];
     for (int e = t; e < kBW * kLdH; e += kWG) {
@@ -446,9 +537,9 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
             } else if (t >= kBW && t < kBW + ka) {   // right-hand sides
                 const int c = t - kBW;
                 double s = 0.0;
-                for (int i = 0; i <= k; ++i) s += vs[i] * ls.G[(int64_t)c * kLdH + col + i];
+                for (int i = 0; i <= k; ++i) s += vs[i] * gl[c][q + i];
                 s *= beta;
-                for (int i = 0; i <= k; ++i) ls.G[(int64_t)c * kLdH + col + i] -= s * vs[i];
+                for (int i = 0; i <= k; ++i) gl[c][q + i] -= s * vs[i];
             }
         }
         __syncthreads();
@@ -457,13 +548,22 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
         const int col = e / rows, row = e % rows;
         ls.H[(int64_t)(c0 + col) * kLdH + row] = h[col][row];
     }
+    for (int e = t; e < kBW * 2 * kBW; e += kWG) {
+        const int c = e / (2 * kBW), r = e % (2 * kBW);
+        if (c < ka && r < 2 * k) ls.G[(int64_t)c * kLdH + c0 + r] = gl[c][r];
+    }
+    // Residual estimate of each right-hand side: the norm of its transformed
+    // rows (j+1)k .. (j+2)k-1 (rows k .. 2k-1 of the staged block).
+    if (t < ka) {
+        double e2 = 0.0;
+        for (int i = k; i < 2 * k; ++i) e2 += gl[t][i] * gl[t][i];
+        est2[t] = e2;
+    }
     __syncthreads();
     if (t == 0) {
         int conv = 1;
         for (int c = 0; c < ka; ++c) {
-            double e2 = 0.0;
-            for (int i = (j + 1) * k; i < rows; ++i) e2 += ls.G[(int64_t)c * kLdH + i] * ls.G[(int64_t)c * kLdH + i];
-            const double est = sqrt(e2);
+            const double est = sqrt(est2[c]);
             ls.est[c] = est;
             if (est > rtol * ls.rho0[c]) conv = 0;
         }
@@ -662,6 +762,43 @@ void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
     blaunch(tm, 6, bytes, k_bgemm, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT);
 }
 
+// W -= V C (C: the first projection's coefficients in w.C), then the second
+// projection's coefficients V^T W into w.C, accumulated into acc_into (as the
+// dots() call without a Gram block would); one sweep over the panels.
+constexpr int kFuseMax = 8;   // panels of the fused sweep (accumulators per lane)
+
+// Workgroups of the fused sweep: one round of resident workgroups (at most
+// kDotGrid, the partial-sum capacity), looked up once per device.
+int fused_grid() {
+    static std::mutex mu;
+    static int grid[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kDotGrid;
+    std::lock_guard<std::mutex> lk(mu);
+    if (grid[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bgemm_dots<kFuseMax>, kWG, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 1;
+        grid[dev] = std::min(kDotGrid, per_cu * cus);
+    }
+    return grid[dev];
+}
+
+void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, double* W,
+               double* acc_into, int acc_blocks) {
+    const double bytes = (double)(nb + 2) * (double)w.n * kBW * sizeof(double);   // panels once, W in and out
+    const int grid = fused_grid();
+    blaunch(tm, 6, bytes, k_bgemm_dots<kFuseMax>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb,
+            (const double*)w.C, (const double*)W, W, w.part);
+    const int cnt = nb * kPan;
+    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(grid, cnt, w.part, w.p2);
+    k_breduce2<<<(cnt + kWG - 1) / kWG, kWG, 0, st>>>(cnt, w.p2, w.C, acc_into, acc_blocks * kPan, 0, -1,
+                                                      nullptr);
+}
+
 // Cholesky QR applied twice to the panel `src` into `dst` (may alias):
 // dst R = src, R = R2 R1 (into w.R).  test: breakdown test of the first pass
 // against nb2 (NULL: the Gram diagonal).
@@ -788,8 +925,13 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             // BCGS2: two projections onto V_0..V_j; the first also gives the
             // squared column norms of A V_j (the breakdown reference).
             dots(*w, a.timer, st, w->V(), j + 1, w->W(), 1, w->Csum, j + 1, 1, j + 1, w->nb2);
-            gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W());
-            dots(*w, a.timer, st, w->V(), j + 1, w->W(), 0, w->Csum, j + 1, 0, -1, nullptr);
+            if (j + 1 <= kFuseMax) {
+                // First projection and second dot pass in one sweep.
+                gemm_dots(*w, a.timer, st, w->V(), j + 1, w->W(), w->Csum, j + 1);
+            } else {
+                gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W());
+                dots(*w, a.timer, st, w->V(), j + 1, w->W(), 0, w->Csum, j + 1, 0, -1, nullptr);
+            }
             gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W());
             cholqr2(*w, a.timer, st, kb, w->W(), Vn, 1, w->nb2);
             k_bls<<<1, kWG, 0, st>>>(j, kb, ka, a.rtol, w->Csum, w->R, w->ls, w->flag);
