@@ -1423,16 +1423,26 @@ static gmres_status solve_block_impl(gmres_plan p, int32_t k, int32_t m_block, c
     // Timing (set_timing > 0): every block kernel launch carries its events.
     struct Hook final : gm::BlockTimer {
         gmres_plan_s* p;
+        int cur = -1;            // block step of the launches being recorded (-1: outside steps)
+        size_t cyc_first = 0;    // first record of the current cycle
         explicit Hook(gmres_plan_s* q) : p(q) {}
         void begin(int kind, double bytes) override {
             Timer& t = p->timer;
             const int e0 = t.used++;
             t.used++;
             arm_kernel_events(t.ev(e0), t.ev(e0 + 1));
-            t.recs.push_back({kind, 0, 0, bytes, e0});
+            t.recs.push_back({kind, 0, cur, bytes, e0});
         }
         void end() override {
             if (disarm_kernel_events()) p->timer.recs.back().cycle = -1;
+        }
+        void step(int j) override { cur = j; }
+        void cycle_done(int jd) override {
+            auto& recs = p->timer.recs;
+            for (size_t i = cyc_first; i < recs.size(); ++i)
+                if (recs[i].j >= jd) recs[i].cycle = -1;
+            cyc_first = recs.size();
+            cur = -1;
         }
     } hook(p);
     p->timer.reset();

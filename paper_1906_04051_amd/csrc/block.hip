@@ -80,8 +80,9 @@ __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict_
                                                const double* __restrict__ vals,
                                                const double* __restrict__ X,
                                                const double* __restrict__ B, double* __restrict__ Y,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, const int* __restrict__ stop) {
     __shared__ double red[kWG];
+    if (stop && *stop) return;   // a later step of a cycle that has ended
     const int c = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
     double nrm = 0.0;
     for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
@@ -152,8 +153,10 @@ __global__ __launch_bounds__(kWG) void k_bcolsum(int nblk, const double* __restr
 template <int NG>
 __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const double* __restrict__ V,
                                                int nv, const double* __restrict__ W, int gram,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, const int* __restrict__ stop) {
     __shared__ double red[kWG / kWave][kPan];
+    if (stop && *stop) return;   // a later step of a cycle that has ended
+
     const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int nb = nv + gram, i0 = blockIdx.y * NG;
     d4 acc[NG];
@@ -190,7 +193,8 @@ __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const 
 
 // Sum of the dot partials over the workgroups, in two fixed-order levels.
 __global__ __launch_bounds__(kWG) void k_breduce1(int nblk, int cnt, const double* __restrict__ part,
-                                                  double* __restrict__ p2) {
+                                                  double* __restrict__ p2, const int* __restrict__ stop) {
+    if (stop && *stop) return;   // a later step of a cycle that has ended
     const int e = blockIdx.x * kWG + threadIdx.x, s = blockIdx.y;
     if (e >= cnt) return;
     double acc = 0.0;
@@ -205,7 +209,8 @@ __global__ __launch_bounds__(kWG) void k_breduce1(int nblk, int cnt, const doubl
 __global__ __launch_bounds__(kWG) void k_breduce2(int cnt, const double* __restrict__ p2,
                                                   double* __restrict__ out, double* acc_into,
                                                   int acc_cnt, int first, int diag_blk,
-                                                  double* __restrict__ nb2) {
+                                                  double* __restrict__ nb2, const int* __restrict__ stop) {
+    if (stop && *stop) return;   // a later step of a cycle that has ended
     const int e = blockIdx.x * kWG + threadIdx.x;
     if (e >= cnt) return;
     double acc = 0.0;
@@ -224,7 +229,8 @@ __global__ __launch_bounds__(kWG) void k_breduce2(int cnt, const double* __restr
 // the same wavefront).
 __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const double* V, int nb,
                                                const double* __restrict__ C, const double* IN,
-                                               double sign, double* OUT) {
+                                               double sign, double* OUT, const int* __restrict__ stop) {
+    if (stop && *stop) return;   // a later step of a cycle that has ended
     __shared__ double cs[(kBlockStepsMax + 1) * kPan];
     for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
     __syncthreads();
@@ -266,7 +272,9 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
 template <int NBMAX>
 __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, const double* V, int nb,
                                                     const double* __restrict__ C, const double* IN,
-                                                    double* OUT, double* __restrict__ part) {
+                                                    double* OUT, double* __restrict__ part,
+                                                    const int* __restrict__ stop) {
+    if (stop && *stop) return;   // a later step of a cycle that has ended
     __shared__ double cs[NBMAX * kPan];
     __shared__ double red[kWG / kWave][kPan];
     for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
@@ -337,7 +345,9 @@ __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, c
 // row c of R and of R^{-1} zero (the column counts as dependent).
 __global__ void k_bchol(int k, const double* __restrict__ G, const double* __restrict__ nb2, int test,
                         const double* __restrict__ Rprev, double* __restrict__ Rout,
-                        double* __restrict__ Rinv, int* flag, int* __restrict__ bdmask) {
+                        double* __restrict__ Rinv, int* flag, int* __restrict__ bdmask,
+                        const int* __restrict__ stop) {
+    if (stop && *stop) return;   // a later step of a cycle that has ended
     __shared__ double R[kPan], Ri[kPan], Gs[kPan], Rp[kPan], nbs[kBW];
     __shared__ int bd[kBW];
     const int t = threadIdx.x;   // 64 threads; t < 16 active in the triangular loops
@@ -460,10 +470,13 @@ __global__ __launch_bounds__(kWG) void k_bls_init(int kb, int ka, const double* 
 // block column (rows 0 .. (j+2)k-1) built from the accumulated projection
 // coefficients Csum (blocks 0..j) and H_{j+1,j} = Rj, apply the previous
 // reflectors, make k new ones, apply them to G, and estimate each right-hand
-// side's residual.  *flag |= 1 when every one passes.
+// side's residual.  flag[0] |= 1 when every one passes.  It ends the block
+// step: flag[2] counts the cycle's steps, and flag[1] (the gate of every later
+// kernel of the cycle) is set once flag[0] is (this step ended the cycle).
 __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
                                              const double* __restrict__ Csum,
                                              const double* __restrict__ Rj, LsView ls, int* flag) {
+    if (flag[1]) return;   // a later step of a cycle that has ended
     __shared__ double h[kBW][kLdH];
     __shared__ double vl[(kBlockStepsMax - 1) * kBW * (kBW + 1)];   // previous reflectors
     __shared__ double bl[(kBlockStepsMax - 1) * kBW];
@@ -567,7 +580,10 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
             ls.est[c] = est;
             if (est > rtol * ls.rho0[c]) conv = 0;
         }
-        if (conv) *flag |= 1;
+        const int f = flag[0] | (conv ? 1 : 0);
+        flag[0] = f;
+        flag[2] += 1;
+        if (f) flag[1] = 1;
     }
 }
 
@@ -699,7 +715,7 @@ void block_carve(BlockWork* w, Arena& ar, int64_t n, int m) {
     w->nsq = ar.take_n<double>(kBW);
     w->lsbuf = ar.take_n<double>(ls_entries());
     w->S = ar.take_n<double>(kPan);
-    w->flag = ar.take_n<int>(1);
+    w->flag = ar.take_n<int>(3);
     w->imap = ar.take_n<int>(3 * kBW);
 }
 
@@ -742,24 +758,25 @@ namespace {
 
 // C[0 .. nb) = P^T W (panels of V, then W itself when gram), summed.
 void dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nv, const double* W,
-          int gram, double* acc_into, int acc_blocks, int first, int diag_blk, double* nb2) {
+          int gram, double* acc_into, int acc_blocks, int first, int diag_blk, double* nb2,
+          const int* stop) {
     const int nb = nv + gram;
     const double bytes = (double)(nv + 1) * (double)w.n * kBW * sizeof(double);   // panels and W, once
     const int groups = (nb + kDotGroup - 1) / kDotGroup;
     blaunch(tm, 5, bytes, k_bdots<kDotGroup>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv, W,
-            gram, w.part);
+            gram, w.part, stop);
     const int cnt = nb * kPan;
-    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(kDotGrid, cnt, w.part, w.p2);
+    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(kDotGrid, cnt, w.part, w.p2, stop);
     k_breduce2<<<(cnt + kWG - 1) / kWG, kWG, 0, st>>>(cnt, w.p2, w.C, acc_into, acc_blocks * kPan, first,
-                                                      diag_blk, nb2);
+                                                      diag_blk, nb2, stop);
 }
 
 void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, const double* C,
-          const double* IN, double sign, double* OUT) {
+          const double* IN, double sign, double* OUT, const int* stop) {
     const int64_t ntile = w.n_pad / kBW;
     const int grid = (int)std::min<int64_t>((ntile + 3) / 4, 8192);
     const double bytes = (double)(nb + (IN ? 1 : 0) + 1) * (double)w.n * kBW * sizeof(double);
-    blaunch(tm, 6, bytes, k_bgemm, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT);
+    blaunch(tm, 6, bytes, k_bgemm, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT, stop);
 }
 
 // W -= V C (C: the first projection's coefficients in w.C), then the second
@@ -788,28 +805,28 @@ int fused_grid() {
 }
 
 void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, double* W,
-               double* acc_into, int acc_blocks) {
+               double* acc_into, int acc_blocks, const int* stop) {
     const double bytes = (double)(nb + 2) * (double)w.n * kBW * sizeof(double);   // panels once, W in and out
     const int grid = fused_grid();
     blaunch(tm, 6, bytes, k_bgemm_dots<kFuseMax>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb,
-            (const double*)w.C, (const double*)W, W, w.part);
+            (const double*)w.C, (const double*)W, W, w.part, stop);
     const int cnt = nb * kPan;
-    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(grid, cnt, w.part, w.p2);
+    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(grid, cnt, w.part, w.p2, stop);
     k_breduce2<<<(cnt + kWG - 1) / kWG, kWG, 0, st>>>(cnt, w.p2, w.C, acc_into, acc_blocks * kPan, 0, -1,
-                                                      nullptr);
+                                                      nullptr, stop);
 }
 
 // Cholesky QR applied twice to the panel `src` into `dst` (may alias):
 // dst R = src, R = R2 R1 (into w.R).  test: breakdown test of the first pass
 // against nb2 (NULL: the Gram diagonal).
 void cholqr2(const BlockWork& w, BlockTimer* tm, hipStream_t st, int k, const double* src, double* dst,
-             int test, const double* nb2) {
-    dots(w, tm, st, nullptr, 0, src, 1, nullptr, 0, 0, -1, nullptr);
-    k_bchol<<<1, kWave, 0, st>>>(k, w.C, nb2, test, nullptr, w.R1, w.Rinv, w.flag, w.imap + 2 * kBW);
-    gemm(w, tm, st, src, 1, w.Rinv, nullptr, 1.0, dst);
-    dots(w, tm, st, nullptr, 0, dst, 1, nullptr, 0, 0, -1, nullptr);
-    k_bchol<<<1, kWave, 0, st>>>(k, w.C, nullptr, 0, w.R1, w.R, w.Rinv, w.flag, nullptr);
-    gemm(w, tm, st, dst, 1, w.Rinv, nullptr, 1.0, dst);
+             int test, const double* nb2, const int* stop) {
+    dots(w, tm, st, nullptr, 0, src, 1, nullptr, 0, 0, -1, nullptr, stop);
+    k_bchol<<<1, kWave, 0, st>>>(k, w.C, nb2, test, nullptr, w.R1, w.Rinv, w.flag, w.imap + 2 * kBW, stop);
+    gemm(w, tm, st, src, 1, w.Rinv, nullptr, 1.0, dst, stop);
+    dots(w, tm, st, nullptr, 0, dst, 1, nullptr, 0, 0, -1, nullptr, stop);
+    k_bchol<<<1, kWave, 0, st>>>(k, w.C, nullptr, 0, w.R1, w.R, w.Rinv, w.flag, nullptr, stop);
+    gemm(w, tm, st, dst, 1, w.Rinv, nullptr, 1.0, dst, stop);
 }
 
 // Residual panel W = B - A X and the column norms on the host.
@@ -821,7 +838,7 @@ double spmm_bytes(const BlockWork& w, const BlockArgs& a, int mode) {
 
 int residual(const BlockWork& w, const BlockArgs& a, double* h_nrm) {
     blaunch(a.timer, 7, spmm_bytes(w, a, 1), k_bspmm<1>, dim3(kNormGrid), dim3(kWG), a.st, w.n, a.rowptr,
-            a.colind, a.vals, (const double*)w.Xp(), (const double*)w.Bp(), w.W(), w.npart);
+            a.colind, a.vals, (const double*)w.Xp(), (const double*)w.Bp(), w.W(), w.npart, (const int*)nullptr);
     k_bcolsum<<<1, kWG, 0, a.st>>>(kNormGrid, w.npart, w.nsq);
     double sq[kBW];
     if (hipMemcpyAsync(sq, w.nsq, sizeof(sq), hipMemcpyDeviceToHost, a.st) != hipSuccess ||
@@ -831,12 +848,6 @@ int residual(const BlockWork& w, const BlockArgs& a, double* h_nrm) {
     return kStatusOk;
 }
 
-int read_flag(const BlockWork& w, hipStream_t st, int* f) {
-    if (hipMemcpyAsync(f, w.flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return kStatusDevice;
-    return kStatusOk;
-}
 
 }  // namespace
 
@@ -885,7 +896,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             hipMemsetAsync(w->imap + 2 * kBW, 0, kBW * sizeof(int), st) != hipSuccess)
             return kStatusDevice;
         k_bselect<<<grow, kWG, 0, st>>>(w->n, w->imap, w->W());
-        cholqr2(*w, a.timer, st, ka, w->W(), w->V(), 1, nullptr);
+        cholqr2(*w, a.timer, st, ka, w->W(), w->V(), 1, nullptr, nullptr);
         // A residual column dependent on the earlier ones adds no basis
         // vector: keep kb independent columns, S = their rows of R (kb x ka).
         double hR[kPan];
@@ -912,43 +923,51 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
                 return kStatusDevice;
             k_bselect<<<grow, kWG, 0, st>>>(w->n, w->imap, w->V());
         }
-        if (hipMemsetAsync(w->flag, 0, sizeof(int), st) != hipSuccess) return kStatusDevice;
+        // flag[0]: breakdown / convergence bits, flag[1]: the cycle has
+        // ended (gate of its later kernels), flag[2]: steps done.  The
+        // cycle's steps are enqueued without waiting for the host; the steps
+        // after the one that ends the cycle return at once.
+        if (hipMemsetAsync(w->flag, 0, 3 * sizeof(int), st) != hipSuccess) return kStatusDevice;
         k_bls_init<<<1, kWG, 0, st>>>(kb, ka, w->S, w->ls);
         ++cycles;
-        int jd = 0, f = 0;
-        for (int j = 0; j < m && steps < a.max_steps; ++j) {
+        const int* stop = w->flag + 1;
+        const int nst = (int)std::min<int64_t>(m, a.max_steps - steps);
+        for (int j = 0; j < nst; ++j) {
+            if (a.timer) a.timer->step(j);
             double* Vj = w->V() + (int64_t)j * w->ps;
             double* Vn = w->V() + (int64_t)(j + 1) * w->ps;
             const unsigned g16 = (unsigned)((w->n + kWG / kBW - 1) / (kWG / kBW));
             blaunch(a.timer, 7, spmm_bytes(*w, a, 0), k_bspmm<0>, dim3(g16), dim3(kWG), st, w->n, a.rowptr,
-                    a.colind, a.vals, (const double*)Vj, (const double*)nullptr, w->W(), (double*)nullptr);
+                    a.colind, a.vals, (const double*)Vj, (const double*)nullptr, w->W(), (double*)nullptr,
+                    stop);
             // BCGS2: two projections onto V_0..V_j; the first also gives the
             // squared column norms of A V_j (the breakdown reference).
-            dots(*w, a.timer, st, w->V(), j + 1, w->W(), 1, w->Csum, j + 1, 1, j + 1, w->nb2);
+            dots(*w, a.timer, st, w->V(), j + 1, w->W(), 1, w->Csum, j + 1, 1, j + 1, w->nb2, stop);
             if (j + 1 <= kFuseMax) {
                 // First projection and second dot pass in one sweep.
-                gemm_dots(*w, a.timer, st, w->V(), j + 1, w->W(), w->Csum, j + 1);
+                gemm_dots(*w, a.timer, st, w->V(), j + 1, w->W(), w->Csum, j + 1, stop);
             } else {
-                gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W());
-                dots(*w, a.timer, st, w->V(), j + 1, w->W(), 0, w->Csum, j + 1, 0, -1, nullptr);
+                gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W(), stop);
+                dots(*w, a.timer, st, w->V(), j + 1, w->W(), 0, w->Csum, j + 1, 0, -1, nullptr, stop);
             }
-            gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W());
-            cholqr2(*w, a.timer, st, kb, w->W(), Vn, 1, w->nb2);
+            gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W(), stop);
+            cholqr2(*w, a.timer, st, kb, w->W(), Vn, 1, w->nb2, stop);
             k_bls<<<1, kWG, 0, st>>>(j, kb, ka, a.rtol, w->Csum, w->R, w->ls, w->flag);
-            ++steps;
-            jd = j + 1;
-            if ((s = read_flag(*w, st, &f)) != kStatusOk) return s;
-            if (f) break;
         }
         double est[kBW];
+        int hf[3] = {0, 0, 0};
         if (hipMemcpyAsync(est, w->ls.est, sizeof(est), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hf, w->flag, sizeof(hf), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return kStatusDevice;
+        const int jd = hf[2];
+        steps += jd;
+        if (a.timer) a.timer->cycle_done(jd);
         est_max = 0.0;
         for (int c = 0; c < ka; ++c) est_max = std::max(est_max, est[c] / r0a[c]);
         // X[:, act] += V Y (through the free W panel).
         k_bsolve<<<1, kWG, 0, st>>>(jd, kb, ka, w->ls, w->Cy);
-        gemm(*w, a.timer, st, w->V(), jd, w->Cy, nullptr, 1.0, w->W());
+        gemm(*w, a.timer, st, w->V(), jd, w->Cy, nullptr, 1.0, w->W(), nullptr);
         k_bscatter<<<gpe, kWG, 0, st>>>(w->n, ka, w->imap + kBW, w->W(), w->Xp());
         if ((s = residual(*w, a, rn)) != kStatusOk) return s;
         for (int c = 0; c < k; ++c)

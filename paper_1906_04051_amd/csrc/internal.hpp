@@ -339,6 +339,11 @@ constexpr int kBlockStepsMax = 16;   // block steps per cycle
 struct BlockTimer {
     virtual void begin(int kind, double bytes) = 0;
     virtual void end() = 0;
+    // Launches after step(j) belong to block step j of the current cycle;
+    // cycle_done(jd): the cycle ran jd steps (launches of later steps found
+    // it ended and are not counted).
+    virtual void step(int j) = 0;
+    virtual void cycle_done(int jd) = 0;
     virtual ~BlockTimer() = default;
 };
 struct BlockArgs {
