@@ -477,14 +477,16 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
                                              const double* __restrict__ Csum,
                                              const double* __restrict__ Rj, LsView ls, int* flag) {
     if (flag[1]) return;   // a later step of a cycle that has ended
-    __shared__ double h[kBW][kLdH];
+    // Columns padded by one entry: threads that walk different columns at
+    // the same row then hit different LDS banks.
+    __shared__ double h[kBW][kLdH + 1];
     __shared__ double vl[(kBlockStepsMax - 1) * kBW * (kBW + 1)];   // previous reflectors
     __shared__ double bl[(kBlockStepsMax - 1) * kBW];
     __shared__ double vs[kBW + 1];
     __shared__ double bs;
     // Rows c0 .. c0 + 2k - 1 of the right-hand sides' columns of G: the only
     // rows this step's reflectors touch, kept in LDS until the end.
-    __shared__ double gl[kBW][2 * kBW];
+    __shared__ double gl[kBW][2 * kBW + 1];
     __shared__ double est2[kBW];
     const int t = threadIdx.x;
     const int rows = (j + 2) * k, c0 = j * k;
@@ -492,67 +494,125 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
         const int c = e / (2 * kBW), r = e % (2 * kBW);
         gl[c][r] = (c < ka && r < 2 * k) ? ls.G[(int64_t)c * kLdH + c0 + r] : 0.0;
     }
-    for (int e = t; e < c0 * (kBW + 1); e += kWG) vl[e] = ls.v[e];
-    for (int e = t; e < c0; e += kWG) bl[e] = ls.beta[e];
-    for (int e = t; e < kBW * kLdH; e += kWG) {
+    // Every global load of the inputs is issued before the first is stored
+    // to LDS (fixed trip counts, registers in between).
+    constexpr int kVIt = ((kBlockStepsMax - 1) * kBW * (kBW + 1) + kWG - 1) / kWG;
+    constexpr int kHIt = (kBW * kLdH + kWG - 1) / kWG;
+    double vr[kVIt], hr[kHIt];
+#pragma unroll
+    for (int u = 0; u < kVIt; ++u) {
+        const int e = t + u * kWG;
+        vr[u] = e < c0 * (kBW + 1) ? ls.v[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kHIt; ++u) {
+        const int e = t + u * kWG;
         const int col = e / kLdH, row = e % kLdH;
         double val = 0.0;
-        if (col < k && row < rows) {
+        if (e < kBW * kLdH && col < k && row < rows) {
             const int blk = row / k, kk = row % k;
             if (blk <= j) val = Csum[blk * kPan + kk * kBW + col];
             else val = kk <= col ? Rj[kk * kBW + col] : 0.0;
         }
-        h[col][row] = val;
+        hr[u] = val;
+    }
+    for (int e = t; e < c0; e += kWG) bl[e] = ls.beta[e];
+#pragma unroll
+    for (int u = 0; u < kVIt; ++u) {
+        const int e = t + u * kWG;
+        if (e < c0 * (kBW + 1)) vl[e] = vr[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kHIt; ++u) {
+        const int e = t + u * kWG;
+        if (e < kBW * kLdH) h[e / kLdH][e % kLdH] = hr[u];
     }
     __syncthreads();
-    // Previous reflectors, in order; column t of the new block per thread.
-    if (t < k) {
-        for (int p = 0; p < c0; ++p) {
-            const double* vp = vl + p * (kBW + 1);
-            const double bp = bl[p];
-            double s = 0.0;
-            for (int i = 0; i <= k; ++i) s += vp[i] * h[t][p + i];
-            s *= bp;
-            for (int i = 0; i <= k; ++i) h[t][p + i] -= s * vp[i];
+    // Previous reflectors, in order, on every column of the new block: 16
+    // lanes per column, lane i holding entry p + i of reflector p's window
+    // (lane 0 also entry p + 16 when k = 16); the dot product by shuffles
+    // inside the 16-lane group.  Each group walks its own column, so the
+    // groups need no barrier between reflectors.
+    {
+        const int ct = t / kBW, li = t & (kBW - 1);
+        if (ct < k) {
+            for (int p = 0; p < c0; ++p) {
+                const double* vp = vl + p * (kBW + 1);
+                const double v0 = li <= k ? vp[li] : 0.0;
+                const double v16 = (li == 0 && k == kBW) ? vp[kBW] : 0.0;
+                const double h0 = h[ct][p + li];
+                const double h16 = (li == 0 && k == kBW) ? h[ct][p + kBW] : 0.0;
+                double part = v0 * h0 + v16 * h16;
+#pragma unroll
+                for (int o = kBW / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kBW);
+                const double sp = part * bl[p];
+                if (li <= k) h[ct][p + li] = h0 - sp * v0;
+                if (li == 0 && k == kBW) h[ct][p + kBW] = h16 - sp * v16;
+            }
         }
     }
     __syncthreads();
+    // New reflectors, one per column of the block, each built by the first
+    // 16 lanes (entries as above, norms by shuffles) and applied to the
+    // block's later columns and to the right-hand sides by 16-lane groups.
+    const int ct = t / kBW, li = t & (kBW - 1);
     for (int q = 0; q < k; ++q) {
         const int col = c0 + q;
-        if (t == 0) {
-            double nrm = 0.0;
-            for (int i = 0; i <= k; ++i) nrm += h[q][col + i] * h[q][col + i];
-            nrm = sqrt(nrm);
-            double beta = 0.0;
-            if (nrm > 0.0) {
-                const double a0 = h[q][col];
-                const double alpha = a0 >= 0.0 ? -nrm : nrm;
-                vs[0] = a0 - alpha;
-                for (int i = 1; i <= k; ++i) vs[i] = h[q][col + i];
-                double vv = 0.0;
-                for (int i = 0; i <= k; ++i) vv += vs[i] * vs[i];
-                beta = vv > 0.0 ? 2.0 / vv : 0.0;
-            } else {
-                for (int i = 0; i <= k; ++i) vs[i] = 0.0;
+        if (t < kBW) {
+            const double x0 = li <= k ? h[q][col + li] : 0.0;
+            const double x16 = (li == 0 && k == kBW) ? h[q][col + kBW] : 0.0;
+            double n2 = x0 * x0 + x16 * x16;
+#pragma unroll
+            for (int o = kBW / 2; o > 0; o >>= 1) n2 += __shfl_xor(n2, o, kBW);
+            const double nrm = sqrt(n2);
+            const double a0 = __shfl(x0, 0, kBW);
+            const double alpha = a0 >= 0.0 ? -nrm : nrm;
+            const double w0 = nrm > 0.0 ? (li == 0 ? a0 - alpha : x0) : 0.0;
+            const double w16 = nrm > 0.0 ? x16 : 0.0;
+            double vv = w0 * w0 + w16 * w16;
+#pragma unroll
+            for (int o = kBW / 2; o > 0; o >>= 1) vv += __shfl_xor(vv, o, kBW);
+            const double beta = (nrm > 0.0 && vv > 0.0) ? 2.0 / vv : 0.0;
+            if (li <= k) {
+                vs[li] = w0;
+                ls.v[(int64_t)col * (kBW + 1) + li] = w0;
             }
-            bs = beta;
-            for (int i = 0; i <= k; ++i) ls.v[(int64_t)col * (kBW + 1) + i] = vs[i];
-            ls.beta[col] = beta;
+            if (li == 0 && k == kBW) {
+                vs[kBW] = w16;
+                ls.v[(int64_t)col * (kBW + 1) + kBW] = w16;
+            }
+            if (li == 0) {
+                bs = beta;
+                ls.beta[col] = beta;
+            }
         }
         __syncthreads();
         const double beta = bs;
         if (beta != 0.0) {
-            if (t >= q && t < k) {   // columns q.. of the block
-                double s = 0.0;
-                for (int i = 0; i <= k; ++i) s += vs[i] * h[t][col + i];
-                s *= beta;
-                for (int i = 0; i <= k; ++i) h[t][col + i] -= s * vs[i];
-            } else if (t >= kBW && t < kBW + ka) {   // right-hand sides
-                const int c = t - kBW;
-                double s = 0.0;
-                for (int i = 0; i <= k; ++i) s += vs[i] * gl[c][q + i];
-                s *= beta;
-                for (int i = 0; i <= k; ++i) gl[c][q + i] -= s * vs[i];
+            const double v0 = li <= k ? vs[li] : 0.0;
+            const double v16 = (li == 0 && k == kBW) ? vs[kBW] : 0.0;
+            // Columns q.. of the block.
+            if (q + ct < k) {
+                const int cc = q + ct;
+                const double h0 = h[cc][col + li];
+                const double h16 = (li == 0 && k == kBW) ? h[cc][col + kBW] : 0.0;
+                double sp = v0 * h0 + v16 * h16;
+#pragma unroll
+                for (int o = kBW / 2; o > 0; o >>= 1) sp += __shfl_xor(sp, o, kBW);
+                sp *= beta;
+                if (li <= k) h[cc][col + li] = h0 - sp * v0;
+                if (li == 0 && k == kBW) h[cc][col + kBW] = h16 - sp * v16;
+            }
+            // Right-hand sides (rows q .. q + k of the staged block).
+            if (ct < ka) {
+                const double g0 = q + li < 2 * kBW ? gl[ct][q + li] : 0.0;
+                const double g16 = (li == 0 && k == kBW) ? gl[ct][q + kBW] : 0.0;
+                double sp = v0 * g0 + v16 * g16;
+#pragma unroll
+                for (int o = kBW / 2; o > 0; o >>= 1) sp += __shfl_xor(sp, o, kBW);
+                sp *= beta;
+                if (li <= k) gl[ct][q + li] = g0 - sp * v0;
+                if (li == 0 && k == kBW) gl[ct][q + kBW] = g16 - sp * v16;
             }
         }
         __syncthreads();
