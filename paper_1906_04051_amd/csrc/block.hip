@@ -191,35 +191,37 @@ __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const 
     }
 }
 
-// Sum of the dot partials over the workgroups, in two fixed-order levels.
-__global__ __launch_bounds__(kWG) void k_breduce1(int nblk, int cnt, const double* __restrict__ part,
-                                                  double* __restrict__ p2, const int* __restrict__ stop) {
+// Sum of the dot partials over the workgroups, fixed order: a workgroup
+// takes 16 entries; its 16 x 16 threads each sum split s (workgroups s,
+// s + 16, ...) of one entry, then the splits are added in order.  out = the
+// sums; with acc_into: acc_into[e] = (first ? 0 : acc_into[e]) + out[e] for
+// e < acc_cnt, and (diag_blk >= 0) the diagonal of block diag_blk saved to
+// nb2.
+__global__ __launch_bounds__(kWG) void k_breduce(int nblk, int cnt, const double* __restrict__ part,
+                                                 double* __restrict__ out, double* acc_into, int acc_cnt,
+                                                 int first, int diag_blk, double* __restrict__ nb2,
+                                                 const int* __restrict__ stop) {
+    static_assert(kSplit * kBW == kWG, "16 entries x 16 splits per workgroup");
+    __shared__ double ps[kSplit][kBW + 1];
     if (stop && *stop) return;   // a later step of a cycle that has ended
-    const int e = blockIdx.x * kWG + threadIdx.x, s = blockIdx.y;
-    if (e >= cnt) return;
+    const int el = threadIdx.x % kBW, sp = threadIdx.x / kBW;
+    const int e = blockIdx.x * kBW + el;
     double acc = 0.0;
+    if (e < cnt) {
 #pragma unroll 8
-    for (int b = s; b < nblk; b += kSplit) acc += part[(int64_t)b * cnt + e];
-    p2[(int64_t)s * cnt + e] = acc;
-}
-
-// out = sum of the splits; with acc_into: acc_into[e] = (first ? 0 :
-// acc_into[e]) + out[e] for e < acc_cnt, and (first) the diagonal of block
-// diag_blk saved to nb2.
-__global__ __launch_bounds__(kWG) void k_breduce2(int cnt, const double* __restrict__ p2,
-                                                  double* __restrict__ out, double* acc_into,
-                                                  int acc_cnt, int first, int diag_blk,
-                                                  double* __restrict__ nb2, const int* __restrict__ stop) {
-    if (stop && *stop) return;   // a later step of a cycle that has ended
-    const int e = blockIdx.x * kWG + threadIdx.x;
-    if (e >= cnt) return;
-    double acc = 0.0;
-    for (int s = 0; s < kSplit; ++s) acc += p2[(int64_t)s * cnt + e];
-    out[e] = acc;
-    if (acc_into && e < acc_cnt) acc_into[e] = (first ? 0.0 : acc_into[e]) + acc;
-    if (nb2 && diag_blk >= 0) {
-        const int d = e - diag_blk * kPan;
-        if (d >= 0 && d < kPan && d / kBW == d % kBW) nb2[d / kBW] = acc;
+        for (int b = sp; b < nblk; b += kSplit) acc += part[(int64_t)b * cnt + e];
+    }
+    ps[sp][el] = acc;
+    __syncthreads();
+    if (sp == 0 && e < cnt) {
+        double a = 0.0;
+        for (int q = 0; q < kSplit; ++q) a += ps[q][el];
+        out[e] = a;
+        if (acc_into && e < acc_cnt) acc_into[e] = (first ? 0.0 : acc_into[e]) + a;
+        if (nb2 && diag_blk >= 0) {
+            const int d = e - diag_blk * kPan;
+            if (d >= 0 && d < kPan && d / kBW == d % kBW) nb2[d / kBW] = a;
+        }
     }
 }
 
@@ -698,7 +700,7 @@ struct BlockWork {
     int64_t n = 0, n_pad = 0, ps = 0;
     int m = 0;
     double* panels = nullptr;   // (m + 1) basis panels, W, B, X
-    double *part = nullptr, *p2 = nullptr, *C = nullptr, *Csum = nullptr;
+    double *part = nullptr, *C = nullptr, *Csum = nullptr;
     double *R1 = nullptr, *R = nullptr, *Rinv = nullptr, *nb2 = nullptr, *Cy = nullptr;
     double *npart = nullptr, *nsq = nullptr;
     double *lsbuf = nullptr, *S = nullptr;
@@ -763,7 +765,6 @@ void block_carve(BlockWork* w, Arena& ar, int64_t n, int m) {
     const int64_t nbmax = m + 2;
     w->panels = ar.take_n<double>((int64_t)(m + 4) * w->ps);
     w->part = ar.take_n<double>((int64_t)kDotGrid * nbmax * kPan);
-    w->p2 = ar.take_n<double>((int64_t)kSplit * nbmax * kPan);
     w->C = ar.take_n<double>(nbmax * kPan);
     w->Csum = ar.take_n<double>(nbmax * kPan);
     w->R1 = ar.take_n<double>(kPan);
@@ -826,9 +827,8 @@ void dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
     blaunch(tm, 5, bytes, k_bdots<kDotGroup>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv, W,
             gram, w.part, stop);
     const int cnt = nb * kPan;
-    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(kDotGrid, cnt, w.part, w.p2, stop);
-    k_breduce2<<<(cnt + kWG - 1) / kWG, kWG, 0, st>>>(cnt, w.p2, w.C, acc_into, acc_blocks * kPan, first,
-                                                      diag_blk, nb2, stop);
+    k_breduce<<<(cnt + kBW - 1) / kBW, kWG, 0, st>>>(kDotGrid, cnt, w.part, w.C, acc_into, acc_blocks * kPan,
+                                                     first, diag_blk, nb2, stop);
 }
 
 void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, const double* C,
@@ -871,9 +871,8 @@ void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double*
     blaunch(tm, 6, bytes, k_bgemm_dots<kFuseMax>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb,
             (const double*)w.C, (const double*)W, W, w.part, stop);
     const int cnt = nb * kPan;
-    k_breduce1<<<dim3((cnt + kWG - 1) / kWG, kSplit), kWG, 0, st>>>(grid, cnt, w.part, w.p2, stop);
-    k_breduce2<<<(cnt + kWG - 1) / kWG, kWG, 0, st>>>(cnt, w.p2, w.C, acc_into, acc_blocks * kPan, 0, -1,
-                                                      nullptr, stop);
+    k_breduce<<<(cnt + kBW - 1) / kBW, kWG, 0, st>>>(grid, cnt, w.part, w.C, acc_into, acc_blocks * kPan, 0,
+                                                     -1, nullptr, stop);
 }
 
 // Cholesky QR applied twice to the panel `src` into `dst` (may alias):
