@@ -397,6 +397,31 @@ def test_batched_fixed_count_trajectory():
         assert rel(x[batch.row_off[i]:batch.row_off[i + 1]], ref.x) <= 1e-8
 
 
+@pytest.mark.parametrize("m,wg", [(40, 512), (64, 256), (7, 512)])
+def test_batched_restart_lengths(m, wg):
+    """Restart lengths beyond 32 take the kernel instance with 64-column
+    sweeps (lanes per row pair up to 8); m = 7 restarts often.  Fixed-count
+    trajectories over two cycles and to-tolerance solves against the
+    per-system oracle."""
+    batch = _small_batch(nsys=7, lo=10, hi=36)
+    K = 2 * m + 3
+    plan, d = G().plan_for(batch, m=m, rtol=0.0, max_iters=K, batch_wg=wg)
+    x, infos = plan.solve_batched(d["b"])
+    x = x.cpu().numpy()
+    for i, s in enumerate(batch.systems):
+        ref = oracle.gmres(s, m, 0.0, K)
+        assert infos[i]["iters"] == ref.iters, (i, infos[i]["iters"], ref.iters)
+        assert rel(x[batch.row_off[i]:batch.row_off[i + 1]], ref.x) <= 1e-8, i
+    plan2, d2 = G().plan_for(batch, m=m, rtol=1e-8, max_iters=20000, batch_wg=wg)
+    x2, infos2 = plan2.solve_batched(d2["b"])
+    x2 = x2.cpu().numpy()
+    for i, s in enumerate(batch.systems):
+        ref = oracle.gmres(s, m, 1e-8, 20000)
+        assert infos2[i]["status_name"] == "OK", (i, infos2[i])
+        assert abs(infos2[i]["iters"] - ref.iters) <= 1, (i, infos2[i]["iters"], ref.iters)
+        assert rel(x2[batch.row_off[i]:batch.row_off[i + 1]], ref.x) <= 1e-8, i
+
+
 def test_single_system_batch_equals_solve():
     s = W.make_config(1, mesh=40)
     b = W.concat_systems([s])
