@@ -278,9 +278,11 @@ gmres_status gmres_autotune(gmres_plan p, int32_t* chosen_h);
  * adjoint, or block solve): for kernel class k (0 SpMV, 1 first Gram-Schmidt
  * sweep, 2 second sweep, 3 third sweep of the three-sweep variant, 4 first
  * sweep of the two-sweep variant at steps j > 0, 5 block dot products
- * P^T W, 6 block panel products W +/- P C, 7 block SpMM) writes {launches,
- * total_ms, total_algorithmic_bytes} to out_h[3*k ..]; launches that found
- * their cycle already ended are not counted. */
+ * P^T W, 6 block panel products W +/- P C (and the sweep that applies the
+ * first block projection and takes the second dot products, counted with
+ * its product bytes), 7 block SpMM) writes {launches, total_ms,
+ * total_algorithmic_bytes} to out_h[3*k ..]; launches that found their cycle
+ * (or block cycle) already ended are not counted. */
 gmres_status gmres_set_timing(gmres_plan p, int32_t period);
 gmres_status gmres_kernel_times(gmres_plan p, double* out_h /* 24 doubles */);
 
