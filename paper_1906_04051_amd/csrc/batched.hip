@@ -457,7 +457,8 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                     }
                     bsum_cols<WGS, MB, JT>(acc, accn, nvr, TA, red, h1);
                     const double dj = bsum<WGS>(accd, sred);
-                    wpre2 = h1[nvr];
+                    wpre2 = h1[nvr];   // ||w||^2, the breakdown reference
+                    __syncthreads();   // every wave has read it before the slot is reused
                     if (threadIdx.x == 0) h1[nvr] = dj;
                     __syncthreads();
                 }
