@@ -74,6 +74,35 @@ def host_info():
     return dict(cpu_model=model, nproc=os.cpu_count(), omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
 
 
+def stream_ceilings():
+    """What plain streaming library kernels (torch) reach on this GPU, beside
+    the 8 TB/s peak: a 1 GiB device copy (bytes read + written) and a 1 GiB
+    sum (bytes read), each the best of 10 timed with events."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    s = torch.empty((), dtype=torch.float64, device="cuda")
+
+    def best_ms(fn):
+        fn()
+        best = 1e30
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    copy_ms = best_ms(lambda: b.copy_(a))
+    sum_ms = best_ms(lambda: torch.sum(a, dim=0, out=s))
+    del a, b, s
+    torch.cuda.empty_cache()
+    return (2.0 * (1 << 30) / (copy_ms * 1e-3) / 1e9, (1 << 30) / (sum_ms * 1e-3) / 1e9)
+
+
 def cpu_baseline(sysm, m, fp64_iters, sample_iters, adapt_rmax=0):
     """Oracle (plain C, FP64, one thread) on the same system: its setup (copy
     of A and Z, A Z, E and its LU, the initial residual) timed alone with a
@@ -407,6 +436,32 @@ def batched_config4(args):
                                    sample=f"the first {k} systems of the batch solved to rtol 1e-8 one "
                                           f"after another ({dt:.1f} s)", sample_seconds=dt,
                                    threads=1, **host_info())
+        # The same oracle on all host cores: independent systems in parallel
+        # (one oracle call per thread at a time; the calls release the GIL).
+        import concurrent.futures as cf
+        nt = max(1, min(16, os.cpu_count() or 1))
+        t1 = time.perf_counter()
+        done = 0
+        with cf.ThreadPoolExecutor(max_workers=nt) as ex:
+            futs = []
+            nxt = 0
+            while nxt < min(batch.nsys, nt):
+                futs.append(ex.submit(oracle.gmres, batch.systems[nxt], 30, 1e-8, 200000))
+                nxt += 1
+            while futs:
+                fin, pend = cf.wait(futs, return_when=cf.FIRST_COMPLETED)
+                done += len(fin)
+                futs = list(pend)
+                for _ in fin:
+                    if nxt < batch.nsys and time.perf_counter() - t1 < 15.0:
+                        futs.append(ex.submit(oracle.gmres, batch.systems[nxt], 30, 1e-8, 200000))
+                        nxt += 1
+        dt2 = time.perf_counter() - t1
+        out["cpu_baseline_all_cores"] = dict(
+            value=done / dt2, unit="solves/s", cores=nt, kind="oracle",
+            sample=f"the first {done} systems of the batch solved to rtol 1e-8 on {nt} threads, one "
+                   f"system per thread at a time ({dt2:.1f} s)", sample_seconds=dt2, threads=nt,
+            **host_info())
     print(json.dumps(out), flush=True)
 
 
@@ -526,6 +581,12 @@ def single_config(args):
                            "kernel": f"{src}.{dom}", "launches": int(v["launches"]),
                            "avg_launch_us": 1000 * v["ms"] / v["launches"],
                            "bytes_per_launch_avg": v["bytes"] / v["launches"]}
+        # A measured ceiling beside the published peak (outside the timed steps).
+        copy_gbs, read_gbs = stream_ceilings()
+        out["stream_ceiling"] = {"copy_GBs": copy_gbs, "read_GBs": read_gbs, "unit": "GB/s",
+                                 "kind": "torch 1 GiB device copy (read + written bytes) and "
+                                         "1 GiB sum (read bytes), best of 10",
+                                 "dominant_kernel_frac_of_best": achieved / max(copy_gbs, read_gbs)}
     if k == 5 and "mixed" in plans and not args.no_adjoint:
         # Backward of the differentiable solve (outside the timed steps):
         # L = 1/2 ||x - x_target||^2, adjoint FP64 GMRES on A^T.
