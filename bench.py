@@ -374,8 +374,11 @@ def block_rhs(args):
 def batched_config4(args):
     """Config 4: 512 independent Q1 systems (meshes 32^2 .. 256^2, own seeded
     coefficients, beta and rhs) solved by one call of the batched solver
-    (GMRES(30), 16 deflation vectors each, rtol 1e-8).  Reports solves/s over
-    the whole call and p50/p99 of the per-system device solve times."""
+    (GMRES(30), 16 deflation vectors each, rtol 1e-8).  Systems of at least
+    --cont-rows rows get continuation plans: one still running after
+    --cont-work row-steps leaves the persistent launch at a restart and goes on
+    on the multi-workgroup engine within the same call.  Reports solves/s over
+    the whole call and p50/p99 of the per-system solve times."""
     import numpy as np
     import torch
     from paper_1906_04051_amd import gmres as G
@@ -387,6 +390,17 @@ def batched_config4(args):
     plan, d = G.plan_for(batch, m=30, rtol=1e-8, max_iters=200000)
     tuned = plan.autotune()
     log(f"[bench] autotune: {tuned}")
+    steps_at = {}
+    if args.cont_rows > 0:
+        # Continuation plans: a system of at least cont_rows rows that is still
+        # running after cont_work row-steps goes on on the multi-workgroup
+        # single-system engine (outside the timed region: plan construction).
+        t1 = time.perf_counter()
+        subs = G.attach_continuations(plan, batch, args.cont_rows, args.cont_work,
+                                      m=30, rtol=1e-8, max_iters=200000)
+        rows = np.diff(batch.row_off)
+        steps_at = {s: 30 * max(1, int(np.ceil(args.cont_work / (float(rows[s]) * 30)))) for s in subs}
+        log(f"[bench] {len(subs)} continuation plans ({time.perf_counter() - t1:.1f} s)")
     b = d["b"]
     x = torch.empty_like(b)
     for _ in range(args.warmup):
@@ -415,7 +429,9 @@ def batched_config4(args):
         "config": {"workload": "q1_convection_diffusion_batch_512_mesh32to256", "systems": batch.nsys,
                    "unknowns_total": int(batch.rowptr.size - 1), "nnz_total": int(batch.rowptr[-1]),
                    "restart_m": 30, "deflation_vectors_each": 16, "rtol": 1e-8,
-                   "batch_wg": tuned["batch_wg"], "batch_lanes": tuned["batch_lanes"]},
+                   "batch_wg": tuned["batch_wg"], "batch_lanes": tuned["batch_lanes"],
+                   "continuation_min_rows": args.cont_rows, "continuation_row_steps": args.cont_work},
+        "continued_systems": sum(1 for s, k in steps_at.items() if infos[s]["iters"] > k),
         "call_s": med,
         "solve_s_p50": float(np.percentile(per_sys, 50)), "solve_s_p99": float(np.percentile(per_sys, 99)),
         "solve_s_max": float(np.max(per_sys)),
@@ -687,6 +703,10 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=50,
                     help="oracle steps of the CPU baseline (default: one restart cycle of GMRES(50))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cont-rows", type=int, default=20000,
+                    help="config 4: systems of at least this many rows get a continuation plan (0: none)")
+    ap.add_argument("--cont-work", type=float, default=128e6,
+                    help="config 4: row-steps after which such a system leaves the batched launch")
     ap.add_argument("--no-adjoint", action="store_true", help="config 5: skip the adjoint measurement")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--timing-period", type=int, default=8,

@@ -193,6 +193,30 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
                                  gmres_info* infos_h);
 
 /*
+ * Continuation plan for system s of a batched plan (nsys > 1).  In
+ * gmres_solve_batched, system s leaves the persistent launch at the first
+ * restart after `steps` inner steps (counted over its cycles) unless it has
+ * converged, with its iterate corrected as at exit, x_s = x_hat + Z E^{-1}
+ * Z^T (b_s - A x_hat); the call then continues it on `sub` -- the
+ * multi-workgroup single-system engine, several such systems at a time on
+ * their plans' streams -- restarted from x_s with the batch's rho0_s as the
+ * tolerance reference and max_iters less the steps taken.  Restarted GMRES(m)
+ * carries only the iterate from one cycle to the next (Sec. 3.2), and P A Z
+ * = 0 leaves P r unchanged by the correction, so the continued solve is the
+ * same iteration as staying in the batch, up to rounding.  infos_h[s] then
+ * sums steps and cycles of both parts; solve_ms adds the continuation's host
+ * wall time.  sub: a single-system plan (FP64 engine used whatever its
+ * precision option) built on system s's rows with local indices, the same
+ * values, Z columns, m and device, no adaptive deflation; it stays owned by
+ * the caller and must outlive its attachment; one sub per system, and a sub
+ * must not be used elsewhere while a batched solve runs.  sub = NULL
+ * detaches.  gmres_update_values on the batched plan detaches every
+ * continuation.  Errors: EINVAL (not a batched plan, s out of range, a sub of
+ * another size, r or m, steps < 1), EDEVICE.
+ */
+gmres_status gmres_batched_attach(gmres_plan p, int32_t s, gmres_plan sub, int64_t steps);
+
+/*
  * Block GMRES(m_block) for k right-hand sides sharing the plan's A (several
  * right-hand sides; the paper solves one at a time, Sec. 3.2, and this is
  * the block form of the same minimisation): after j block steps of a cycle

@@ -17,7 +17,9 @@
 #include <fstream>
 #include <new>
 #include <sstream>
+#include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/gmres.h"
@@ -185,6 +187,12 @@ struct gmres_plan_s {
     double* bout_d = nullptr;
     int64_t* d_v_off = nullptr;
     int64_t* d_w_off = nullptr;
+    // continuation plans of a batch (gmres_batched_attach): per system the
+    // plan and the step limit after which the system leaves the batched launch
+    std::vector<gmres_plan_s*> cont;
+    std::vector<int64_t> cont_steps;
+    int64_t* d_hand = nullptr;   // device copy of cont_steps (0: no continuation)
+    int ncont = 0;
 
     Timer timer;
 };
@@ -391,6 +399,7 @@ void carve_batched(gmres_plan_s* p, Arena& A) {
     p->bout_i = A.take_n<int64_t>(3 * (int64_t)ns);
     p->bout_d = A.take_n<double>(5 * (int64_t)ns);
     p->d_v_off = A.take_n<int64_t>(ns);
+    if (ns > 1) p->d_hand = A.take_n<int64_t>(ns);
 }
 
 // Phase 1: buffers sized by the plan's sizes and options.
@@ -836,66 +845,126 @@ gmres_status ensure_graph(gmres_plan_s* p, int op, int prec, const void* b) {
     return GMRES_OK;
 }
 
+// One run of restarted cycles of an engine from p->xh.  The host keeps two
+// cycles enqueued ahead of the one whose control snapshot it reads; a cycle
+// that starts after the solve has ended does nothing (device-side gate).
+// Timed cycles (one in timer.period) are enqueued kernel by kernel with
+// events in their timed dispatches; the others replay the cycle graph.
+struct EngineRun {
+    gmres_plan_s* p;
+    int op, prec;
+    const void* b = nullptr;
+    int64_t cap = 0;
+    int64_t c = 1;             // the host waits next on cycle c - 1
+    bool finished = false;     // a snapshot said done
+    bool exhausted = false;    // cap + 2 cycles without done
+    EngineArgs a{}, at{};
+    TimerHook hook;
+    TraceSpan span[2];
+    EngineRun(gmres_plan_s* pp, int o, int pr) : p(pp), op(o), prec(pr), hook(pp, pr, o) {}
+    EngineRun(const EngineRun&) = delete;
+    EngineRun& operator=(const EngineRun&) = delete;
+};
+
+gmres_status engine_enqueue(EngineRun& r, int64_t c) {
+    static const char* const kCycleName[2][3] = {{"cycle fp64", "cycle fp32", "cycle fp16-basis"},
+                                                 {"cycle adjoint fp64", "cycle adjoint fp32",
+                                                  "cycle adjoint fp16-basis"}};
+    gmres_plan_s* p = r.p;
+    r.span[c & 1].start(kCycleName[r.op ? 1 : 0][r.prec]);
+    const int period = p->timer.period;
+    if (period > 0 && c % period == 0) {
+        r.hook.cycle = (int)c;
+        launch_cycle(r.at, r.b);
+    } else if (p->o.use_graph != 0) {
+        HIP_OK(hipGraphLaunch(p->gexec[r.op][r.prec], p->st));
+    } else {
+        launch_cycle(r.a, r.b);
+    }
+    HIP_OK(hipMemcpyAsync(&p->ctrl_h[c & 1], p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipEventRecord(p->ev_cyc[c & 1], p->st));
+    return GMRES_OK;
+}
+
+// Resets the control block, runs the restart set-up and enqueues cycles 0
+// and 1.  b: the engine's right-hand side (type WT).
+gmres_status engine_start(EngineRun& r, const void* b, double rtol, double r0_override, int64_t max_iters,
+                          bool trust_est) {
+    gmres_plan_s* p = r.p;
+    r.a = make_args(p, r.op, r.prec);
+    r.a.trust_est = trust_est ? 1 : 0;
+    r.at = r.a;
+    r.at.timer = &r.hook;
+    r.b = b;
+    if (p->o.use_graph != 0) CHECK(ensure_graph(p, r.op, r.prec, b));
+    if (r.prec != p->last_prec) {
+        CHECK(clear_typed(p));
+        p->last_prec = r.prec;
+    }
+    launch_ctrl_reset(p->st, p->ctrl, max_iters, p->hist_pos);
+    launch_restart_init(r.a, b, rtol, r0_override);
+    r.cap = max_iters + 3;
+    CHECK(engine_enqueue(r, 0));
+    r.c = 1;
+    if (r.c <= r.cap) CHECK(engine_enqueue(r, r.c));
+    return GMRES_OK;
+}
+
+// Reads the snapshot of cycle c - 1 (waiting for it when block, else
+// returning with *ready = false while it is still in flight); when the
+// solve goes on, enqueues the next cycle.
+gmres_status engine_step(EngineRun& r, bool block, bool* ready) {
+    gmres_plan_s* p = r.p;
+    hipEvent_t ev = p->ev_cyc[(r.c - 1) & 1];
+    if (block) {
+        HIP_OK(hipEventSynchronize(ev));
+    } else {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();   // not an error: keep it out of the next launch check
+            *ready = false;
+            return GMRES_OK;
+        }
+        HIP_OK(e);
+    }
+    *ready = true;
+    r.span[(r.c - 1) & 1].stop();
+    if (p->ctrl_h[(r.c - 1) & 1].done) {
+        r.finished = true;
+        return GMRES_OK;
+    }
+    ++r.c;
+    if (r.c > r.cap + 1) {
+        r.exhausted = true;
+        return GMRES_OK;
+    }
+    if (r.c <= r.cap) CHECK(engine_enqueue(r, r.c));
+    return GMRES_OK;
+}
+
+// Waits for the plan's stream and returns the final control block in *out.
+gmres_status engine_end(EngineRun& r, Ctrl* out) {
+    gmres_plan_s* p = r.p;
+    HIP_OK(hipStreamSynchronize(p->st));
+    r.span[0].stop();
+    r.span[1].stop();
+    HIP_OK(hipMemcpy(out, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (p->timer.period > 0) collect_timer(p, out->cycles);
+    p->hist_pos += out->its;   // the next run of the same solve records after these steps
+    if (!r.finished) return fail(GMRES_EDEVICE, "solve loop did not terminate");
+    return GMRES_OK;
+}
+
 // Runs restarted cycles of one engine from p->xh until the control block says
 // done.  b: the engine's right-hand side (type WT).  Returns the final control
 // block in *out.
 gmres_status run_engine(gmres_plan_s* p, int op, int prec, const void* b, double rtol,
                         double r0_override, int64_t max_iters, Ctrl* out, bool trust_est = false) {
-    // Timed cycles (one in timer.period) are enqueued kernel by kernel with
-    // events in their timed dispatches; the others replay the cycle graph.
-    const int period = p->timer.period;
-    const bool graph = p->o.use_graph != 0;
-    EngineArgs a = make_args(p, op, prec);
-    a.trust_est = trust_est ? 1 : 0;
-    TimerHook hook(p, prec, op);
-    EngineArgs at = a;
-    at.timer = &hook;
-    if (graph) CHECK(ensure_graph(p, op, prec, b));
-    if (prec != p->last_prec) {
-        CHECK(clear_typed(p));
-        p->last_prec = prec;
-    }
-    launch_ctrl_reset(p->st, p->ctrl, max_iters, p->hist_pos);
-    launch_restart_init(a, b, rtol, r0_override);
-    static const char* const kCycleName[2][3] = {{"cycle fp64", "cycle fp32", "cycle fp16-basis"},
-                                                 {"cycle adjoint fp64", "cycle adjoint fp32",
-                                                  "cycle adjoint fp16-basis"}};
-    TraceSpan span[2];
-    auto enqueue = [&](int c) -> gmres_status {
-        span[c & 1].start(kCycleName[op ? 1 : 0][prec]);
-        const bool timed = period > 0 && c % period == 0;
-        if (timed) {
-            hook.cycle = c;
-            launch_cycle(at, b);
-        } else if (graph) {
-            HIP_OK(hipGraphLaunch(p->gexec[op][prec], p->st));
-        } else {
-            launch_cycle(a, b);
-        }
-        HIP_OK(hipMemcpyAsync(&p->ctrl_h[c & 1], p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, p->st));
-        HIP_OK(hipEventRecord(p->ev_cyc[c & 1], p->st));
-        return GMRES_OK;
-    };
-    const int64_t cap = max_iters + 3;
-    CHECK(enqueue(0));
-    bool finished = false;
-    for (int64_t c = 1; c <= cap + 1; ++c) {
-        if (c <= cap) CHECK(enqueue((int)c));
-        HIP_OK(hipEventSynchronize(p->ev_cyc[(c - 1) & 1]));
-        span[(c - 1) & 1].stop();
-        if (p->ctrl_h[(c - 1) & 1].done) {
-            finished = true;
-            break;
-        }
-    }
-    HIP_OK(hipStreamSynchronize(p->st));
-    span[0].stop();
-    span[1].stop();
-    HIP_OK(hipMemcpy(out, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
-    if (period > 0) collect_timer(p, out->cycles);
-    p->hist_pos += out->its;   // the next run of the same solve records after these steps
-    if (!finished) return fail(GMRES_EDEVICE, "solve loop did not terminate");
-    return GMRES_OK;
+    EngineRun r(p, op, prec);
+    CHECK(engine_start(r, b, rtol, r0_override, max_iters, trust_est));
+    bool ready = false;
+    while (!r.finished && !r.exhausted) CHECK(engine_step(r, true, &ready));
+    return engine_end(r, out);
 }
 
 // ||b - A x|| in FP64 (scratch: p->w, partial slot of p->part).
@@ -1545,6 +1614,13 @@ gmres_status gmres_update_values(gmres_plan p, const double* vals) {
                  p->rowptr, p->colind, p->vals, p->zrp, p->zci, p->zv};
     CHECK(to_status(setup_validate(sa, p->d_flags), "value validation"));
     CHECK(refresh_values(p));
+    if (p->ncont > 0) {
+        // Attached continuation plans hold the old values: detach them all.
+        std::fill(p->cont.begin(), p->cont.end(), nullptr);
+        std::fill(p->cont_steps.begin(), p->cont_steps.end(), 0);
+        p->ncont = 0;
+        HIP_OK(hipMemsetAsync(p->d_hand, 0, p->nsys * sizeof(int64_t), p->st));
+    }
     CHECK(leave(p));
     return GMRES_OK;
 }
@@ -1605,6 +1681,9 @@ static gmres_status init_batched(gmres_plan_s* p) {
     // Padding rows of the work vectors (and, for batches, of the basis) read as zero.
     HIP_OK(hipMemsetAsync(p->bW, 0, 3 * (size_t)(p->n + ns) * sizeof(double), p->st));
     if (ns > 1) {
+        HIP_OK(hipMemsetAsync(p->d_hand, 0, ns * sizeof(int64_t), p->st));
+        p->cont.assign(ns, nullptr);
+        p->cont_steps.assign(ns, 0);
         HIP_OK(hipMemsetAsync(p->bV, 0, (size_t)(m + 1) * (p->n + ns) * sizeof(double), p->st));
         if (p->R > 0) {
             HIP_OK(hipMemsetAsync(p->azc1, 0xFF, 2 * (size_t)p->n * sizeof(int), p->st));
@@ -1645,6 +1724,7 @@ static gmres_status run_batched(gmres_plan_s* p, const double* b, const double* 
         a.sell_val = p->sell_v64;
     }
     a.order = p->border;
+    a.hand = p->ncont > 0 ? p->d_hand : nullptr;
     a.rowptr = p->rowptr;
     a.colind = p->colind;
     a.vals = p->vals;
@@ -1675,6 +1755,139 @@ static gmres_status run_batched(gmres_plan_s* p, const double* b, const double* 
     return GMRES_OK;
 }
 
+gmres_status gmres_batched_attach(gmres_plan p, int32_t s, gmres_plan sub, int64_t steps) {
+    if (!p || p->nsys < 2 || !p->d_hand) return fail(GMRES_EINVAL, "attach needs a plan of several systems");
+    if (s < 0 || s >= p->nsys) return fail(GMRES_EINVAL, "system index out of range");
+    if (sub) {
+        const int64_t rows = p->row_off[s + 1] - p->row_off[s];
+        const int64_t r_s = p->zcol_off[s + 1] - p->zcol_off[s];
+        if (sub == p || sub->nsys != 1 || sub->n != rows || sub->R != r_s)
+            return fail(GMRES_EINVAL, "the attached plan must be a single-system plan of system s's size and r");
+        if (sub->o.m != p->o.m || sub->o.adapt_rmax > 0 || sub->device != p->device)
+            return fail(GMRES_EINVAL, "the attached plan must share m and the device, without adaptive deflation");
+        if (steps < 1) return fail(GMRES_EINVAL, "steps must be >= 1");
+    }
+    HIP_OK(hipSetDevice(p->device));
+    if (!p->cont[s] && sub) ++p->ncont;
+    if (p->cont[s] && !sub) --p->ncont;
+    p->cont[s] = sub;
+    p->cont_steps[s] = sub ? steps : 0;
+    HIP_OK(hipMemcpyAsync(p->d_hand + s, &p->cont_steps[s], sizeof(int64_t), hipMemcpyHostToDevice, p->st));
+    HIP_OK(hipStreamSynchronize(p->st));
+    return GMRES_OK;
+}
+
+namespace {
+
+// System s of a batched solve, continued on its attached plan q: restarted
+// GMRES carries only the iterate from one cycle to the next, so restarting
+// from the batch's x_s (with the batch's rho0 as the tolerance reference) is
+// the same iteration (Sec. 3.2, restarts); P r is unchanged by the coarse
+// correction the batched kernel applied to x_s, since P A Z = 0.
+struct Continuation {
+    gmres_plan_s* q = nullptr;
+    int s = 0;
+    int stage = 0;   // 0 not started, 1 cycles in flight, 2 final copy in flight, 3 done
+    int slot = 0;
+    int saved_period = 0;
+    std::unique_ptr<EngineRun> run;
+    std::chrono::steady_clock::time_point t0;
+    double ms = 0;
+    Ctrl out{};
+};
+
+gmres_status cont_start(gmres_plan_s* p, Continuation& c, const double* b, double* x, double rho0,
+                        int64_t steps_left) {
+    gmres_plan_s* q = c.q;
+    const int64_t off = p->row_off[c.s];
+    c.t0 = std::chrono::steady_clock::now();
+    HIP_OK(hipStreamWaitEvent(q->st, p->ev_out, 0));   // the batched launch has written x
+    launch_copy(q->st, b + off, q->bws, q->n);
+    launch_copy(q->st, x + off, q->xh, q->n);
+    c.saved_period = q->timer.period;
+    q->timer.period = 0;   // kernel timing is not collected for continuations
+    q->hist_pos = 0;
+    c.run.reset(new EngineRun(q, 0, kPrecF64));
+    CHECK(engine_start(*c.run, q->bws, p->o.rtol, rho0, steps_left, false));
+    c.stage = 1;
+    return GMRES_OK;
+}
+
+// Advances one continuation without blocking; *moved reports progress.
+gmres_status cont_poll(gmres_plan_s* p, Continuation& c, double* x, bool* moved) {
+    gmres_plan_s* q = c.q;
+    *moved = false;
+    if (c.stage == 1) {
+        bool ready = false;
+        CHECK(engine_step(*c.run, false, &ready));
+        if (!ready) return GMRES_OK;
+        *moved = true;
+        if (c.run->exhausted) return fail(GMRES_EDEVICE, "continuation loop did not terminate");
+        if (!c.run->finished) return GMRES_OK;
+        // x_s = x_hat + Z E^{-1} Z^T r, then the final control block; the copy
+        // lands after the last enqueued cycle's snapshot in the same slot.
+        launch_correct(q->st, q->NB, (int)q->n, q->zrp, q->zci, q->zv, q->s_res, q->R, q->xh,
+                       x + p->row_off[c.s]);
+        c.slot = (int)(c.run->c & 1);
+        HIP_OK(hipMemcpyAsync(&q->ctrl_h[c.slot], q->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, q->st));
+        HIP_OK(hipEventRecord(q->ev_cyc[c.slot], q->st));
+        c.stage = 2;
+        return GMRES_OK;
+    }
+    if (c.stage == 2) {
+        const hipError_t e = hipEventQuery(q->ev_cyc[c.slot]);
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();
+            return GMRES_OK;
+        }
+        HIP_OK(e);
+        c.run->span[0].stop();
+        c.run->span[1].stop();
+        c.out = q->ctrl_h[c.slot];
+        q->timer.period = c.saved_period;
+        q->hist_len = std::min<int64_t>(c.out.its, q->hist_cap);
+        c.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c.t0).count();
+        c.stage = 3;
+        *moved = true;
+    }
+    return GMRES_OK;
+}
+
+// Runs the continuations, at most kActive at a time (each on its plan's own
+// stream), polling from this thread.
+gmres_status run_continuations(gmres_plan_s* p, std::vector<Continuation>& cs, const double* b, double* x,
+                               const std::vector<int64_t>& oi, const std::vector<double>& od) {
+    constexpr int kActive = 16;
+    TraceRange tr_("batched continuations");
+    HIP_OK(hipEventRecord(p->ev_out, p->st));
+    size_t next = 0, done = 0;
+    int active = 0;
+    while (done < cs.size()) {
+        while (active < kActive && next < cs.size()) {
+            Continuation& c = cs[next++];
+            const int64_t left = p->o.max_iters - oi[3 * c.s];
+            CHECK(cont_start(p, c, b, x, od[4 * c.s], left));
+            ++active;
+        }
+        bool any = false;
+        for (size_t i = 0; i < next; ++i) {
+            Continuation& c = cs[i];
+            if (c.stage == 0 || c.stage == 3) continue;
+            bool moved = false;
+            CHECK(cont_poll(p, c, x, &moved));
+            any = any || moved;
+            if (c.stage == 3) {
+                --active;
+                ++done;
+            }
+        }
+        if (!any) std::this_thread::yield();
+    }
+    return GMRES_OK;
+}
+
+}  // namespace
+
 gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0, double* x,
                                  gmres_info* infos_h) {
     TraceRange tr_("gmres_solve_batched");
@@ -1685,12 +1898,28 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
     const auto t0 = std::chrono::steady_clock::now();
     CHECK(enter(p));
     CHECK(run_batched(p, b, x0, x, p->o.max_iters, p->batch_wg, p->batch_L));
-    double* nr = p->bout_d + 4 * (int64_t)p->nsys;
-    launch_seg_resid(p->st, p->nsys, p->d_row_off, p->rowptr, p->colind, p->vals, x, b, nr);
-    if (p->nsys == 1) p->last_prec = -1;   // the shared basis (and its padding) is cleared before the next solve
     const int ns = p->nsys;
+    double* nr = p->bout_d + 4 * (int64_t)ns;
     std::vector<int64_t> oi(3 * (size_t)ns);
     std::vector<double> od(5 * (size_t)ns);
+    if (p->ncont > 0) {
+        // Systems that reached their step limit go on on their attached plans.
+        HIP_OK(hipMemcpyAsync(oi.data(), p->bout_i, oi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p->st));
+        HIP_OK(hipMemcpyAsync(od.data(), p->bout_d, 4 * (size_t)ns * sizeof(double), hipMemcpyDeviceToHost,
+                              p->st));
+        HIP_OK(hipStreamSynchronize(p->st));
+    }
+    std::vector<Continuation> cs;
+    for (int s = 0; p->ncont > 0 && s < ns; ++s) {
+        if (oi[3 * s + 2] != kStatusHandoff) continue;
+        if (!p->cont[s]) return fail(GMRES_EDEVICE, "a system left the batch without a continuation plan");
+        cs.emplace_back();
+        cs.back().q = p->cont[s];
+        cs.back().s = s;
+    }
+    if (!cs.empty()) CHECK(run_continuations(p, cs, b, x, oi, od));
+    launch_seg_resid(p->st, ns, p->d_row_off, p->rowptr, p->colind, p->vals, x, b, nr);
+    if (ns == 1) p->last_prec = -1;   // the shared basis (and its padding) is cleared before the next solve
     HIP_OK(hipMemcpyAsync(oi.data(), p->bout_i, oi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p->st));
     HIP_OK(hipMemcpyAsync(od.data(), p->bout_d, od.size() * sizeof(double), hipMemcpyDeviceToHost, p->st));
     HIP_OK(hipStreamSynchronize(p->st));
@@ -1698,6 +1927,8 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
     int clk_khz = 0;
     HIP_OK(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, p->device));
     const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::vector<const Continuation*> by_sys(ns, nullptr);
+    for (const Continuation& c : cs) by_sys[c.s] = &c;
     gmres_status worst = GMRES_OK;
     for (int s = 0; s < ns; ++s) {
         gmres_info in{};
@@ -1708,6 +1939,13 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
         in.rel_res = od[4 * s + 1];
         in.rel_res_true = in.rho0 > 0 ? std::sqrt(od[4 * ns + s]) / in.rho0 : 0.0;
         in.solve_ms = clk_khz > 0 ? (od[4 * s + 3] - od[4 * s + 2]) / (double)clk_khz : wall;
+        if (const Continuation* c = by_sys[s]) {
+            in.iters += c->out.its;
+            in.cycles += c->out.cycles;
+            in.status = c->out.status;
+            in.rel_res = in.rho0 > 0 ? c->out.beta / in.rho0 : 0.0;
+            in.solve_ms += c->ms;
+        }
         if (infos_h) infos_h[s] = in;
         if (worst == GMRES_OK && in.status != GMRES_OK) worst = (gmres_status)in.status;
     }

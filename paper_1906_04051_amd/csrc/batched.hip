@@ -149,10 +149,9 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
         };
         // Per-lane Z^T partials of one row value, summed over the workgroup
         // in fixed order by zt_finish.
-        auto zt_add = [&](double (&zacc)[kZf], int64_t gi, double v) {
-            const int zc = a.zc1[gi];
+        auto zt_add = [&](double (&zacc)[kZf], int64_t gi, double v, int zc, double zv) {
             if (zc >= 0) {
-                const double t = a.zv1[gi] * v;
+                const double t = zv * v;
 #pragma unroll
                 for (int c = 0; c < kZf; ++c) zacc[c] += (zc - (int)c0 == c) ? t : 0.0;
             } else if (zc == -2) {
@@ -190,7 +189,9 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
             if (a.sell_col) {
                 // Sliced ELL: one wavefront per 64-row slice overlapping the
                 // system (rows of other systems in an edge slice are skipped);
-                // the entries of a chunk are loaded before any gather.
+                // the entries of a chunk, the row's b value and its Z row copy
+                // are loaded before any gather (two memory round trips per
+                // slice).
                 constexpr int CH = 16;
                 const int64_t sl0 = r0 / kWave, sl1 = (r0 + n + kWave - 1) / kWave;
                 for (int64_t sl = sl0 + wv; sl < sl1; sl += NW) {
@@ -205,6 +206,8 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                         w = (__builtin_amdgcn_readfirstlane(a.sell_off[sl + 1]) - q0) / kWave;
                     }
                     const double bvv = (resid && ok) ? b[gi - r0] : 0.0;
+                    const int zc = (fz && ok) ? a.zc1[gi] : -1;
+                    const double zv = (fz && ok) ? a.zv1[gi] : 0.0;
                     // Rows outside the system gather from the system's own first row.
                     const double* xr = xin + (ok ? gi - r0 : 0);
                     double s = 0;
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                         const double v = resid ? bvv - s : s * scale;
                         out[gi - r0] = v;
                         if (resid) acc += v * v;
-                        if (fz) zt_add(zacc, gi, v);
+                        if (fz) zt_add(zacc, gi, v, zc, zv);
                     }
                 }
                 __syncthreads();
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                         const double v = resid ? bv[u] - sacc[u] : sacc[u] * scale;
                         out[row] = v;
                         if (resid) acc += v * v;
-                        if (fz) zt_add(zacc, r0 + row, v);
+                        if (fz) zt_add(zacc, r0 + row, v, a.zc1[r0 + row], a.zv1[r0 + row]);
                     }
                 }
             }
@@ -280,18 +283,49 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
             else if (R > 0) zt_waves(out);
             return resid ? bsum<WGS>(acc, sred) : 0.0;
         };
-        // v - (A Z)_row svec for local row i < n (two-entry row copy, else CSR).
-        auto deflate_row = [&](int i, double v) -> double {
-            const int64_t gi = r0 + i;
-            const int2 c2 = *reinterpret_cast<const int2*>(a.az2c + 2 * gi);
+        // v - (A Z)_row svec for local row i < n from the row's two-entry copy
+        // (c2, v2; c2.x == -2: three or more entries, read from the CSR copy).
+        auto deflate_pre = [&](int i, double v, int2 c2, double2 v2) -> double {
             if (c2.x >= 0) {
-                const double2 v2 = ld2(a.az2v + 2 * gi);
                 v -= v2.x * svec[c2.x - c0];
                 if (c2.y >= 0) v -= v2.y * svec[c2.y - c0];
             } else if (c2.x == -2) {
+                const int64_t gi = r0 + i;
                 for (int q = a.azrp[gi]; q < a.azrp[gi + 1]; ++q) v -= a.azv[q] * svec[a.azci[q] - c0];
             }
             return v;
+        };
+        auto deflate_row = [&](int i, double v) -> double {
+            const int64_t gi = r0 + i;
+            const int2 c2 = *reinterpret_cast<const int2*>(a.az2c + 2 * gi);
+            const double2 v2 = c2.x >= 0 ? ld2(a.az2v + 2 * gi) : make_double2(0.0, 0.0);
+            return deflate_pre(i, v, c2, v2);
+        };
+        // vec -= (A Z) svec over the system's rows, in place; four rows per
+        // thread with their loads issued together (the sweeps then read a
+        // projected vector and wait on one round trip per row pair).
+        auto deflate_vec = [&](double* vec) {
+            constexpr int DU = 4;
+            for (int i0 = threadIdx.x; i0 < n; i0 += DU * WGS) {
+                double v[DU];
+                int2 c2[DU];
+                double2 v2[DU];
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    const int i = i0 + u * WGS;
+                    const bool ok = i < n;
+                    const int64_t gi = r0 + (ok ? i : 0);
+                    v[u] = ok ? vec[i] : 0.0;
+                    c2[u] = ok ? *reinterpret_cast<const int2*>(a.az2c + 2 * gi) : make_int2(-1, -1);
+                    v2[u] = ok ? ld2(a.az2v + 2 * gi) : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    const int i = i0 + u * WGS;
+                    if (i < n) vec[i] = deflate_pre(i, v[u], c2[u], v2[u]);
+                }
+            }
+            __syncthreads();
         };
 
         // x0
@@ -319,6 +353,9 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
             if (!isfinite(beta)) { status = kStatusNonFinite; break; }
             if (beta <= target) { status = kStatusOk; break; }
             if (its >= a.max_iters) { status = kStatusMaxIter; break; }
+            // A system with a continuation plan leaves at the first restart
+            // past its step limit, with x = x_hat + Z E^{-1} Z^T r (below).
+            if (a.hand && a.hand[sys] > 0 && its >= a.hand[sys]) { status = kStatusHandoff; break; }
             ++cycles;
             if (threadIdx.x == 0) {
                 g[0] = beta;
@@ -346,7 +383,10 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 double wpre2;
                 if (j == 0) {
                     spmv(V, vscale[0], false, y);
-                    if (R > 0) coarse_solve();
+                    if (R > 0) {
+                        coarse_solve();
+                        deflate_vec(y);   // y = P A v_0
+                    }
                     // pass 1: w = P y; dots with v_0; ||w||^2
                     double acc[JT];
 #pragma unroll
@@ -371,10 +411,7 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                             if (pp >= np) continue;
                             const int i = 2 * pp;
                             double2 wv2 = yy[u];
-                            if (R > 0) {
-                                wv2.x = deflate_row(i, wv2.x);
-                                wv2.y = (i + 1 < n) ? deflate_row(i + 1, wv2.y) : 0.0;
-                            }
+                            if (i + 1 >= n) wv2.y = 0.0;
                             if (sub == 0) {
                                 st2(w + i, wv2);
                                 accn += wv2.x * wv2.x + wv2.y * wv2.y;
@@ -387,7 +424,10 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                     wpre2 = h1[nv];
                 } else {
                     spmv(w, 1.0, false, y);
-                    if (R > 0) coarse_solve();
+                    if (R > 0) {
+                        coarse_solve();
+                        deflate_vec(y);   // y = P A w1
+                    }
                     // sweep A over the j stored columns (lanes chosen for j).
                     const int nvr = j;
                     const int TA = nvr <= 8 ? 1 : (nvr <= 16 ? 2 : (nvr <= 32 ? 4 : 8));
@@ -437,10 +477,7 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                             if (pp >= np) continue;
                             const int i = 2 * pp;
                             double2 u2 = yy[u];
-                            if (R > 0) {
-                                u2.x = deflate_row(i, u2.x);
-                                u2.y = (i + 1 < n) ? deflate_row(i + 1, u2.y) : 0.0;
-                            }
+                            if (i + 1 >= n) u2.y = 0.0;
                             const double2 w2 = make_double2(ww[u].x - a2x, ww[u].y - a2y);
                             double2 wn = make_double2((u2.x - a3x - w2.x * h2l) * ihn,
                                                       (u2.y - a3y - w2.y * h2l) * ihn);

@@ -22,6 +22,7 @@ constexpr int kStatusSingular = -2;
 constexpr int kStatusNonFinite = -3;
 constexpr int kStatusDevice = -4;
 constexpr int kStatusNoMem = -5;      // workspace too small (gmres_status EWORKSPACE)
+constexpr int kStatusHandoff = 100;   // batched: the system continues on its attached plan (internal)
 
 // Device memory carved out of one caller-owned workspace: persistent buffers
 // grow from the bottom, the temporaries of a setup step from the top (given
@@ -293,6 +294,7 @@ struct BatchArgs {
     const int64_t *row_off, *zcol_off, *e_off, *v_off;   // device
     const int64_t* w_off;                                 // per-system work-vector regions
     const int* order;                                     // systems by decreasing work
+    const int64_t* hand;   // per system: steps after which it leaves at a restart (0: never; NULL: none)
     const int *rowptr, *colind;
     const double* vals;
     const int *azrp, *azci;

@@ -24,7 +24,8 @@ GMRES_EWORKSPACE = -5
 
 # Every symbol include/gmres.h declares.
 EXPORTS = ["gmres_default_opts", "gmres_workspace_bytes", "gmres_workspace_required", "gmres_setup",
-           "gmres_solve", "gmres_solve_batched", "gmres_block_workspace_bytes", "gmres_solve_block",
+           "gmres_solve", "gmres_solve_batched", "gmres_batched_attach", "gmres_block_workspace_bytes",
+           "gmres_solve_block",
            "gmres_solve_block_noalloc",
            "gmres_adjoint", "gmres_update_values", "gmres_spmv", "gmres_history",
            "gmres_autotune", "gmres_set_timing", "gmres_kernel_times", "gmres_set_stream",
@@ -88,6 +89,7 @@ def load_library():
     lib.gmres_block_workspace_bytes.restype = sz
     lib.gmres_solve.argtypes = [vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_solve_batched.argtypes = [vp, vp, vp, vp, C.POINTER(GmresInfo)]
+    lib.gmres_batched_attach.argtypes = [vp, i32, vp, i64]
     lib.gmres_adjoint.argtypes = [vp, vp, vp, vp, vp, C.POINTER(GmresInfo)]
     lib.gmres_solve_block.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, C.POINTER(GmresInfo)]
     lib.gmres_solve_block_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(GmresInfo)]
@@ -103,7 +105,7 @@ def load_library():
     lib.gmres_destroy.restype = None
     lib.gmres_last_error.argtypes = []
     lib.gmres_last_error.restype = C.c_char_p
-    for name in ("gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_solve_block",
+    for name in ("gmres_setup", "gmres_solve", "gmres_solve_batched", "gmres_batched_attach", "gmres_solve_block",
                  "gmres_solve_block_noalloc", "gmres_adjoint",
                  "gmres_update_values", "gmres_spmv", "gmres_autotune", "gmres_set_timing",
                  "gmres_kernel_times", "gmres_set_stream"):
@@ -201,6 +203,7 @@ class Plan:
         _check(st, allow_positive=False)
         self.workspace_bytes = nbytes
         self._block_ws = None
+        self._subs = {}   # attached continuation plans by system (kept alive here)
         self._h = h
         self._device = vals.device
 
@@ -284,6 +287,19 @@ class Plan:
         self._keep = (self._keep[0], self._keep[1], vals) + self._keep[3:]
         self._vals_version += 1
         _check(self._lib.gmres_update_values(self._h, _ptr(vals)), allow_positive=False)
+        self._subs = {}   # the library detached every continuation plan
+
+    def attach(self, s: int, sub, steps: int):
+        """Continuation plan for system s of this batched plan (None detaches):
+        the system leaves the batched launch at the first restart after `steps`
+        inner steps and goes on on `sub` (gmres_batched_attach)."""
+        h = None if sub is None else sub._h
+        _check(self._lib.gmres_batched_attach(self._h, int(s), h, int(steps) if sub is not None else 0),
+               allow_positive=False)
+        if sub is None:
+            self._subs.pop(int(s), None)
+        else:
+            self._subs[int(s)] = sub
 
     def spmv(self, x):
         import torch
@@ -339,6 +355,24 @@ def plan_for(sysm, device="cuda", need_adjoint=False, **opts):
         plan = Plan(d["rowptr"], d["colind"], d["vals"], d["z_rowptr"], d["z_colind"], d["z_vals"],
                     r=sysm.r, need_adjoint=need_adjoint, **opts)
     return plan, d
+
+
+def attach_continuations(plan: Plan, batch, min_rows: int, work: float, device="cuda", **opts):
+    """Builds single-system plans for the systems of `batch` (a
+    workloads.Batch planned as `plan`) with at least min_rows rows and
+    attaches them with a step limit of `work` row-steps, rounded up to whole
+    cycles: steps_s = m * ceil(work / (rows_s * m)).  opts: the batch's plan
+    options (m, rtol, max_iters, ...).  Returns {system: plan}."""
+    m = int(plan.opts.m)
+    subs = {}
+    rows = np.diff(batch.row_off)
+    for s in np.nonzero(rows >= min_rows)[0]:
+        s = int(s)
+        sub, _ = plan_for(batch.systems[s], device=device, **opts)
+        steps = m * max(1, int(np.ceil(work / (float(rows[s]) * m))))
+        plan.attach(s, sub, steps)
+        subs[s] = sub
+    return subs
 
 
 class DeflatedGMRES:

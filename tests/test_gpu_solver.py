@@ -422,6 +422,89 @@ def test_batched_restart_lengths(m, wg):
         assert rel(x2[batch.row_off[i]:batch.row_off[i + 1]], ref.x) <= 1e-8, i
 
 
+def _attach_all(plan, batch, steps, **opts):
+    subs = {}
+    for s in range(len(batch.systems)):
+        sub, _ = G().plan_for(batch.systems[s], **opts)
+        plan.attach(s, sub, steps)
+        subs[s] = sub
+    return subs
+
+
+def test_batched_continuation_fixed_count():
+    """Every system leaves the batched launch after its first cycle and goes
+    on on its own single-system plan: at a fixed count over three cycles the
+    result is the oracle's GMRES(20) trajectory (restarting from the
+    corrected iterate is the same iteration)."""
+    batch = _small_batch(nsys=9)
+    K = 45
+    opts = dict(m=20, rtol=0.0, max_iters=K)
+    plan, d = G().plan_for(batch, **opts)
+    subs = _attach_all(plan, batch, 20, **opts)
+    x, infos = plan.solve_batched(d["b"])
+    x = x.cpu().numpy()
+    for i, s in enumerate(batch.systems):
+        ref = oracle.gmres(s, 20, 0.0, K)
+        assert infos[i]["iters"] == K and infos[i]["status_name"] == "MAXITER", (i, infos[i])
+        assert infos[i]["cycles"] == ref.cycles, (i, infos[i]["cycles"], ref.cycles)
+        assert rel(x[batch.row_off[i]:batch.row_off[i + 1]], ref.x) <= 1e-8, i
+    assert len(subs) == 9
+
+
+def test_batched_continuation_to_tolerance():
+    """Continuations after one cycle, up to 16 running at once: solutions,
+    iteration counts and true residuals as in the per-system oracle solve;
+    a second call reuses the plans; detaching restores the plain launch."""
+    batch = _small_batch()
+    opts = dict(m=30, rtol=1e-8, max_iters=5000)
+    plan, d = G().plan_for(batch, **opts)
+    _attach_all(plan, batch, 30, **opts)
+    refs = [oracle.gmres(s, 30, 1e-8, 5000) for s in batch.systems]
+    assert sum(r.iters > 30 for r in refs) >= 17   # more continuations than run at once
+    for call in range(2):
+        x, infos = plan.solve_batched(d["b"])
+        x = x.cpu().numpy()
+        for i, ref in enumerate(refs):
+            xi = x[batch.row_off[i]:batch.row_off[i + 1]]
+            assert infos[i]["status_name"] == "OK", (call, i, infos[i])
+            assert abs(infos[i]["iters"] - ref.iters) <= 1, (call, i, infos[i]["iters"], ref.iters)
+            assert rel(xi, ref.x) <= 1e-8, (call, i)
+            assert infos[i]["rel_res_true"] <= 1e-8 * (1 + 1e-6)
+    for s in range(len(batch.systems)):
+        plan.attach(s, None, 0)
+    x2, infos2 = plan.solve_batched(d["b"])
+    for i, ref in enumerate(refs):
+        assert abs(infos2[i]["iters"] - ref.iters) <= 1, i
+
+
+def test_batched_attach_errors_and_update_detaches():
+    Gm = G()
+    batch = _small_batch(nsys=5)
+    opts = dict(m=30, rtol=1e-8, max_iters=5000)
+    plan, d = Gm.plan_for(batch, **opts)
+    sizes = np.diff(batch.row_off)
+    other = int(np.nonzero(sizes != sizes[0])[0][0])
+    wrong, _ = Gm.plan_for(batch.systems[other], **opts)
+    with pytest.raises(Gm.GmresError):
+        plan.attach(0, wrong, 30)               # another system's size
+    right, _ = Gm.plan_for(batch.systems[0], **opts)
+    with pytest.raises(Gm.GmresError):
+        plan.attach(0, right, 0)                # steps < 1
+    with pytest.raises(Gm.GmresError):
+        plan.attach(len(batch.systems), right, 30)
+    m20, _ = Gm.plan_for(batch.systems[0], m=20, rtol=1e-8, max_iters=5000)
+    with pytest.raises(Gm.GmresError):
+        plan.attach(0, m20, 30)                 # another restart length
+    with pytest.raises(Gm.GmresError):
+        right.attach(0, right, 30)              # not a batched plan
+    plan.attach(0, right, 30)
+    plan.update_values(d["vals"])
+    assert plan._subs == {}
+    x, infos = plan.solve_batched(d["b"])
+    ref = oracle.gmres(batch.systems[0], 30, 1e-8, 5000)
+    assert abs(infos[0]["iters"] - ref.iters) <= 1
+
+
 def test_single_system_batch_equals_solve():
     s = W.make_config(1, mesh=40)
     b = W.concat_systems([s])
