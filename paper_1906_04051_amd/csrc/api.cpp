@@ -193,6 +193,8 @@ struct gmres_plan_s {
     std::vector<int64_t> cont_steps;
     int64_t* d_hand = nullptr;   // device copy of cont_steps (0: no continuation)
     int ncont = 0;
+    HandRec* hrec_h = nullptr;   // pinned, coherent: systems that have left, while the launch runs
+    HandRec* hrec_d = nullptr;   // the same records as the device addresses them
 
     Timer timer;
 };
@@ -1175,6 +1177,7 @@ void gmres_destroy(gmres_plan p) {
         }
     gm::block_delete(p->block);
     if (p->ctrl_h) hipHostFree(p->ctrl_h);
+    if (p->hrec_h) hipHostFree(p->hrec_h);
     for (auto e : {p->ev_cyc[0], p->ev_cyc[1], p->ev_in, p->ev_out})
         if (e) hipEventDestroy(e);
     if (p->st) hipStreamDestroy(p->st);
@@ -1725,6 +1728,8 @@ static gmres_status run_batched(gmres_plan_s* p, const double* b, const double* 
     }
     a.order = p->border;
     a.hand = p->ncont > 0 ? p->d_hand : nullptr;
+    a.rec = p->ncont > 0 ? p->hrec_d : nullptr;
+    if (a.rec) std::memset(p->hrec_h, 0, (size_t)p->nsys * sizeof(HandRec));   // the last launch has ended
     a.rowptr = p->rowptr;
     a.colind = p->colind;
     a.vals = p->vals;
@@ -1768,6 +1773,11 @@ gmres_status gmres_batched_attach(gmres_plan p, int32_t s, gmres_plan sub, int64
         if (steps < 1) return fail(GMRES_EINVAL, "steps must be >= 1");
     }
     HIP_OK(hipSetDevice(p->device));
+    if (sub && !p->hrec_h) {
+        HIP_OK(hipHostMalloc((void**)&p->hrec_h, (size_t)p->nsys * sizeof(HandRec),
+                             hipHostMallocCoherent | hipHostMallocMapped));
+        HIP_OK(hipHostGetDevicePointer((void**)&p->hrec_d, p->hrec_h, 0));
+    }
     if (!p->cont[s] && sub) ++p->ncont;
     if (p->cont[s] && !sub) --p->ncont;
     p->cont[s] = sub;
@@ -1801,7 +1811,8 @@ gmres_status cont_start(gmres_plan_s* p, Continuation& c, const double* b, doubl
     gmres_plan_s* q = c.q;
     const int64_t off = p->row_off[c.s];
     c.t0 = std::chrono::steady_clock::now();
-    HIP_OK(hipStreamWaitEvent(q->st, p->ev_out, 0));   // the batched launch has written x
+    // x_s is in memory (the launch released it before the flag, or has
+    // ended), and these kernels start after this point.
     launch_copy(q->st, b + off, q->bws, q->n);
     launch_copy(q->st, x + off, q->xh, q->n);
     c.saved_period = q->timer.period;
@@ -1853,20 +1864,47 @@ gmres_status cont_poll(gmres_plan_s* p, Continuation& c, double* x, bool* moved)
     return GMRES_OK;
 }
 
-// Runs the continuations, at most kActive at a time (each on its plan's own
-// stream), polling from this thread.
-gmres_status run_continuations(gmres_plan_s* p, std::vector<Continuation>& cs, const double* b, double* x,
-                               const std::vector<int64_t>& oi, const std::vector<double>& od) {
+// Runs the continuations of the systems that leave the batched launch, at
+// most kActive at a time (each on its plan's own stream), polling from this
+// thread: a system starts as soon as its host-visible record is flagged,
+// while the launch still runs; once the launch has ended, one more scan
+// finds every remaining one.
+gmres_status run_continuations(gmres_plan_s* p, std::vector<Continuation>& cs, const double* b, double* x) {
     constexpr int kActive = 16;
     TraceRange tr_("batched continuations");
-    HIP_OK(hipEventRecord(p->ev_out, p->st));
+    const int ns = p->nsys;
+    HIP_OK(hipEventRecord(p->ev_out, p->st));   // the batched launch has ended
+    std::vector<int> watch;
+    for (int s = 0; s < ns; ++s)
+        if (p->cont[s]) watch.push_back(s);
+    std::vector<int64_t> its0;
+    std::vector<double> rho0;
+    bool launch_done = false, scanned_after = false;
     size_t next = 0, done = 0;
     int active = 0;
-    while (done < cs.size()) {
+    for (;;) {
+        if (!launch_done) {
+            const hipError_t e = hipEventQuery(p->ev_out);
+            if (e == hipSuccess) launch_done = true;
+            else if (e == hipErrorNotReady) (void)hipGetLastError();
+            else HIP_OK(e);
+        }
+        const bool final_scan = launch_done && !scanned_after;
+        for (size_t k = 0; k < watch.size(); ++k) {
+            const int s = watch[k];
+            if (s < 0 || __atomic_load_n(&p->hrec_h[s].flag, __ATOMIC_ACQUIRE) == 0) continue;
+            cs.emplace_back();
+            cs.back().q = p->cont[s];
+            cs.back().s = s;
+            its0.push_back(p->hrec_h[s].its);
+            rho0.push_back(p->hrec_h[s].rho0);
+            watch[k] = -1;
+        }
+        if (final_scan) scanned_after = true;
         while (active < kActive && next < cs.size()) {
-            Continuation& c = cs[next++];
-            const int64_t left = p->o.max_iters - oi[3 * c.s];
-            CHECK(cont_start(p, c, b, x, od[4 * c.s], left));
+            Continuation& c = cs[next];
+            CHECK(cont_start(p, c, b, x, rho0[next], p->o.max_iters - its0[next]));
+            ++next;
             ++active;
         }
         bool any = false;
@@ -1881,6 +1919,7 @@ gmres_status run_continuations(gmres_plan_s* p, std::vector<Continuation>& cs, c
                 ++done;
             }
         }
+        if (scanned_after && done == cs.size()) break;
         if (!any) std::this_thread::yield();
     }
     return GMRES_OK;
@@ -1902,22 +1941,12 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
     double* nr = p->bout_d + 4 * (int64_t)ns;
     std::vector<int64_t> oi(3 * (size_t)ns);
     std::vector<double> od(5 * (size_t)ns);
-    if (p->ncont > 0) {
-        // Systems that reached their step limit go on on their attached plans.
-        HIP_OK(hipMemcpyAsync(oi.data(), p->bout_i, oi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p->st));
-        HIP_OK(hipMemcpyAsync(od.data(), p->bout_d, 4 * (size_t)ns * sizeof(double), hipMemcpyDeviceToHost,
-                              p->st));
-        HIP_OK(hipStreamSynchronize(p->st));
-    }
+    // Systems that reach their step limit go on on their attached plans.
     std::vector<Continuation> cs;
-    for (int s = 0; p->ncont > 0 && s < ns; ++s) {
-        if (oi[3 * s + 2] != kStatusHandoff) continue;
-        if (!p->cont[s]) return fail(GMRES_EDEVICE, "a system left the batch without a continuation plan");
-        cs.emplace_back();
-        cs.back().q = p->cont[s];
-        cs.back().s = s;
+    if (p->ncont > 0) {
+        cs.reserve(p->ncont);
+        CHECK(run_continuations(p, cs, b, x));
     }
-    if (!cs.empty()) CHECK(run_continuations(p, cs, b, x, oi, od));
     launch_seg_resid(p->st, ns, p->d_row_off, p->rowptr, p->colind, p->vals, x, b, nr);
     if (ns == 1) p->last_prec = -1;   // the shared basis (and its padding) is cleared before the next solve
     HIP_OK(hipMemcpyAsync(oi.data(), p->bout_i, oi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p->st));
@@ -1939,6 +1968,8 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
         in.rel_res = od[4 * s + 1];
         in.rel_res_true = in.rho0 > 0 ? std::sqrt(od[4 * ns + s]) / in.rho0 : 0.0;
         in.solve_ms = clk_khz > 0 ? (od[4 * s + 3] - od[4 * s + 2]) / (double)clk_khz : wall;
+        if (in.status == kStatusHandoff && !by_sys[s])
+            return fail(GMRES_EDEVICE, "a system left the batch without being continued");
         if (const Continuation* c = by_sys[s]) {
             in.iters += c->out.its;
             in.cycles += c->out.cycles;

@@ -618,6 +618,9 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
                 x[i] = v;
             }
         }
+        // A system leaving for its continuation plan: each wave's x stores
+        // reach memory (agent-scope release) before the flag below.
+        if (status == kStatusHandoff && a.rec) __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) {
             const uint64_t t_end = wall_clock64();
@@ -628,6 +631,11 @@ __global__ __launch_bounds__(WGS) void k_batched(BatchArgs a) {
             a.out_d[4 * sys + 1] = rho0 > 0.0 ? beta / rho0 : 0.0;
             a.out_d[4 * sys + 2] = (double)t_start;
             a.out_d[4 * sys + 3] = (double)t_end;
+            if (status == kStatusHandoff && a.rec) {
+                a.rec[sys].its = its;
+                a.rec[sys].rho0 = rho0;
+                __hip_atomic_store(&a.rec[sys].flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
         __syncthreads();
     }

@@ -286,6 +286,16 @@ inline int64_t block_slots_bound(int64_t n, int RB, int R, int64_t znnz) {
 }
 
 // batched.hip
+// Host-visible record of a system that left the batched launch for its
+// continuation plan: written before the flag, the flag last with a
+// system-scope release (the system's x is in memory by then).
+struct HandRec {
+    int64_t its;
+    double rho0;
+    int32_t flag;
+    int32_t pad;
+};
+
 struct BatchArgs {
     hipStream_t st;
     int nsys, m, L, wg;
@@ -295,6 +305,7 @@ struct BatchArgs {
     const int64_t* w_off;                                 // per-system work-vector regions
     const int* order;                                     // systems by decreasing work
     const int64_t* hand;   // per system: steps after which it leaves at a restart (0: never; NULL: none)
+    HandRec* rec;          // per system, host-visible (pinned, coherent); NULL: none
     const int *rowptr, *colind;
     const double* vals;
     const int *azrp, *azci;
