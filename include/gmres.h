@@ -212,7 +212,8 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
  * must not be used elsewhere while a batched solve runs.  sub = NULL
  * detaches.  gmres_update_values on the batched plan detaches every
  * continuation.  Errors: EINVAL (not a batched plan, s out of range, a sub of
- * another size, r or m, steps < 1), EDEVICE.
+ * another size, r or m, steps < 1, a sub already continuing another system of
+ * the batch), EDEVICE.
  */
 gmres_status gmres_batched_attach(gmres_plan p, int32_t s, gmres_plan sub, int64_t steps);
 

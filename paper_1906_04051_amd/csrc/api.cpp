@@ -1771,6 +1771,9 @@ gmres_status gmres_batched_attach(gmres_plan p, int32_t s, gmres_plan sub, int64
         if (sub->o.m != p->o.m || sub->o.adapt_rmax > 0 || sub->device != p->device)
             return fail(GMRES_EINVAL, "the attached plan must share m and the device, without adaptive deflation");
         if (steps < 1) return fail(GMRES_EINVAL, "steps must be >= 1");
+        for (int t = 0; t < p->nsys; ++t)
+            if (t != s && p->cont[t] == sub)
+                return fail(GMRES_EINVAL, "a plan continues at most one system of the batch");
     }
     HIP_OK(hipSetDevice(p->device));
     if (sub && !p->hrec_h) {

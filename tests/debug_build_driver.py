@@ -100,6 +100,21 @@ def main():
             e = rel(xb[batch.row_off[i]:batch.row_off[i + 1]], rb.x)
             check(infos[i]["status_name"] == "OK" and e <= 1e-8, f"batched {lanes} {i} {e}")
         say("batched lanes", lanes, "ok")
+    # Batched with continuation plans: every system leaves after one cycle.
+    plan, d = G.plan_for(batch, m=20, rtol=1e-8, max_iters=4000)
+    subs = []
+    for i, si in enumerate(systems):
+        sp, _ = G.plan_for(si, m=20, rtol=1e-8, max_iters=4000)
+        plan.attach(i, sp, 20)
+        subs.append(sp)
+    xb, infos = plan.solve_batched(d["b"])
+    xb = xb.cpu().numpy()
+    for i, si in enumerate(systems):
+        rb = oracle.gmres(si, 20, 1e-8, 4000)
+        e = rel(xb[batch.row_off[i]:batch.row_off[i + 1]], rb.x)
+        check(infos[i]["status_name"] == "OK" and e <= 1e-8 and abs(infos[i]["iters"] - rb.iters) <= 1,
+              f"batched continuation {i} {e} {infos[i]['iters']} {rb.iters}")
+    say("batched continuations ok")
     # Block GMRES, fixed count.
     sb = W.make_config(1, mesh=20)
     sb = copy.copy(sb)

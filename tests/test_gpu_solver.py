@@ -498,6 +498,10 @@ def test_batched_attach_errors_and_update_detaches():
     with pytest.raises(Gm.GmresError):
         right.attach(0, right, 30)              # not a batched plan
     plan.attach(0, right, 30)
+    twin = int(np.nonzero(sizes == sizes[0])[0][1]) if (sizes == sizes[0]).sum() > 1 else None
+    if twin is not None:
+        with pytest.raises(Gm.GmresError):
+            plan.attach(twin, right, 30)        # one plan, two systems
     plan.update_values(d["vals"])
     assert plan._subs == {}
     x, infos = plan.solve_batched(d["b"])
