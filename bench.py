@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # while the kernel sources hash to `sources_sha256`; None until measured.
 TRAFFIC = {
     5: {"kind": "pass1_lag",
-        "sources_sha256": "951f026af6c76a9dd05ce311fd927694ec34e459f5283db9e8fa64f412530565",
+        "sources_sha256": "10f6a89f6f99be17dd2e943a7d5b0432145bd8a05ad43a7bcdc3f01b0c05691f",
         "bytes_per_launch": 1076.4e6},   # 1,008.6 MB read + 67.8 MB written (98 launches)
 }
 KERNEL_SOURCES = ("paper_1906_04051_amd/csrc/krylov.hip", "paper_1906_04051_amd/csrc/common.hpp",
