@@ -252,6 +252,29 @@ def test_config4_batched_512_systems():
     for i in np.random.default_rng(3).choice(batch.nsys, 32, replace=False):
         s = batch.systems[i]
         residual_checks(s, x[batch.row_off[i]:batch.row_off[i + 1]], 1e-8, infos[i]["rho0"], f"system {i}")
+    # The benchmark's continuation plans: systems of at least 20,000 rows still
+    # running after 128 M row-steps go on on the multi-workgroup engine.
+    subs = G().attach_continuations(plan, batch, 20000, 128e6, m=30, rtol=1e-8, max_iters=200000)
+    rows = np.diff(batch.row_off)
+    x2, infos2 = plan.solve_batched(d["b"])
+    x2 = x2.cpu().numpy()
+    cont = [s for s in subs if infos2[s]["iters"] > 30 * int(np.ceil(128e6 / (rows[s] * 30)))]
+    say(f"config 4 with continuation plans: {len(subs)} attached, {len(cont)} continued")
+    assert len(cont) >= 10
+    # The continued solve is the same iteration, but its rounding differs from
+    # the persistent kernel's (other reduction orders); over hundreds of
+    # restarts that moves the step at which the tolerance is met by up to about
+    # a cycle, so the step counts are compared to one cycle plus 2%.
+    d_its = [infos2[i]["iters"] - infos[i]["iters"] for i in cont]
+    say(f"continued systems: steps vs the persistent kernel alone: min {min(d_its)}, max {max(d_its)}")
+    for i in range(batch.nsys):
+        assert infos2[i]["status_name"] == "OK", (i, infos2[i])
+        assert infos2[i]["rel_res_true"] <= 1e-8 * (1 + 1e-6), (i, infos2[i])
+        tol = 2 if i not in subs else 30 + 0.02 * infos[i]["iters"]
+        assert abs(infos2[i]["iters"] - infos[i]["iters"]) <= tol, (i, infos2[i]["iters"], infos[i]["iters"])
+    for i in cont[:8]:
+        residual_checks(batch.systems[i], x2[batch.row_off[i]:batch.row_off[i + 1]], 1e-8,
+                        infos2[i]["rho0"], f"continued system {i}")
 
 
 def test_config2_adaptive_deflation_fixed_count(cfg2):
