@@ -211,7 +211,10 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
  * the caller and must outlive its attachment; one sub per system, and a sub
  * must not be used elsewhere while a batched solve runs.  sub = NULL
  * detaches.  gmres_update_values on the batched plan detaches every
- * continuation.  Errors: EINVAL (not a batched plan, s out of range, a sub of
+ * continuation.  Kernel timing (gmres_set_timing) is not collected on a sub
+ * while it continues a system.  The first attach allocates the plan's
+ * pinned host records of the systems that leave (nsys x 24 bytes; no device
+ * memory).  Errors: EINVAL (not a batched plan, s out of range, a sub of
  * another size, r or m, steps < 1, a sub already continuing another system of
  * the batch), EDEVICE.
  */
