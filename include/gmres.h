@@ -204,8 +204,8 @@ gmres_status gmres_solve_batched(gmres_plan p, const double* b, const double* x0
  * carries only the iterate from one cycle to the next (Sec. 3.2), and P A Z
  * = 0 leaves P r unchanged by the correction, so the continued solve is the
  * same iteration as staying in the batch, up to rounding.  infos_h[s] then
- * sums steps and cycles of both parts; solve_ms adds the continuation's host
- * wall time.  sub: a single-system plan (FP64 engine used whatever its
+ * sums steps and cycles of both parts; solve_ms adds the host wall time from
+ * the moment the system was seen leaving to the end of its continuation.  sub: a single-system plan (FP64 engine used whatever its
  * precision option) built on system s's rows with local indices, the same
  * values, Z columns, m and device, no adaptive deflation; it stays owned by
  * the caller and must outlive its attachment; one sub per system, and a sub

@@ -1813,7 +1813,6 @@ gmres_status cont_start(gmres_plan_s* p, Continuation& c, const double* b, doubl
                         int64_t steps_left) {
     gmres_plan_s* q = c.q;
     const int64_t off = p->row_off[c.s];
-    c.t0 = std::chrono::steady_clock::now();
     // x_s is in memory (the launch released it before the flag, or has
     // ended), and these kernels start after this point.
     launch_copy(q->st, b + off, q->bws, q->n);
@@ -1899,6 +1898,7 @@ gmres_status run_continuations(gmres_plan_s* p, std::vector<Continuation>& cs, c
             cs.emplace_back();
             cs.back().q = p->cont[s];
             cs.back().s = s;
+            cs.back().t0 = std::chrono::steady_clock::now();   // waiting for a slot counts too
             its0.push_back(p->hrec_h[s].its);
             rho0.push_back(p->hrec_h[s].rho0);
             watch[k] = -1;
