@@ -78,8 +78,8 @@ def _load():
     lib.oracle_dgmres.argtypes = [C.c_int64, i32p, i32p, f64p, f64p, vp, C.c_int32, C.c_int64,
                                   C.c_double, C.c_int32, f64p, i64p, f64p, vp, vp, vp]
     lib.oracle_dgmres.restype = C.c_int
-    lib.oracle_bgmres.argtypes = [C.c_int64, i32p, i32p, f64p, C.c_int32, f64p, vp, C.c_int32,
-                                  C.c_int64, C.c_double, f64p, i64p, f64p, vp]
+    lib.oracle_bgmres.argtypes = [C.c_int64, i32p, i32p, f64p, C.c_int32, vp, vp, vp, C.c_int32, f64p, vp,
+                                  C.c_int32, C.c_int64, C.c_double, f64p, i64p, f64p, vp]
     lib.oracle_bgmres.restype = C.c_int
     lib.oracle_power_iteration.argtypes = [C.c_int32, f64p, f64p]
     lib.oracle_power_iteration.restype = C.c_double
@@ -206,9 +206,11 @@ def dgmres(sysm, m: int, rtol: float, max_iters: int, rmax: int = 20, x0=None, b
 
 
 def bgmres(rowptr, colind, vals, B, m: int, rtol: float, max_steps: int, X0=None,
-           history: bool = False) -> Result:
+           history: bool = False, z=None) -> Result:
     """Block GMRES(m) for A X = B with the k columns of B (n x k) as right-hand
-    sides (definition and readings in bgmres.c).  Iterations are block steps."""
+    sides (definition and readings in bgmres.c).  Iterations are block steps.
+    z: None, or (r, z_rowptr, z_colind, z_vals) of a deflation basis Z (n x r,
+    CSR): every column deflated as in the single-vector method."""
     lib = _load()
     B = np.ascontiguousarray(B, dtype=np.float64)
     n, k = B.shape
@@ -217,8 +219,12 @@ def bgmres(rowptr, colind, vals, B, m: int, rtol: float, max_steps: int, X0=None
     info_i = np.zeros(4, np.int64)
     info_d = np.zeros(4, np.float64)
     hist = np.zeros(max(max_steps, 1), np.float64) if history else None
-    st = lib.oracle_bgmres(n, _i32(rowptr), _i32(colind), _f64(vals), k, B, _ptr(X0a), m, max_steps,
-                           rtol, X, info_i, info_d, _ptr(hist))
+    if z is None or int(z[0]) == 0:
+        zr, zrp, zci, zvv = 0, None, None, None
+    else:
+        zr, zrp, zci, zvv = int(z[0]), _i32(z[1]), _i32(z[2]), _f64(z[3])
+    st = lib.oracle_bgmres(n, _i32(rowptr), _i32(colind), _f64(vals), zr, _ptr(zrp), _ptr(zci), _ptr(zvv),
+                           k, B, _ptr(X0a), m, max_steps, rtol, X, info_i, info_d, _ptr(hist))
     res = Result(x=X, iters=int(info_i[0]), cycles=int(info_i[1]), status=int(st),
                  status_name=STATUS.get(int(st), str(st)), rho0_max=float(info_d[0]),
                  rel_res_est=float(info_d[1]), rel_res_true=float(info_d[2]))

@@ -43,6 +43,15 @@
  *     (G = [S; 0], S kb x ka), so restarted residuals that have become
  *     nearly dependent do not stop the solve;
  *   - a column with rho0_c = 0 is rejected (EINVAL), as is k < 1 or m < 1.
+ *
+ * With a deflation basis Z (r > 0), every column is deflated as in the
+ * single-vector method (Sec. 3.3, eq. precond1): the operator is P A with
+ * P = I - A Z E^{-1} Z^T, the starting residuals are P (b_c - A x0_c), the
+ * tests compare ||P (b_c - A x_hat_c)|| with rtol * rho0_c where rho0_c =
+ * ||b_c - A x0_c|| (unprojected, as for one right-hand side), and at exit
+ * x_c = x_hat_c + Z E^{-1} Z^T (b_c - A x_hat_c) (eq. precond2), whose true
+ * residual is P (b_c - A x_hat_c).  With k = 1 this is the deflated GMRES(m)
+ * of oracle.c.
  * Build with -ffp-contract=off; sums run in index order.
  */
 #include <float.h>
@@ -64,6 +73,12 @@ void oracle_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const 
                  const double *x, double *y);
 double oracle_dot(int64_t n, const double *a, const double *b);
 double oracle_nrm2(int64_t n, const double *a);
+void *oracle_defl_create(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+                         int32_t r, const int32_t *zrp, const int32_t *zci, const double *zv,
+                         int *status);
+void oracle_defl_apply(void *d, const double *y, double *w);
+void oracle_defl_correct(void *d, const double *r, double *x);
+void oracle_defl_destroy(void *d);
 
 /* Householder QR of the (rows x cols) column-major matrix M (rows >= cols),
  * applied to the (rows x k) column-major right-hand side G: on return the
@@ -121,6 +136,7 @@ static void get_col(int64_t n, int k, const double *M, int c, double *out)
  * hist (nullable, max_steps entries): per block step, max_c estimate / rho0_c.
  */
 int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+                  int32_t r, const int32_t *zrp, const int32_t *zci, const double *zv,
                   int32_t k, const double *B, const double *X0, int32_t m, int64_t max_steps,
                   double rtol, double *X, int64_t *info_i, double *info_d, double *hist)
 {
@@ -128,7 +144,7 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
         info_i[q] = 0;
         info_d[q] = 0.0;
     }
-    if (n < 1 || k < 1 || m < 1 || max_steps < 0 || !(rtol >= 0.0)) return BG_EINVAL;
+    if (n < 1 || k < 1 || m < 1 || max_steps < 0 || !(rtol >= 0.0) || r < 0) return BG_EINVAL;
     if (!finite_all(n * (int64_t)k, B) || !finite_all(rowptr[n], vals) ||
         (X0 && !finite_all(n * (int64_t)k, X0)))
         return BG_ENONFINITE;
@@ -142,24 +158,39 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
     double *rho0 = (double *)malloc(sizeof(double) * (size_t)k);
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     double *w = (double *)malloc(sizeof(double) * (size_t)n);
-    if (!V || !Hb || !M || !G || !S || !Y || !rho0 || !t || !w) {
-        free(V); free(Hb); free(M); free(G); free(S); free(Y); free(rho0); free(t); free(w);
+    double *raw = (double *)malloc(sizeof(double) * (size_t)k);
+    if (!V || !Hb || !M || !G || !S || !Y || !rho0 || !t || !w || !raw) {
+        free(V); free(Hb); free(M); free(G); free(S); free(Y); free(rho0); free(t); free(w); free(raw);
         return BG_ENOMEM;
+    }
+    void *defl = NULL;
+    if (r > 0) {
+        int dst = 0;
+        defl = oracle_defl_create(n, rowptr, colind, vals, r, zrp, zci, zv, &dst);
+        if (!defl) {
+            free(V); free(Hb); free(M); free(G); free(S); free(Y); free(rho0); free(t); free(w); free(raw);
+            return dst == BG_ENOMEM ? BG_ENOMEM : (dst == -2 ? -2 : BG_EINVAL);
+        }
     }
     for (int64_t i = 0; i < n * (int64_t)k; ++i) X[i] = X0 ? X0[i] : 0.0;
 
-    /* R = B - A X for every column, into V's first block (column vectors). */
+    /* R = P (B - A X) for every column, into V's first block (column
+     * vectors); raw[c] = ||b_c - A x_c|| before the projection. */
 #define RESIDUALS(NORMS)                                                         \
     for (int c = 0; c < k; ++c) {                                                \
         get_col(n, k, X, c, t);                                                  \
         oracle_spmv(n, rowptr, colind, vals, t, w);                              \
-        for (int64_t i = 0; i < n; ++i) V[(size_t)c * n + i] = B[i * k + c] - w[i]; \
+        for (int64_t i = 0; i < n; ++i) w[i] = B[i * k + c] - w[i];              \
+        raw[c] = oracle_nrm2(n, w);                                              \
+        if (defl) oracle_defl_apply(defl, w, V + (size_t)c * n);                 \
+        else memcpy(V + (size_t)c * n, w, sizeof(double) * (size_t)n);           \
         NORMS[c] = oracle_nrm2(n, V + (size_t)c * n);                            \
     }
 
     double *rn = (double *)malloc(sizeof(double) * (size_t)k);
     int *act = (int *)malloc(sizeof(int) * (size_t)k);
-    RESIDUALS(rho0);
+    RESIDUALS(rn);
+    for (int c = 0; c < k; ++c) rho0[c] = raw[c];
     double rho_max = 0.0;
     int bad = 0;
     for (int c = 0; c < k; ++c) {
@@ -174,7 +205,6 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
         status = BG_EINVAL;
         goto done;
     }
-    for (int c = 0; c < k; ++c) rn[c] = rho0[c];
     for (;;) {
         int all = 1;
         for (int c = 0; c < k; ++c)
@@ -228,6 +258,10 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
             for (int c = 0; c < kk; ++c) {
                 const int col = j * kk + c, newq = (j + 1) * kk + c;
                 oracle_spmv(n, rowptr, colind, vals, V + (size_t)col * n, w);
+                if (defl) {
+                    oracle_defl_apply(defl, w, t);
+                    memcpy(w, t, sizeof(double) * (size_t)n);
+                }
                 const double before = oracle_nrm2(n, w);
                 for (int q = 0; q < newq; ++q) {
                     const double h = oracle_dot(n, V + (size_t)q * n, w);
@@ -290,11 +324,21 @@ int oracle_bgmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const
         RESIDUALS(rn);
     }
 done:
+    if (defl && status != BG_EINVAL && status != BG_ENONFINITE) {
+        /* x_c = x_hat_c + Z E^{-1} Z^T (b_c - A x_hat_c). */
+        for (int c = 0; c < k; ++c) {
+            get_col(n, k, X, c, t);
+            oracle_spmv(n, rowptr, colind, vals, t, w);
+            for (int64_t i = 0; i < n; ++i) w[i] = B[i * k + c] - w[i];
+            oracle_defl_correct(defl, w, t);
+            for (int64_t i = 0; i < n; ++i) X[i * k + c] = t[i];
+        }
+    }
     {
         double tr = 0.0;
         RESIDUALS(rn);
         for (int c = 0; c < k; ++c)
-            if (rho0[c] > 0.0 && rn[c] / rho0[c] > tr) tr = rn[c] / rho0[c];
+            if (rho0[c] > 0.0 && raw[c] / rho0[c] > tr) tr = raw[c] / rho0[c];
         info_d[2] = tr;
     }
     info_i[0] = steps;
@@ -302,6 +346,7 @@ done:
     info_d[1] = est_max;
 #undef RESIDUALS
     free(V); free(Hb); free(M); free(G); free(S); free(Y); free(rho0); free(t); free(w); free(rn);
-    free(act);
+    free(act); free(raw);
+    oracle_defl_destroy(defl);
     return status;
 }

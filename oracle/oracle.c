@@ -192,6 +192,38 @@ static void defl_correct(const oracle_defl *d, const double *r, double *x)
             x[i] += d->zv[q] * d->t[d->zci[q]];
 }
 
+/* The same operator for the block oracle (bgmres.c), as an opaque handle:
+ * create (NULL and *status != OR_OK on failure), w = P y, x += Z E^{-1} Z^T r,
+ * destroy. */
+void *oracle_defl_create(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+                         int32_t r, const int32_t *zrp, const int32_t *zci, const double *zv,
+                         int *status)
+{
+    oracle_defl *d = (oracle_defl *)calloc(1, sizeof(oracle_defl));
+    if (!d) {
+        *status = OR_ENOMEM;
+        return NULL;
+    }
+    *status = defl_setup(d, n, rowptr, colind, vals, r, zrp, zci, zv);
+    if (*status != OR_OK) {
+        defl_free(d);
+        free(d);
+        return NULL;
+    }
+    return d;
+}
+
+void oracle_defl_apply(void *d, const double *y, double *w) { defl_apply_P((const oracle_defl *)d, y, w); }
+
+void oracle_defl_correct(void *d, const double *r, double *x) { defl_correct((const oracle_defl *)d, r, x); }
+
+void oracle_defl_destroy(void *d)
+{
+    if (!d) return;
+    defl_free((oracle_defl *)d);
+    free(d);
+}
+
 /* Exposed for tests: w = P y for one vector (sets up and frees the coarse
  * operator on each call). */
 int oracle_apply_projector(int64_t n, const int32_t *rowptr, const int32_t *colind,

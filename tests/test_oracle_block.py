@@ -194,3 +194,59 @@ def test_dependent_right_hand_sides_keep_linearity():
     for c in range(5):
         r = B[:, c] - oracle.spmv(s.rowptr, s.colind, s.vals, X[:, c])
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(B[:, c]) * (1 + 1e-6)
+
+
+def _z(s):
+    return (s.r, s.z_rowptr, s.z_colind, s.z_vals)
+
+
+@pytest.mark.parametrize("rtol,K", [(0.0, 37), (1e-9, 3000)])
+def test_deflated_single_column_is_deflated_gmres(rtol, K):
+    """With a deflation basis and one right-hand side the block method is the
+    deflated GMRES(m) of the single-vector oracle (Sec. 3.3): the same
+    iterate at a fixed count over several cycles, the same step count and
+    solution to tolerance."""
+    s = W.make_config(1, mesh=16)
+    assert s.r > 0
+    ref = oracle.gmres(s, 10, rtol, K)
+    res = oracle.bgmres(s.rowptr, s.colind, s.vals, s.b[:, None], 10, rtol, K, z=_z(s))
+    assert res.iters == ref.iters, (res.iters, ref.iters)
+    assert np.linalg.norm(res.x[:, 0] - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    if rtol > 0:
+        assert res.status_name == "OK" and ref.status_name == "OK"
+    # Without the projection the block method is another iteration.
+    plain = oracle.bgmres(s.rowptr, s.colind, s.vals, s.b[:, None], 10, rtol, K)
+    assert np.linalg.norm(plain.x[:, 0] - ref.x) > 1e-6 * np.linalg.norm(ref.x) or plain.iters != ref.iters
+
+
+def test_deflation_with_full_basis_is_exact():
+    """Z = I: P A = 0, the projected residual vanishes at the start and the
+    coarse correction alone gives X = A^{-1} B, after no block step."""
+    n, k = 30, 3
+    A = _nonsym(n, 21)
+    rp, ci, v = _csr(A)
+    B = np.random.default_rng(8).standard_normal((n, k))
+    z = (n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    res = oracle.bgmres(rp, ci, v, B, 4, 1e-12, 40, z=z)
+    assert res.status_name == "OK" and res.iters == 0
+    ex = np.linalg.solve(A.toarray(), B)
+    assert np.abs(res.x - ex).max() <= 1e-12 * np.abs(ex).max()
+
+
+def test_deflated_block_to_tolerance():
+    """Four right-hand sides with the indicator basis: every column's true
+    residual meets rtol times its unprojected initial residual, and Z^T r = 0
+    to rounding (the coarse correction at exit)."""
+    s = W.make_config(1, mesh=16)
+    k = 4
+    B = np.random.default_rng(9).standard_normal((s.n, k))
+    res = oracle.bgmres(s.rowptr, s.colind, s.vals, B, 8, 1e-10, 5000, z=_z(s))
+    assert res.status_name == "OK"
+    A = sp.csr_matrix((s.vals, s.colind, s.rowptr), shape=(s.n, s.n))
+    Z = sp.csr_matrix((s.z_vals, s.z_colind, s.z_rowptr), shape=(s.n, s.r))
+    for c in range(k):
+        r = B[:, c] - A @ res.x[:, c]
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(B[:, c]) * (1 + 1e-6)
+        zr = Z.T @ r
+        zscale = abs(Z).T @ (abs(A) @ np.abs(res.x[:, c]) + np.abs(B[:, c]))
+        assert np.all(np.abs(zr) <= 1e3 * np.finfo(float).eps * zscale)
