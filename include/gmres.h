@@ -226,10 +226,13 @@ gmres_status gmres_batched_attach(gmres_plan p, int32_t s, gmres_plan sub, int64
  * the block form of the same minimisation): after j block steps of a cycle
  * X = X0 + V Y with Y minimising ||B - A X||_F over the block Krylov space
  * span{R0, A R0, ..., A^{j-1} R0}, R0 = B - A X0; cycles restart from X.
- * Single-system plans without a deflation basis (R = 0) and without adaptive
- * deflation, any precision setting (the solve is FP64).  The plan's rtol
- * applies to every column: the solve ends when ||b_c - A x_c|| <= rtol *
- * ||b_c - A x0_c|| for all c (true residuals); max_iters caps the block
+ * Single-system plans without adaptive deflation, any precision setting
+ * (the solve is FP64).  With a deflation basis (R <= 64) every column is
+ * deflated as in gmres_solve (Sec. 3.3): the operator is P A, R0 = P (B -
+ * A X0), and at exit X = X_hat + Z E^{-1} Z^T (B - A X_hat) (eq. precond2).
+ * The plan's rtol applies to every column: the solve ends when ||P (b_c -
+ * A x_hat_c)|| (= ||b_c - A x_c|| after the correction; plain residuals
+ * without Z) <= rtol * ||b_c - A x0_c|| for all c; max_iters caps the block
  * steps.  k in [1, 16]; m_block in [1, 16] block steps per cycle (block
  * Krylov dimension m_block * k).  B, X0 (or NULL: zero), X: n x k row-major
  * device arrays owned by the caller; X must not alias B (it may alias X0).
@@ -242,8 +245,8 @@ gmres_status gmres_batched_attach(gmres_plan p, int32_t s, gmres_plan sub, int64
  * cycle runs on the columns not yet converged; a residual column that has
  * become dependent on the others adds no basis vector (the block basis may be
  * narrower than the number of right-hand sides).  Returns OK or MAXITER, or
- * EINVAL (sizes, a plan with deflation, a zero column of B - A X0),
- * ENONFINITE, EWORKSPACE, EDEVICE.
+ * EINVAL (sizes, a deflation basis of more than 64 columns, adaptive
+ * deflation, a zero column of B - A X0), ENONFINITE, EWORKSPACE, EDEVICE.
  */
 size_t gmres_block_workspace_bytes(gmres_plan p, int32_t m_block);
 gmres_status gmres_solve_block(gmres_plan p, int32_t k, int32_t m_block, const double* B,

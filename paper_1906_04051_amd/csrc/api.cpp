@@ -1478,8 +1478,9 @@ static gmres_status solve_block_impl(gmres_plan p, int32_t k, int32_t m_block, c
     TraceRange tr_("gmres_solve_block");
     if (!p || !B || !X) return fail(GMRES_EINVAL, "plan, B and X are required");
     if (p->nsys != 1) return fail(GMRES_EINVAL, "gmres_solve_block needs a single-system plan");
-    if (p->R > 0 || p->o.adapt_rmax > 0)
-        return fail(GMRES_EINVAL, "gmres_solve_block runs on A alone (no deflation basis, no adaptive deflation)");
+    if (p->o.adapt_rmax > 0) return fail(GMRES_EINVAL, "gmres_solve_block does not run adaptive deflation");
+    if (p->R > gm::kBlockZMax)
+        return fail(GMRES_EINVAL, "gmres_solve_block supports deflation bases of at most 64 columns");
     if (k < 1 || k > 16) return fail(GMRES_EINVAL, "k must be in [1, 16]");
     if (m_block < 1 || m_block > gm::kBlockStepsMax) return fail(GMRES_EINVAL, "m_block must be in [1, 16]");
     if (X == B) return fail(GMRES_EINVAL, "X must not alias B");
@@ -1519,7 +1520,8 @@ static gmres_status solve_block_impl(gmres_plan p, int32_t k, int32_t m_block, c
     } hook(p);
     p->timer.reset();
     gm::BlockArgs a{p->st, p->rowptr, p->colind, p->vals, k, m_block, p->o.rtol, p->o.max_iters, B, X0, X,
-                    p->nnz, p->timer.period > 0 ? &hook : nullptr};
+                    p->nnz, p->timer.period > 0 ? &hook : nullptr, p->R, p->ztrp, p->ztci, p->ztv, p->zrp,
+                    p->zci, p->zv, p->azrp, p->azci, p->azv, p->Einv};
     gm::BlockResult r;
     const int s = gm::block_solve(p->block, a, &r);
     if (p->timer.period > 0) {

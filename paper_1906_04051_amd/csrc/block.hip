@@ -44,6 +44,7 @@ constexpr int kSplit = 16;         // first-level splits of the partial sums
 constexpr int kNormGrid = 1024;    // workgroups of the residual kernel
 constexpr int kLdH = (kBlockStepsMax + 1) * kBW;   // rows of the least-squares arrays
 constexpr double kBdTol = 1e-10;
+constexpr int kZtChunks = 16;      // workgroups per row of Z^T in the panel's Z^T W
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -70,6 +71,103 @@ __global__ __launch_bounds__(kWG) void k_bunpack(int64_t n, int k, const double*
     const int64_t row = e / k;
     const int c = (int)(e % k);
     dst[e] = P[row * kBW + c];
+}
+
+// Deflation of a panel (Sec. 3.3, eq. precond1, applied to each of the 16
+// columns): T = Z^T W, S = E^{-1} T, then W -= (A Z) S (projection) or
+// X += Z S (coarse correction at exit, eq. precond2).
+//
+// Partial sums of T: workgroup (c, ch) sums chunk ch of row c of Z^T, 16
+// entries at a time, one lane per panel column; fixed order.
+__global__ __launch_bounds__(kWG) void k_bzt(const int* __restrict__ ztrp, const int* __restrict__ ztci,
+                                             const double* __restrict__ ztv, const double* __restrict__ W,
+                                             double* __restrict__ zpart, const int* __restrict__ stop) {
+    __shared__ double red[kWG];
+    if (stop && *stop) return;   // a later step of a cycle that has ended
+    const int c = blockIdx.x, ch = blockIdx.y;
+    const int q0 = ztrp[c], q1 = ztrp[c + 1];
+    const int cl = (q1 - q0 + kZtChunks - 1) / kZtChunks;
+    const int a0 = q0 + ch * cl, a1 = min(q1, a0 + cl);
+    const int l = threadIdx.x & (kBW - 1), g = threadIdx.x / kBW;
+    double acc = 0.0;
+    for (int q = a0 + g; q < a1; q += kWG / kBW) acc += ztv[q] * W[(int64_t)ztci[q] * kBW + l];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < kBW) {
+        double t = 0.0;
+        for (int i = 0; i < kWG / kBW; ++i) t += red[i * kBW + threadIdx.x];
+        zpart[((int64_t)c * kZtChunks + ch) * kBW + threadIdx.x] = t;
+    }
+}
+
+// S = E^{-1} T (R x 16, row c of T the sum of its chunks in order); one
+// workgroup, T and E^{-1} staged in LDS.
+__global__ __launch_bounds__(kWG) void k_bcoarse(int R, const double* __restrict__ zpart,
+                                                 const double* __restrict__ Einv, double* __restrict__ S,
+                                                 const int* __restrict__ stop) {
+    __shared__ double T[kBlockZMax * kBW];
+    __shared__ double Ei[kBlockZMax * kBlockZMax];
+    if (stop && *stop) return;
+    for (int e = threadIdx.x; e < R * kBW; e += kWG) {
+        const int c = e / kBW, l = e % kBW;
+        double t = 0.0;
+        for (int ch = 0; ch < kZtChunks; ++ch) t += zpart[((int64_t)c * kZtChunks + ch) * kBW + l];
+        T[e] = t;
+    }
+    for (int e = threadIdx.x; e < R * R; e += kWG) Ei[e] = Einv[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * kBW; e += kWG) {
+        const int i = e / kBW, l = e % kBW;
+        double t = 0.0;
+        for (int a = 0; a < R; ++a) t += Ei[a * R + i] * T[a * kBW + l];
+        S[e] = t;
+    }
+}
+
+// P += sign * M S over the rows of the CSR matrix M (n x R, local columns):
+// sign -1 with M = A Z projects W, sign +1 with M = Z corrects X.  16 lanes
+// per row, S staged in LDS.
+__global__ __launch_bounds__(kWG) void k_bzapply(int64_t n, int R, const int* __restrict__ mrp,
+                                                 const int* __restrict__ mci, const double* __restrict__ mv,
+                                                 const double* __restrict__ S, double sign, double* __restrict__ P,
+                                                 const int* __restrict__ stop) {
+    __shared__ double Ss[kBlockZMax * kBW];
+    if (stop && *stop) return;
+    for (int e = threadIdx.x; e < R * kBW; e += kWG) Ss[e] = S[e];
+    __syncthreads();
+    const int l = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
+    for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
+        const int64_t row = r0 + rl;
+        if (row >= n) continue;
+        double t = 0.0;
+        for (int q = mrp[row]; q < mrp[row + 1]; ++q) {
+            GM_DCHECK(mci[q] >= 0 && mci[q] < R, kDbgBlockCol);
+            t += mv[q] * Ss[mci[q] * kBW + l];
+        }
+        P[row * kBW + l] += sign * t;
+    }
+}
+
+// Per-workgroup partial sums of squares of the 16 columns of a panel.
+__global__ __launch_bounds__(kWG) void k_bnorm(int64_t n, const double* __restrict__ W,
+                                               double* __restrict__ part) {
+    __shared__ double red[kWG];
+    const int l = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
+    double acc = 0.0;
+    for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
+        const int64_t row = r0 + rl;
+        if (row < n) {
+            const double y = W[row * kBW + l];
+            acc += y * y;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < kBW) {
+        double t = 0.0;
+        for (int i = 0; i < kWG / kBW; ++i) t += red[i * kBW + threadIdx.x];
+        part[(int64_t)blockIdx.x * kBW + threadIdx.x] = t;
+    }
 }
 
 // Y = A X (MODE 0), or Y = B - A X with per-workgroup partial sums of squares
@@ -704,6 +802,7 @@ struct BlockWork {
     double *R1 = nullptr, *R = nullptr, *Rinv = nullptr, *nb2 = nullptr, *Cy = nullptr;
     double *npart = nullptr, *nsq = nullptr;
     double *lsbuf = nullptr, *S = nullptr;
+    double *zpart = nullptr, *Sz = nullptr;   // deflation: Z^T W partials, E^{-1} Z^T W
     int* flag = nullptr;
     int* imap = nullptr;   // [0,16): column map; [16,32): active columns; [32,48): broken mask
     LsView ls{};
@@ -776,6 +875,8 @@ void block_carve(BlockWork* w, Arena& ar, int64_t n, int m) {
     w->nsq = ar.take_n<double>(kBW);
     w->lsbuf = ar.take_n<double>(ls_entries());
     w->S = ar.take_n<double>(kPan);
+    w->zpart = ar.take_n<double>((int64_t)kBlockZMax * kZtChunks * kBW);
+    w->Sz = ar.take_n<double>((int64_t)kBlockZMax * kBW);
     w->flag = ar.take_n<int>(3);
     w->imap = ar.take_n<int>(3 * kBW);
 }
@@ -895,15 +996,40 @@ double spmm_bytes(const BlockWork& w, const BlockArgs& a, int mode) {
     return 12.0 * (double)a.nnz + 4.0 * (double)(w.n + 1) + (2.0 + mode) * (double)w.n * kBW * sizeof(double);
 }
 
-int residual(const BlockWork& w, const BlockArgs& a, double* h_nrm) {
+// S = E^{-1} Z^T P into w.Sz (deflation basis of a).
+void coarse(const BlockWork& w, const BlockArgs& a, const double* P, const int* stop) {
+    k_bzt<<<dim3((unsigned)a.R, kZtChunks), kWG, 0, a.st>>>(a.ztrp, a.ztci, a.ztv, P, w.zpart, stop);
+    k_bcoarse<<<1, kWG, 0, a.st>>>(a.R, w.zpart, a.Einv, w.Sz, stop);
+}
+
+// W = P W = W - A Z E^{-1} Z^T W (no-op without a deflation basis).
+void project(const BlockWork& w, const BlockArgs& a, double* W, const int* stop) {
+    if (a.R == 0) return;
+    coarse(w, a, W, stop);
+    const unsigned g16 = (unsigned)std::min<int64_t>((w.n + kWG / kBW - 1) / (kWG / kBW), 4096);
+    k_bzapply<<<g16, kWG, 0, a.st>>>(w.n, a.R, a.azrp, a.azci, a.azv, w.Sz, -1.0, W, stop);
+}
+
+// W = B - A X, h_raw[c] = ||w_c||; then W = P W and h_nrm[c] = ||P w_c||
+// (h_nrm = h_raw without a deflation basis).
+int residual(const BlockWork& w, const BlockArgs& a, double* h_raw, double* h_nrm) {
     blaunch(a.timer, 7, spmm_bytes(w, a, 1), k_bspmm<1>, dim3(kNormGrid), dim3(kWG), a.st, w.n, a.rowptr,
             a.colind, a.vals, (const double*)w.Xp(), (const double*)w.Bp(), w.W(), w.npart, (const int*)nullptr);
     k_bcolsum<<<1, kWG, 0, a.st>>>(kNormGrid, w.npart, w.nsq);
-    double sq[kBW];
-    if (hipMemcpyAsync(sq, w.nsq, sizeof(sq), hipMemcpyDeviceToHost, a.st) != hipSuccess ||
-        hipStreamSynchronize(a.st) != hipSuccess)
-        return kStatusDevice;
-    for (int c = 0; c < kBW; ++c) h_nrm[c] = std::sqrt(sq[c]);
+    double sq[kBW], sp[kBW];
+    if (hipMemcpyAsync(sq, w.nsq, sizeof(sq), hipMemcpyDeviceToHost, a.st) != hipSuccess) return kStatusDevice;
+    if (a.R > 0) {
+        project(w, a, w.W(), nullptr);
+        k_bnorm<<<kNormGrid, kWG, 0, a.st>>>(w.n, w.W(), w.npart);
+        k_bcolsum<<<1, kWG, 0, a.st>>>(kNormGrid, w.npart, w.nsq);
+        if (hipMemcpyAsync(sp, w.nsq, sizeof(sp), hipMemcpyDeviceToHost, a.st) != hipSuccess)
+            return kStatusDevice;
+    }
+    if (hipStreamSynchronize(a.st) != hipSuccess) return kStatusDevice;
+    for (int c = 0; c < kBW; ++c) {
+        h_raw[c] = std::sqrt(sq[c]);
+        h_nrm[c] = a.R > 0 ? std::sqrt(sp[c]) : h_raw[c];
+    }
     return kStatusOk;
 }
 
@@ -918,8 +1044,9 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
     const unsigned gpe = (unsigned)((pe + kWG - 1) / kWG), grow = (unsigned)((w->n + kWG - 1) / kWG);
     k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, a.B, w->Bp());
     k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, a.X0, w->Xp());
-    double rho0[kBW], rn[kBW];
-    int s = residual(*w, a, rho0);
+    // rho0_c = ||b_c - A x0_c|| (unprojected); the tests use ||P (b_c - A x_c)||.
+    double rho0[kBW], rn[kBW], raw[kBW];
+    int s = residual(*w, a, rho0, rn);
     if (s != kStatusOk) return s;
     double rho_max = 0.0;
     for (int c = 0; c < k; ++c) {
@@ -927,7 +1054,6 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
         rho_max = std::max(rho_max, rho0[c]);
     }
     res->rho0 = rho_max;
-    for (int c = 0; c < kBW; ++c) rn[c] = rho0[c];
     int64_t steps = 0;
     int cycles = 0, status = kStatusMaxIter;
     double est_max = 1.0;
@@ -999,6 +1125,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             blaunch(a.timer, 7, spmm_bytes(*w, a, 0), k_bspmm<0>, dim3(g16), dim3(kWG), st, w->n, a.rowptr,
                     a.colind, a.vals, (const double*)Vj, (const double*)nullptr, w->W(), (double*)nullptr,
                     stop);
+            project(*w, a, w->W(), stop);   // W = P A V_j
             // BCGS2: two projections onto V_0..V_j; the first also gives the
             // squared column norms of A V_j (the breakdown reference).
             dots(*w, a.timer, st, w->V(), j + 1, w->W(), 1, w->Csum, j + 1, 1, j + 1, w->nb2, stop);
@@ -1028,9 +1155,21 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
         k_bsolve<<<1, kWG, 0, st>>>(jd, kb, ka, w->ls, w->Cy);
         gemm(*w, a.timer, st, w->V(), jd, w->Cy, nullptr, 1.0, w->W(), nullptr);
         k_bscatter<<<gpe, kWG, 0, st>>>(w->n, ka, w->imap + kBW, w->W(), w->Xp());
-        if ((s = residual(*w, a, rn)) != kStatusOk) return s;
+        if ((s = residual(*w, a, raw, rn)) != kStatusOk) return s;
         for (int c = 0; c < k; ++c)
             if (!std::isfinite(rn[c])) return kStatusNonFinite;
+    }
+    if (a.R > 0) {
+        // x_c = x_hat_c + Z E^{-1} Z^T (b_c - A x_hat_c) (eq. precond2); the
+        // true residuals are then recomputed.
+        blaunch(a.timer, 7, spmm_bytes(*w, a, 1), k_bspmm<1>, dim3(kNormGrid), dim3(kWG), st, w->n, a.rowptr,
+                a.colind, a.vals, (const double*)w->Xp(), (const double*)w->Bp(), w->W(), w->npart,
+                (const int*)nullptr);
+        coarse(*w, a, w->W(), nullptr);
+        const unsigned g16 = (unsigned)std::min<int64_t>((w->n + kWG / kBW - 1) / (kWG / kBW), 4096);
+        k_bzapply<<<g16, kWG, 0, st>>>(w->n, a.R, a.zrp, a.zci, a.zv, w->Sz, 1.0, w->Xp(), nullptr);
+        if ((s = residual(*w, a, raw, rn)) != kStatusOk) return s;
+        for (int c = 0; c < k; ++c) rn[c] = raw[c];
     }
     const int64_t ue = w->n * k;
     k_bunpack<<<(unsigned)((ue + kWG - 1) / kWG), kWG, 0, st>>>(w->n, k, w->Xp(), a.X);

@@ -372,7 +372,19 @@ struct BlockArgs {
     double* X;                 // n x k row-major (device, output)
     int64_t nnz;
     BlockTimer* timer;         // NULL: untimed
+    // Deflation basis (R = 0: none; R <= kBlockZMax): Z^T and Z (CSR), the
+    // compact A Z (CSR over rows, local columns) and E^{-1} (R x R,
+    // column-major: (E^{-1})_{i,a} at Einv[a R + i]).
+    int R;
+    const int *ztrp, *ztci;
+    const double* ztv;
+    const int *zrp, *zci;
+    const double* zv;
+    const int *azrp, *azci;
+    const double* azv;
+    const double* Einv;
 };
+constexpr int kBlockZMax = 64;   // deflation columns the block path supports
 struct BlockResult {
     int64_t steps = 0;
     int cycles = 0;

@@ -52,6 +52,20 @@ def no_defl(s):
     return s
 
 
+def wide_z(s, r):
+    """The system with an indicator basis of r contiguous row groups."""
+    s = copy.copy(s)
+    s.r = r
+    s.z_rowptr = np.arange(s.n + 1, dtype=np.int32)
+    s.z_colind = (np.arange(s.n) * r // s.n).astype(np.int32)
+    s.z_vals = np.ones(s.n)
+    return s
+
+
+def zt(s):
+    return (s.r, s.z_rowptr, s.z_colind, s.z_vals)
+
+
 def relF(a, b):
     """Larger of the Frobenius ||a - b||_F / ||b||_F and the elementwise
     max|a - b| / max|b| relative differences."""
@@ -146,7 +160,7 @@ def test_rejects_invalid_inputs():
     with pytest.raises(G().GmresError):
         plan.solve_block(torch.ones((s.n, 2), dtype=torch.float64, device="cuda"), 0)
     plan.close()
-    sd = W.make_config(1, mesh=16)               # with a deflation basis
+    sd = wide_z(W.make_config(1, mesh=24), 65)   # a deflation basis beyond 64 columns
     plan, d = G().plan_for(sd, m=8)
     with pytest.raises(G().GmresError):
         plan.solve_block(torch.ones((sd.n, 2), dtype=torch.float64, device="cuda"), 4)
@@ -193,3 +207,56 @@ def test_dependent_right_hand_sides():
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(B[:, c]) * (1 + 1e-6)
         bound = ainv * (np.linalg.norm(r) + np.linalg.norm(r_ref))
         assert np.linalg.norm(X[:, c] - ref.x[:, c]) <= bound * (1 + 1e-6), c
+
+
+@pytest.mark.parametrize("k,m,r", [(1, 6, 0), (1, 6, -1), (3, 4, -1), (16, 2, -1), (5, 3, 64)])
+def test_deflated_fixed_count_parity(k, m, r):
+    """Block GMRES with the deflation basis (r = -1: the configuration's own
+    indicator basis; 64: 64 contiguous row groups) against the block oracle
+    with the same basis, over two cycles; k = 1 is also the single-vector
+    deflated GMRES of the plan."""
+    s = W.make_config(1, mesh=24)
+    if r > 0:
+        s = wide_z(s, r)
+    elif r == 0:
+        s = no_defl(s)
+    rng = np.random.default_rng(300 + k)
+    B = rng.standard_normal((s.n, k))
+    X0 = rng.standard_normal((s.n, k)) * 0.1
+    say("deflated block fixed count k", k, "m", m, "r", s.r)
+    ref = oracle.bgmres(s.rowptr, s.colind, s.vals, B, m, 0.0, 2 * m, X0=X0, z=zt(s))
+    X, info, _ = gpu_block(s, B, m, 0.0, 2 * m, X0=X0)
+    assert info["iters"] == ref.iters == 2 * m and info["cycles"] == 2
+    assert relF(X, ref.x) <= 1e-8, relF(X, ref.x)
+    assert abs(info["rel_res_true"] - ref.rel_res_true) <= 1e-6 * ref.rel_res_true + 1e-14
+    if k == 1 and s.r > 0:
+        single = oracle.gmres(s, m, 0.0, 2 * m, x0=X0[:, 0], b=B[:, 0])
+        assert relF(X[:, 0], single.x) <= 1e-8
+
+
+def test_deflated_to_tolerance():
+    """Four right-hand sides with the indicator basis to rtol: every column's
+    true residual meets rtol times its initial residual, Z^T r = 0 to
+    rounding, and the block-step count is the oracle's."""
+    s = W.make_config(1)                           # 4,225 unknowns
+    k, rtol = 4, 1e-8
+    B = np.random.default_rng(17).standard_normal((s.n, k))
+    ref = oracle.bgmres(s.rowptr, s.colind, s.vals, B, 8, rtol, 3000, z=zt(s))
+    X, info, _ = gpu_block(s, B, 8, rtol, 3000)
+    say("deflated block to tolerance: gpu steps", info["iters"], "oracle", ref.iters)
+    assert ref.status_name == "OK" and info["status_name"] == "OK"
+    assert abs(info["iters"] - ref.iters) <= 1
+    plain = oracle.bgmres(s.rowptr, s.colind, s.vals, B, 8, rtol, 3000)
+    say("without the basis the oracle takes", plain.iters, "block steps")
+    import scipy.sparse as sp
+    Z = sp.csr_matrix((s.z_vals, s.z_colind, s.z_rowptr), shape=(s.n, s.r))
+    for c in range(k):
+        r = B[:, c] - oracle.spmv(s.rowptr, s.colind, s.vals, X[:, c])
+        assert np.linalg.norm(r) <= rtol * np.linalg.norm(B[:, c]) * (1 + 1e-6), c
+        absax = oracle.spmv(s.rowptr, s.colind, np.abs(s.vals), np.abs(X[:, c])) + np.abs(B[:, c])
+        assert np.all(np.abs(Z.T @ r) <= 1e3 * np.finfo(float).eps * (abs(Z).T @ absax)), c
+    # Solutions to rtol 1e-12 agree with the oracle's to the FP64 gate.
+    ref12 = oracle.bgmres(s.rowptr, s.colind, s.vals, B, 8, 1e-12, 6000, z=zt(s))
+    X12, info12, _ = gpu_block(s, B, 8, 1e-12, 6000)
+    assert info12["status_name"] == "OK"
+    assert relF(X12, ref12.x) <= 1e-8, relF(X12, ref12.x)
