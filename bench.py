@@ -290,10 +290,11 @@ def block_rhs(args):
     k, mb, steps_fixed = args.block, args.block_m, args.block_steps
     log(f"[bench] generating the kappa = 1 problem at mesh {args.mesh}")
     sysm = copy.copy(W.make_config(1, mesh=args.mesh))
-    sysm.r = 0
-    sysm.z_rowptr = np.zeros(sysm.n + 1, np.int32)
-    sysm.z_colind = np.zeros(0, np.int32)
-    sysm.z_vals = np.zeros(0)
+    if not args.block_defl:
+        sysm.r = 0
+        sysm.z_rowptr = np.zeros(sysm.n + 1, np.int32)
+        sysm.z_colind = np.zeros(0, np.int32)
+        sysm.z_vals = np.zeros(0)
     rng = np.random.default_rng(20190610)
     B = rng.standard_normal((sysm.n, k))
     plan, d = G.plan_for(sysm, m=50, rtol=0.0, max_iters=steps_fixed)
@@ -342,7 +343,7 @@ def block_rhs(args):
         "data": "synthetic",
         "config": {"workload": f"q1_convection_diffusion_{args.mesh}x{args.mesh}_kappa1_{k}rhs",
                    "unknowns": sysm.n, "nnz": sysm.nnz, "rhs": k, "block_steps_per_cycle": mb,
-                   "block_steps": steps_fixed},
+                   "block_steps": steps_fixed, "deflation_vectors": int(sysm.r)},
         "solve_s": med, "block_steps": info["iters"], "cycles": info["cycles"],
         "rhs_step_equivalent_us": 1e6 * med / max(info["iters"], 1) / k,
         "single_vector_gmres50_step_us": 1e6 * single_s,
@@ -738,6 +739,8 @@ def main():
                     help="instead of the default step: block GMRES for K right-hand sides (<= 16) on the "
                          "kappa = 1 system, fixed count, against single-vector GMRES(50)")
     ap.add_argument("--block-m", type=int, default=8, help="block steps per cycle of --block")
+    ap.add_argument("--block-defl", action="store_true",
+                    help="--block with the configuration's deflation basis (default: without Z)")
     ap.add_argument("--block-steps", type=int, default=48, help="block steps of --block (fixed count)")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short fixed-count FP64 run (two restart cycles) plus a copy of known "

@@ -44,7 +44,7 @@ constexpr int kSplit = 16;         // first-level splits of the partial sums
 constexpr int kNormGrid = 1024;    // workgroups of the residual kernel
 constexpr int kLdH = (kBlockStepsMax + 1) * kBW;   // rows of the least-squares arrays
 constexpr double kBdTol = 1e-10;
-constexpr int kZtChunks = 16;      // workgroups per row of Z^T in the panel's Z^T W
+constexpr int kZtChunksMax = 64;   // workgroups per row of Z^T in the panel's Z^T W (at most)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -77,32 +77,47 @@ __global__ __launch_bounds__(kWG) void k_bunpack(int64_t n, int k, const double*
 // columns): T = Z^T W, S = E^{-1} T, then W -= (A Z) S (projection) or
 // X += Z S (coarse correction at exit, eq. precond2).
 //
-// Partial sums of T: workgroup (c, ch) sums chunk ch of row c of Z^T, 16
-// entries at a time, one lane per panel column; fixed order.
-__global__ __launch_bounds__(kWG) void k_bzt(const int* __restrict__ ztrp, const int* __restrict__ ztci,
-                                             const double* __restrict__ ztv, const double* __restrict__ W,
-                                             double* __restrict__ zpart, const int* __restrict__ stop) {
+// Partial sums of T: workgroup (c, ch) sums chunk ch (of nch) of row c of
+// Z^T, 16 entries per round with one lane per panel column, four rounds'
+// index loads issued before their gathers; fixed order.
+__global__ __launch_bounds__(kWG) void k_bzt(int nch, const int* __restrict__ ztrp,
+                                             const int* __restrict__ ztci, const double* __restrict__ ztv,
+                                             const double* __restrict__ W, double* __restrict__ zpart,
+                                             const int* __restrict__ stop) {
+    constexpr int RG = kWG / kBW;   // entries per round
+    constexpr int U = 4;
     __shared__ double red[kWG];
     if (stop && *stop) return;   // a later step of a cycle that has ended
     const int c = blockIdx.x, ch = blockIdx.y;
     const int q0 = ztrp[c], q1 = ztrp[c + 1];
-    const int cl = (q1 - q0 + kZtChunks - 1) / kZtChunks;
+    const int cl = (q1 - q0 + nch - 1) / nch;
     const int a0 = q0 + ch * cl, a1 = min(q1, a0 + cl);
     const int l = threadIdx.x & (kBW - 1), g = threadIdx.x / kBW;
     double acc = 0.0;
-    for (int q = a0 + g; q < a1; q += kWG / kBW) acc += ztv[q] * W[(int64_t)ztci[q] * kBW + l];
+    for (int q = a0 + g; q < a1; q += U * RG) {
+        int row[U];
+        double zvv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int qu = q + u * RG;
+            row[u] = qu < a1 ? ztci[qu] : 0;
+            zvv[u] = qu < a1 ? ztv[qu] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += zvv[u] * W[(int64_t)row[u] * kBW + l];
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < kBW) {
         double t = 0.0;
-        for (int i = 0; i < kWG / kBW; ++i) t += red[i * kBW + threadIdx.x];
-        zpart[((int64_t)c * kZtChunks + ch) * kBW + threadIdx.x] = t;
+        for (int i = 0; i < RG; ++i) t += red[i * kBW + threadIdx.x];
+        zpart[((int64_t)c * nch + ch) * kBW + threadIdx.x] = t;
     }
 }
 
 // S = E^{-1} T (R x 16, row c of T the sum of its chunks in order); one
 // workgroup, T and E^{-1} staged in LDS.
-__global__ __launch_bounds__(kWG) void k_bcoarse(int R, const double* __restrict__ zpart,
+__global__ __launch_bounds__(kWG) void k_bcoarse(int R, int nch, const double* __restrict__ zpart,
                                                  const double* __restrict__ Einv, double* __restrict__ S,
                                                  const int* __restrict__ stop) {
     __shared__ double T[kBlockZMax * kBW];
@@ -111,7 +126,7 @@ __global__ __launch_bounds__(kWG) void k_bcoarse(int R, const double* __restrict
     for (int e = threadIdx.x; e < R * kBW; e += kWG) {
         const int c = e / kBW, l = e % kBW;
         double t = 0.0;
-        for (int ch = 0; ch < kZtChunks; ++ch) t += zpart[((int64_t)c * kZtChunks + ch) * kBW + l];
+        for (int ch = 0; ch < nch; ++ch) t += zpart[((int64_t)c * nch + ch) * kBW + l];
         T[e] = t;
     }
     for (int e = threadIdx.x; e < R * R; e += kWG) Ei[e] = Einv[e];
@@ -875,7 +890,7 @@ void block_carve(BlockWork* w, Arena& ar, int64_t n, int m) {
     w->nsq = ar.take_n<double>(kBW);
     w->lsbuf = ar.take_n<double>(ls_entries());
     w->S = ar.take_n<double>(kPan);
-    w->zpart = ar.take_n<double>((int64_t)kBlockZMax * kZtChunks * kBW);
+    w->zpart = ar.take_n<double>((int64_t)kBlockZMax * kZtChunksMax * kBW);
     w->Sz = ar.take_n<double>((int64_t)kBlockZMax * kBW);
     w->flag = ar.take_n<int>(3);
     w->imap = ar.take_n<int>(3 * kBW);
@@ -998,8 +1013,11 @@ double spmm_bytes(const BlockWork& w, const BlockArgs& a, int mode) {
 
 // S = E^{-1} Z^T P into w.Sz (deflation basis of a).
 void coarse(const BlockWork& w, const BlockArgs& a, const double* P, const int* stop) {
-    k_bzt<<<dim3((unsigned)a.R, kZtChunks), kWG, 0, a.st>>>(a.ztrp, a.ztci, a.ztv, P, w.zpart, stop);
-    k_bcoarse<<<1, kWG, 0, a.st>>>(a.R, w.zpart, a.Einv, w.Sz, stop);
+    // About 256 entries of Z^T per workgroup (Z's rows are shared out over
+    // its columns), at most kZtChunksMax workgroups per column.
+    const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(kZtChunksMax, (w.n + 256LL * a.R - 1) / (256LL * a.R)));
+    k_bzt<<<dim3((unsigned)a.R, (unsigned)nch), kWG, 0, a.st>>>(nch, a.ztrp, a.ztci, a.ztv, P, w.zpart, stop);
+    k_bcoarse<<<1, kWG, 0, a.st>>>(a.R, nch, w.zpart, a.Einv, w.Sz, stop);
 }
 
 // W = P W = W - A Z E^{-1} Z^T W (no-op without a deflation basis).
