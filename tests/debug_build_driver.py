@@ -129,6 +129,15 @@ def main():
     e = rel(X.cpu().numpy(), rbk.x)
     say("block", info["iters"], f"{e:.2e}")
     check(e <= 1e-8, "block")
+    # Block GMRES with the indicator deflation basis, fixed count.
+    sz = W.make_config(1, mesh=20)
+    rbz = oracle.bgmres(sz.rowptr, sz.colind, sz.vals, B, 6, 0.0, 12,
+                        z=(sz.r, sz.z_rowptr, sz.z_colind, sz.z_vals))
+    plan, d = G.plan_for(sz, m=8, rtol=0.0, max_iters=12)
+    X, info = plan.solve_block(torch.from_numpy(B).cuda(), 6)
+    e = rel(X.cpu().numpy(), rbz.x)
+    say("deflated block", info["iters"], f"{e:.2e}")
+    check(e <= 1e-8, "deflated block")
     # Adaptive deflation, fixed count.
     sd = W.make_config(1, mesh=30)
     sd = copy.copy(sd)
