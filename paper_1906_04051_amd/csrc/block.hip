@@ -54,23 +54,24 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Row-major n x k (caller layout) <-> 16-wide panel.
-__global__ __launch_bounds__(kWG) void k_bpack(int64_t n, int k, const double* __restrict__ src,
+// Row-major n x k (caller layout) <-> panel of pw columns (pw = 8 or 16,
+// k <= pw; rows of pw doubles).
+__global__ __launch_bounds__(kWG) void k_bpack(int64_t n, int k, int pw, const double* __restrict__ src,
                                                double* __restrict__ P) {
     const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (e >= n * kBW) return;
-    const int64_t row = e / kBW;
-    const int c = (int)(e % kBW);
+    if (e >= n * pw) return;
+    const int64_t row = e / pw;
+    const int c = (int)(e % pw);
     P[e] = (c < k && src) ? src[row * k + c] : 0.0;
 }
 
-__global__ __launch_bounds__(kWG) void k_bunpack(int64_t n, int k, const double* __restrict__ P,
+__global__ __launch_bounds__(kWG) void k_bunpack(int64_t n, int k, int pw, const double* __restrict__ P,
                                                  double* __restrict__ dst) {
     const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (e >= n * k) return;
     const int64_t row = e / k;
     const int c = (int)(e % k);
-    dst[e] = P[row * kBW + c];
+    dst[e] = P[row * pw + c];
 }
 
 // Deflation of a panel (Sec. 3.3, eq. precond1, applied to each of the 16
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(kWG) void k_bunpack(int64_t n, int k, const double*
 // Partial sums of T: workgroup (c, ch) sums chunk ch (of nch) of row c of
 // Z^T, 16 entries per round with one lane per panel column, four rounds'
 // index loads issued before their gathers; fixed order.
-__global__ __launch_bounds__(kWG) void k_bzt(int nch, const int* __restrict__ ztrp,
+__global__ __launch_bounds__(kWG) void k_bzt(int nch, int pw, const int* __restrict__ ztrp,
                                              const int* __restrict__ ztci, const double* __restrict__ ztv,
                                              const double* __restrict__ W, double* __restrict__ zpart,
                                              const int* __restrict__ stop) {
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kWG) void k_bzt(int nch, const int* __restrict__ zt
             zvv[u] = qu < a1 ? ztv[qu] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc += zvv[u] * W[(int64_t)row[u] * kBW + l];
+        for (int u = 0; u < U; ++u) acc += l < pw ? zvv[u] * W[(int64_t)row[u] * pw + l] : 0.0;
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kWG) void k_bcoarse(int R, int nch, const double* _
 // P += sign * M S over the rows of the CSR matrix M (n x R, local columns):
 // sign -1 with M = A Z projects W, sign +1 with M = Z corrects X.  16 lanes
 // per row, S staged in LDS.
-__global__ __launch_bounds__(kWG) void k_bzapply(int64_t n, int R, const int* __restrict__ mrp,
+__global__ __launch_bounds__(kWG) void k_bzapply(int64_t n, int R, int pw, const int* __restrict__ mrp,
                                                  const int* __restrict__ mci, const double* __restrict__ mv,
                                                  const double* __restrict__ S, double sign, double* __restrict__ P,
                                                  const int* __restrict__ stop) {
@@ -153,26 +154,26 @@ __global__ __launch_bounds__(kWG) void k_bzapply(int64_t n, int R, const int* __
     const int l = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
     for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
         const int64_t row = r0 + rl;
-        if (row >= n) continue;
+        if (row >= n || l >= pw) continue;
         double t = 0.0;
         for (int q = mrp[row]; q < mrp[row + 1]; ++q) {
             GM_DCHECK(mci[q] >= 0 && mci[q] < R, kDbgBlockCol);
             t += mv[q] * Ss[mci[q] * kBW + l];
         }
-        P[row * kBW + l] += sign * t;
+        P[row * pw + l] += sign * t;
     }
 }
 
 // Per-workgroup partial sums of squares of the 16 columns of a panel.
-__global__ __launch_bounds__(kWG) void k_bnorm(int64_t n, const double* __restrict__ W,
+__global__ __launch_bounds__(kWG) void k_bnorm(int64_t n, int pw, const double* __restrict__ W,
                                                double* __restrict__ part) {
     __shared__ double red[kWG];
     const int l = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
     double acc = 0.0;
     for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
         const int64_t row = r0 + rl;
-        if (row < n) {
-            const double y = W[row * kBW + l];
+        if (row < n && l < pw) {
+            const double y = W[row * pw + l];
             acc += y * y;
         }
     }
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(kWG) void k_bnorm(int64_t n, const double* __restri
 
 // Y = A X (MODE 0), or Y = B - A X with per-workgroup partial sums of squares
 // of every column (MODE 1).  16 lanes per row, 16 rows per workgroup.
-template <int MODE>
+template <int MODE, int PW>
 __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict__ rowptr,
                                                const int* __restrict__ colind,
                                                const double* __restrict__ vals,
@@ -196,9 +197,11 @@ __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict_
                                                double* __restrict__ part, const int* __restrict__ stop) {
     __shared__ double red[kWG];
     if (stop && *stop) return;   // a later step of a cycle that has ended
-    const int c = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
+    // PW lanes per row (one per panel column), kWG / PW rows per round.
+    constexpr int pw = PW, rpr = kWG / PW;
+    const int c = threadIdx.x & (pw - 1), rl = threadIdx.x / pw;
     double nrm = 0.0;
-    for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
+    for (int64_t r0 = (int64_t)blockIdx.x * rpr; r0 < n; r0 += (int64_t)gridDim.x * rpr) {
         const int64_t row = r0 + rl;
         if (row < n) {
             const int q0 = rowptr[row], q1 = rowptr[row + 1];
@@ -209,8 +212,8 @@ __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict_
                 GM_DCHECK(min(min(c0, c1), min(c2, c3)) >= 0 && max(max(c0, c1), max(c2, c3)) < n,
                           kDbgBlockCol);
                 const double a0 = vals[q], a1 = vals[q + 1], a2 = vals[q + 2], a3 = vals[q + 3];
-                const double x0 = X[(int64_t)c0 * kBW + c], x1 = X[(int64_t)c1 * kBW + c];
-                const double x2 = X[(int64_t)c2 * kBW + c], x3 = X[(int64_t)c3 * kBW + c];
+                const double x0 = X[(int64_t)c0 * pw + c], x1 = X[(int64_t)c1 * pw + c];
+                const double x2 = X[(int64_t)c2 * pw + c], x3 = X[(int64_t)c3 * pw + c];
                 acc += a0 * x0;
                 acc += a1 * x1;
                 acc += a2 * x2;
@@ -218,13 +221,13 @@ __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict_
             }
             for (; q < q1; ++q) {
                 GM_DCHECK(colind[q] >= 0 && colind[q] < n, kDbgBlockCol);
-                acc += vals[q] * X[(int64_t)colind[q] * kBW + c];
+                acc += vals[q] * X[(int64_t)colind[q] * pw + c];
             }
             if (MODE == 0) {
-                Y[row * kBW + c] = acc;
+                Y[row * pw + c] = acc;
             } else {
-                const double y = B[row * kBW + c] - acc;
-                Y[row * kBW + c] = y;
+                const double y = B[row * pw + c] - acc;
+                Y[row * pw + c] = y;
                 nrm += y * y;
             }
         }
@@ -234,7 +237,8 @@ __global__ __launch_bounds__(kWG) void k_bspmm(int64_t n, const int* __restrict_
         __syncthreads();
         if (threadIdx.x < kBW) {
             double s = 0.0;
-            for (int i = 0; i < kWG / kBW; ++i) s += red[i * kBW + threadIdx.x];
+            if (threadIdx.x < pw)
+                for (int i = 0; i < rpr; ++i) s += red[i * pw + threadIdx.x];
             part[(int64_t)blockIdx.x * kBW + threadIdx.x] = s;
         }
     }
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(kWG) void k_bcolsum(int nblk, const double* __restr
 // per-workgroup partials part[(blockIdx.x * nb + i) * 256 + m * 16 + n]
 // (fixed order).  Panels beyond nb are loaded (W again) and multiplied but
 // never stored, so the loop body is branch-free.
-template <int NG>
+template <int NG, int PW>
 __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const double* __restrict__ V,
                                                int nv, const double* __restrict__ W, int gram,
                                                double* __restrict__ part, const int* __restrict__ stop) {
@@ -278,13 +282,16 @@ __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const 
     const double* src[NG];
 #pragma unroll
     for (int i = 0; i < NG; ++i) src[i] = i0 + i < nv ? V + (i0 + i) * ps : W;
-    const int64_t e = (int64_t)(l / kBW) * kBW + (l & (kBW - 1));
+    // Lane l holds row r0 + l/16, column l%16 (zero past the panel's PW columns).
+    constexpr int pw = PW;
+    const bool live = (l & (kBW - 1)) < pw;
+    const int64_t e = (int64_t)(l / kBW) * pw + (l & (kBW - 1));
     const int64_t nw = (int64_t)gridDim.x * (kWG / kWave);
     for (int64_t r0 = ((int64_t)blockIdx.x * (kWG / kWave) + wv) * 4; r0 < n_pad; r0 += nw * 4) {
-        const double b = W[r0 * kBW + e];
+        const double b = live ? W[r0 * pw + e] : 0.0;
         double a[NG];
 #pragma unroll
-        for (int i = 0; i < NG; ++i) a[i] = src[i][r0 * kBW + e];
+        for (int i = 0; i < NG; ++i) a[i] = live ? src[i][r0 * pw + e] : 0.0;
 #pragma unroll
         for (int i = 0; i < NG; ++i) acc[i] = mfma16(a[i], b, acc[i]);
     }
@@ -342,10 +349,12 @@ __global__ __launch_bounds__(kWG) void k_breduce(int nblk, int cnt, const double
 // row-major 16x16), one 16-row tile per wavefront; IN may be NULL; IN, OUT and
 // the panels may alias (a tile is read completely before it is written, by
 // the same wavefront).
+template <int PW>
 __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const double* V, int nb,
                                                const double* __restrict__ C, const double* IN,
                                                double sign, double* OUT, const int* __restrict__ stop) {
     if (stop && *stop) return;   // a later step of a cycle that has ended
+    constexpr int pw = PW;
     __shared__ double cs[(kBlockStepsMax + 1) * kPan];
     for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
     __syncthreads();
@@ -356,21 +365,24 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
         const int64_t r0 = tile * kBW;
         d4 acc = {0.0, 0.0, 0.0, 0.0};
         for (int i = 0; i < nb; ++i) {
-            const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * kBW + l / kBW;
+            // A operand: row r0 + l%16, column l/16 + 4q (zero past pw).
+            const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * pw + l / kBW;
             const double* Ci = cs + i * kPan + (l / kBW) * kBW + (l & (kBW - 1));
             double a[4], b[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                a[q] = P[4 * q];
+                a[q] = (l / kBW + 4 * q) < pw ? P[4 * q] : 0.0;
                 b[q] = Ci[4 * q * kBW];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc = mfma16(a[q], b[q], acc);
         }
+        if ((l & (kBW - 1)) < pw) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t idx = (r0 + l / kBW + 4 * r) * kBW + (l & (kBW - 1));
-            OUT[idx] = (IN ? IN[idx] : 0.0) + sign * acc[r];
+            for (int r = 0; r < 4; ++r) {
+                const int64_t idx = (r0 + l / kBW + 4 * r) * pw + (l & (kBW - 1));
+                OUT[idx] = (IN ? IN[idx] : 0.0) + sign * acc[r];
+            }
         }
     }
 }
@@ -384,12 +396,13 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
 // operand layout of the dot products -- so only the panels' tiles are read a
 // second time for the dots, in that layout, right after the first read
 // (from the caches).  nb <= NBMAX accumulators per lane.
-template <int NBMAX>
+template <int NBMAX, int PW>
 __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, const double* V, int nb,
                                                     const double* __restrict__ C, const double* IN,
                                                     double* OUT, double* __restrict__ part,
                                                     const int* __restrict__ stop) {
     if (stop && *stop) return;   // a later step of a cycle that has ended
+    constexpr int pw = PW;
     __shared__ double cs[NBMAX * kPan];
     __shared__ double red[kWG / kWave][kPan];
     for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
@@ -406,12 +419,12 @@ __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, c
 #pragma unroll
         for (int i = 0; i < NBMAX; ++i) {
             if (i < nb) {
-                const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * kBW + l / kBW;
+                const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * pw + l / kBW;
                 const double* Ci = cs + i * kPan + (l / kBW) * kBW + (l & (kBW - 1));
                 double a[4], b[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    a[q] = P[4 * q];
+                    a[q] = (l / kBW + 4 * q) < pw ? P[4 * q] : 0.0;
                     b[q] = Ci[4 * q * kBW];
                 }
 #pragma unroll
@@ -419,19 +432,20 @@ __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, c
             }
         }
         double wn[4];
+        const bool live = (l & (kBW - 1)) < pw;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t idx = (r0 + l / kBW + 4 * r) * kBW + (l & (kBW - 1));
-            wn[r] = IN[idx] - acc[r];
-            OUT[idx] = wn[r];
+            const int64_t idx = (r0 + l / kBW + 4 * r) * pw + (l & (kBW - 1));
+            wn[r] = live ? IN[idx] - acc[r] : 0.0;
+            if (live) OUT[idx] = wn[r];
         }
 #pragma unroll
         for (int i = 0; i < NBMAX; ++i) {
             if (i < nb) {
-                const double* P = V + i * ps + (r0 + l / kBW) * kBW + (l & (kBW - 1));
+                const double* P = V + i * ps + (r0 + l / kBW) * pw + (l & (kBW - 1));
                 double a[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) a[r] = P[4 * r * kBW];
+                for (int r = 0; r < 4; ++r) a[r] = live ? P[4 * r * pw] : 0.0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) dacc[i] = mfma16(a[r], wn[r], dacc[i]);
             }
@@ -536,30 +550,30 @@ __global__ void k_bchol(int k, const double* __restrict__ G, const double* __res
 
 // In-place column selection of a panel: column i <- column map[i] (map[i] < 0:
 // zero), one row per thread.
-__global__ __launch_bounds__(kWG) void k_bselect(int64_t n, const int* __restrict__ map, double* P) {
+__global__ __launch_bounds__(kWG) void k_bselect(int64_t n, int pw, const int* __restrict__ map, double* P) {
     const int64_t row = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (row >= n) return;
     double v[kBW];
 #pragma unroll
-    for (int c = 0; c < kBW; ++c) v[c] = P[row * kBW + c];
+    for (int c = 0; c < kBW; ++c) v[c] = c < pw ? P[row * pw + c] : 0.0;
 #pragma unroll
     for (int c = 0; c < kBW; ++c) {
         const int q = map[c];
         double o = 0.0;
 #pragma unroll
         for (int s = 0; s < kBW; ++s) o = (q == s) ? v[s] : o;
-        P[row * kBW + c] = o;
+        if (c < pw) P[row * pw + c] = o;
     }
 }
 
 // X[:, act[c]] += T[:, c] for c < ka.
-__global__ __launch_bounds__(kWG) void k_bscatter(int64_t n, int ka, const int* __restrict__ act,
+__global__ __launch_bounds__(kWG) void k_bscatter(int64_t n, int pw, int ka, const int* __restrict__ act,
                                                   const double* __restrict__ T, double* __restrict__ X) {
     const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (e >= n * kBW) return;
-    const int64_t row = e / kBW;
-    const int c = (int)(e % kBW);
-    if (c < ka) X[row * kBW + act[c]] += T[e];
+    if (e >= n * pw) return;
+    const int64_t row = e / pw;
+    const int c = (int)(e % pw);
+    if (c < ka) X[row * pw + act[c]] += T[e];
 }
 
 // Least-squares state, column-major with kLdH rows: H (transformed Hbar),
@@ -812,6 +826,7 @@ constexpr int kDotGroup = 4;   // panels per workgroup of the dot kernel
 struct BlockWork {
     int64_t n = 0, n_pad = 0, ps = 0;
     int m = 0;
+    int pw = kBW;                // panel width of the current solve (8 for k <= 8, else 16)
     double* panels = nullptr;   // (m + 1) basis panels, W, B, X
     double *part = nullptr, *C = nullptr, *Csum = nullptr;
     double *R1 = nullptr, *R = nullptr, *Rinv = nullptr, *nb2 = nullptr, *Cy = nullptr;
@@ -938,10 +953,14 @@ void dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
           int gram, double* acc_into, int acc_blocks, int first, int diag_blk, double* nb2,
           const int* stop) {
     const int nb = nv + gram;
-    const double bytes = (double)(nv + 1) * (double)w.n * kBW * sizeof(double);   // panels and W, once
+    const double bytes = (double)(nv + 1) * (double)w.n * w.pw * sizeof(double);   // panels and W, once
     const int groups = (nb + kDotGroup - 1) / kDotGroup;
-    blaunch(tm, 5, bytes, k_bdots<kDotGroup>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv, W,
-            gram, w.part, stop);
+    if (w.pw == 8)
+        blaunch(tm, 5, bytes, k_bdots<kDotGroup, 8>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv, W,
+                gram, w.part, stop);
+    else
+        blaunch(tm, 5, bytes, k_bdots<kDotGroup, kBW>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv,
+                W, gram, w.part, stop);
     const int cnt = nb * kPan;
     k_breduce<<<(cnt + kBW - 1) / kBW, kWG, 0, st>>>(kDotGrid, cnt, w.part, w.C, acc_into, acc_blocks * kPan,
                                                      first, diag_blk, nb2, stop);
@@ -951,8 +970,11 @@ void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
           const double* IN, double sign, double* OUT, const int* stop) {
     const int64_t ntile = w.n_pad / kBW;
     const int grid = (int)std::min<int64_t>((ntile + 3) / 4, 8192);
-    const double bytes = (double)(nb + (IN ? 1 : 0) + 1) * (double)w.n * kBW * sizeof(double);
-    blaunch(tm, 6, bytes, k_bgemm, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT, stop);
+    const double bytes = (double)(nb + (IN ? 1 : 0) + 1) * (double)w.n * w.pw * sizeof(double);
+    if (w.pw == 8)
+        blaunch(tm, 6, bytes, k_bgemm<8>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT, stop);
+    else
+        blaunch(tm, 6, bytes, k_bgemm<kBW>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT, stop);
 }
 
 // W -= V C (C: the first projection's coefficients in w.C), then the second
@@ -970,7 +992,7 @@ int fused_grid() {
     std::lock_guard<std::mutex> lk(mu);
     if (grid[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bgemm_dots<kFuseMax>, kWG, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bgemm_dots<kFuseMax, kBW>, kWG, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -982,10 +1004,14 @@ int fused_grid() {
 
 void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, double* W,
                double* acc_into, int acc_blocks, const int* stop) {
-    const double bytes = (double)(nb + 2) * (double)w.n * kBW * sizeof(double);   // panels once, W in and out
+    const double bytes = (double)(nb + 2) * (double)w.n * w.pw * sizeof(double);   // panels once, W in and out
     const int grid = fused_grid();
-    blaunch(tm, 6, bytes, k_bgemm_dots<kFuseMax>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb,
-            (const double*)w.C, (const double*)W, W, w.part, stop);
+    if (w.pw == 8)
+        blaunch(tm, 6, bytes, k_bgemm_dots<kFuseMax, 8>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb,
+                (const double*)w.C, (const double*)W, W, w.part, stop);
+    else
+        blaunch(tm, 6, bytes, k_bgemm_dots<kFuseMax, kBW>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb,
+                (const double*)w.C, (const double*)W, W, w.part, stop);
     const int cnt = nb * kPan;
     k_breduce<<<(cnt + kBW - 1) / kBW, kWG, 0, st>>>(grid, cnt, w.part, w.C, acc_into, acc_blocks * kPan, 0,
                                                      -1, nullptr, stop);
@@ -1008,7 +1034,26 @@ void cholqr2(const BlockWork& w, BlockTimer* tm, hipStream_t st, int k, const do
 // Algorithmic bytes of one SpMM: A (8-byte values, 4-byte indices, row
 // pointers), the input panel (one line per row), the output panel (and B).
 double spmm_bytes(const BlockWork& w, const BlockArgs& a, int mode) {
-    return 12.0 * (double)a.nnz + 4.0 * (double)(w.n + 1) + (2.0 + mode) * (double)w.n * kBW * sizeof(double);
+    return 12.0 * (double)a.nnz + 4.0 * (double)(w.n + 1) + (2.0 + mode) * (double)w.n * w.pw * sizeof(double);
+}
+
+// Y = A X (mode 0) or Y = B - A X with column partial sums of squares
+// (mode 1), the instance for the solve's panel width.
+void spmm(const BlockWork& w, const BlockArgs& a, int mode, dim3 grid, hipStream_t st, const double* X,
+          const double* B, double* Y, double* part, const int* stop) {
+    const double bytes = spmm_bytes(w, a, mode);
+    if (mode == 0 && w.pw == 8)
+        blaunch(a.timer, 7, bytes, k_bspmm<0, 8>, grid, dim3(kWG), st, w.n, a.rowptr, a.colind, a.vals, X, B, Y,
+                part, stop);
+    else if (mode == 0)
+        blaunch(a.timer, 7, bytes, k_bspmm<0, kBW>, grid, dim3(kWG), st, w.n, a.rowptr, a.colind, a.vals, X, B, Y,
+                part, stop);
+    else if (w.pw == 8)
+        blaunch(a.timer, 7, bytes, k_bspmm<1, 8>, grid, dim3(kWG), st, w.n, a.rowptr, a.colind, a.vals, X, B, Y,
+                part, stop);
+    else
+        blaunch(a.timer, 7, bytes, k_bspmm<1, kBW>, grid, dim3(kWG), st, w.n, a.rowptr, a.colind, a.vals, X, B, Y,
+                part, stop);
 }
 
 // S = E^{-1} Z^T P into w.Sz (deflation basis of a).
@@ -1016,7 +1061,7 @@ void coarse(const BlockWork& w, const BlockArgs& a, const double* P, const int* 
     // About 256 entries of Z^T per workgroup (Z's rows are shared out over
     // its columns), at most kZtChunksMax workgroups per column.
     const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(kZtChunksMax, (w.n + 256LL * a.R - 1) / (256LL * a.R)));
-    k_bzt<<<dim3((unsigned)a.R, (unsigned)nch), kWG, 0, a.st>>>(nch, a.ztrp, a.ztci, a.ztv, P, w.zpart, stop);
+    k_bzt<<<dim3((unsigned)a.R, (unsigned)nch), kWG, 0, a.st>>>(nch, w.pw, a.ztrp, a.ztci, a.ztv, P, w.zpart, stop);
     k_bcoarse<<<1, kWG, 0, a.st>>>(a.R, nch, w.zpart, a.Einv, w.Sz, stop);
 }
 
@@ -1025,20 +1070,19 @@ void project(const BlockWork& w, const BlockArgs& a, double* W, const int* stop)
     if (a.R == 0) return;
     coarse(w, a, W, stop);
     const unsigned g16 = (unsigned)std::min<int64_t>((w.n + kWG / kBW - 1) / (kWG / kBW), 4096);
-    k_bzapply<<<g16, kWG, 0, a.st>>>(w.n, a.R, a.azrp, a.azci, a.azv, w.Sz, -1.0, W, stop);
+    k_bzapply<<<g16, kWG, 0, a.st>>>(w.n, a.R, w.pw, a.azrp, a.azci, a.azv, w.Sz, -1.0, W, stop);
 }
 
 // W = B - A X, h_raw[c] = ||w_c||; then W = P W and h_nrm[c] = ||P w_c||
 // (h_nrm = h_raw without a deflation basis).
 int residual(const BlockWork& w, const BlockArgs& a, double* h_raw, double* h_nrm) {
-    blaunch(a.timer, 7, spmm_bytes(w, a, 1), k_bspmm<1>, dim3(kNormGrid), dim3(kWG), a.st, w.n, a.rowptr,
-            a.colind, a.vals, (const double*)w.Xp(), (const double*)w.Bp(), w.W(), w.npart, (const int*)nullptr);
+    spmm(w, a, 1, dim3(kNormGrid), a.st, (const double*)w.Xp(), (const double*)w.Bp(), w.W(), w.npart, nullptr);
     k_bcolsum<<<1, kWG, 0, a.st>>>(kNormGrid, w.npart, w.nsq);
     double sq[kBW], sp[kBW];
     if (hipMemcpyAsync(sq, w.nsq, sizeof(sq), hipMemcpyDeviceToHost, a.st) != hipSuccess) return kStatusDevice;
     if (a.R > 0) {
         project(w, a, w.W(), nullptr);
-        k_bnorm<<<kNormGrid, kWG, 0, a.st>>>(w.n, w.W(), w.npart);
+        k_bnorm<<<kNormGrid, kWG, 0, a.st>>>(w.n, w.pw, w.W(), w.npart);
         k_bcolsum<<<1, kWG, 0, a.st>>>(kNormGrid, w.npart, w.nsq);
         if (hipMemcpyAsync(sp, w.nsq, sizeof(sp), hipMemcpyDeviceToHost, a.st) != hipSuccess)
             return kStatusDevice;
@@ -1058,10 +1102,14 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
     const hipStream_t st = a.st;
     const int k = a.k, m = a.m;
     *res = BlockResult{};
-    const int64_t pe = w->n * kBW;
+    // Panels of 8 columns for up to 8 right-hand sides (half the bytes of
+    // the 16-wide rows), else 16; both fit the workspace carved for 16.
+    w->pw = k <= 8 ? 8 : kBW;
+    w->ps = w->n_pad * w->pw;
+    const int64_t pe = w->n * w->pw;
     const unsigned gpe = (unsigned)((pe + kWG - 1) / kWG), grow = (unsigned)((w->n + kWG - 1) / kWG);
-    k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, a.B, w->Bp());
-    k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, a.X0, w->Xp());
+    k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, w->pw, a.B, w->Bp());
+    k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, w->pw, a.X0, w->Xp());
     // rho0_c = ||b_c - A x0_c|| (unprojected); the tests use ||P (b_c - A x_c)||.
     double rho0[kBW], rn[kBW], raw[kBW];
     int s = residual(*w, a, rho0, rn);
@@ -1098,7 +1146,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             hipMemsetAsync(w->flag, 0, sizeof(int), st) != hipSuccess ||
             hipMemsetAsync(w->imap + 2 * kBW, 0, kBW * sizeof(int), st) != hipSuccess)
             return kStatusDevice;
-        k_bselect<<<grow, kWG, 0, st>>>(w->n, w->imap, w->W());
+        k_bselect<<<grow, kWG, 0, st>>>(w->n, w->pw, w->imap, w->W());
         cholqr2(*w, a.timer, st, ka, w->W(), w->V(), 1, nullptr, nullptr);
         // A residual column dependent on the earlier ones adds no basis
         // vector: keep kb independent columns, S = their rows of R (kb x ka).
@@ -1124,7 +1172,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             for (int c = 0; c < kBW; ++c) cmap[c] = c < kb ? indep[c] : -1;
             if (hipMemcpyAsync(w->imap, cmap, kBW * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
                 return kStatusDevice;
-            k_bselect<<<grow, kWG, 0, st>>>(w->n, w->imap, w->V());
+            k_bselect<<<grow, kWG, 0, st>>>(w->n, w->pw, w->imap, w->V());
         }
         // flag[0]: breakdown / convergence bits, flag[1]: the cycle has
         // ended (gate of its later kernels), flag[2]: steps done.  The
@@ -1139,10 +1187,8 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             if (a.timer) a.timer->step(j);
             double* Vj = w->V() + (int64_t)j * w->ps;
             double* Vn = w->V() + (int64_t)(j + 1) * w->ps;
-            const unsigned g16 = (unsigned)((w->n + kWG / kBW - 1) / (kWG / kBW));
-            blaunch(a.timer, 7, spmm_bytes(*w, a, 0), k_bspmm<0>, dim3(g16), dim3(kWG), st, w->n, a.rowptr,
-                    a.colind, a.vals, (const double*)Vj, (const double*)nullptr, w->W(), (double*)nullptr,
-                    stop);
+            const unsigned g16 = (unsigned)((w->n + kWG / w->pw - 1) / (kWG / w->pw));
+            spmm(*w, a, 0, dim3(g16), st, (const double*)Vj, nullptr, w->W(), nullptr, stop);
             project(*w, a, w->W(), stop);   // W = P A V_j
             // BCGS2: two projections onto V_0..V_j; the first also gives the
             // squared column norms of A V_j (the breakdown reference).
@@ -1172,7 +1218,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
         // X[:, act] += V Y (through the free W panel).
         k_bsolve<<<1, kWG, 0, st>>>(jd, kb, ka, w->ls, w->Cy);
         gemm(*w, a.timer, st, w->V(), jd, w->Cy, nullptr, 1.0, w->W(), nullptr);
-        k_bscatter<<<gpe, kWG, 0, st>>>(w->n, ka, w->imap + kBW, w->W(), w->Xp());
+        k_bscatter<<<gpe, kWG, 0, st>>>(w->n, w->pw, ka, w->imap + kBW, w->W(), w->Xp());
         if ((s = residual(*w, a, raw, rn)) != kStatusOk) return s;
         for (int c = 0; c < k; ++c)
             if (!std::isfinite(rn[c])) return kStatusNonFinite;
@@ -1180,17 +1226,16 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
     if (a.R > 0) {
         // x_c = x_hat_c + Z E^{-1} Z^T (b_c - A x_hat_c) (eq. precond2); the
         // true residuals are then recomputed.
-        blaunch(a.timer, 7, spmm_bytes(*w, a, 1), k_bspmm<1>, dim3(kNormGrid), dim3(kWG), st, w->n, a.rowptr,
-                a.colind, a.vals, (const double*)w->Xp(), (const double*)w->Bp(), w->W(), w->npart,
-                (const int*)nullptr);
+        spmm(*w, a, 1, dim3(kNormGrid), st, (const double*)w->Xp(), (const double*)w->Bp(), w->W(), w->npart,
+             nullptr);
         coarse(*w, a, w->W(), nullptr);
         const unsigned g16 = (unsigned)std::min<int64_t>((w->n + kWG / kBW - 1) / (kWG / kBW), 4096);
-        k_bzapply<<<g16, kWG, 0, st>>>(w->n, a.R, a.zrp, a.zci, a.zv, w->Sz, 1.0, w->Xp(), nullptr);
+        k_bzapply<<<g16, kWG, 0, st>>>(w->n, a.R, w->pw, a.zrp, a.zci, a.zv, w->Sz, 1.0, w->Xp(), nullptr);
         if ((s = residual(*w, a, raw, rn)) != kStatusOk) return s;
         for (int c = 0; c < k; ++c) rn[c] = raw[c];
     }
     const int64_t ue = w->n * k;
-    k_bunpack<<<(unsigned)((ue + kWG - 1) / kWG), kWG, 0, st>>>(w->n, k, w->Xp(), a.X);
+    k_bunpack<<<(unsigned)((ue + kWG - 1) / kWG), kWG, 0, st>>>(w->n, k, w->pw, w->Xp(), a.X);
     if (hipStreamSynchronize(st) != hipSuccess) return kStatusDevice;
     double tr = 0.0;
     for (int c = 0; c < k; ++c) tr = std::max(tr, rn[c] / rho0[c]);
