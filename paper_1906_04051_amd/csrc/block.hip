@@ -267,6 +267,24 @@ __global__ __launch_bounds__(kWG) void k_bcolsum(int nblk, const double* __restr
 // per-workgroup partials part[(blockIdx.x * nb + i) * 256 + m * 16 + n]
 // (fixed order).  Panels beyond nb are loaded (W again) and multiplied but
 // never stored, so the loop body is branch-free.
+// Entry t of a workgroup's 16 x 16 block of partial dots from the
+// wavefronts' accumulators red[w] (row-major).  16-wide panels: the sum over
+// the wavefronts.  8-wide panels (lanes l%16 >= 8 on the second half of each
+// 8-row run): entry (i, j) < 8 is quadrant (i, j) plus quadrant (i+8, j+8);
+// the other entries are zero, as the 16-wide layout leaves them.
+template <int PW>
+__device__ __forceinline__ double fold_partial(const double (*red)[kPan], int t) {
+    double s = 0.0;
+    if (PW == 16) {
+#pragma unroll
+        for (int w = 0; w < kWG / kWave; ++w) s += red[w][t];
+    } else if (t / kBW < 8 && t % kBW < 8) {
+#pragma unroll
+        for (int w = 0; w < kWG / kWave; ++w) s += red[w][t] + red[w][t + 8 * kBW + 8];
+    }
+    return s;
+}
+
 template <int NG, int PW>
 __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const double* __restrict__ V,
                                                int nv, const double* __restrict__ W, int gram,
@@ -282,16 +300,23 @@ __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const 
     const double* src[NG];
 #pragma unroll
     for (int i = 0; i < NG; ++i) src[i] = i0 + i < nv ? V + (i0 + i) * ps : W;
-    // Lane l holds row r0 + l/16, column l%16 (zero past the panel's PW columns).
+    // 16-wide panels: lane l holds row r0 + l/16, column l%16, four rows a
+    // step.  8-wide panels: lanes with l%16 >= 8 take the next four rows,
+    // row r0 + l/16 + 4, column l%16 - 8, so a step covers eight whole rows
+    // (one contiguous 512-byte run) with no idle lane; the 8x8 diagonal
+    // quadrants of the accumulator then hold the products of the two row
+    // halves (the off-diagonal quadrants mix them and are dropped), and their
+    // sum is the 8x8 block of dots.
     constexpr int pw = PW;
-    const bool live = (l & (kBW - 1)) < pw;
-    const int64_t e = (int64_t)(l / kBW) * pw + (l & (kBW - 1));
+    constexpr int rows = PW == 8 ? 8 : 4;   // rows per step and wavefront
+    const int64_t e = PW == 8 ? (int64_t)(l / kBW + 4 * ((l & (kBW - 1)) >> 3)) * pw + (l & 7)
+                              : (int64_t)(l / kBW) * pw + (l & (kBW - 1));
     const int64_t nw = (int64_t)gridDim.x * (kWG / kWave);
-    for (int64_t r0 = ((int64_t)blockIdx.x * (kWG / kWave) + wv) * 4; r0 < n_pad; r0 += nw * 4) {
-        const double b = live ? W[r0 * pw + e] : 0.0;
+    for (int64_t r0 = ((int64_t)blockIdx.x * (kWG / kWave) + wv) * rows; r0 < n_pad; r0 += nw * rows) {
+        const double b = W[r0 * pw + e];
         double a[NG];
 #pragma unroll
-        for (int i = 0; i < NG; ++i) a[i] = live ? src[i][r0 * pw + e] : 0.0;
+        for (int i = 0; i < NG; ++i) a[i] = src[i][r0 * pw + e];
 #pragma unroll
         for (int i = 0; i < NG; ++i) acc[i] = mfma16(a[i], b, acc[i]);
     }
@@ -301,11 +326,7 @@ __global__ __launch_bounds__(kWG) void k_bdots(int64_t n_pad, int64_t ps, const 
 #pragma unroll
             for (int r = 0; r < 4; ++r) red[wv][(l / kBW + 4 * r) * kBW + (l & (kBW - 1))] = acc[i][r];
             __syncthreads();
-            const int t = threadIdx.x;
-            double s = red[0][t];
-#pragma unroll
-            for (int w = 1; w < kWG / kWave; ++w) s += red[w][t];
-            part[((int64_t)blockIdx.x * nb + i0 + i) * kPan + t] = s;
+            part[((int64_t)blockIdx.x * nb + i0 + i) * kPan + threadIdx.x] = fold_partial<PW>(red, threadIdx.x);
             __syncthreads();
         }
     }
@@ -345,6 +366,31 @@ __global__ __launch_bounds__(kWG) void k_breduce(int nblk, int cnt, const double
     }
 }
 
+// sum_{i < nb} P_i C_i over the 16-row tile at r0 (C_i row-major 16 x 16 in
+// LDS): lane l feeds row r0 + l%16, columns l/16 + 4q of each panel (the
+// MFMA A operand, pw/4 steps a panel) and comes out holding rows
+// r0 + l/16 + 4r, column l%16.  For 8-wide panels the B operand repeats C's
+// first 8 columns in its upper 8, so both halves of the result hold the tile.
+template <int PW>
+__device__ __forceinline__ d4 tile_product(const double* V, int64_t ps, int nb, const double* cs, int64_t r0,
+                                           int l) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int col = PW == 8 ? (l & 7) : (l & (kBW - 1));
+    for (int i = 0; i < nb; ++i) {
+        const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * PW + l / kBW;
+        const double* Ci = cs + i * kPan + (l / kBW) * kBW + col;
+        double a[PW / 4], b[PW / 4];
+#pragma unroll
+        for (int q = 0; q < PW / 4; ++q) {
+            a[q] = P[4 * q];
+            b[q] = Ci[4 * q * kBW];
+        }
+#pragma unroll
+        for (int q = 0; q < PW / 4; ++q) acc = mfma16(a[q], b[q], acc);
+    }
+    return acc;
+}
+
 // OUT = IN + sign * sum_{i < nb} P_i C_i (P_i = panel i of V, C_i = C[i*256 ..]
 // row-major 16x16), one 16-row tile per wavefront; IN may be NULL; IN, OUT and
 // the panels may alias (a tile is read completely before it is written, by
@@ -363,21 +409,17 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
     for (int64_t tile = (int64_t)blockIdx.x * (kWG / kWave) + wv; tile < ntile;
          tile += (int64_t)gridDim.x * (kWG / kWave)) {
         const int64_t r0 = tile * kBW;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int i = 0; i < nb; ++i) {
-            // A operand: row r0 + l%16, column l/16 + 4q (zero past pw).
-            const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * pw + l / kBW;
-            const double* Ci = cs + i * kPan + (l / kBW) * kBW + (l & (kBW - 1));
-            double a[4], b[4];
+        d4 acc = tile_product<PW>(V, ps, nb, cs, r0, l);
+        if (PW == 8) {
+            // both column halves of the accumulator hold the tile; lane l
+            // stores rows r0 + l/16 + 4 h + 8 s (h = its half, s = 0, 1)
+            const int h = (l & (kBW - 1)) >> 3;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = (l / kBW + 4 * q) < pw ? P[4 * q] : 0.0;
-                b[q] = Ci[4 * q * kBW];
+            for (int s = 0; s < 2; ++s) {
+                const int64_t idx = (r0 + l / kBW + 4 * (2 * s + h)) * pw + (l & 7);
+                OUT[idx] = (IN ? IN[idx] : 0.0) + sign * (h ? acc[2 * s + 1] : acc[2 * s]);
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc = mfma16(a[q], b[q], acc);
-        }
-        if ((l & (kBW - 1)) < pw) {
+        } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t idx = (r0 + l / kBW + 4 * r) * pw + (l & (kBW - 1));
@@ -416,38 +458,63 @@ __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, c
          tile += (int64_t)gridDim.x * (kWG / kWave)) {
         const int64_t r0 = tile * kBW;
         d4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int col = PW == 8 ? (l & 7) : (l & (kBW - 1));   // 8-wide: C's columns repeated
 #pragma unroll
         for (int i = 0; i < NBMAX; ++i) {
             if (i < nb) {
                 const double* P = V + i * ps + (r0 + (l & (kBW - 1))) * pw + l / kBW;
-                const double* Ci = cs + i * kPan + (l / kBW) * kBW + (l & (kBW - 1));
-                double a[4], b[4];
+                const double* Ci = cs + i * kPan + (l / kBW) * kBW + col;
+                double a[PW / 4], b[PW / 4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    a[q] = (l / kBW + 4 * q) < pw ? P[4 * q] : 0.0;
+                for (int q = 0; q < PW / 4; ++q) {
+                    a[q] = P[4 * q];
                     b[q] = Ci[4 * q * kBW];
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc = mfma16(a[q], b[q], acc);
+                for (int q = 0; q < PW / 4; ++q) acc = mfma16(a[q], b[q], acc);
             }
         }
-        double wn[4];
-        const bool live = (l & (kBW - 1)) < pw;
+        if (PW == 8) {
+            // Both halves of acc hold the tile.  Lane l takes rows
+            // r0 + l/16 + 4 h + 8 s (h = its column half, s = 0, 1), column
+            // l%8: two contiguous 8-row runs, and for each s the dot step's
+            // operands in the layout k_bdots uses for 8-wide panels.
+            const int h = (l & (kBW - 1)) >> 3;
+            double wn[2];
+            int64_t idx[2];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t idx = (r0 + l / kBW + 4 * r) * pw + (l & (kBW - 1));
-            wn[r] = live ? IN[idx] - acc[r] : 0.0;
-            if (live) OUT[idx] = wn[r];
-        }
+            for (int s = 0; s < 2; ++s) {
+                idx[s] = (r0 + l / kBW + 4 * (2 * s + h)) * pw + (l & 7);
+                wn[s] = IN[idx[s]] - (h ? acc[2 * s + 1] : acc[2 * s]);
+                OUT[idx[s]] = wn[s];
+            }
 #pragma unroll
-        for (int i = 0; i < NBMAX; ++i) {
-            if (i < nb) {
-                const double* P = V + i * ps + (r0 + l / kBW) * pw + (l & (kBW - 1));
-                double a[4];
+            for (int i = 0; i < NBMAX; ++i) {
+                if (i < nb) {
+                    const double* P = V + i * ps;
+                    const double a0 = P[idx[0]], a1 = P[idx[1]];
+                    dacc[i] = mfma16(a0, wn[0], dacc[i]);
+                    dacc[i] = mfma16(a1, wn[1], dacc[i]);
+                }
+            }
+        } else {
+            double wn[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) a[r] = live ? P[4 * r * pw] : 0.0;
+            for (int r = 0; r < 4; ++r) {
+                const int64_t idx = (r0 + l / kBW + 4 * r) * pw + (l & (kBW - 1));
+                wn[r] = IN[idx] - acc[r];
+                OUT[idx] = wn[r];
+            }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) dacc[i] = mfma16(a[r], wn[r], dacc[i]);
+            for (int i = 0; i < NBMAX; ++i) {
+                if (i < nb) {
+                    const double* P = V + i * ps + (r0 + l / kBW) * pw + (l & (kBW - 1));
+                    double a[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[r] = P[4 * r * pw];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dacc[i] = mfma16(a[r], wn[r], dacc[i]);
+                }
             }
         }
     }
@@ -457,11 +524,7 @@ __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, c
 #pragma unroll
             for (int r = 0; r < 4; ++r) red[wv][(l / kBW + 4 * r) * kBW + (l & (kBW - 1))] = dacc[i][r];
             __syncthreads();
-            const int t = threadIdx.x;
-            double s = red[0][t];
-#pragma unroll
-            for (int w = 1; w < kWG / kWave; ++w) s += red[w][t];
-            part[((int64_t)blockIdx.x * nb + i) * kPan + t] = s;
+            part[((int64_t)blockIdx.x * nb + i) * kPan + threadIdx.x] = fold_partial<PW>(red, threadIdx.x);
             __syncthreads();
         }
     }
