@@ -1011,19 +1011,37 @@ int block_bind(BlockWork* w, void* mem, size_t bytes, hipStream_t st, int64_t n,
 
 namespace {
 
+// k_bdots over nb = nv + gram blocks with the fewest slots per workgroup
+// that hold them (1, 2, 4, then kDotGroup): every slot loads a panel and
+// issues a matrix-core step per row step, used or not, so a Gram block alone
+// runs on one slot.
+template <int PW>
+void launch_dots(const BlockWork& w, BlockTimer* tm, double bytes, hipStream_t st, const double* V, int nv,
+                 const double* W, int gram, const int* stop) {
+    const int nb = nv + gram;
+    const int ng = nb <= 1 ? 1 : nb <= 2 ? 2 : nb <= 4 ? 4 : kDotGroup;
+    const dim3 grid(kDotGrid, (nb + ng - 1) / ng);
+    if (ng == 1)
+        blaunch(tm, 5, bytes, k_bdots<1, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
+    else if (ng == 2)
+        blaunch(tm, 5, bytes, k_bdots<2, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
+    else if (ng == 4)
+        blaunch(tm, 5, bytes, k_bdots<4, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
+    else
+        blaunch(tm, 5, bytes, k_bdots<kDotGroup, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part,
+                stop);
+}
+
 // C[0 .. nb) = P^T W (panels of V, then W itself when gram), summed.
 void dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nv, const double* W,
           int gram, double* acc_into, int acc_blocks, int first, int diag_blk, double* nb2,
           const int* stop) {
     const int nb = nv + gram;
     const double bytes = (double)(nv + 1) * (double)w.n * w.pw * sizeof(double);   // panels and W, once
-    const int groups = (nb + kDotGroup - 1) / kDotGroup;
     if (w.pw == 8)
-        blaunch(tm, 5, bytes, k_bdots<kDotGroup, 8>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv, W,
-                gram, w.part, stop);
+        launch_dots<8>(w, tm, bytes, st, V, nv, W, gram, stop);
     else
-        blaunch(tm, 5, bytes, k_bdots<kDotGroup, kBW>, dim3(kDotGrid, groups), dim3(kWG), st, w.n_pad, w.ps, V, nv,
-                W, gram, w.part, stop);
+        launch_dots<kBW>(w, tm, bytes, st, V, nv, W, gram, stop);
     const int cnt = nb * kPan;
     k_breduce<<<(cnt + kBW - 1) / kBW, kWG, 0, st>>>(kDotGrid, cnt, w.part, w.C, acc_into, acc_blocks * kPan,
                                                      first, diag_blk, nb2, stop);
