@@ -530,6 +530,60 @@ __global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, c
     }
 }
 
+// OUT = IN + sign * sum_{i < nb} P_i C_i (as k_bgemm), then the partial Gram
+// block OUT^T OUT of this workgroup's tiles.  The new tile leaves the product
+// in the layout both operands of the dot step take (as in k_bgemm_dots), so
+// the Gram block needs no second read of OUT.  One 16-row tile per wavefront;
+// the coefficients' LDS holds the wavefronts' accumulators at the end.
+template <int PW>
+__global__ __launch_bounds__(kWG) void k_bgemm_gram(int64_t n_pad, int64_t ps, const double* V, int nb,
+                                                    const double* __restrict__ C, const double* IN, double sign,
+                                                    double* OUT, double* __restrict__ part,
+                                                    const int* __restrict__ stop) {
+    static_assert((kBlockStepsMax + 1) * kPan >= (kWG / kWave) * kPan, "accumulators fit in the coefficients' LDS");
+    if (stop && *stop) return;   // a later step of a cycle that has ended
+    constexpr int pw = PW;
+    __shared__ double cs[(kBlockStepsMax + 1) * kPan];
+    for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
+    __syncthreads();
+    const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    d4 g = {0.0, 0.0, 0.0, 0.0};
+    const int64_t ntile = n_pad / kBW;
+    for (int64_t tile = (int64_t)blockIdx.x * (kWG / kWave) + wv; tile < ntile;
+         tile += (int64_t)gridDim.x * (kWG / kWave)) {
+        const int64_t r0 = tile * kBW;
+        const d4 acc = tile_product<PW>(V, ps, nb, cs, r0, l);
+        if (PW == 8) {
+            // lane l: rows r0 + l/16 + 4 h + 8 s, column l%8 (h = its column
+            // half); each s is one 8-row Gram step in the k_bdots layout
+            const int h = (l & (kBW - 1)) >> 3;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int64_t idx = (r0 + l / kBW + 4 * (2 * s + h)) * pw + (l & 7);
+                const double v = (IN ? IN[idx] : 0.0) + sign * (h ? acc[2 * s + 1] : acc[2 * s]);
+                OUT[idx] = v;
+                g = mfma16(v, v, g);
+            }
+        } else {
+            double v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t idx = (r0 + l / kBW + 4 * r) * pw + (l & (kBW - 1));
+                v[r] = (IN ? IN[idx] : 0.0) + sign * acc[r];
+                OUT[idx] = v[r];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g = mfma16(v[r], v[r], g);
+        }
+    }
+    __syncthreads();   // every wavefront is done with the coefficients
+    double (*red)[kPan] = reinterpret_cast<double (*)[kPan]>(cs);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wv][(l / kBW + 4 * r) * kBW + (l & (kBW - 1))] = g[r];
+    __syncthreads();
+    part[(int64_t)blockIdx.x * kPan + threadIdx.x] = fold_partial<PW>(red, threadIdx.x);
+}
+
 // R^T R = G for the 16x16 Gram matrix G (row-major); rows/columns >= k are
 // the identity.  Rinv = R^{-1}; Rout = R Rprev (Rprev NULL: R).  With test,
 // a pivot <= kBdTol times the column's norm before orthogonalisation
@@ -1063,24 +1117,33 @@ void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
 // dots() call without a Gram block would); one sweep over the panels.
 constexpr int kFuseMax = 8;   // panels of the fused sweep (accumulators per lane)
 
-// Workgroups of the fused sweep: one round of resident workgroups (at most
-// kDotGrid, the partial-sum capacity), looked up once per device.
-int fused_grid() {
-    static std::mutex mu;
-    static int grid[64] = {};
+// Workgroups of a sweep that leaves one partial per workgroup: one round of
+// resident workgroups of `kernel` (at most kDotGrid, the partial-sum
+// capacity), looked up once per device into cache.
+std::mutex g_grid_mu;
+int resident_grid(const void* kernel, int* cache) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kDotGrid;
-    std::lock_guard<std::mutex> lk(mu);
-    if (grid[dev] == 0) {
+    std::lock_guard<std::mutex> lk(g_grid_mu);
+    if (cache[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bgemm_dots<kFuseMax, kBW>, kWG, 0) != hipSuccess ||
-            per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWG, 0) != hipSuccess || per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 1;
-        grid[dev] = std::min(kDotGrid, per_cu * cus);
+        cache[dev] = std::min(kDotGrid, per_cu * cus);
     }
-    return grid[dev];
+    return cache[dev];
+}
+
+int fused_grid() {
+    static int cache[64] = {};
+    return resident_grid(reinterpret_cast<const void*>(k_bgemm_dots<kFuseMax, kBW>), cache);
+}
+
+int gram_grid() {
+    static int cache[64] = {};
+    return resident_grid(reinterpret_cast<const void*>(k_bgemm_gram<kBW>), cache);
 }
 
 void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, double* W,
@@ -1098,15 +1161,30 @@ void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double*
                                                      -1, nullptr, stop);
 }
 
+// OUT = IN + sign * V C (as gemm), and OUT^T OUT summed into w.C (as the
+// dots() call of OUT's Gram block alone would); one sweep.
+void gemm_gram(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, const double* C,
+               const double* IN, double sign, double* OUT, const int* stop) {
+    const int grid = gram_grid();
+    const double bytes = (double)(nb + (IN ? 1 : 0) + 1) * (double)w.n * w.pw * sizeof(double);
+    if (w.pw == 8)
+        blaunch(tm, 6, bytes, k_bgemm_gram<8>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT,
+                w.part, stop);
+    else
+        blaunch(tm, 6, bytes, k_bgemm_gram<kBW>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT,
+                w.part, stop);
+    k_breduce<<<kPan / kBW, kWG, 0, st>>>(grid, kPan, w.part, w.C, nullptr, 0, 0, -1, nullptr, stop);
+}
+
 // Cholesky QR applied twice to the panel `src` into `dst` (may alias):
 // dst R = src, R = R2 R1 (into w.R).  test: breakdown test of the first pass
-// against nb2 (NULL: the Gram diagonal).
+// against nb2 (NULL: the Gram diagonal).  gram_ready: w.C already holds
+// src^T src (the sweep that wrote src formed it).
 void cholqr2(const BlockWork& w, BlockTimer* tm, hipStream_t st, int k, const double* src, double* dst,
-             int test, const double* nb2, const int* stop) {
-    dots(w, tm, st, nullptr, 0, src, 1, nullptr, 0, 0, -1, nullptr, stop);
+             int test, const double* nb2, const int* stop, bool gram_ready = false) {
+    if (!gram_ready) dots(w, tm, st, nullptr, 0, src, 1, nullptr, 0, 0, -1, nullptr, stop);
     k_bchol<<<1, kWave, 0, st>>>(k, w.C, nb2, test, nullptr, w.R1, w.Rinv, w.flag, w.imap + 2 * kBW, stop);
-    gemm(w, tm, st, src, 1, w.Rinv, nullptr, 1.0, dst, stop);
-    dots(w, tm, st, nullptr, 0, dst, 1, nullptr, 0, 0, -1, nullptr, stop);
+    gemm_gram(w, tm, st, src, 1, w.Rinv, nullptr, 1.0, dst, stop);   // and dst^T dst into w.C
     k_bchol<<<1, kWave, 0, st>>>(k, w.C, nullptr, 0, w.R1, w.R, w.Rinv, w.flag, nullptr, stop);
     gemm(w, tm, st, dst, 1, w.Rinv, nullptr, 1.0, dst, stop);
 }
@@ -1281,8 +1359,9 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
                 gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W(), stop);
                 dots(*w, a.timer, st, w->V(), j + 1, w->W(), 0, w->Csum, j + 1, 0, -1, nullptr, stop);
             }
-            gemm(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W(), stop);
-            cholqr2(*w, a.timer, st, kb, w->W(), Vn, 1, w->nb2, stop);
+            // Second projection; its sweep also forms W^T W for the CholQR.
+            gemm_gram(*w, a.timer, st, w->V(), j + 1, w->C, w->W(), -1.0, w->W(), stop);
+            cholqr2(*w, a.timer, st, kb, w->W(), Vn, 1, w->nb2, stop, true);
             k_bls<<<1, kWG, 0, st>>>(j, kb, ka, a.rtol, w->Csum, w->R, w->ls, w->flag);
         }
         double est[kBW];
