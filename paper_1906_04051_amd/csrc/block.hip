@@ -666,21 +666,15 @@ __global__ void k_bchol(int k, const double* __restrict__ G, const double* __res
 }
 
 // In-place column selection of a panel: column i <- column map[i] (map[i] < 0:
-// zero), one row per thread.
+// zero), one entry per thread.  pw divides the wavefront, so a row lies in
+// one wavefront, whose loads of the row complete before any of its stores.
 __global__ __launch_bounds__(kWG) void k_bselect(int64_t n, int pw, const int* __restrict__ map, double* P) {
-    const int64_t row = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (row >= n) return;
-    double v[kBW];
-#pragma unroll
-    for (int c = 0; c < kBW; ++c) v[c] = c < pw ? P[row * pw + c] : 0.0;
-#pragma unroll
-    for (int c = 0; c < kBW; ++c) {
-        const int q = map[c];
-        double o = 0.0;
-#pragma unroll
-        for (int s = 0; s < kBW; ++s) o = (q == s) ? v[s] : o;
-        if (c < pw) P[row * pw + c] = o;
-    }
+    const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n * pw) return;
+    const int c = (int)(e % pw);
+    const int q = map[c];
+    const double v = q >= 0 && q < pw ? P[e - c + q] : 0.0;
+    P[e] = v;
 }
 
 // X[:, act[c]] += T[:, c] for c < ka.
@@ -897,25 +891,40 @@ __global__ __launch_bounds__(kWG) void k_bls(int j, int k, int ka, double rtol,
 // right-hand sides), written as nblk padded 16x16 coefficient blocks
 // Cy[blk * 256 + kk * 16 + c].
 __global__ __launch_bounds__(kWG) void k_bsolve(int nblk, int k, int ka, LsView ls, double* __restrict__ Cy) {
+    constexpr int kStrip = 8;   // rows of H staged in LDS at a time
     __shared__ double y[kLdH][kBW];
     __shared__ double part[kBW][kBW + 1];
+    __shared__ double hs[kStrip][kBlockStepsMax * kBW + 1];
     const int J = nblk * k;
     const int c = threadIdx.x & (kBW - 1), g = threadIdx.x / kBW;
-    for (int e = threadIdx.x; e < kLdH * kBW; e += kWG) y[e / kBW][e % kBW] = 0.0;
-    __syncthreads();
-    for (int i = J - 1; i >= 0; --i) {
-        double s = 0.0;
-        if (c < ka)
-            for (int q = i + 1 + g; q < J; q += kBW) s += ls.H[(int64_t)q * kLdH + i] * y[q][c];
-        part[g][c] = s;
-        __syncthreads();
-        if (g == 0 && c < ka) {
-            double acc = ls.G[(int64_t)c * kLdH + i];
-            for (int q = 0; q < kBW; ++q) acc -= part[q][c];
-            y[i][c] = acc / ls.H[(int64_t)i * kLdH + i];
+    // y starts as the right-hand side G; row i is overwritten by the solution
+    // once the rows below it are solved.
+    for (int e = threadIdx.x; e < kLdH * kBW; e += kWG) {
+        const int i = e / kBW, cc = e % kBW;
+        y[i][cc] = i < J ? ls.G[(int64_t)cc * kLdH + i] : 0.0;
+    }
+    for (int i0 = (J - 1) / kStrip * kStrip; i0 >= 0 && J > 0; i0 -= kStrip) {
+        __syncthreads();   // the previous strip is done with hs
+        for (int e = threadIdx.x; e < kStrip * J; e += kWG) {
+            const int q = e / kStrip, r = e % kStrip;
+            hs[r][q] = i0 + r < J ? ls.H[(int64_t)q * kLdH + i0 + r] : 0.0;
         }
         __syncthreads();
+        for (int i = min(J - 1, i0 + kStrip - 1); i >= i0; --i) {
+            double s = 0.0;
+            if (c < ka)
+                for (int q = i + 1 + g; q < J; q += kBW) s += hs[i - i0][q] * y[q][c];
+            part[g][c] = s;
+            __syncthreads();
+            if (g == 0 && c < ka) {
+                double acc = y[i][c];
+                for (int q = 0; q < kBW; ++q) acc -= part[q][c];
+                y[i][c] = acc / hs[i - i0][i];
+            }
+            __syncthreads();
+        }
     }
+    __syncthreads();
     for (int e = threadIdx.x; e < nblk * kPan; e += kWG) {
         const int blk = e / kPan, kk = (e % kPan) / kBW, cc = e % kBW;
         Cy[e] = (kk < k && cc < ka) ? y[blk * k + kk][cc] : 0.0;
@@ -1266,7 +1275,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
     w->pw = k <= 8 ? 8 : kBW;
     w->ps = w->n_pad * w->pw;
     const int64_t pe = w->n * w->pw;
-    const unsigned gpe = (unsigned)((pe + kWG - 1) / kWG), grow = (unsigned)((w->n + kWG - 1) / kWG);
+    const unsigned gpe = (unsigned)((pe + kWG - 1) / kWG);
     k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, w->pw, a.B, w->Bp());
     k_bpack<<<gpe, kWG, 0, st>>>(w->n, k, w->pw, a.X0, w->Xp());
     // rho0_c = ||b_c - A x0_c|| (unprojected); the tests use ||P (b_c - A x_c)||.
@@ -1305,7 +1314,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             hipMemsetAsync(w->flag, 0, sizeof(int), st) != hipSuccess ||
             hipMemsetAsync(w->imap + 2 * kBW, 0, kBW * sizeof(int), st) != hipSuccess)
             return kStatusDevice;
-        k_bselect<<<grow, kWG, 0, st>>>(w->n, w->pw, w->imap, w->W());
+        k_bselect<<<gpe, kWG, 0, st>>>(w->n, w->pw, w->imap, w->W());
         cholqr2(*w, a.timer, st, ka, w->W(), w->V(), 1, nullptr, nullptr);
         // A residual column dependent on the earlier ones adds no basis
         // vector: keep kb independent columns, S = their rows of R (kb x ka).
@@ -1331,7 +1340,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
             for (int c = 0; c < kBW; ++c) cmap[c] = c < kb ? indep[c] : -1;
             if (hipMemcpyAsync(w->imap, cmap, kBW * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
                 return kStatusDevice;
-            k_bselect<<<grow, kWG, 0, st>>>(w->n, w->pw, w->imap, w->V());
+            k_bselect<<<gpe, kWG, 0, st>>>(w->n, w->pw, w->imap, w->V());
         }
         // flag[0]: breakdown / convergence bits, flag[1]: the cycle has
         // ended (gate of its later kernels), flag[2]: steps done.  The
