@@ -79,13 +79,15 @@ __global__ __launch_bounds__(kWG) void k_bunpack(int64_t n, int k, int pw, const
 // X += Z S (coarse correction at exit, eq. precond2).
 //
 // Partial sums of T: workgroup (c, ch) sums chunk ch (of nch) of row c of
-// Z^T, 16 entries per round with one lane per panel column, four rounds'
-// index loads issued before their gathers; fixed order.
-__global__ __launch_bounds__(kWG) void k_bzt(int nch, int pw, const int* __restrict__ ztrp,
+// Z^T, kWG / PW entries per round with one lane per panel column, four
+// rounds' index loads issued before their gathers; fixed order.  Columns
+// PW..15 of a partial are zero.
+template <int PW>
+__global__ __launch_bounds__(kWG) void k_bzt(int nch, const int* __restrict__ ztrp,
                                              const int* __restrict__ ztci, const double* __restrict__ ztv,
                                              const double* __restrict__ W, double* __restrict__ zpart,
                                              const int* __restrict__ stop) {
-    constexpr int RG = kWG / kBW;   // entries per round
+    constexpr int RG = kWG / PW;   // entries per round
     constexpr int U = 4;
     __shared__ double red[kWG];
     if (stop && *stop) return;   // a later step of a cycle that has ended
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(kWG) void k_bzt(int nch, int pw, const int* __restr
     const int q0 = ztrp[c], q1 = ztrp[c + 1];
     const int cl = (q1 - q0 + nch - 1) / nch;
     const int a0 = q0 + ch * cl, a1 = min(q1, a0 + cl);
-    const int l = threadIdx.x & (kBW - 1), g = threadIdx.x / kBW;
+    const int l = threadIdx.x & (PW - 1), g = threadIdx.x / PW;
     double acc = 0.0;
     for (int q = a0 + g; q < a1; q += U * RG) {
         int row[U];
@@ -105,13 +107,14 @@ __global__ __launch_bounds__(kWG) void k_bzt(int nch, int pw, const int* __restr
             zvv[u] = qu < a1 ? ztv[qu] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc += l < pw ? zvv[u] * W[(int64_t)row[u] * pw + l] : 0.0;
+        for (int u = 0; u < U; ++u) acc += zvv[u] * W[(int64_t)row[u] * PW + l];
     }
     red[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < kBW) {
         double t = 0.0;
-        for (int i = 0; i < RG; ++i) t += red[i * kBW + threadIdx.x];
+        if (threadIdx.x < PW)
+            for (int i = 0; i < RG; ++i) t += red[i * PW + threadIdx.x];
         zpart[((int64_t)c * nch + ch) * kBW + threadIdx.x] = t;
     }
 }
@@ -1229,7 +1232,11 @@ void coarse(const BlockWork& w, const BlockArgs& a, const double* P, const int* 
     // About 256 entries of Z^T per workgroup (Z's rows are shared out over
     // its columns), at most kZtChunksMax workgroups per column.
     const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(kZtChunksMax, (w.n + 256LL * a.R - 1) / (256LL * a.R)));
-    k_bzt<<<dim3((unsigned)a.R, (unsigned)nch), kWG, 0, a.st>>>(nch, w.pw, a.ztrp, a.ztci, a.ztv, P, w.zpart, stop);
+    if (w.pw == 8)
+        k_bzt<8><<<dim3((unsigned)a.R, (unsigned)nch), kWG, 0, a.st>>>(nch, a.ztrp, a.ztci, a.ztv, P, w.zpart, stop);
+    else
+        k_bzt<kBW><<<dim3((unsigned)a.R, (unsigned)nch), kWG, 0, a.st>>>(nch, a.ztrp, a.ztci, a.ztv, P, w.zpart,
+                                                                        stop);
     k_bcoarse<<<1, kWG, 0, a.st>>>(a.R, nch, w.zpart, a.Einv, w.Sz, stop);
 }
 
