@@ -1077,25 +1077,26 @@ int block_bind(BlockWork* w, void* mem, size_t bytes, hipStream_t st, int64_t n,
 
 namespace {
 
-// k_bdots over nb = nv + gram blocks with the fewest slots per workgroup
-// that hold them (1, 2, 4, then kDotGroup): every slot loads a panel and
-// issues a matrix-core step per row step, used or not, so a Gram block alone
-// runs on one slot.
+// k_bdots over nb = nv + gram blocks: ceil(nb / kDotGroup) groups of workgroups
+// with the fewest slots each that hold the blocks (nb = 9: three groups of
+// three).  Every slot loads a panel and issues a matrix-core step per row
+// step, used or not, so unused slots cost loads and matrix-core time.
 template <int PW>
 void launch_dots(const BlockWork& w, BlockTimer* tm, double bytes, hipStream_t st, const double* V, int nv,
                  const double* W, int gram, const int* stop) {
+    static_assert(kDotGroup == 4, "slot counts 1..4 are instantiated");
     const int nb = nv + gram;
-    const int ng = nb <= 1 ? 1 : nb <= 2 ? 2 : nb <= 4 ? 4 : kDotGroup;
-    const dim3 grid(kDotGrid, (nb + ng - 1) / ng);
+    const int groups = (nb + kDotGroup - 1) / kDotGroup;
+    const int ng = (nb + groups - 1) / groups;
+    const dim3 grid(kDotGrid, groups);
     if (ng == 1)
         blaunch(tm, 5, bytes, k_bdots<1, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
     else if (ng == 2)
         blaunch(tm, 5, bytes, k_bdots<2, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
-    else if (ng == 4)
-        blaunch(tm, 5, bytes, k_bdots<4, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
+    else if (ng == 3)
+        blaunch(tm, 5, bytes, k_bdots<3, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
     else
-        blaunch(tm, 5, bytes, k_bdots<kDotGroup, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part,
-                stop);
+        blaunch(tm, 5, bytes, k_bdots<4, PW>, grid, dim3(kWG), st, w.n_pad, w.ps, V, nv, W, gram, w.part, stop);
 }
 
 // C[0 .. nb) = P^T W (panels of V, then W itself when gram), summed.
