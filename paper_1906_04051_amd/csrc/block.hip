@@ -440,9 +440,12 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
 // comes out with lane l holding rows r0 + l/16 + 4r, column l%16 -- the B
 // operand layout of the dot products -- so only the panels' tiles are read a
 // second time for the dots, in that layout, right after the first read
-// (from the caches).  nb <= NBMAX accumulators per lane.
+// (from the caches).  nb <= NBMAX accumulators per lane.  The 16-wide
+// instance is held to 128 registers (four wavefronts per SIMD, no spills);
+// the 8-wide one would spill there and keeps three.
 template <int NBMAX, int PW>
-__global__ __launch_bounds__(kWG) void k_bgemm_dots(int64_t n_pad, int64_t ps, const double* V, int nb,
+__global__ __launch_bounds__(kWG, PW == 16 ? 4 : 1) void k_bgemm_dots(int64_t n_pad, int64_t ps, const double* V,
+                                                                     int nb,
                                                     const double* __restrict__ C, const double* IN,
                                                     double* OUT, double* __restrict__ part,
                                                     const int* __restrict__ stop) {
@@ -1149,9 +1152,10 @@ int resident_grid(const void* kernel, int* cache) {
     return cache[dev];
 }
 
+template <int PW>
 int fused_grid() {
     static int cache[64] = {};
-    return resident_grid(reinterpret_cast<const void*>(k_bgemm_dots<kFuseMax, kBW>), cache);
+    return resident_grid(reinterpret_cast<const void*>(k_bgemm_dots<kFuseMax, PW>), cache);
 }
 
 int gram_grid() {
@@ -1162,7 +1166,7 @@ int gram_grid() {
 void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, double* W,
                double* acc_into, int acc_blocks, const int* stop) {
     const double bytes = (double)(nb + 2) * (double)w.n * w.pw * sizeof(double);   // panels once, W in and out
-    const int grid = fused_grid();
+    const int grid = w.pw == 8 ? fused_grid<8>() : fused_grid<kBW>();
     if (w.pw == 8)
         blaunch(tm, 6, bytes, k_bgemm_dots<kFuseMax, 8>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb,
                 (const double*)w.C, (const double*)W, W, w.part, stop);
