@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const 
                                                double sign, double* OUT, const int* __restrict__ stop) {
     if (stop && *stop) return;   // a later step of a cycle that has ended
     constexpr int pw = PW;
-    __shared__ double cs[(kBlockStepsMax + 1) * kPan];
+    extern __shared__ double cs[];   // nb coefficient blocks (dynamic)
     for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
     __syncthreads();
     const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -540,16 +540,16 @@ __global__ __launch_bounds__(kWG, PW == 16 ? 4 : 1) void k_bgemm_dots(int64_t n_
 // block OUT^T OUT of this workgroup's tiles.  The new tile leaves the product
 // in the layout both operands of the dot step take (as in k_bgemm_dots), so
 // the Gram block needs no second read of OUT.  One 16-row tile per wavefront;
-// the coefficients' LDS holds the wavefronts' accumulators at the end.
+// the coefficients' LDS (sized for max(nb, kWG / kWave) blocks at launch)
+// holds the wavefronts' accumulators at the end.
 template <int PW>
 __global__ __launch_bounds__(kWG) void k_bgemm_gram(int64_t n_pad, int64_t ps, const double* V, int nb,
                                                     const double* __restrict__ C, const double* IN, double sign,
                                                     double* OUT, double* __restrict__ part,
                                                     const int* __restrict__ stop) {
-    static_assert((kBlockStepsMax + 1) * kPan >= (kWG / kWave) * kPan, "accumulators fit in the coefficients' LDS");
     if (stop && *stop) return;   // a later step of a cycle that has ended
     constexpr int pw = PW;
-    __shared__ double cs[(kBlockStepsMax + 1) * kPan];
+    extern __shared__ double cs[];   // max(nb, 4) blocks (dynamic): coefficients, then accumulators
     for (int t = threadIdx.x; t < nb * kPan; t += kWG) cs[t] = C[t];
     __syncthreads();
     const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -940,15 +940,21 @@ __global__ __launch_bounds__(kWG) void k_bsolve(int nblk, int k, int ka, LsView 
 // Launch through the timing hook when there is one: the kernel carries the
 // armed start/stop events in its own dispatch.
 template <typename... KA, typename... A>
-void blaunch(BlockTimer* tm, int kind, double bytes, void (*k)(KA...), dim3 g, dim3 b, hipStream_t st,
-             A... args) {
+void blaunch_shm(BlockTimer* tm, int kind, double bytes, void (*k)(KA...), dim3 g, dim3 b, size_t shm,
+                 hipStream_t st, A... args) {
     hipEvent_t e0, e1;
     if (tm) tm->begin(kind, bytes);
     if (tm && take_kernel_events(&e0, &e1))
-        hipExtLaunchKernelGGL(k, g, b, 0, st, e0, e1, 0u, static_cast<KA>(args)...);
+        hipExtLaunchKernelGGL(k, g, b, shm, st, e0, e1, 0u, static_cast<KA>(args)...);
     else
-        k<<<g, b, 0, st>>>(static_cast<KA>(args)...);
+        k<<<g, b, shm, st>>>(static_cast<KA>(args)...);
     if (tm) tm->end();
+}
+
+template <typename... KA, typename... A>
+void blaunch(BlockTimer* tm, int kind, double bytes, void (*k)(KA...), dim3 g, dim3 b, hipStream_t st,
+             A... args) {
+    blaunch_shm(tm, kind, bytes, k, g, b, 0, st, args...);
 }
 
 constexpr int kDotGroup = 4;   // panels per workgroup of the dot kernel
@@ -1122,10 +1128,13 @@ void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
     const int64_t ntile = w.n_pad / kBW;
     const int grid = (int)std::min<int64_t>((ntile + 3) / 4, 8192);
     const double bytes = (double)(nb + (IN ? 1 : 0) + 1) * (double)w.n * w.pw * sizeof(double);
+    const size_t shm = (size_t)nb * kPan * sizeof(double);   // the coefficient blocks
     if (w.pw == 8)
-        blaunch(tm, 6, bytes, k_bgemm<8>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT, stop);
+        blaunch_shm(tm, 6, bytes, k_bgemm<8>, dim3(grid), dim3(kWG), shm, st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT,
+                    stop);
     else
-        blaunch(tm, 6, bytes, k_bgemm<kBW>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT, stop);
+        blaunch_shm(tm, 6, bytes, k_bgemm<kBW>, dim3(grid), dim3(kWG), shm, st, w.n_pad, w.ps, V, nb, C, IN, sign,
+                    OUT, stop);
 }
 
 // W -= V C (C: the first projection's coefficients in w.C), then the second
@@ -1134,16 +1143,16 @@ void gemm(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, i
 constexpr int kFuseMax = 8;   // panels of the fused sweep (accumulators per lane)
 
 // Workgroups of a sweep that leaves one partial per workgroup: one round of
-// resident workgroups of `kernel` (at most kDotGrid, the partial-sum
-// capacity), looked up once per device into cache.
+// resident workgroups of `kernel` with shm bytes of dynamic LDS (at most
+// kDotGrid, the partial-sum capacity), looked up once per device into cache.
 std::mutex g_grid_mu;
-int resident_grid(const void* kernel, int* cache) {
+int resident_grid(const void* kernel, int* cache, size_t shm = 0) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kDotGrid;
     std::lock_guard<std::mutex> lk(g_grid_mu);
     if (cache[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWG, 0) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWG, shm) != hipSuccess || per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 1;
@@ -1158,9 +1167,15 @@ int fused_grid() {
     return resident_grid(reinterpret_cast<const void*>(k_bgemm_dots<kFuseMax, PW>), cache);
 }
 
-int gram_grid() {
-    static int cache[64] = {};
-    return resident_grid(reinterpret_cast<const void*>(k_bgemm_gram<kBW>), cache);
+// Dynamic LDS of k_bgemm_gram for nb coefficient blocks (the wavefronts'
+// accumulators reuse it), and its resident grid.
+size_t gram_shm(int nb) { return (size_t)std::max(nb, kWG / kWave) * kPan * sizeof(double); }
+
+template <int PW>
+int gram_grid(int nb) {
+    static int cache[kBlockStepsMax + 2][64] = {};
+    const int blocks = std::max(nb, kWG / kWave);
+    return resident_grid(reinterpret_cast<const void*>(k_bgemm_gram<PW>), cache[blocks], gram_shm(nb));
 }
 
 void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, double* W,
@@ -1182,14 +1197,17 @@ void gemm_dots(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double*
 // dots() call of OUT's Gram block alone would); one sweep.
 void gemm_gram(const BlockWork& w, BlockTimer* tm, hipStream_t st, const double* V, int nb, const double* C,
                const double* IN, double sign, double* OUT, const int* stop) {
-    const int grid = gram_grid();
     const double bytes = (double)(nb + (IN ? 1 : 0) + 1) * (double)w.n * w.pw * sizeof(double);
-    if (w.pw == 8)
-        blaunch(tm, 6, bytes, k_bgemm_gram<8>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT,
-                w.part, stop);
-    else
-        blaunch(tm, 6, bytes, k_bgemm_gram<kBW>, dim3(grid), dim3(kWG), st, w.n_pad, w.ps, V, nb, C, IN, sign, OUT,
-                w.part, stop);
+    int grid;
+    if (w.pw == 8) {
+        grid = gram_grid<8>(nb);
+        blaunch_shm(tm, 6, bytes, k_bgemm_gram<8>, dim3(grid), dim3(kWG), gram_shm(nb), st, w.n_pad, w.ps, V, nb, C,
+                    IN, sign, OUT, w.part, stop);
+    } else {
+        grid = gram_grid<kBW>(nb);
+        blaunch_shm(tm, 6, bytes, k_bgemm_gram<kBW>, dim3(grid), dim3(kWG), gram_shm(nb), st, w.n_pad, w.ps, V, nb,
+                    C, IN, sign, OUT, w.part, stop);
+    }
     k_breduce<<<kPan / kBW, kWG, 0, st>>>(grid, kPan, w.part, w.C, nullptr, 0, 0, -1, nullptr, stop);
 }
 
