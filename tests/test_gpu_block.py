@@ -85,7 +85,10 @@ def gpu_block(s, B, m_block, rtol, max_steps, X0=None, timing=0):
     return out, info, kt
 
 
-@pytest.mark.parametrize("k,m", [(1, 6), (3, 4), (8, 3), (16, 2)])
+# m > 8 runs the first projection and the second dots as separate sweeps (the
+# fused sweep holds 8 panels) and sizes the products' coefficient LDS up to
+# 16 blocks; m = 16 is the largest cycle.
+@pytest.mark.parametrize("k,m", [(1, 6), (3, 4), (8, 3), (16, 2), (2, 12), (9, 10), (5, 16)])
 def test_fixed_count_parity(k, m):
     s = no_defl(W.make_config(1, mesh=24))      # 625 unknowns (ragged against 64)
     rng = np.random.default_rng(100 + k)
