@@ -395,9 +395,9 @@ __device__ __forceinline__ d4 tile_product(const double* V, int64_t ps, int nb, 
 }
 
 // OUT = IN + sign * sum_{i < nb} P_i C_i (P_i = panel i of V, C_i = C[i*256 ..]
-// row-major 16x16), one 16-row tile per wavefront; IN may be NULL; IN, OUT and
-// the panels may alias (a tile is read completely before it is written, by
-// the same wavefront).
+// row-major 16x16, staged in nb * 2 KB of dynamic LDS given at launch), one
+// 16-row tile per wavefront; IN may be NULL; IN, OUT and the panels may alias
+// (a tile is read completely before it is written, by the same wavefront).
 template <int PW>
 __global__ __launch_bounds__(kWG) void k_bgemm(int64_t n_pad, int64_t ps, const double* V, int nb,
                                                const double* __restrict__ C, const double* IN,
