@@ -144,26 +144,28 @@ __global__ __launch_bounds__(kWG) void k_bcoarse(int R, int nch, const double* _
 }
 
 // P += sign * M S over the rows of the CSR matrix M (n x R, local columns):
-// sign -1 with M = A Z projects W, sign +1 with M = Z corrects X.  16 lanes
-// per row, S staged in LDS.
-__global__ __launch_bounds__(kWG) void k_bzapply(int64_t n, int R, int pw, const int* __restrict__ mrp,
+// sign -1 with M = A Z projects W, sign +1 with M = Z corrects X.  PW lanes
+// per row (one per panel column), S (R x 16) staged in LDS.
+template <int PW>
+__global__ __launch_bounds__(kWG) void k_bzapply(int64_t n, int R, const int* __restrict__ mrp,
                                                  const int* __restrict__ mci, const double* __restrict__ mv,
                                                  const double* __restrict__ S, double sign, double* __restrict__ P,
                                                  const int* __restrict__ stop) {
+    constexpr int rpr = kWG / PW;   // rows per round
     __shared__ double Ss[kBlockZMax * kBW];
     if (stop && *stop) return;
     for (int e = threadIdx.x; e < R * kBW; e += kWG) Ss[e] = S[e];
     __syncthreads();
-    const int l = threadIdx.x & (kBW - 1), rl = threadIdx.x / kBW;
-    for (int64_t r0 = (int64_t)blockIdx.x * (kWG / kBW); r0 < n; r0 += (int64_t)gridDim.x * (kWG / kBW)) {
+    const int l = threadIdx.x & (PW - 1), rl = threadIdx.x / PW;
+    for (int64_t r0 = (int64_t)blockIdx.x * rpr; r0 < n; r0 += (int64_t)gridDim.x * rpr) {
         const int64_t row = r0 + rl;
-        if (row >= n || l >= pw) continue;
+        if (row >= n) continue;
         double t = 0.0;
         for (int q = mrp[row]; q < mrp[row + 1]; ++q) {
             GM_DCHECK(mci[q] >= 0 && mci[q] < R, kDbgBlockCol);
             t += mv[q] * Ss[mci[q] * kBW + l];
         }
-        P[row * pw + l] += sign * t;
+        P[row * PW + l] += sign * t;
     }
 }
 
@@ -1263,12 +1265,23 @@ void coarse(const BlockWork& w, const BlockArgs& a, const double* P, const int* 
     k_bcoarse<<<1, kWG, 0, a.st>>>(a.R, nch, w.zpart, a.Einv, w.Sz, stop);
 }
 
+// P += sign * M S (k_bzapply, S in w.Sz): pw lanes per row, kWG / pw rows per
+// workgroup and round, 4096 workgroups at most.
+void zapply(const BlockWork& w, hipStream_t st, int R, const int* mrp, const int* mci, const double* mv,
+            double sign, double* P, const int* stop) {
+    const int rpr = kWG / w.pw;
+    const unsigned g = (unsigned)std::min<int64_t>((w.n + rpr - 1) / rpr, 4096);
+    if (w.pw == 8)
+        k_bzapply<8><<<g, kWG, 0, st>>>(w.n, R, mrp, mci, mv, w.Sz, sign, P, stop);
+    else
+        k_bzapply<kBW><<<g, kWG, 0, st>>>(w.n, R, mrp, mci, mv, w.Sz, sign, P, stop);
+}
+
 // W = P W = W - A Z E^{-1} Z^T W (no-op without a deflation basis).
 void project(const BlockWork& w, const BlockArgs& a, double* W, const int* stop) {
     if (a.R == 0) return;
     coarse(w, a, W, stop);
-    const unsigned g16 = (unsigned)std::min<int64_t>((w.n + kWG / kBW - 1) / (kWG / kBW), 4096);
-    k_bzapply<<<g16, kWG, 0, a.st>>>(w.n, a.R, w.pw, a.azrp, a.azci, a.azv, w.Sz, -1.0, W, stop);
+    zapply(w, a.st, a.R, a.azrp, a.azci, a.azv, -1.0, W, stop);
 }
 
 // W = B - A X, h_raw[c] = ||w_c||; then W = P W and h_nrm[c] = ||P w_c||
@@ -1428,8 +1441,7 @@ int block_solve(BlockWork* w, const BlockArgs& a, BlockResult* res) {
         spmm(*w, a, 1, dim3(kNormGrid), st, (const double*)w->Xp(), (const double*)w->Bp(), w->W(), w->npart,
              nullptr);
         coarse(*w, a, w->W(), nullptr);
-        const unsigned g16 = (unsigned)std::min<int64_t>((w->n + kWG / kBW - 1) / (kWG / kBW), 4096);
-        k_bzapply<<<g16, kWG, 0, st>>>(w->n, a.R, w->pw, a.zrp, a.zci, a.zv, w->Sz, 1.0, w->Xp(), nullptr);
+        zapply(*w, st, a.R, a.zrp, a.zci, a.zv, 1.0, w->Xp(), nullptr);
         if ((s = residual(*w, a, raw, rn)) != kStatusOk) return s;
         for (int c = 0; c < k; ++c) rn[c] = raw[c];
     }
